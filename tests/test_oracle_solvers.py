@@ -1,0 +1,252 @@
+"""Pins for the oracle's Krylov solvers, block-Jacobi and mixed-precision IR.
+
+The paper (Sec. 6.2) benchmarks memory-bound Krylov solvers built on SpMV but
+does not write them out; the oracle follows the textbook algorithms (CG:
+Hestenes-Stiefel / Saad Alg. 9.1; BiCGSTAB: van der Vorst 1992).  Pinned by
+finite termination, closed-form spectra (condition numbers, iteration bounds),
+manufactured solutions and exact preconditioners.
+"""
+import math
+
+import numpy as np
+import pytest
+
+
+def diag_csr(d):
+    n = len(d)
+    return (np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.asarray(d, float))
+
+
+def dense_to_csr(D):
+    rp, col, val = [0], [], []
+    for i in range(D.shape[0]):
+        for j in range(D.shape[1]):
+            if D[i, j] != 0:
+                col.append(j)
+                val.append(D[i, j])
+        rp.append(len(col))
+    return np.array(rp, np.int32), np.array(col, np.int32), np.array(val)
+
+
+# --------------------------------------------------------------------------- BLAS-1
+def test_dot_norm_closed_forms(orc):
+    assert orc.dot(np.ones(1000), np.ones(1000)) == 1000.0
+    assert orc.norm2(np.array([3.0, 4.0])) == 5.0
+    x = np.arange(1, 101, dtype=float)
+    assert orc.dot(x, x) == 100 * 101 * 201 / 6          # sum of squares, exact in FP64
+    e = np.zeros(50)
+    e[17] = 1.0
+    y = np.linspace(-1, 1, 50)
+    assert orc.dot(e, y) == y[17]
+    assert orc.dot(np.zeros(0), np.zeros(0)) == 0.0
+
+
+# --------------------------------------------------------------------------- CG
+def test_cg_finite_termination_three_eigenvalues(orc, gen_mod):
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    b = gen_mod.uniform(31, 50)
+    rc, x, info = orc.cg(diag_csr(d), b, tol=1e-12, maxit=100)
+    assert rc == orc.OK
+    assert info["iters"] <= 3 and info["true_relres"] <= 1e-12
+    assert np.allclose(x, b / d, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n", [1, 2, 5, 8])
+def test_cg_tiny_spd_terminates_in_n(orc, n):
+    rng = np.random.default_rng(n)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    D = Q @ np.diag(np.linspace(1.0, 4.0, n)) @ Q.T       # SPD, kappa = 4
+    D = (D + D.T) / 2
+    b = rng.uniform(-1, 1, n)
+    rc, x, info = orc.cg(dense_to_csr(D), b, tol=1e-10, maxit=100)
+    assert rc == orc.OK and info["iters"] <= n
+    assert np.linalg.norm(D @ x - b) <= 1e-10 * np.linalg.norm(b) * 1.0001
+
+
+def test_cg_config1_manufactured_and_iteration_bound(orc, gen_mod):
+    N = 64
+    A = gen_mod.laplace2d(N)
+    xs = gen_mod.uniform(2, N * N)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.cg(A, b, tol=1e-10, maxit=5000)
+    assert rc == orc.OK and info["true_relres"] <= 1e-10
+    lmin = 4 - 4 * math.cos(math.pi / (N + 1))
+    lmax = 4 + 4 * math.cos(math.pi / (N + 1))
+    kappa = lmax / lmin
+    assert abs(kappa - 1711.7) < 0.5
+    bound = math.ceil(0.5 * math.sqrt(kappa) * math.log(2 / 1e-10))
+    assert bound == 491 and info["iters"] <= bound
+    err = np.linalg.norm(x - xs) / np.linalg.norm(xs)
+    assert err <= kappa * info["true_relres"]
+
+
+def test_cg_zero_rhs_nan_and_indefinite(orc, gen_mod):
+    A = gen_mod.laplace1d(20)
+    rc, x, info = orc.cg(A, np.zeros(20), x0=np.ones(20))
+    assert rc == orc.OK and info["iters"] == 0 and np.all(x == 0)
+    b = np.ones(20)
+    b[3] = np.nan
+    rc, x, info = orc.cg(A, b)
+    assert rc == orc.BREAKDOWN
+    rc, x, info = orc.cg(diag_csr([1.0, 2.0, -1.0, 3.0]), np.ones(4))
+    assert rc == orc.NOT_SPD
+    rc, x, info = orc.cg(gen_mod.laplace2d(32), np.ones(1024), tol=1e-10, maxit=5)
+    assert rc == orc.NOT_CONVERGED and info["iters"] == 5
+
+
+def test_cg_initial_guess_already_solution(orc, gen_mod):
+    A = gen_mod.laplace1d(30)
+    xs = gen_mod.uniform(5, 30)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.cg(A, b, x0=xs)
+    assert rc == orc.OK and info["iters"] == 0
+
+
+# --------------------------------------------------------------------------- block-Jacobi
+def cheb_u(k, t):
+    """Chebyshev polynomial of the second kind U_k(t)."""
+    if k < 0:
+        return 0.0
+    a, b = 1.0, 2 * t
+    if k == 0:
+        return a
+    for _ in range(k - 1):
+        a, b = b, 2 * t * b - a
+    return b
+
+
+def tridiag_inverse(m, a):
+    """Closed form inverse of tridiag(-1, a, -1) (order m): U_{i-1} U_{m-j} / U_m at a/2, i <= j."""
+    t = a / 2
+    inv = np.empty((m, m))
+    for i in range(1, m + 1):
+        for j in range(1, m + 1):
+            lo, hi = min(i, j), max(i, j)
+            inv[i - 1, j - 1] = cheb_u(lo - 1, t) * cheb_u(m - hi, t) / cheb_u(m, t)
+    return inv
+
+
+def test_bj_blocks_of_poisson_match_closed_form(orc, gen_mod):
+    A = gen_mod.laplace3d(16)        # blocks of 8 rows along x: tridiag(-1, 6, -1)
+    rc, inv = orc.bj_invert(A, 8)
+    assert rc == orc.OK
+    ref = tridiag_inverse(8, 6.0)
+    assert np.max(np.abs(inv - ref[None])) <= 1e-15 * 8
+    A = gen_mod.laplace2d(24)        # tridiag(-1, 4, -1)
+    rc, inv = orc.bj_invert(A, 8)
+    assert np.max(np.abs(inv - tridiag_inverse(8, 4.0)[None])) <= 1e-15 * 8
+
+
+def test_bj_pivoting_short_last_block_and_identity(orc):
+    rng = np.random.default_rng(7)
+    n, bs = 21, 8                      # last block has 5 rows
+    D = np.zeros((n, n))
+    for b0 in range(0, n, bs):
+        m = min(bs, n - b0)
+        B = rng.uniform(-1, 1, (m, m))
+        B[0, 0] = 0.0                  # forces a row exchange
+        D[b0:b0 + m, b0:b0 + m] = B
+    D[3, 15] = 0.5                     # off-block entries are ignored
+    rc, inv = orc.bj_invert(dense_to_csr(D), bs)
+    assert rc == orc.OK
+    for k, b0 in enumerate(range(0, n, bs)):
+        m = min(bs, n - b0)
+        P = D[b0:b0 + m, b0:b0 + m] @ inv[k, :m, :m]
+        assert np.max(np.abs(P - np.eye(m))) <= 1e-13 * np.linalg.cond(D[b0:b0 + m, b0:b0 + m])
+    singular = dense_to_csr(np.diag([1.0, 0.0, 2.0]))
+    assert orc.bj_invert(singular, 8)[0] == orc.BREAKDOWN
+
+
+def test_pcg_exact_block_preconditioner_converges_in_one(orc):
+    rng = np.random.default_rng(9)
+    n, bs = 40, 8
+    D = np.zeros((n, n))
+    for b0 in range(0, n, bs):
+        G = rng.standard_normal((bs, bs))
+        D[b0:b0 + bs, b0:b0 + bs] = G @ G.T + bs * np.eye(bs)
+    A = dense_to_csr(D)
+    rc, inv = orc.bj_invert(A, bs)
+    b = rng.uniform(-1, 1, n)
+    rc, x, info = orc.cg(A, b, tol=1e-12, bj_inv=inv, bs=bs)
+    assert rc == orc.OK and info["iters"] == 1
+
+
+# --------------------------------------------------------------------------- BiCGSTAB
+def test_bicgstab_convdiff_manufactured(orc, gen_mod):
+    A = gen_mod.convdiff2d(40, 0.5)
+    xs = gen_mod.uniform(8, 1600)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.bicgstab(A, b, tol=1e-10, maxit=2000)
+    assert rc == orc.OK and info["true_relres"] <= 1e-10 * 1.01
+    r = b - orc.spmv(A, x)
+    assert np.linalg.norm(r) <= 1.01e-10 * np.linalg.norm(b)
+
+
+def test_bicgstab_scaled_identity_one_step_and_spd(orc, gen_mod):
+    b = gen_mod.uniform(3, 10)
+    rc, x, info = orc.bicgstab(diag_csr([2.5] * 10), b)
+    assert rc == orc.OK and info["iters"] == 1 and np.allclose(x, b / 2.5, rtol=1e-15, atol=0)
+    A = gen_mod.laplace2d(64)
+    xs = gen_mod.uniform(2, 4096)
+    rc, x, info = orc.bicgstab(A, orc.spmv(A, xs), tol=1e-10)
+    assert rc == orc.OK and info["true_relres"] <= 1.01e-10
+
+
+def test_bicgstab_breakdown(orc):
+    # A = [[0,1],[1,0]], b = e1: rhat.v = e1 . e2 = 0 at the first step
+    A = (np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    rc, x, info = orc.bicgstab(A, np.array([1.0, 0.0]))
+    assert rc == orc.BREAKDOWN
+
+
+# --------------------------------------------------------------------------- mixed precision
+def test_ir_cg_reaches_fp64_accuracy(orc, gen_mod):
+    N = 16
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    xs = gen_mod.uniform(5, n)
+    b = orc.spmv(A, xs)
+    rc, inv = orc.bj_invert(A, 8)
+    rc, x, info = orc.ir_cg(A, b, tol=1e-10, inner_tol=1e-5, bj_inv=inv)
+    assert rc == orc.OK
+    true = np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
+    assert true <= 1e-10
+    lmin = 6 - 6 * math.cos(math.pi / (N + 1))
+    lmax = 6 + 6 * math.cos(math.pi / (N + 1))
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= (lmax / lmin) * 1e-10
+    # an FP32-only solve cannot get there: the refinement is what carries it
+    assert 2 <= info["outer_iters"] <= 6
+    rc64, x64, _ = orc.cg(A, b, tol=1e-10, bj_inv=inv)
+    assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 2 * (lmax / lmin) * 1e-10
+
+
+def test_ir_cg_stagnation_reported(orc, gen_mod):
+    A = gen_mod.laplace2d(32)
+    b = orc.spmv(A, gen_mod.uniform(1, 1024))
+    # one inner iteration per outer step cannot halve the residual every time
+    rc, x, info = orc.ir_cg(A, b, tol=1e-10, max_outer=50, inner_tol=1e-5, max_inner=1)
+    assert rc == orc.NOT_CONVERGED
+
+
+# --------------------------------------------------------------------------- batched
+def test_batch_cg_closed_form_bounds(orc, gen_mod):
+    B = gen_mod.batch_systems(40, master_seed=6)
+    b = np.empty_like(B.xstar)
+    for i in range(B.nsys):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        b[r0:r1] = orc.spmv(B.system(i), B.xstar[r0:r1])
+    rc, x, iters, rr = orc.batch_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val, b, tol=1e-10)
+    assert rc == orc.OK and np.all(rr <= 1e-10)
+    for i in range(B.nsys):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        m, s = int(B.m[i]), float(B.shift[i])
+        if B.pattern[i] == 3:
+            kappa = (2 + s + 2 * math.cos(math.pi / (m + 1))) / (2 + s - 2 * math.cos(math.pi / (m + 1)))
+            assert kappa <= 41
+        else:
+            kappa = (8 + s) / s            # Gershgorin bound, strictly diagonally dominant
+        err = np.linalg.norm(x[r0:r1] - B.xstar[r0:r1]) / np.linalg.norm(B.xstar[r0:r1])
+        assert err <= kappa * 1e-10
+        # identical to a standalone solve of the same system
+        rc1, x1, info = orc.cg(B.system(i), b[r0:r1], tol=1e-10)
+        assert info["iters"] == iters[i] and np.array_equal(x1, x[r0:r1])
