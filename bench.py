@@ -1,0 +1,306 @@
+"""SpMV sweep benchmark on one MI355X, plus the solver measurements.
+
+One step = one FP64 SpMV (y = A x) in every storage format on both matrices
+of the sweep workload: the 3D 27-point stencil on a 128^3 grid (n = 2,097,152,
+nnz = 55,742,968) and a random matrix with n = 1,000,000, lognormal row
+lengths (mean 16, longest row 10,000) and uniform columns.  ELL on the random
+matrix is infeasible (width 10,000) and is skipped.  The two matrices'
+SpMVs alternate so the random matrix (213 MB, small enough for the 256 MB
+last-level cache) never runs right after itself.  Inputs are synthetic and
+seeded, resident in HBM before timing starts.
+
+value = algorithmic bytes of all SpMVs of a step / step time (GB/s).
+Algorithmic bytes per SpMV (value size s, beta = 0; x read once, y written once):
+  CSR, CSR_MERGE: nnz (s+4) + (n+1) 4 + n_cols s + n s
+  COO:            nnz (s+8) + n_cols s + n s
+  ELL:            n K (s+4) + n_cols s + n s
+  HYBRID:         n K (s+4) + tail (s+8) + n_cols s + n s (+ n s when a tail exists)
+The paper's own model (Sec. 6.1) counts only the matrix entries: 12 bytes per
+CSR entry and 16 per COO entry.
+
+After the timed sweep (outside it): CG on the 2D 5-point Laplacian 64x64
+(to 1e-10), and block-Jacobi PCG on the 3D 7-point Poisson 256^3 in FP64 and
+in mixed precision (FP32 inner solve, FP64 refinement), each to 1e-10.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def spmv_bytes(desc, s=8):
+    n, m, nnz = desc.n_rows, desc.n_cols, desc.nnz
+    f = desc.format
+    if f in ("csr", "csr_merge"):
+        return nnz * (s + 4) + (n + 1) * 4 + m * s + n * s
+    if f == "coo":
+        return nnz * (s + 8) + m * s + n * s
+    if f == "ell":
+        return n * desc.ell_width * (s + 4) + m * s + n * s
+    if f == "hybrid":
+        b = n * desc.ell_width * (s + 4) + desc.coo_nnz * (s + 8) + m * s + n * s
+        return b + (n * s if desc.coo_nnz else 0)
+    raise ValueError(f)
+
+
+def csr_bytes(n, m, nnz, s=8):
+    return nnz * (s + 4) + (n + 1) * 4 + m * s + n * s
+
+
+def log(msg):
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def build_sweep(g, gen, torch):
+    mats = []
+    t0 = time.time()
+    st = gen.stencil27(128)
+    log("stencil27 128^3 generated (%.1fs)" % (time.time() - t0))
+    t0 = time.time()
+    rnd = gen.random_lognormal(4, 1_000_000, mean=16.0, sigma=1.56, max_len=10000)
+    log("lognormal 1M generated (%.1fs)" % (time.time() - t0))
+    inputs = {"stencil27_128": st, "lognormal_1M": rnd}
+    xs = {name: torch.from_numpy(gen.uniform(3 if name.startswith("st") else 5,
+                                              len(A[0]) - 1)).cuda() for name, A in inputs.items()}
+    base = {name: g.Matrix.from_csr(*A) for name, A in inputs.items()}
+    order = [("stencil27_128", "csr"), ("lognormal_1M", "csr"),
+             ("stencil27_128", "csr_merge"), ("lognormal_1M", "csr_merge"),
+             ("stencil27_128", "coo"), ("lognormal_1M", "coo"),
+             ("stencil27_128", "ell"), ("stencil27_128", "hybrid"), ("lognormal_1M", "hybrid")]
+    for name, fmt in order:
+        M = base[name].clone().convert(fmt)
+        d = M.describe()
+        y = torch.empty(d.n_rows, dtype=torch.float64, device="cuda")
+        mats.append({"matrix": name, "format": fmt, "M": M, "x": xs[name], "y": y, "desc": d,
+                     "bytes": spmv_bytes(d), "useful_bytes": csr_bytes(d.n_rows, d.n_cols, d.nnz),
+                     "flops": 2 * d.nnz})
+    skipped = [{"matrix": "lognormal_1M", "format": "ell", "reason": "unsupported: width 10000"}]
+    try:
+        base["lognormal_1M"].clone().convert("ell")
+        skipped = []
+    except g.GkoError as e:
+        assert e.status == g.ERR_UNSUPPORTED
+    return mats, skipped, inputs, base
+
+
+def cpu_baseline(inputs, budget_s=12.0):
+    """The oracle's serial FP64 CSR SpMV on the stencil matrix, on one host core."""
+    import oracle
+    if not os.path.exists(oracle._LIB):
+        oracle.build()
+    A = inputs["stencil27_128"]
+    n = len(A[0]) - 1
+    x = np.random.default_rng(0).uniform(-1, 1, n)
+    oracle.spmv(A, x)  # warm the pages
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.spmv(A, x)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 200:
+            break
+    per = el / reps
+    gbs = csr_bytes(n, n, len(A[1])) / per / 1e9
+    return {"value": round(gbs, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "%d serial FP64 CSR SpMVs of the 27-point 128^3 stencil (%.1f s); "
+                      "same algorithmic byte count as the GPU CSR line" % (reps, el),
+            "seconds_per_spmv": round(per, 4)}
+
+
+def run_solvers(g, gen, torch):
+    import scipy.sparse as sp
+    out = {}
+    ctx = g.default_context()
+    # config 1: 2D 5-point Laplacian 64x64, unpreconditioned FP64 CG to 1e-10
+    A = gen.laplace2d(64)
+    n = 4096
+    S = sp.csr_matrix((A[2], A[1], A[0]), shape=(n, n))
+    xs = gen.uniform(2, n)
+    b = torch.from_numpy(S @ xs).cuda()
+    M = g.Matrix.from_csr(*A)
+    ctx.set_solver_opts()
+    best = None
+    for _ in range(5):
+        x = torch.zeros(n, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = g.cg(M, b, x, tol=1e-10)
+        el = time.perf_counter() - t0
+        best = el if best is None else min(best, el)
+    xh = x.cpu().numpy()
+    out["cg_laplace2d_64"] = {"seconds": round(best, 5), "iterations": info["iterations"],
+                              "true_rel_residual": info["true_rel_residual"],
+                              "rel_error_vs_xstar": float(np.linalg.norm(xh - xs) / np.linalg.norm(xs)),
+                              "status": info["status_name"]}
+    log("config-1 CG: %.2f ms, %d it" % (best * 1e3, info["iterations"]))
+    # config 3: 3D 7-point Poisson 256^3, block-Jacobi(8), FP64 PCG vs mixed IR
+    t0 = time.time()
+    A = gen.laplace3d(256)
+    n = 256 ** 3
+    S = sp.csr_matrix((A[2], A[1], A[0]), shape=(n, n))
+    xs = gen.uniform(5, n)
+    bh = S @ xs
+    log("poisson 256^3 ready (%.1fs)" % (time.time() - t0))
+    b = torch.from_numpy(bh).cuda()
+    M = g.Matrix.from_csr(*A)
+    del A
+    res = {}
+    for label, prec in (("fp64", g.PREC_FP64), ("mixed", g.PREC_MIXED_IR)):
+        ctx.set_solver_opts(precision=prec, precond=g.PRECOND_BLOCK_JACOBI, block_size=8,
+                            inner_tol=1e-5)
+        runs = []
+        for rep in range(2):
+            M2 = M.clone()   # fresh handle: the preconditioner setup is part of the solve
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = g.cg(M2, b, x, tol=1e-10, maxit=20000)
+            el = time.perf_counter() - t0
+            runs.append(el)
+            M2.close()
+        xh = x.cpu().numpy()
+        r = bh - S @ xh
+        res[label] = {"seconds": round(min(runs), 4), "iterations": info["iterations"],
+                      "outer_iterations": info["outer_iterations"],
+                      "setup_seconds": round(info["setup_seconds"], 4),
+                      "true_rel_residual": float(np.linalg.norm(r) / np.linalg.norm(bh)),
+                      "rel_error_vs_xstar": float(np.linalg.norm(xh - xs) / np.linalg.norm(xs)),
+                      "status": info["status_name"]}
+        res[label + "_x"] = xh
+        log("config-3 %s: %.3f s, %d it (%d outer)" % (label, min(runs), info["iterations"],
+                                                      info["outer_iterations"]))
+    x64, xmx = res.pop("fp64_x"), res.pop("mixed_x")
+    res["mixed"]["rel_diff_vs_fp64_solution"] = float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64))
+    res["speedup_mixed_over_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 3)
+    out["pcg_bj8_poisson3d_256"] = res
+    ctx.set_solver_opts()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_2011_08879_amd as g
+
+    if not os.path.exists(gen._LIB):
+        gen.build()
+    torch.cuda.set_device(0)
+    g.default_context()
+    mats, skipped, inputs, base = build_sweep(g, gen, torch)
+    log("sweep matrices on device: %d SpMV kernels per step" % len(mats))
+
+    def step(events=None):
+        for k, e in enumerate(mats):
+            if events is not None:
+                events[k][0].record()
+            g.spmv(e["M"], 1.0, e["x"], 0.0, e["y"])
+            if events is not None:
+                events[k][1].record()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in mats] for _ in range(args.steps)]
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record()
+    for s in range(args.steps):
+        step(ev[s])
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = t_start.elapsed_time(t_end)
+    ms_per_step = total_ms / args.steps
+    step_bytes = sum(e["bytes"] for e in mats)
+    value = step_bytes / (ms_per_step * 1e-3) / 1e9
+
+    per_kernel = []
+    for k, e in enumerate(mats):
+        ms = float(np.mean([ev[s][k][0].elapsed_time(ev[s][k][1]) for s in range(args.steps)]))
+        per_kernel.append({"matrix": e["matrix"], "format": e["format"], "ms": round(ms, 5),
+                           "GB/s": round(e["bytes"] / (ms * 1e-3) / 1e9, 1),
+                           "useful_GB/s": round(e["useful_bytes"] / (ms * 1e-3) / 1e9, 1),
+                           "GFLOP/s": round(e["flops"] / (ms * 1e-3) / 1e9, 1),
+                           "frac_hbm_peak": round(e["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                           "alg_bytes": int(e["bytes"])})
+    dom = max(range(len(mats)), key=lambda k: per_kernel[k]["ms"])
+    d = per_kernel[dom]
+    achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "spmv %s on %s" % (d["format"], d["matrix"]),
+                "alg_bytes_per_launch": d["alg_bytes"]}
+
+    result = {
+        "metric": "SpMV GB/s (% HBM peak); CG s to 1e-10, FP64 vs mixed; batch solves/s",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "FP64 SpMV sweep, formats csr/csr_merge/coo/ell/hybrid: 27-point "
+                               "stencil 128^3 (n=2097152, nnz=55742968) and lognormal random "
+                               "n=1e6 (mean 16, max 10000); one SpMV per format and matrix per step",
+                   "frac_hbm_peak": round(value / HBM_PEAK_GBS, 4),
+                   "step_alg_bytes": int(step_bytes),
+                   "wall_s_timed": round(wall, 4),
+                   "skipped": skipped},
+        "roofline": roofline,
+        "per_kernel": per_kernel,
+    }
+    log("sweep: %.1f GB/s aggregate (%.1f%% of 8 TB/s), %.3f ms/step" %
+        (value, 100 * value / HBM_PEAK_GBS, ms_per_step))
+    for p in per_kernel:
+        log("  %-14s %-10s %8.4f ms %8.1f GB/s" % (p["matrix"], p["format"], p["ms"], p["GB/s"]))
+    for e in mats:
+        e["M"].close()
+    for M in base.values():
+        M.close()
+    del mats
+    torch.cuda.empty_cache()
+
+    if not args.no_solvers:
+        result["solvers"] = run_solvers(g, gen, torch)
+    if not args.no_cpu:
+        log("cpu baseline (oracle, 1 core) ...")
+        result["cpu_baseline"] = cpu_baseline(inputs)
+        log("cpu baseline: %.2f GB/s" % result["cpu_baseline"]["value"])
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * gko.h -- C ABI of the MI355X (gfx950) sparse linear-algebra library.
+ *
+ * The operations are the ones the paper benchmarks: sparse matrix-vector
+ * products in several storage formats (Sec. 6.1) and memory-bound Krylov
+ * solvers built on them (Sec. 6.2).  Device memory and streams are supplied
+ * by the caller (in practice PyTorch); every compute step runs in this
+ * library's own HIP kernels.
+ *
+ * Conventions for every call:
+ *  - Pointers named as device pointers must point to device memory on the
+ *    context's GPU, suitably aligned for their element type.  The library
+ *    never takes ownership of caller memory.
+ *  - Column indices are int32.  Row offsets are int32 internally; int64 row
+ *    offsets are accepted at creation when nnz < 2^31.
+ *  - Work is enqueued on the context's stream.  Calls documented as
+ *    asynchronous return before the GPU finishes; caller buffers must stay
+ *    valid until the stream reaches the call.
+ *  - No call aborts or throws.  Every call returns a gko_status; on failure
+ *    gko_last_error() returns a message for the calling thread.
+ *  - A context and everything created from it belong to one host thread at a
+ *    time (like a BLAS handle).
+ */
+#ifndef GKO_MI355X_H
+#define GKO_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gko_status {
+    GKO_OK = 0,
+    GKO_ERR_INVALID_ARG = 1,   /* bad pointer, size, option or malformed matrix */
+    GKO_ERR_DIM_MISMATCH = 2,  /* operand shapes do not agree */
+    GKO_ERR_UNSUPPORTED = 3,   /* valid request this library does not do (e.g. infeasible ELL) */
+    GKO_ERR_ALLOC = 4,         /* device allocation failed */
+    GKO_ERR_HIP = 5,           /* a HIP runtime call failed */
+    GKO_ERR_NOT_CONVERGED = 6, /* iteration limit reached; x holds the last iterate */
+    GKO_ERR_BREAKDOWN = 7,     /* NaN/Inf, or a zero denominator in the recurrence */
+    GKO_ERR_NOT_SPD = 8        /* CG found p^T A p <= 0 */
+} gko_status;
+
+typedef enum gko_dtype { GKO_F64 = 0, GKO_F32 = 1 } gko_dtype;
+typedef enum gko_itype { GKO_I32 = 0, GKO_I64 = 1 } gko_itype;
+
+/* Storage formats of the SpMV family (Sec. 6.1 compares SpMV kernels that
+ * differ in storage format and processing strategy).
+ *  CSR       : row offsets, columns, values; a subwarp of w lanes per row,
+ *              w in {1,...,64} picked from the mean row length.
+ *  CSR_MERGE : the same arrays plus a merge-path partition; equal shares of
+ *              (rows + nonzeros) per workgroup, independent of row lengths.
+ *  COO       : row-major sorted (row, col, val) triplets; equal nonzero
+ *              shares per wavefront, segmented reduction keyed on row.
+ *  ELL       : column-major padded slots, width K = longest row, leading
+ *              dimension n rounded up to 64, padding col = -1, val = +0.0.
+ *  HYBRID    : ELL of width K* plus a COO tail holding the rest, where K*
+ *              minimises n*K*(s+4) + (s+8)*tail(K) bytes (s = value size),
+ *              ties to the smaller K.
+ *  AUTO      : (gko_convert only) pick the fastest by timing every format. */
+typedef enum gko_format {
+    GKO_FMT_CSR = 0,
+    GKO_FMT_CSR_MERGE = 1,
+    GKO_FMT_COO = 2,
+    GKO_FMT_ELL = 3,
+    GKO_FMT_HYBRID = 4,
+    GKO_FMT_AUTO = 5
+} gko_format;
+
+typedef struct gko_context_s *gko_context;
+typedef struct gko_matrix_s *gko_matrix;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context bound to hip_stream (a hipStream_t; NULL = the null
+ * stream) on the current HIP device.  *out receives the handle. */
+gko_status gko_context_create(void *hip_stream, gko_context *out);
+gko_status gko_context_destroy(gko_context ctx);
+/* Rebind the context to another stream of the same device. */
+gko_status gko_context_set_stream(gko_context ctx, void *hip_stream);
+
+/* Device allocator used for every buffer the library owns (matrix storage,
+ * solver workspaces).  alloc(bytes, stream, user) returns device memory or
+ * NULL; dealloc(ptr, stream, user) releases it.  Passing NULL for both
+ * restores the default (hipMallocAsync / hipFreeAsync on the context
+ * stream).  Must be called before matrices are created. */
+typedef void *(*gko_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*gko_dealloc_fn)(void *ptr, void *stream, void *user);
+gko_status gko_context_set_allocator(gko_context ctx, gko_alloc_fn alloc,
+                                     gko_dealloc_fn dealloc, void *user);
+
+/* ---------------------------------------------------------------- matrices */
+
+/* Create a matrix in CSR format from caller-owned device arrays, which are
+ * copied: the handle owns its storage and the caller may free its arrays
+ * once the call returns (the call synchronises the stream).
+ *   row_ptr : n_rows + 1 offsets of type row_ptr_type, row_ptr[0] = 0,
+ *             non-decreasing, row_ptr[n_rows] = nnz.
+ *   col_idx : nnz int32 columns in [0, n_cols), strictly increasing per row.
+ *   values  : nnz values of type dt.
+ * The structure is validated on the device; a violation returns
+ * GKO_ERR_INVALID_ARG and creates nothing. */
+gko_status gko_matrix_create_csr(gko_context ctx, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                 gko_dtype dt, const void *row_ptr, gko_itype row_ptr_type,
+                                 const int32_t *col_idx, const void *values, gko_matrix *out);
+gko_status gko_matrix_destroy(gko_matrix A);
+/* Deep copy (same format and storage). */
+gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out);
+
+typedef struct gko_matrix_desc {
+    int32_t format;        /* gko_format currently stored */
+    int32_t dtype;         /* gko_dtype */
+    int64_t n_rows, n_cols, nnz;
+    int64_t ell_width;     /* ELL / HYBRID: K (slots per row), else 0 */
+    int64_t ell_ld;        /* ELL / HYBRID: leading dimension, else 0 */
+    int64_t coo_nnz;       /* COO: nnz; HYBRID: tail entries; else 0 */
+    int64_t stored_bytes;  /* bytes of device storage held by the handle */
+} gko_matrix_desc;
+gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out);
+
+/* Export the logical matrix as CSR into caller device buffers (n_rows+1
+ * int32 offsets, nnz columns, nnz values), whatever the stored format; the
+ * stored format is not changed.  Synchronises the stream. */
+gko_status gko_matrix_export_csr(gko_matrix A, int32_t *row_ptr, int32_t *col_idx, void *values);
+/* Export the raw stored arrays (for layout checks).  Each pointer may be
+ * NULL to skip it; the call fails with GKO_ERR_INVALID_ARG if the format
+ * stores no such array.  Sizes follow gko_matrix_desc:
+ *   ell_col/ell_val   : ell_width * ell_ld     (ELL, HYBRID)
+ *   coo_row/coo_col/coo_val : coo_nnz          (COO; HYBRID tail) */
+gko_status gko_matrix_export_storage(gko_matrix A, int32_t *ell_col, void *ell_val,
+                                     int32_t *coo_row, int32_t *coo_col, void *coo_val);
+
+/* ---------------------------------------------------------------- SpMV (Sec. 6.1) */
+
+/* y <- alpha * A * x + beta * y in A's value type (alpha and beta rounded to
+ * it).  x: n_cols device values, y: n_rows device values, both of A's dtype.
+ * beta == 0 means y is not read.  x and y must not overlap
+ * (GKO_ERR_INVALID_ARG).  Asynchronous; deterministic (bitwise repeatable). */
+gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void *y);
+
+/* Convert A's storage in place to fmt; the logical matrix is unchanged.
+ * Converting between any two formats is bit-exact.  ELL is refused with
+ * GKO_ERR_UNSUPPORTED (A unchanged) when its padded storage would exceed 4x
+ * the CSR storage.  GKO_FMT_AUTO times one SpMV in every feasible format and
+ * keeps the fastest.  Synchronises the stream. */
+gko_status gko_convert(gko_matrix A, gko_format fmt);
+
+/* ---------------------------------------------------------------- reductions */
+
+/* *result (device, one double) <- sum_i x_i y_i, and <- ||x||_2 for
+ * gko_norm2.  x, y: n device values of dtype dt.  Accumulates in FP64 with a
+ * fixed reduction tree (bitwise repeatable).  Asynchronous. */
+gko_status gko_dot(gko_context ctx, gko_dtype dt, int64_t n, const void *x, const void *y,
+                   double *result);
+gko_status gko_norm2(gko_context ctx, gko_dtype dt, int64_t n, const void *x, double *result);
+
+/* ---------------------------------------------------------------- Krylov solvers (Sec. 6.2) */
+
+typedef enum gko_precision { GKO_PREC_FP64 = 0, GKO_PREC_MIXED_IR = 1 } gko_precision;
+typedef enum gko_precond { GKO_PRECOND_NONE = 0, GKO_PRECOND_BLOCK_JACOBI = 1 } gko_precond;
+
+typedef struct gko_solver_opts {
+    int32_t precision;   /* gko_precision; MIXED_IR = FP64 refinement around an FP32 inner PCG */
+    int32_t precond;     /* gko_precond */
+    int32_t block_size;  /* block-Jacobi block size, 1..32 (default 8) */
+    int32_t check_every; /* host convergence polls every this many iterations (default 16) */
+    double inner_tol;    /* MIXED_IR: inner relative tolerance (default 1e-5) */
+    int32_t max_inner;   /* MIXED_IR: inner iteration cap per outer step (default 1000) */
+    int32_t max_outer;   /* MIXED_IR: outer step cap (default 20) */
+} gko_solver_opts;
+
+typedef struct gko_solve_info {
+    int32_t status;            /* gko_status of the solve */
+    int32_t iterations;        /* Krylov iterations (FP64) or total inner iterations (MIXED_IR) */
+    int32_t outer_iterations;  /* MIXED_IR refinement steps, else 0 */
+    int32_t restarts;          /* true-residual restarts */
+    double rel_residual;       /* recursive ||r|| / ||b|| at exit */
+    double true_rel_residual;  /* ||b - A x|| / ||b|| recomputed at exit */
+    double seconds;            /* wall time of the solve call */
+    double setup_seconds;      /* part of it spent building the preconditioner */
+} gko_solve_info;
+
+gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *opts);
+gko_status gko_context_get_solver_opts(gko_context ctx, gko_solver_opts *out);
+gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out);
+
+/* Solve A x = b by (preconditioned) CG, Hestenes-Stiefel form: q = A p,
+ * alpha = rho / p.q, x += alpha p, r -= alpha q, z = M^-1 r, rho' = r.z,
+ * p = z + (rho'/rho) p.  A square, SPD, FP64.  b, x: device FP64 arrays of
+ * n_rows; x is the initial guess on entry and the solution on return.  Stops
+ * when ||r||_2 <= tol ||b||_2; the true residual is then recomputed and the
+ * iteration restarted from x if it misses tol (at most twice).  ||b|| = 0
+ * gives x = 0.  tol > 0 and finite, maxit >= 0.  Synchronous.  Returns
+ * GKO_OK, GKO_ERR_NOT_CONVERGED, GKO_ERR_NOT_SPD or GKO_ERR_BREAKDOWN. */
+gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
+/* Solve A x = b by unpreconditioned BiCGSTAB (van der Vorst), shadow
+ * residual r0, same conventions as gko_cg_solve.  Breakdown (|rho|, |rhat.v|
+ * or t.t below 1e-300, or omega = 0) returns GKO_ERR_BREAKDOWN. */
+gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
+/* ---------------------------------------------------------------- errors */
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *gko_last_error(void);
+const char *gko_status_string(gko_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GKO_MI355X_H */

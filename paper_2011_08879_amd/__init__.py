@@ -1,0 +1,372 @@
+"""Python binding of libgko_mi355x.so (the C ABI declared in include/gko.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+PyTorch supplies device memory (its caching allocator is installed as the
+library's allocator) and the current stream.  Importing this module does not
+need a GPU; creating a Context does.  If the shared library has not been
+built, importing raises ImportError -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgko_mi355x.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError("libgko_mi355x.so is not built; run `python -m paper_2011_08879_amd.build` "
+                      "(or __graft_entry__.build())")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------------------- enums
+OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = 0, 1, 2, 3, 4, 5
+ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NOT_SPD = 6, 7, 8
+F64, F32 = 0, 1
+I32, I64 = 0, 1
+FORMATS = {"csr": 0, "csr_merge": 1, "coo": 2, "ell": 3, "hybrid": 4, "auto": 5}
+FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
+PREC_FP64, PREC_MIXED_IR = 0, 1
+PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1
+
+_vp = ctypes.c_void_p
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_f64 = ctypes.c_double
+_st = ctypes.c_int
+
+
+class _MatrixDesc(ctypes.Structure):
+    _fields_ = [("format", _i32), ("dtype", _i32), ("n_rows", _i64), ("n_cols", _i64),
+                ("nnz", _i64), ("ell_width", _i64), ("ell_ld", _i64), ("coo_nnz", _i64),
+                ("stored_bytes", _i64)]
+
+
+class SolverOpts(ctypes.Structure):
+    _fields_ = [("precision", _i32), ("precond", _i32), ("block_size", _i32),
+                ("check_every", _i32), ("inner_tol", _f64), ("max_inner", _i32),
+                ("max_outer", _i32)]
+
+
+class _SolveInfo(ctypes.Structure):
+    _fields_ = [("status", _i32), ("iterations", _i32), ("outer_iterations", _i32),
+                ("restarts", _i32), ("rel_residual", _f64), ("true_rel_residual", _f64),
+                ("seconds", _f64), ("setup_seconds", _f64)]
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, _vp, _vp, _vp)
+
+_SIGS = {
+    "gko_context_create": [_vp, ctypes.POINTER(_vp)],
+    "gko_context_destroy": [_vp],
+    "gko_context_set_stream": [_vp, _vp],
+    "gko_context_set_allocator": [_vp, ALLOC_FN, DEALLOC_FN, _vp],
+    "gko_matrix_create_csr": [_vp, _i64, _i64, _i64, _st, _vp, _st, _vp, _vp, ctypes.POINTER(_vp)],
+    "gko_matrix_destroy": [_vp],
+    "gko_matrix_clone": [_vp, ctypes.POINTER(_vp)],
+    "gko_matrix_describe": [_vp, ctypes.POINTER(_MatrixDesc)],
+    "gko_matrix_export_csr": [_vp, _vp, _vp, _vp],
+    "gko_matrix_export_storage": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "gko_spmv": [_vp, _f64, _vp, _f64, _vp],
+    "gko_convert": [_vp, _st],
+    "gko_dot": [_vp, _st, _i64, _vp, _vp, _vp],
+    "gko_norm2": [_vp, _st, _i64, _vp, _vp],
+    "gko_context_set_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
+    "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
+    "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
+    "gko_cg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
+}
+for _name, _args in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _st
+_lib.gko_last_error.argtypes = []
+_lib.gko_last_error.restype = ctypes.c_char_p
+_lib.gko_status_string.argtypes = [_st]
+_lib.gko_status_string.restype = ctypes.c_char_p
+
+EXPORTED = tuple(_SIGS) + ("gko_last_error", "gko_status_string")
+
+
+class GkoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s (%d): %s" % (status_string(status), status, message))
+        self.status = status
+
+
+def status_string(status: int) -> str:
+    return _lib.gko_status_string(status).decode()
+
+
+def last_error() -> str:
+    return _lib.gko_last_error().decode()
+
+
+def _check(status: int):
+    if status != OK:
+        raise GkoError(status, last_error())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _ptr(t) -> int:
+    return 0 if t is None else int(t.data_ptr())
+
+
+def _dtype_code(t) -> int:
+    torch = _torch()
+    if t.dtype == torch.float64:
+        return F64
+    if t.dtype == torch.float32:
+        return F32
+    raise TypeError("values must be float64 or float32, got %s" % t.dtype)
+
+
+# ----------------------------------------------------------------------------- context
+class Context:
+    """Binds the library to the current torch stream and torch's caching allocator."""
+
+    def __init__(self, device: int | None = None, use_torch_allocator: bool = True):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the library has no CPU path")
+        if device is not None:
+            torch.cuda.set_device(device)
+        self.device = torch.cuda.current_device()
+        h = _vp()
+        _check(_lib.gko_context_create(_vp(torch.cuda.current_stream().cuda_stream),
+                                       ctypes.byref(h)))
+        self.handle = h
+        self._cbs = None
+        if use_torch_allocator:
+            dev = self.device
+
+            def _alloc(nbytes, stream, user):
+                try:
+                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream or 0)
+                except Exception:  # surfaced to C as NULL -> GKO_ERR_ALLOC
+                    return None
+
+            def _dealloc(p, stream, user):
+                torch.cuda.caching_allocator_delete(p)
+
+            self._cbs = (ALLOC_FN(_alloc), DEALLOC_FN(_dealloc))
+            _check(_lib.gko_context_set_allocator(h, self._cbs[0], self._cbs[1], None))
+
+    def sync_stream(self):
+        """Rebind to torch's current stream (call after switching streams)."""
+        torch = _torch()
+        _check(_lib.gko_context_set_stream(self.handle,
+                                           _vp(torch.cuda.current_stream().cuda_stream)))
+
+    @property
+    def stream(self) -> int:
+        return _torch().cuda.current_stream().cuda_stream
+
+    def set_solver_opts(self, precision: int = PREC_FP64, precond: int = PRECOND_NONE,
+                        block_size: int = 8, check_every: int = 16, inner_tol: float = 1e-5,
+                        max_inner: int = 1000, max_outer: int = 20):
+        o = SolverOpts(precision, precond, block_size, check_every, inner_tol, max_inner, max_outer)
+        _check(_lib.gko_context_set_solver_opts(self.handle, ctypes.byref(o)))
+
+    def solver_opts(self) -> dict:
+        o = SolverOpts()
+        _check(_lib.gko_context_get_solver_opts(self.handle, ctypes.byref(o)))
+        return {f: getattr(o, f) for f, _ in SolverOpts._fields_}
+
+    def solve_info(self) -> dict:
+        i = _SolveInfo()
+        _check(_lib.gko_context_get_solve_info(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in _SolveInfo._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gko_context_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_default_ctx: Context | None = None
+
+
+def default_context() -> Context:
+    global _default_ctx
+    if _default_ctx is None:
+        _default_ctx = Context()
+    return _default_ctx
+
+
+# ----------------------------------------------------------------------------- matrices
+@dataclass
+class Desc:
+    format: str
+    dtype: str
+    n_rows: int
+    n_cols: int
+    nnz: int
+    ell_width: int
+    ell_ld: int
+    coo_nnz: int
+    stored_bytes: int
+
+
+class Matrix:
+    """A sparse matrix owned by the library (device storage, any format)."""
+
+    def __init__(self, handle, ctx: Context):
+        self.handle = handle
+        self.ctx = ctx
+
+    @classmethod
+    def from_csr(cls, row_ptr, col, val, n_cols: int | None = None, ctx: Context | None = None,
+                 dtype=None):
+        """Create from CSR arrays (numpy or torch, host or device); they are copied."""
+        torch = _torch()
+        ctx = ctx or default_context()
+        dev = torch.device("cuda", ctx.device)
+
+        def dev_tensor(a, dt):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=dev, dtype=dt).contiguous()
+
+        rp_t = row_ptr if isinstance(row_ptr, torch.Tensor) else torch.from_numpy(
+            np.ascontiguousarray(row_ptr))
+        itype = I64 if rp_t.dtype == torch.int64 else I32
+        rp = dev_tensor(rp_t, torch.int64 if itype == I64 else torch.int32)
+        ci = dev_tensor(col, torch.int32)
+        vdt = dtype or (val.dtype if isinstance(val, torch.Tensor) else
+                        (torch.float32 if np.asarray(val).dtype == np.float32 else torch.float64))
+        va = dev_tensor(val, vdt)
+        n = rp.numel() - 1
+        m = n if n_cols is None else int(n_cols)
+        h = _vp()
+        _check(_lib.gko_matrix_create_csr(ctx.handle, n, m, ci.numel(), _dtype_code(va), _ptr(rp),
+                                          itype, _ptr(ci), _ptr(va), ctypes.byref(h)))
+        return cls(h, ctx)
+
+    def describe(self) -> Desc:
+        d = _MatrixDesc()
+        _check(_lib.gko_matrix_describe(self.handle, ctypes.byref(d)))
+        return Desc(FORMAT_NAMES[d.format], "f64" if d.dtype == F64 else "f32", d.n_rows,
+                    d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes)
+
+    @property
+    def shape(self):
+        d = self.describe()
+        return d.n_rows, d.n_cols
+
+    @property
+    def torch_dtype(self):
+        torch = _torch()
+        return torch.float64 if self.describe().dtype == "f64" else torch.float32
+
+    def convert(self, fmt: str) -> "Matrix":
+        _check(_lib.gko_convert(self.handle, FORMATS[fmt]))
+        return self
+
+    def clone(self) -> "Matrix":
+        h = _vp()
+        _check(_lib.gko_matrix_clone(self.handle, ctypes.byref(h)))
+        return Matrix(h, self.ctx)
+
+    def export_csr(self):
+        torch = _torch()
+        d = self.describe()
+        dev = torch.device("cuda", self.ctx.device)
+        rp = torch.empty(d.n_rows + 1, dtype=torch.int32, device=dev)
+        ci = torch.empty(d.nnz, dtype=torch.int32, device=dev)
+        va = torch.empty(d.nnz, dtype=self.torch_dtype, device=dev)
+        _check(_lib.gko_matrix_export_csr(self.handle, _ptr(rp), _ptr(ci), _ptr(va)))
+        return rp, ci, va
+
+    def export_storage(self) -> dict:
+        """Raw stored arrays of ELL / COO / HYBRID formats (for layout checks)."""
+        torch = _torch()
+        d = self.describe()
+        dev = torch.device("cuda", self.ctx.device)
+        out = {}
+        ec = ev = cr = cc = cv = None
+        if d.format in ("ell", "hybrid"):
+            ec = torch.empty(d.ell_width * d.ell_ld, dtype=torch.int32, device=dev)
+            ev = torch.empty(d.ell_width * d.ell_ld, dtype=self.torch_dtype, device=dev)
+            out.update(ell_col=ec, ell_val=ev, K=d.ell_width, ld=d.ell_ld)
+        if d.format in ("coo", "hybrid"):
+            cr = torch.empty(d.coo_nnz, dtype=torch.int32, device=dev)
+            cc = torch.empty(d.coo_nnz, dtype=torch.int32, device=dev)
+            cv = torch.empty(d.coo_nnz, dtype=self.torch_dtype, device=dev)
+            out.update(coo_row=cr, coo_col=cc, coo_val=cv)
+        _check(_lib.gko_matrix_export_storage(self.handle, _ptr(ec), _ptr(ev), _ptr(cr), _ptr(cc),
+                                              _ptr(cv)))
+        return out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gko_matrix_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ----------------------------------------------------------------------------- operations
+def spmv(A: Matrix, alpha: float, x, beta: float, y):
+    """y <- alpha A x + beta y (asynchronous on the current stream)."""
+    _check(_lib.gko_spmv(A.handle, alpha, _ptr(x), beta, _ptr(y)))
+    return y
+
+
+def convert(A: Matrix, fmt: str) -> Matrix:
+    return A.convert(fmt)
+
+
+def dot(x, y, ctx: Context | None = None):
+    """x.y accumulated in FP64; returns a 0-d float64 device tensor."""
+    torch = _torch()
+    ctx = ctx or default_context()
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(_lib.gko_dot(ctx.handle, _dtype_code(x), x.numel(), _ptr(x), _ptr(y), _ptr(out)))
+    return out
+
+
+def norm2(x, ctx: Context | None = None):
+    torch = _torch()
+    ctx = ctx or default_context()
+    out = torch.empty((), dtype=torch.float64, device=x.device)
+    _check(_lib.gko_norm2(ctx.handle, _dtype_code(x), x.numel(), _ptr(x), _ptr(out)))
+    return out
+
+
+def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):
+    st = fn(A.handle, _ptr(b), _ptr(x), tol, maxit)
+    info = A.ctx.solve_info()
+    info["status_name"] = status_string(st)
+    if st != OK and raise_on_failure:
+        raise GkoError(st, last_error())
+    return info
+
+
+def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
+    """(P)CG, options from the context.  x: initial guess in, solution out.  Returns solve info."""
+    return _solve(_lib.gko_cg_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+def bicgstab(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
+             raise_on_failure: bool = False):
+    return _solve(_lib.gko_bicgstab_solve, A, b, x, tol, maxit, raise_on_failure)

@@ -1,0 +1,1124 @@
+// The C ABI (include/gko.h): handles, argument checks, format dispatch,
+// conversions, and the host drivers of the Krylov solvers.  All arithmetic
+// runs in the HIP kernels; this file only orders launches and moves a few
+// scalars to the host for convergence checks.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <limits>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "gko.h"
+#include "kernels.hpp"
+#include "solver_kernels.hpp"
+
+using namespace gko;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+struct api_error : std::runtime_error {
+    gko_status status;
+    api_error(gko_status s, const std::string &m) : std::runtime_error(m), status(s) {}
+};
+
+[[noreturn]] void fail(gko_status s, const std::string &m) { throw api_error(s, m); }
+
+void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(GKO_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+#define HIPC(expr) hip_check((expr), #expr)
+
+template <typename F>
+gko_status guarded(F &&f) {
+    try {
+        f();
+        g_last_error.clear();
+        return GKO_OK;
+    } catch (const api_error &e) {
+        g_last_error = e.what();
+        return e.status;
+    } catch (const std::bad_alloc &) {
+        g_last_error = "host allocation failed";
+        return GKO_ERR_ALLOC;
+    } catch (const std::exception &e) {
+        g_last_error = e.what();
+        return GKO_ERR_INVALID_ARG;
+    } catch (...) {
+        g_last_error = "unknown error";
+        return GKO_ERR_INVALID_ARG;
+    }
+}
+
+double now_seconds() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+gko_solver_opts default_opts() {
+    gko_solver_opts o;
+    o.precision = GKO_PREC_FP64;
+    o.precond = GKO_PRECOND_NONE;
+    o.block_size = 8;
+    o.check_every = 16;
+    o.inner_tol = 1e-5;
+    o.max_inner = 1000;
+    o.max_outer = 20;
+    return o;
+}
+
+}  // namespace
+
+// ====================================================================== handles
+struct gko_context_s {
+    hipStream_t stream = nullptr;
+    int device = 0;
+    gko_alloc_fn alloc = nullptr;
+    gko_dealloc_fn dealloc = nullptr;
+    void *user = nullptr;
+    gko_solver_opts opts = default_opts();
+    gko_solve_info info{};
+    double *red_partials = nullptr;  // scratch of gko_dot / gko_norm2
+    unsigned *red_ticket = nullptr;
+
+    void *alloc_bytes(size_t bytes) {
+        if (bytes == 0) bytes = 8;
+        void *p = nullptr;
+        if (alloc) {
+            p = alloc(bytes, (void *)stream, user);
+            if (!p) fail(GKO_ERR_ALLOC, "allocator returned NULL for " + std::to_string(bytes) + " bytes");
+        } else {
+            hipError_t e = hipMallocAsync(&p, bytes, stream);
+            if (e != hipSuccess || !p)
+                fail(GKO_ERR_ALLOC, "hipMallocAsync(" + std::to_string(bytes) + "): " + hipGetErrorString(e));
+        }
+        return p;
+    }
+    void free_bytes(void *p) {
+        if (!p) return;
+        if (dealloc) dealloc(p, (void *)stream, user);
+        else (void)hipFreeAsync(p, stream);
+    }
+    void sync() { HIPC(hipStreamSynchronize(stream)); }
+};
+
+namespace {
+
+// Device buffer owned by a context, released on scope exit.
+struct dbuf {
+    gko_context ctx = nullptr;
+    void *p = nullptr;
+    dbuf() = default;
+    dbuf(gko_context c, size_t bytes) : ctx(c), p(c->alloc_bytes(bytes)) {}
+    dbuf(const dbuf &) = delete;
+    dbuf &operator=(const dbuf &) = delete;
+    dbuf(dbuf &&o) noexcept : ctx(o.ctx), p(o.p) { o.p = nullptr; }
+    dbuf &operator=(dbuf &&o) noexcept {
+        if (this != &o) {
+            if (p) ctx->free_bytes(p);
+            ctx = o.ctx;
+            p = o.p;
+            o.p = nullptr;
+        }
+        return *this;
+    }
+    ~dbuf() {
+        if (p) ctx->free_bytes(p);
+    }
+    template <typename T>
+    T *as() const { return static_cast<T *>(p); }
+    void *release() {
+        void *q = p;
+        p = nullptr;
+        return q;
+    }
+};
+
+}  // namespace
+
+struct gko_matrix_s {
+    gko_context ctx = nullptr;
+    gko_format fmt = GKO_FMT_CSR;
+    gko_dtype dt = GKO_F64;
+    int64_t n = 0, m = 0, nnz = 0;
+    int32_t *rp = nullptr;    // CSR, CSR_MERGE
+    int32_t *row = nullptr;   // COO
+    int32_t *col = nullptr;   // CSR, CSR_MERGE, COO
+    void *val = nullptr;      // CSR, CSR_MERGE, COO
+    int32_t *part = nullptr;  // CSR_MERGE partition, 2 * (tiles + 1)
+    int64_t tiles = 0;
+    int64_t K = 0, ld = 0;    // ELL, HYBRID
+    int32_t *ecol = nullptr;
+    void *eval = nullptr;
+    int64_t tnnz = 0;         // HYBRID tail
+    int32_t *trow = nullptr, *tcol = nullptr;
+    void *tval = nullptr;
+    int subwarp = 1;
+    void *carry_a = nullptr, *carry_b = nullptr;  // merge / COO carries
+    int64_t carry_elems = 0;
+    // FP32 copies of the value arrays, made on demand for mixed precision
+    void *val32 = nullptr, *eval32 = nullptr, *tval32 = nullptr;
+    // block-Jacobi inverse cache
+    int bj_bs = 0;
+    double *bj64 = nullptr;
+    float *bj32 = nullptr;
+
+    vt type() const { return dt == GKO_F64 ? vt::f64 : vt::f32; }
+    size_t vs() const { return vsize(type()); }
+
+    void drop(void *&p) {
+        ctx->free_bytes(p);
+        p = nullptr;
+    }
+    template <typename T>
+    void drop(T *&p) {
+        ctx->free_bytes((void *)p);
+        p = nullptr;
+    }
+    void drop_caches() {
+        drop(val32);
+        drop(eval32);
+        drop(tval32);
+        drop(bj64);
+        drop(bj32);
+        bj_bs = 0;
+    }
+    void drop_storage() {
+        drop(rp); drop(row); drop(col); drop(val); drop(part); drop(ecol); drop(eval);
+        drop(trow); drop(tcol); drop(tval); drop(carry_a); drop(carry_b);
+        tiles = K = ld = tnnz = carry_elems = 0;
+        drop_caches();
+    }
+    int64_t stored_bytes() const {
+        const int64_t s = (int64_t)vs();
+        switch (fmt) {
+            case GKO_FMT_CSR: return (n + 1) * 4 + nnz * (4 + s);
+            case GKO_FMT_CSR_MERGE: return (n + 1) * 4 + nnz * (4 + s) + 8 * (tiles + 1);
+            case GKO_FMT_COO: return nnz * (8 + s);
+            case GKO_FMT_ELL: return K * ld * (4 + s);
+            case GKO_FMT_HYBRID: return K * ld * (4 + s) + tnnz * (8 + s);
+            default: return 0;
+        }
+    }
+};
+
+namespace {
+
+void require(bool ok, gko_status s, const std::string &m) {
+    if (!ok) fail(s, m);
+}
+
+int64_t round_up64(int64_t v) { return (v + 63) / 64 * 64; }
+
+// Scratch of the grid reductions: up to 3 values per block for the largest
+// grid any reduction kernel launches.
+constexpr size_t kPartialBytes = (size_t)3 * kMaxReductionBlocks * sizeof(double);
+
+void ensure_carries(gko_matrix A, int64_t elems) {
+    if (A->carry_elems >= elems && A->carry_a) return;
+    A->drop(A->carry_a);
+    A->drop(A->carry_b);
+    A->carry_a = A->ctx->alloc_bytes((size_t)std::max<int64_t>(elems, 1) * 8);
+    A->carry_b = A->ctx->alloc_bytes((size_t)std::max<int64_t>(elems, 1) * 8);
+    A->carry_elems = elems;
+}
+
+// Value arrays of one precision: the stored ones, or the FP32 copies.
+struct values {
+    vt t;
+    const void *val, *eval, *tval;
+};
+
+values own_values(gko_matrix A) { return {A->type(), A->val, A->eval, A->tval}; }
+
+void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, double beta, void *y) {
+    hipStream_t s = A->ctx->stream;
+    switch (A->fmt) {
+        case GKO_FMT_CSR:
+            HIPC(spmv_csr(s, v.t, A->n, A->rp, A->col, v.val, x, alpha, beta, y, A->subwarp));
+            break;
+        case GKO_FMT_CSR_MERGE:
+            HIPC(spmv_merge(s, v.t, A->n, A->nnz, A->rp, A->col, v.val, A->part, x, alpha, beta, y,
+                            static_cast<int32_t *>(A->carry_a), A->carry_b));
+            break;
+        case GKO_FMT_COO:
+            HIPC(spmv_coo(s, v.t, A->n, A->nnz, A->row, A->col, v.val, x, alpha, beta, y, false,
+                          A->carry_a, A->carry_b));
+            break;
+        case GKO_FMT_ELL:
+            HIPC(spmv_ell(s, v.t, A->n, A->K, A->ld, A->ecol, v.eval, x, alpha, beta, y));
+            break;
+        case GKO_FMT_HYBRID:
+            HIPC(spmv_ell(s, v.t, A->n, A->K, A->ld, A->ecol, v.eval, x, alpha, beta, y));
+            if (A->tnnz > 0)
+                HIPC(spmv_coo(s, v.t, A->n, A->tnnz, A->trow, A->tcol, v.tval, x, alpha, 1.0, y,
+                              true, A->carry_a, A->carry_b));
+            break;
+        default:
+            fail(GKO_ERR_INVALID_ARG, "matrix has no storage format");
+    }
+}
+
+// ---------------------------------------------------------------- conversions
+// Writes the logical matrix as CSR (n+1 offsets, nnz columns, nnz values of
+// the given value arrays) into device buffers, whatever the stored format.
+void export_csr_into(gko_matrix A, const values &v, int32_t *rp, int32_t *col, void *val) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    const size_t vb = vsize(v.t);
+    switch (A->fmt) {
+        case GKO_FMT_CSR:
+        case GKO_FMT_CSR_MERGE:
+            HIPC(hipMemcpyAsync(rp, A->rp, (A->n + 1) * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(col, A->col, A->nnz * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(val, v.val, A->nnz * vb, hipMemcpyDeviceToDevice, s));
+            break;
+        case GKO_FMT_COO:
+            HIPC(rows_to_ptr(s, A->n, A->nnz, A->row, rp));
+            HIPC(hipMemcpyAsync(col, A->col, A->nnz * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(val, v.val, A->nnz * vb, hipMemcpyDeviceToDevice, s));
+            break;
+        case GKO_FMT_ELL:
+        case GKO_FMT_HYBRID: {
+            dbuf tptr;
+            if (A->fmt == GKO_FMT_HYBRID) {
+                tptr = dbuf(c, (A->n + 1) * 4);
+                HIPC(rows_to_ptr(s, A->n, A->tnnz, A->trow, tptr.as<int32_t>()));
+            }
+            dbuf len(c, std::max<int64_t>(A->n, 1) * 4);
+            dbuf tmp(c, scan_tmp_elems(A->n) * 4);
+            HIPC(hyb_lengths(s, A->n, A->K, A->ld, A->ecol, tptr.as<int32_t>(), len.as<int32_t>()));
+            HIPC(exclusive_scan(s, A->n, len.as<int32_t>(), rp, tmp.as<int32_t>()));
+            HIPC(hyb_to_csr(s, v.t, A->n, A->K, A->ld, A->ecol, v.eval, tptr.as<int32_t>(), A->tcol,
+                            v.tval, rp, col, val));
+            c->sync();
+            break;
+        }
+        default:
+            fail(GKO_ERR_INVALID_ARG, "matrix has no storage format");
+    }
+}
+
+void to_csr(gko_matrix A) {
+    if (A->fmt == GKO_FMT_CSR) return;
+    if (A->fmt == GKO_FMT_CSR_MERGE) {
+        A->drop(A->part);
+        A->tiles = 0;
+        A->fmt = GKO_FMT_CSR;
+        return;
+    }
+    gko_context c = A->ctx;
+    dbuf rp(c, (A->n + 1) * 4), col(c, A->nnz * 4), val(c, A->nnz * A->vs());
+    export_csr_into(A, own_values(A), rp.as<int32_t>(), col.as<int32_t>(), val.p);
+    c->sync();
+    A->drop_storage();
+    A->rp = static_cast<int32_t *>(rp.release());
+    A->col = static_cast<int32_t *>(col.release());
+    A->val = val.release();
+    A->fmt = GKO_FMT_CSR;
+    A->subwarp = csr_subwarp_width(A->n, A->nnz);
+}
+
+int64_t read_int(gko_context c, const int *d) {
+    int h = 0;
+    HIPC(hipMemcpyAsync(&h, d, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return h;
+}
+
+int64_t max_len_of_csr(gko_matrix A) {
+    dbuf ml(A->ctx, 4);
+    HIPC(hipMemsetAsync(ml.p, 0, 4, A->ctx->stream));
+    HIPC(max_row_len(A->ctx->stream, A->n, A->rp, ml.as<int>()));
+    return read_int(A->ctx, ml.as<int>());
+}
+
+// K* = argmin_K n*K*(s+4) + (s+8)*sum_i max(0, len_i - K), ties to the smaller K,
+// from the row-length histogram (integer arithmetic, exact).
+int64_t hyb_width_of_csr(gko_matrix A, int64_t maxlen) {
+    gko_context c = A->ctx;
+    dbuf hist(c, (maxlen + 1) * 4);
+    HIPC(hipMemsetAsync(hist.p, 0, (maxlen + 1) * 4, c->stream));
+    HIPC(row_len_hist(c->stream, A->n, A->rp, hist.as<int>()));
+    std::vector<int> h(maxlen + 1);
+    HIPC(hipMemcpyAsync(h.data(), hist.p, (maxlen + 1) * 4, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    const int64_t s = (int64_t)A->vs();
+    // rows_gt[K] = #rows with len > K, ent_gt[K] = sum of len over those rows
+    int64_t rows_gt = 0, ent_gt = 0;
+    std::vector<int64_t> tail(maxlen + 1);
+    for (int64_t K = maxlen; K >= 0; --K) {
+        tail[K] = ent_gt - K * rows_gt;
+        rows_gt += h[K];
+        ent_gt += (int64_t)h[K] * K;
+    }
+    int64_t best = 0, best_cost = -1;
+    for (int64_t K = 0; K <= maxlen; ++K) {
+        const int64_t cost = A->n * K * (s + 4) + (s + 8) * tail[K];
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = K;
+        }
+    }
+    return best;
+}
+
+void csr_to_format(gko_matrix A, gko_format fmt) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    switch (fmt) {
+        case GKO_FMT_CSR:
+            return;
+        case GKO_FMT_CSR_MERGE: {
+            const int64_t tiles = merge_tiles(A->n, A->nnz);
+            dbuf part(c, 2 * (tiles + 1) * 4);
+            HIPC(merge_partition(s, A->n, A->nnz, A->rp, part.as<int32_t>()));
+            ensure_carries(A, tiles);
+            c->sync();
+            A->part = static_cast<int32_t *>(part.release());
+            A->tiles = tiles;
+            A->fmt = GKO_FMT_CSR_MERGE;
+            return;
+        }
+        case GKO_FMT_COO: {
+            dbuf row(c, A->nnz * 4);
+            HIPC(csr_rows(s, A->n, A->rp, row.as<int32_t>()));
+            ensure_carries(A, coo_chunks(A->nnz));
+            c->sync();
+            A->drop(A->rp);
+            A->row = static_cast<int32_t *>(row.release());
+            A->fmt = GKO_FMT_COO;
+            return;
+        }
+        case GKO_FMT_ELL:
+        case GKO_FMT_HYBRID: {
+            const int64_t maxlen = max_len_of_csr(A);
+            const int64_t K = fmt == GKO_FMT_ELL ? maxlen : hyb_width_of_csr(A, maxlen);
+            const int64_t ld = round_up64(A->n);
+            const int64_t vsz = (int64_t)A->vs();
+            dbuf tptr, trow, tcol, tval;
+            int64_t tnnz = 0;
+            if (fmt == GKO_FMT_HYBRID) {
+                dbuf len(c, std::max<int64_t>(A->n, 1) * 4), tmp(c, scan_tmp_elems(A->n) * 4);
+                tptr = dbuf(c, (A->n + 1) * 4);
+                HIPC(tail_lengths(s, A->n, A->rp, K, len.as<int32_t>()));
+                HIPC(exclusive_scan(s, A->n, len.as<int32_t>(), tptr.as<int32_t>(), tmp.as<int32_t>()));
+                tnnz = read_int(c, tptr.as<int>() + A->n);
+                trow = dbuf(c, tnnz * 4);
+                tcol = dbuf(c, tnnz * 4);
+                tval = dbuf(c, tnnz * vsz);
+                HIPC(csr_to_tail(s, A->type(), A->n, A->rp, A->col, A->val, K, tptr.as<int32_t>(),
+                                 trow.as<int32_t>(), tcol.as<int32_t>(), tval.p));
+            }
+            dbuf ecol(c, K * ld * 4), eval(c, K * ld * vsz);
+            HIPC(csr_to_ell(s, A->type(), A->n, A->rp, A->col, A->val, K, ld, ecol.as<int32_t>(), eval.p));
+            if (tnnz > 0) ensure_carries(A, coo_chunks(tnnz));
+            c->sync();
+            void *ca = A->carry_a, *cb = A->carry_b;
+            const int64_t ce = A->carry_elems;
+            A->carry_a = A->carry_b = nullptr;
+            A->drop_storage();
+            A->carry_a = ca;
+            A->carry_b = cb;
+            A->carry_elems = ce;
+            A->K = K;
+            A->ld = ld;
+            A->ecol = static_cast<int32_t *>(ecol.release());
+            A->eval = eval.release();
+            A->tnnz = tnnz;
+            A->trow = static_cast<int32_t *>(trow.release());
+            A->tcol = static_cast<int32_t *>(tcol.release());
+            A->tval = tval.release();
+            A->fmt = fmt;
+            return;
+        }
+        default:
+            fail(GKO_ERR_INVALID_ARG, "unknown format");
+    }
+}
+
+bool ell_feasible(gko_matrix A, int64_t maxlen) {
+    const int64_t s = (int64_t)A->vs();
+    const double ell = (double)maxlen * (double)round_up64(A->n) * (double)(s + 4);
+    const double csr = (double)A->nnz * (double)(s + 4) + (double)(A->n + 1) * 4.0;
+    return ell <= 4.0 * csr;
+}
+
+// Maximum row length of the logical matrix, whatever the format.
+int64_t max_len_any(gko_matrix A) {
+    if (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE) return max_len_of_csr(A);
+    gko_context c = A->ctx;
+    dbuf rp(c, (A->n + 1) * 4), col(c, A->nnz * 4), val(c, A->nnz * A->vs());
+    export_csr_into(A, own_values(A), rp.as<int32_t>(), col.as<int32_t>(), val.p);
+    dbuf ml(c, 4);
+    HIPC(hipMemsetAsync(ml.p, 0, 4, c->stream));
+    HIPC(max_row_len(c->stream, A->n, rp.as<int32_t>(), ml.as<int>()));
+    return read_int(c, ml.as<int>());
+}
+
+void convert_to(gko_matrix A, gko_format fmt) {
+    if (fmt == A->fmt) return;
+    if (fmt == GKO_FMT_ELL) {
+        const int64_t maxlen = max_len_any(A);
+        if (!ell_feasible(A, maxlen))
+            fail(GKO_ERR_UNSUPPORTED, "ELL storage would exceed 4x the CSR storage (max row length " +
+                                          std::to_string(maxlen) + ")");
+    }
+    A->drop_caches();
+    to_csr(A);
+    csr_to_format(A, fmt);
+}
+
+// ---------------------------------------------------------------- FP32 copies
+values f32_values(gko_matrix A) {
+    if (A->dt == GKO_F32) return own_values(A);
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    if (A->val && !A->val32) {
+        A->val32 = c->alloc_bytes(A->nnz * 4);
+        HIPC(cast_values(s, vt::f64, vt::f32, A->nnz, A->val, A->val32));
+    }
+    if (A->eval && !A->eval32) {
+        A->eval32 = c->alloc_bytes(A->K * A->ld * 4);
+        HIPC(cast_values(s, vt::f64, vt::f32, A->K * A->ld, A->eval, A->eval32));
+    }
+    if (A->tval && !A->tval32) {
+        A->tval32 = c->alloc_bytes(A->tnnz * 4);
+        HIPC(cast_values(s, vt::f64, vt::f32, A->tnnz, A->tval, A->tval32));
+    }
+    return {vt::f32, A->val32, A->eval32, A->tval32};
+}
+
+// ---------------------------------------------------------------- block-Jacobi
+void ensure_block_jacobi(gko_matrix A, int bs, bool need32) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    if (A->bj_bs != bs) {
+        A->drop(A->bj64);
+        A->drop(A->bj32);
+        A->bj_bs = 0;
+        const int64_t nb = (A->n + bs - 1) / bs;
+        dbuf inv(c, nb * bs * bs * 8), err(c, 4);
+        HIPC(hipMemsetAsync(err.p, 0, 4, s));
+        if (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE) {
+            HIPC(bj_invert(s, A->n, A->rp, A->col, static_cast<const double *>(A->val), bs,
+                           inv.as<double>(), err.as<int>()));
+        } else {
+            dbuf rp(c, (A->n + 1) * 4), col(c, A->nnz * 4), val(c, A->nnz * 8);
+            export_csr_into(A, own_values(A), rp.as<int32_t>(), col.as<int32_t>(), val.p);
+            HIPC(bj_invert(s, A->n, rp.as<int32_t>(), col.as<int32_t>(), val.as<double>(), bs,
+                           inv.as<double>(), err.as<int>()));
+            c->sync();
+        }
+        if (read_int(c, err.as<int>()))
+            fail(GKO_ERR_BREAKDOWN, "block-Jacobi: a diagonal block is singular");
+        A->bj64 = inv.as<double>();
+        inv.release();
+        A->bj_bs = bs;
+    }
+    if (need32 && !A->bj32) {
+        const int64_t nb = (A->n + bs - 1) / bs;
+        A->bj32 = static_cast<float *>(c->alloc_bytes(nb * bs * bs * 4));
+        HIPC(cast_values(s, vt::f64, vt::f32, nb * bs * bs, A->bj64, A->bj32));
+    }
+}
+
+// ---------------------------------------------------------------- solver drivers
+template <typename T>
+T read_back(gko_context c, const T *d) {
+    T h;
+    HIPC(hipMemcpyAsync(&h, d, sizeof(T), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    return h;
+}
+
+double device_norm(gko_context c, vt t, int64_t n, const void *x, double *out, double *partials,
+                   unsigned *ticket) {
+    HIPC(dot(c->stream, t, n, x, x, out, partials, ticket, true));
+    return read_back(c, out);
+}
+
+struct solve_result {
+    int32_t flag = kRunning;
+    int32_t iters = 0;
+    int32_t restarts = 0;
+    double relres = 0.0;
+    double true_relres = 0.0;
+};
+
+gko_status flag_status(int32_t f) {
+    switch (f) {
+        case kConverged: return GKO_OK;
+        case kNotSpd: return GKO_ERR_NOT_SPD;
+        case kBreakdown: return GKO_ERR_BREAKDOWN;
+        default: return GKO_ERR_NOT_CONVERGED;
+    }
+}
+
+// (P)CG on A with the value arrays `v` (FP64 or FP32), b and x of that type.
+// inv: block-Jacobi inverse of type v.t (bs > 0) or null.
+solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, double tol, int32_t maxit,
+                     const void *inv, int bs, int check_every, bool true_check) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    const int64_t n = A->n;
+    const size_t vb = vsize(v.t);
+    dbuf r(c, n * vb), p(c, n * vb), q(c, n * vb), z(c, bs > 0 ? n * vb : 8);
+    dbuf partials(c, kPartialBytes), ticket(c, 8), sc(c, sizeof(krylov_scalars)), nrm(c, 8);
+    HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+    auto *S = sc.as<krylov_scalars>();
+    HIPC(scalars_reset(s, S, maxit));
+    void *zz = bs > 0 ? z.p : r.p;
+    const bool fused = A->fmt == GKO_FMT_CSR;
+    solve_result res;
+    krylov_scalars h{};
+    for (;;) {
+        HIPC(hipMemcpyAsync(r.p, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+        HIPC(cg_init(s, v.t, n, b, r.p, zz, p.p, inv, bs, tol, S, partials.as<double>(),
+                     ticket.as<unsigned>()));
+        h = read_back(c, S);
+        while (h.done == kRunning) {
+            for (int j = 0; j < check_every; ++j) {
+                if (fused) {
+                    HIPC(cg_spmv_csr(s, v.t, n, A->rp, A->col, v.val, p.p, q.p, A->subwarp, S,
+                                     partials.as<double>(), ticket.as<unsigned>()));
+                } else {
+                    spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
+                    HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
+                }
+                HIPC(cg_update(s, v.t, n, x, r.p, zz, p.p, q.p, inv, bs, S, partials.as<double>(),
+                               ticket.as<unsigned>()));
+                HIPC(cg_direction(s, v.t, n, zz, p.p, S));
+            }
+            h = read_back(c, S);
+        }
+        res.flag = h.done;
+        res.iters = h.iter;
+        res.relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        if (!true_check) break;
+        // true residual b - A x (q is free now)
+        HIPC(hipMemcpyAsync(q.p, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, q.p);
+        const double tn = device_norm(c, v.t, n, q.p, nrm.as<double>(), partials.as<double>(),
+                                      ticket.as<unsigned>());
+        res.true_relres = h.bb > 0 ? tn / std::sqrt(h.bb) : 0.0;
+        if (h.done != kConverged) break;
+        if (tn <= tol * std::sqrt(h.bb)) break;
+        if (res.restarts == 2 || h.iter >= maxit) {
+            res.flag = kMaxIter;
+            break;
+        }
+        res.restarts += 1;  // restart from the current x
+    }
+    return res;
+}
+
+struct mixed_result {
+    gko_status status = GKO_OK;
+    int32_t inner = 0, outer = 0;
+    double true_relres = 0.0;
+};
+
+mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gko_solver_opts &o,
+                      int bs, double bnorm) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    const int64_t n = A->n;
+    const values v64 = own_values(A), v32 = f32_values(A);
+    dbuf r(c, n * 8), rt(c, n * 4), d(c, n * 4), nrm(c, 8), partials(c, kPartialBytes), ticket(c, 8);
+    HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+    mixed_result res;
+    double prev = std::numeric_limits<double>::infinity();
+    for (;;) {
+        HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v64, -1.0, x, 1.0, r.p);
+        const double rn = device_norm(c, vt::f64, n, r.p, nrm.as<double>(), partials.as<double>(),
+                                      ticket.as<unsigned>());
+        res.true_relres = rn / bnorm;
+        if (std::isnan(rn)) { res.status = GKO_ERR_BREAKDOWN; break; }
+        if (rn <= tol * bnorm) { res.status = GKO_OK; break; }
+        if (res.outer >= o.max_outer || !(rn <= 0.5 * prev)) {
+            res.status = GKO_ERR_NOT_CONVERGED;
+            break;
+        }
+        prev = rn;
+        HIPC(scaled_cast(s, n, r.as<double>(), nrm.as<double>(), rt.as<float>()));
+        HIPC(fill_zero(s, vt::f32, n, d.p));
+        solve_result in = cg_core(A, v32, rt.p, d.p, o.inner_tol, o.max_inner,
+                                  bs > 0 ? (const void *)A->bj32 : nullptr, bs, o.check_every, false);
+        res.inner += in.iters;
+        if (in.flag == kNotSpd || in.flag == kBreakdown) {
+            res.status = flag_status(in.flag);
+            break;
+        }
+        HIPC(refine_update(s, n, static_cast<double *>(x), nrm.as<double>(), d.as<float>()));
+        res.outer += 1;
+    }
+    return res;
+}
+
+void check_square_f64(gko_matrix A) {
+    require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+    require(A->n == A->m, GKO_ERR_DIM_MISMATCH, "matrix must be square");
+    require(A->dt == GKO_F64, GKO_ERR_UNSUPPORTED, "solvers take FP64 matrices (mixed precision makes its own FP32 copy)");
+}
+
+void check_solve_args(const void *b, void *x, double tol, int32_t maxit) {
+    require(b && x, GKO_ERR_INVALID_ARG, "null b or x");
+    require(tol > 0.0 && std::isfinite(tol), GKO_ERR_INVALID_ARG, "tol must be positive and finite");
+    require(maxit >= 0, GKO_ERR_INVALID_ARG, "maxit must be >= 0");
+}
+
+bool overlap(const void *a, size_t na, const void *b, size_t nb) {
+    const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
+    return pa < pb + nb && pb < pa + na;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+const char *gko_last_error(void) { return g_last_error.c_str(); }
+
+const char *gko_status_string(gko_status s) {
+    switch (s) {
+        case GKO_OK: return "ok";
+        case GKO_ERR_INVALID_ARG: return "invalid argument";
+        case GKO_ERR_DIM_MISMATCH: return "dimension mismatch";
+        case GKO_ERR_UNSUPPORTED: return "unsupported";
+        case GKO_ERR_ALLOC: return "allocation failed";
+        case GKO_ERR_HIP: return "HIP runtime error";
+        case GKO_ERR_NOT_CONVERGED: return "not converged";
+        case GKO_ERR_BREAKDOWN: return "breakdown";
+        case GKO_ERR_NOT_SPD: return "matrix not SPD";
+        default: return "unknown status";
+    }
+}
+
+gko_status gko_context_create(void *hip_stream, gko_context *out) {
+    return guarded([&] {
+        require(out != nullptr, GKO_ERR_INVALID_ARG, "null output handle");
+        *out = nullptr;
+        auto c = new gko_context_s();
+        try {
+            HIPC(hipGetDevice(&c->device));
+            c->stream = static_cast<hipStream_t>(hip_stream);
+            HIPC(hipMalloc(&c->red_partials, kPartialBytes));
+            HIPC(hipMalloc(&c->red_ticket, 8));
+            HIPC(hipMemsetAsync(c->red_ticket, 0, 8, c->stream));
+            HIPC(hipStreamSynchronize(c->stream));
+        } catch (...) {
+            if (c->red_partials) (void)hipFree(c->red_partials);
+            if (c->red_ticket) (void)hipFree(c->red_ticket);
+            delete c;
+            throw;
+        }
+        *out = c;
+    });
+}
+
+gko_status gko_context_destroy(gko_context ctx) {
+    return guarded([&] {
+        if (!ctx) return;
+        (void)hipStreamSynchronize(ctx->stream);
+        (void)hipFree(ctx->red_partials);
+        (void)hipFree(ctx->red_ticket);
+        delete ctx;
+    });
+}
+
+gko_status gko_context_set_stream(gko_context ctx, void *hip_stream) {
+    return guarded([&] {
+        require(ctx != nullptr, GKO_ERR_INVALID_ARG, "null context");
+        ctx->stream = static_cast<hipStream_t>(hip_stream);
+    });
+}
+
+gko_status gko_context_set_allocator(gko_context ctx, gko_alloc_fn alloc, gko_dealloc_fn dealloc,
+                                     void *user) {
+    return guarded([&] {
+        require(ctx != nullptr, GKO_ERR_INVALID_ARG, "null context");
+        require((alloc == nullptr) == (dealloc == nullptr), GKO_ERR_INVALID_ARG,
+                "alloc and dealloc must both be set or both be NULL");
+        ctx->alloc = alloc;
+        ctx->dealloc = dealloc;
+        ctx->user = user;
+    });
+}
+
+gko_status gko_matrix_create_csr(gko_context ctx, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                                 gko_dtype dt, const void *row_ptr, gko_itype row_ptr_type,
+                                 const int32_t *col_idx, const void *values, gko_matrix *out) {
+    return guarded([&] {
+        require(ctx && out, GKO_ERR_INVALID_ARG, "null context or output handle");
+        *out = nullptr;
+        require(n_rows >= 0 && n_cols >= 0 && nnz >= 0, GKO_ERR_INVALID_ARG, "negative size");
+        require(n_rows < std::numeric_limits<int32_t>::max() &&
+                    n_cols <= std::numeric_limits<int32_t>::max(),
+                GKO_ERR_UNSUPPORTED, "dimensions must fit int32 indices");
+        require(nnz < std::numeric_limits<int32_t>::max(), GKO_ERR_UNSUPPORTED,
+                "nnz must be below 2^31");
+        require(dt == GKO_F64 || dt == GKO_F32, GKO_ERR_INVALID_ARG, "bad dtype");
+        require(row_ptr_type == GKO_I32 || row_ptr_type == GKO_I64, GKO_ERR_INVALID_ARG, "bad itype");
+        require(row_ptr != nullptr, GKO_ERR_INVALID_ARG, "null row_ptr");
+        require(nnz == 0 || (col_idx && values), GKO_ERR_INVALID_ARG, "null col_idx or values");
+        hipStream_t s = ctx->stream;
+        const size_t vb = dt == GKO_F64 ? 8 : 4;
+        dbuf rp(ctx, (n_rows + 1) * 4), col(ctx, nnz * 4), val(ctx, nnz * vb), err(ctx, 4);
+        HIPC(hipMemsetAsync(err.p, 0, 4, s));
+        if (row_ptr_type == GKO_I64)
+            HIPC(narrow_row_ptr(s, n_rows, static_cast<const int64_t *>(row_ptr), rp.as<int32_t>(),
+                                err.as<int>()));
+        else
+            HIPC(hipMemcpyAsync(rp.p, row_ptr, (n_rows + 1) * 4, hipMemcpyDeviceToDevice, s));
+        if (nnz > 0) {
+            HIPC(hipMemcpyAsync(col.p, col_idx, nnz * 4, hipMemcpyDeviceToDevice, s));
+            HIPC(hipMemcpyAsync(val.p, values, nnz * vb, hipMemcpyDeviceToDevice, s));
+        }
+        HIPC(validate_csr(s, n_rows, n_cols, nnz, rp.as<int32_t>(), col.as<int32_t>(), err.as<int>()));
+        const int64_t e = read_int(ctx, err.as<int>());
+        if (e & 1) fail(GKO_ERR_INVALID_ARG, "row_ptr must start at 0, be non-decreasing and end at nnz");
+        if (e & 2) fail(GKO_ERR_INVALID_ARG, "column index out of range");
+        if (e & 4) fail(GKO_ERR_INVALID_ARG, "column indices must be strictly increasing within a row");
+        auto A = new gko_matrix_s();
+        A->ctx = ctx;
+        A->fmt = GKO_FMT_CSR;
+        A->dt = dt;
+        A->n = n_rows;
+        A->m = n_cols;
+        A->nnz = nnz;
+        A->rp = static_cast<int32_t *>(rp.release());
+        A->col = static_cast<int32_t *>(col.release());
+        A->val = val.release();
+        A->subwarp = csr_subwarp_width(n_rows, nnz);
+        *out = A;
+    });
+}
+
+gko_status gko_matrix_destroy(gko_matrix A) {
+    return guarded([&] {
+        if (!A) return;
+        A->drop_storage();
+        delete A;
+    });
+}
+
+gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
+    return guarded([&] {
+        require(A && out, GKO_ERR_INVALID_ARG, "null matrix or output handle");
+        *out = nullptr;
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        auto B = new gko_matrix_s();
+        try {
+            B->ctx = c; B->fmt = A->fmt; B->dt = A->dt; B->n = A->n; B->m = A->m; B->nnz = A->nnz;
+            B->tiles = A->tiles; B->K = A->K; B->ld = A->ld; B->tnnz = A->tnnz; B->subwarp = A->subwarp;
+            auto copy = [&](const void *src, size_t bytes) -> void * {
+                if (!src) return nullptr;
+                void *d = c->alloc_bytes(bytes);
+                HIPC(hipMemcpyAsync(d, src, bytes, hipMemcpyDeviceToDevice, s));
+                return d;
+            };
+            const size_t vb = A->vs();
+            B->rp = (int32_t *)copy(A->rp, (A->n + 1) * 4);
+            B->row = (int32_t *)copy(A->row, A->nnz * 4);
+            B->col = (int32_t *)copy(A->col, A->nnz * 4);
+            B->val = copy(A->val, A->nnz * vb);
+            B->part = (int32_t *)copy(A->part, 2 * (A->tiles + 1) * 4);
+            B->ecol = (int32_t *)copy(A->ecol, A->K * A->ld * 4);
+            B->eval = copy(A->eval, A->K * A->ld * vb);
+            B->trow = (int32_t *)copy(A->trow, A->tnnz * 4);
+            B->tcol = (int32_t *)copy(A->tcol, A->tnnz * 4);
+            B->tval = copy(A->tval, A->tnnz * vb);
+            if (A->carry_a) ensure_carries(B, A->carry_elems);
+            c->sync();
+        } catch (...) {
+            B->drop_storage();
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out) {
+    return guarded([&] {
+        require(A && out, GKO_ERR_INVALID_ARG, "null matrix or output");
+        out->format = A->fmt;
+        out->dtype = A->dt;
+        out->n_rows = A->n;
+        out->n_cols = A->m;
+        out->nnz = A->nnz;
+        out->ell_width = (A->fmt == GKO_FMT_ELL || A->fmt == GKO_FMT_HYBRID) ? A->K : 0;
+        out->ell_ld = (A->fmt == GKO_FMT_ELL || A->fmt == GKO_FMT_HYBRID) ? A->ld : 0;
+        out->coo_nnz = A->fmt == GKO_FMT_COO ? A->nnz : (A->fmt == GKO_FMT_HYBRID ? A->tnnz : 0);
+        out->stored_bytes = A->stored_bytes();
+    });
+}
+
+gko_status gko_matrix_export_csr(gko_matrix A, int32_t *row_ptr, int32_t *col_idx, void *values) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        require(row_ptr && (A->nnz == 0 || (col_idx && values)), GKO_ERR_INVALID_ARG, "null output");
+        export_csr_into(A, own_values(A), row_ptr, col_idx, values);
+        A->ctx->sync();
+    });
+}
+
+gko_status gko_matrix_export_storage(gko_matrix A, int32_t *ell_col, void *ell_val, int32_t *coo_row,
+                                     int32_t *coo_col, void *coo_val) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const size_t vb = A->vs();
+        const bool has_ell = A->fmt == GKO_FMT_ELL || A->fmt == GKO_FMT_HYBRID;
+        const bool has_coo = A->fmt == GKO_FMT_COO || A->fmt == GKO_FMT_HYBRID;
+        require(has_ell || (!ell_col && !ell_val), GKO_ERR_INVALID_ARG, "format stores no ELL arrays");
+        require(has_coo || (!coo_row && !coo_col && !coo_val), GKO_ERR_INVALID_ARG,
+                "format stores no COO arrays");
+        const int64_t slots = A->K * A->ld;
+        if (ell_col) HIPC(hipMemcpyAsync(ell_col, A->ecol, slots * 4, hipMemcpyDeviceToDevice, s));
+        if (ell_val) HIPC(hipMemcpyAsync(ell_val, A->eval, slots * vb, hipMemcpyDeviceToDevice, s));
+        const bool hyb = A->fmt == GKO_FMT_HYBRID;
+        const int64_t cn = hyb ? A->tnnz : A->nnz;
+        if (coo_row) HIPC(hipMemcpyAsync(coo_row, hyb ? A->trow : A->row, cn * 4, hipMemcpyDeviceToDevice, s));
+        if (coo_col) HIPC(hipMemcpyAsync(coo_col, hyb ? A->tcol : A->col, cn * 4, hipMemcpyDeviceToDevice, s));
+        if (coo_val) HIPC(hipMemcpyAsync(coo_val, hyb ? A->tval : A->val, cn * vb, hipMemcpyDeviceToDevice, s));
+        c->sync();
+    });
+}
+
+gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void *y) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        require((x || A->m == 0) && (y || A->n == 0), GKO_ERR_INVALID_ARG, "null x or y");
+        const size_t vb = A->vs();
+        require(!(x && y && overlap(x, A->m * vb, y, A->n * vb)), GKO_ERR_INVALID_ARG,
+                "x and y must not overlap");
+        spmv_dispatch(A, own_values(A), alpha, x, beta, y);
+    });
+}
+
+gko_status gko_convert(gko_matrix A, gko_format fmt) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        require(fmt >= GKO_FMT_CSR && fmt <= GKO_FMT_AUTO, GKO_ERR_INVALID_ARG, "unknown format");
+        if (fmt == GKO_FMT_AUTO) {
+            // time one SpMV per feasible format on a scratch x / y, keep the fastest
+            gko_context c = A->ctx;
+            hipStream_t s = c->stream;
+            const size_t vb = A->vs();
+            dbuf x(c, std::max<int64_t>(A->m, 1) * vb), y(c, std::max<int64_t>(A->n, 1) * vb);
+            HIPC(fill_zero(s, A->type(), A->m, x.p));
+            hipEvent_t e0, e1;
+            HIPC(hipEventCreate(&e0));
+            HIPC(hipEventCreate(&e1));
+            gko_format best = A->fmt;
+            float best_ms = std::numeric_limits<float>::infinity();
+            const gko_format cand[5] = {GKO_FMT_CSR, GKO_FMT_CSR_MERGE, GKO_FMT_COO, GKO_FMT_ELL,
+                                        GKO_FMT_HYBRID};
+            for (gko_format f : cand) {
+                try {
+                    convert_to(A, f);
+                } catch (const api_error &e) {
+                    if (e.status == GKO_ERR_UNSUPPORTED) continue;
+                    throw;
+                }
+                spmv_dispatch(A, own_values(A), 1.0, x.p, 0.0, y.p);  // warm-up
+                HIPC(hipEventRecord(e0, s));
+                for (int r = 0; r < 5; ++r) spmv_dispatch(A, own_values(A), 1.0, x.p, 0.0, y.p);
+                HIPC(hipEventRecord(e1, s));
+                HIPC(hipEventSynchronize(e1));
+                float ms = 0.f;
+                HIPC(hipEventElapsedTime(&ms, e0, e1));
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = f;
+                }
+            }
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            convert_to(A, best);
+            return;
+        }
+        convert_to(A, fmt);
+    });
+}
+
+gko_status gko_dot(gko_context ctx, gko_dtype dt, int64_t n, const void *x, const void *y,
+                   double *result) {
+    return guarded([&] {
+        require(ctx && result, GKO_ERR_INVALID_ARG, "null context or result");
+        require(n >= 0 && (n == 0 || (x && y)), GKO_ERR_INVALID_ARG, "bad vectors");
+        require(dt == GKO_F64 || dt == GKO_F32, GKO_ERR_INVALID_ARG, "bad dtype");
+        HIPC(dot(ctx->stream, dt == GKO_F64 ? vt::f64 : vt::f32, n, x, y, result, ctx->red_partials,
+                 ctx->red_ticket, false));
+    });
+}
+
+gko_status gko_norm2(gko_context ctx, gko_dtype dt, int64_t n, const void *x, double *result) {
+    return guarded([&] {
+        require(ctx && result, GKO_ERR_INVALID_ARG, "null context or result");
+        require(n >= 0 && (n == 0 || x), GKO_ERR_INVALID_ARG, "bad vector");
+        require(dt == GKO_F64 || dt == GKO_F32, GKO_ERR_INVALID_ARG, "bad dtype");
+        HIPC(dot(ctx->stream, dt == GKO_F64 ? vt::f64 : vt::f32, n, x, x, result, ctx->red_partials,
+                 ctx->red_ticket, true));
+    });
+}
+
+gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *o) {
+    return guarded([&] {
+        require(ctx && o, GKO_ERR_INVALID_ARG, "null context or options");
+        require(o->precision == GKO_PREC_FP64 || o->precision == GKO_PREC_MIXED_IR,
+                GKO_ERR_INVALID_ARG, "bad precision");
+        require(o->precond == GKO_PRECOND_NONE || o->precond == GKO_PRECOND_BLOCK_JACOBI,
+                GKO_ERR_INVALID_ARG, "bad preconditioner");
+        const int bs = o->block_size;
+        require(bs == 1 || bs == 2 || bs == 4 || bs == 8 || bs == 16, GKO_ERR_UNSUPPORTED,
+                "block size must be 1, 2, 4, 8 or 16");
+        require(o->check_every >= 1, GKO_ERR_INVALID_ARG, "check_every must be >= 1");
+        require(o->inner_tol > 0.0 && o->inner_tol < 1.0, GKO_ERR_INVALID_ARG, "inner_tol in (0,1)");
+        require(o->max_inner >= 1 && o->max_outer >= 1, GKO_ERR_INVALID_ARG, "iteration caps >= 1");
+        ctx->opts = *o;
+    });
+}
+
+gko_status gko_context_get_solver_opts(gko_context ctx, gko_solver_opts *out) {
+    return guarded([&] {
+        require(ctx && out, GKO_ERR_INVALID_ARG, "null context or output");
+        *out = ctx->opts;
+    });
+}
+
+gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out) {
+    return guarded([&] {
+        require(ctx && out, GKO_ERR_INVALID_ARG, "null context or output");
+        *out = ctx->info;
+    });
+}
+
+gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_square_f64(A);
+        check_solve_args(b, x, tol, maxit);
+        gko_context c = A->ctx;
+        const double t0 = now_seconds();
+        c->info = gko_solve_info{};
+        const gko_solver_opts o = c->opts;
+        const int64_t n = A->n;
+        // ||b|| decides the trivial cases before any iteration
+            dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
+        HIPC(hipMemsetAsync(ticket.p, 0, 8, c->stream));
+        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
+                                         ticket.as<unsigned>());
+        if (!std::isfinite(bnorm)) {
+            st = GKO_ERR_BREAKDOWN;
+        } else if (bnorm == 0.0) {
+            HIPC(fill_zero(c->stream, vt::f64, n, x));
+            c->sync();
+            st = GKO_OK;
+        } else {
+            const int bs = o.precond == GKO_PRECOND_BLOCK_JACOBI ? o.block_size : 0;
+            if (bs > 0) {
+                const double ts = now_seconds();
+                ensure_block_jacobi(A, bs, o.precision == GKO_PREC_MIXED_IR);
+                c->sync();
+                c->info.setup_seconds = now_seconds() - ts;
+            }
+            if (o.precision == GKO_PREC_MIXED_IR) {
+                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm);
+                st = r.status;
+                c->info.iterations = r.inner;
+                c->info.outer_iterations = r.outer;
+                c->info.rel_residual = r.true_relres;
+                c->info.true_rel_residual = r.true_relres;
+            } else {
+                solve_result r = cg_core(A, own_values(A), b, x, tol, maxit,
+                                         bs > 0 ? (const void *)A->bj64 : nullptr, bs,
+                                         o.check_every, true);
+                st = flag_status(r.flag);
+                c->info.iterations = r.iters;
+                c->info.restarts = r.restarts;
+                c->info.rel_residual = r.relres;
+                c->info.true_rel_residual = r.true_relres;
+            }
+        }
+        c->sync();
+        c->info.status = st;
+        c->info.seconds = now_seconds() - t0;
+    });
+    if (call != GKO_OK) return call;
+    if (st != GKO_OK) g_last_error = std::string("cg: ") + gko_status_string(st);
+    return st;
+}
+
+gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_square_f64(A);
+        check_solve_args(b, x, tol, maxit);
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const double t0 = now_seconds();
+        c->info = gko_solve_info{};
+        const int64_t n = A->n;
+            const int check_every = c->opts.check_every;
+        const values v = own_values(A);
+        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8), sc(c, sizeof(krylov_scalars));
+        HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
+                                         ticket.as<unsigned>());
+        if (!std::isfinite(bnorm)) {
+            st = GKO_ERR_BREAKDOWN;
+        } else if (bnorm == 0.0) {
+            HIPC(fill_zero(s, vt::f64, n, x));
+            st = GKO_OK;
+        } else {
+            dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), vv(c, n * 8), sv(c, n * 8), t(c, n * 8);
+            auto *S = sc.as<krylov_scalars>();
+            double *P = partials.as<double>();
+            unsigned *T = ticket.as<unsigned>();
+            HIPC(scalars_reset(s, S, maxit));
+            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            HIPC(bicg_init(s, n, b, r.p, rh.p, p.p, vv.p, tol, S, P, T));
+            krylov_scalars h = read_back(c, S);
+            while (h.done == kRunning) {
+                for (int j = 0; j < check_every; ++j) {
+                    HIPC(bicg_p(s, n, r.p, vv.p, p.p, S));
+                    spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
+                    HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
+                    HIPC(bicg_s(s, n, r.p, vv.p, sv.p, S, P, T));
+                    spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
+                    HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
+                    HIPC(bicg_update(s, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
+                }
+                h = read_back(c, S);
+            }
+            st = flag_status(h.done);
+            c->info.iterations = h.iter;
+            c->info.rel_residual = std::sqrt(h.rr / h.bb);
+            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(), P, T) / bnorm;
+        }
+        c->sync();
+        c->info.status = st;
+        c->info.seconds = now_seconds() - t0;
+    });
+    if (call != GKO_OK) return call;
+    if (st != GKO_OK) g_last_error = std::string("bicgstab: ") + gko_status_string(st);
+    return st;
+}
+
+}  // extern "C"

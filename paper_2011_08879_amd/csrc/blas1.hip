@@ -1,0 +1,594 @@
+// Vector kernels of the Krylov solvers: dot/norm reductions and the fused
+// step kernels of CG (with optional block-Jacobi) and BiCGSTAB.
+//
+// The paper's solvers are memory bound (Sec. 6.2), so each step is fused to
+// touch every vector as few times as possible, and the scalars of the
+// recurrences (alpha, beta, rho, ...) never leave the GPU: the last block of
+// each deterministic grid reduction updates them in device memory, and every
+// kernel returns immediately once the solver is flagged done.  Reductions
+// always accumulate in FP64, also for FP32 vectors.
+#include <cmath>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "solver_kernels.hpp"
+#include "solver_state.hpp"
+
+namespace gko {
+
+constexpr int kB = kRedBlock;  // 256 threads, one row per thread per tile
+
+int reduction_blocks(int64_t n) {
+    int64_t g = (n + kB - 1) / kB;
+    if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+// ------------------------------------------------------------------ dot / norm
+template <typename V>
+__global__ __launch_bounds__(kB) void dot_kernel(int64_t n, const V *__restrict__ x,
+                                                 const V *__restrict__ y, double *result,
+                                                 double *partials, unsigned *ticket, bool sq) {
+    double s = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+        s += (double)x[i] * (double)y[i];
+    double v[1] = {s}, out[1];
+    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0)
+        *result = sq ? sqrt(out[0]) : out[0];
+}
+
+hipError_t dot(hipStream_t s, vt t, int64_t n, const void *x, const void *y, double *result,
+               double *partials, unsigned *ticket, bool sqrt_result) {
+    const int g = reduction_blocks(n);
+    if (t == vt::f64)
+        dot_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(x),
+                                            static_cast<const double *>(y), result, partials,
+                                            ticket, sqrt_result);
+    else
+        dot_kernel<float><<<g, kB, 0, s>>>(n, static_cast<const float *>(x),
+                                           static_cast<const float *>(y), result, partials, ticket,
+                                           sqrt_result);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ scalars
+__global__ void scalars_reset_kernel(krylov_scalars *sc, int32_t maxit) {
+    sc->rho = sc->rho_old = sc->alpha = sc->beta = sc->omega = 0.0;
+    sc->rr = sc->bb = sc->stop2 = sc->aux = 0.0;
+    sc->iter = 0;
+    sc->maxit = maxit;
+    sc->done = kRunning;
+    sc->half = 0;
+}
+
+hipError_t scalars_reset(hipStream_t s, krylov_scalars *sc, int32_t maxit) {
+    scalars_reset_kernel<<<1, 1, 0, s>>>(sc, maxit);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ block-Jacobi apply
+// z_i = sum_j D_b^{-1}[i mod bs][j] r_{b*bs + j} for the tile of 256 rows
+// starting at `base`; the tile's inverse blocks (256*BS values, contiguous
+// because BS divides 256) and residuals are staged in LDS with coalesced
+// loads.  Slots of a short last block beyond n are zero in `inv`.
+template <typename V, int BS>
+__device__ inline V bj_tile_apply(int64_t n, int64_t base, V ri, const V *__restrict__ inv,
+                                  V *r_lds, V *inv_lds) {
+    const int tid = threadIdx.x;
+    r_lds[tid] = ri;
+    const int64_t nb = (n + BS - 1) / BS;
+    const int64_t off = base * BS;  // (base / BS) * BS * BS
+    for (int t = tid; t < kB * BS; t += kB)
+        inv_lds[t] = (off + t < nb * BS * BS) ? inv[off + t] : V(0);
+    __syncthreads();
+    V z = V(0);
+    const int b0 = (tid / BS) * BS;
+#pragma unroll
+    for (int j = 0; j < BS; ++j) z += inv_lds[tid * BS + j] * r_lds[b0 + j];
+    __syncthreads();
+    return z;
+}
+
+// ------------------------------------------------------------------ CG
+// Start (or restart) from r = b - A x: z = M^-1 r, p = z, rho = r.z, rr = r.r,
+// bb = b.b; flags convergence at zero iterations.
+template <typename V, int BS>
+__global__ __launch_bounds__(kB) void cg_init_kernel(int64_t n, const V *__restrict__ b,
+                                                     const V *__restrict__ r, V *__restrict__ z,
+                                                     V *__restrict__ p, const V *__restrict__ inv,
+                                                     double tol, krylov_scalars *sc,
+                                                     double *partials, unsigned *ticket) {
+    __shared__ V r_lds[BS > 0 ? kB : 1];
+    __shared__ V inv_lds[BS > 0 ? kB * BS : 1];
+    double a_rz = 0.0, a_rr = 0.0, a_bb = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
+        const int64_t i = base + threadIdx.x;
+        const V ri = i < n ? r[i] : V(0);
+        V zi = ri;
+        if constexpr (BS > 0) zi = bj_tile_apply<V, BS>(n, base, ri, inv, r_lds, inv_lds);
+        if (i < n) {
+            if constexpr (BS > 0) z[i] = zi;
+            p[i] = zi;
+            const double bi = (double)b[i];
+            a_rz += (double)ri * (double)zi;
+            a_rr += (double)ri * (double)ri;
+            a_bb += bi * bi;
+        }
+    }
+    double v[3] = {a_rz, a_rr, a_bb}, out[3];
+    if (grid_reduce<kB, 3>(v, partials, ticket, out) && threadIdx.x == 0) {
+        sc->rho = out[0];
+        sc->rr = out[1];
+        sc->bb = out[2];
+        sc->stop2 = tol * tol * out[2];
+        if (!std::isfinite(out[1]) || !std::isfinite(out[0])) sc->done = kBreakdown;
+        else if (out[1] <= sc->stop2) sc->done = kConverged;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else sc->done = kRunning;
+    }
+}
+
+__device__ inline void cg_set_alpha(krylov_scalars *sc, double pq) {
+    sc->aux = pq;
+    if (!(pq > 0.0)) {
+        sc->done = std::isnan(pq) ? kBreakdown : kNotSpd;
+        sc->iter += 1;
+    } else {
+        sc->alpha = sc->rho / pq;
+    }
+}
+
+// q = A p for CSR with a subwarp of W lanes per row, fused with p.q.
+template <typename V, int W>
+__global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const V *__restrict__ val,
+                                                         const V *__restrict__ p, V *__restrict__ q,
+                                                         krylov_scalars *sc, double *partials,
+                                                         unsigned *ticket) {
+    if (sc->done) return;
+    constexpr int RPB = kB / W;
+    const int lane = threadIdx.x % W;
+    double acc = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
+        const int64_t row = base + threadIdx.x / W;
+        if (row < n) {
+            V s = V(0);
+            for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += W) s += val[k] * p[col[k]];
+            s = subwarp<W>::reduce_sum(s);
+            if (lane == 0) {
+                q[row] = s;
+                acc += (double)p[row] * (double)s;
+            }
+        }
+    }
+    double v[1] = {acc}, out[1];
+    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+}
+
+// p.q after a SpMV done by a format's own kernel.
+template <typename V>
+__global__ __launch_bounds__(kB) void cg_pq_kernel(int64_t n, const V *__restrict__ p,
+                                                   const V *__restrict__ q, krylov_scalars *sc,
+                                                   double *partials, unsigned *ticket) {
+    if (sc->done) return;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+        acc += (double)p[i] * (double)q[i];
+    double v[1] = {acc}, out[1];
+    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+}
+
+// x += alpha p; r -= alpha q; z = M^-1 r; rho' = r.z; rr = r.r; then beta.
+template <typename V, int BS>
+__global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict__ x,
+                                                       V *__restrict__ r, V *__restrict__ z,
+                                                       const V *__restrict__ p,
+                                                       const V *__restrict__ q,
+                                                       const V *__restrict__ inv,
+                                                       krylov_scalars *sc, double *partials,
+                                                       unsigned *ticket) {
+    __shared__ V r_lds[BS > 0 ? kB : 1];
+    __shared__ V inv_lds[BS > 0 ? kB * BS : 1];
+    if (sc->done) return;
+    const double alpha = sc->alpha;
+    double a_rz = 0.0, a_rr = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
+        const int64_t i = base + threadIdx.x;
+        V ri = V(0);
+        if (i < n) {
+            x[i] = (V)((double)x[i] + alpha * (double)p[i]);
+            ri = (V)((double)r[i] - alpha * (double)q[i]);
+            r[i] = ri;
+        }
+        V zi = ri;
+        if constexpr (BS > 0) zi = bj_tile_apply<V, BS>(n, base, ri, inv, r_lds, inv_lds);
+        if (i < n) {
+            if constexpr (BS > 0) z[i] = zi;
+            a_rz += (double)ri * (double)zi;
+            a_rr += (double)ri * (double)ri;
+        }
+    }
+    double v[2] = {a_rz, a_rr}, out[2];
+    if (grid_reduce<kB, 2>(v, partials, ticket, out) && threadIdx.x == 0) {
+        sc->iter += 1;
+        sc->rr = out[1];
+        if (!std::isfinite(out[1]) || !std::isfinite(out[0])) {
+            sc->done = kBreakdown;
+        } else if (out[1] <= sc->stop2) {
+            sc->done = kConverged;
+        } else {
+            sc->beta = out[0] / sc->rho;
+            sc->rho = out[0];
+            if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        }
+    }
+}
+
+// p = z + beta p  (z = r without a preconditioner).
+template <typename V>
+__global__ __launch_bounds__(kB) void cg_direction_kernel(int64_t n, const V *__restrict__ z,
+                                                          V *__restrict__ p,
+                                                          const krylov_scalars *sc) {
+    if (sc->done) return;
+    const double beta = sc->beta;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+        p[i] = (V)((double)z[i] + beta * (double)p[i]);
+}
+
+template <typename V>
+static hipError_t launch_cg_init(hipStream_t s, int64_t n, const void *b, const void *r, void *z,
+                                 void *p, const void *inv, int bs, double tol, krylov_scalars *sc,
+                                 double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    const V *B = static_cast<const V *>(b), *R = static_cast<const V *>(r);
+    V *Z = static_cast<V *>(z), *P = static_cast<V *>(p);
+    const V *I = static_cast<const V *>(inv);
+    switch (bs) {
+        case 0: cg_init_kernel<V, 0><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 1: cg_init_kernel<V, 1><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 2: cg_init_kernel<V, 2><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 4: cg_init_kernel<V, 4><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 8: cg_init_kernel<V, 8><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 16: cg_init_kernel<V, 16><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,
+                   const void *inv, int bs, double tol, krylov_scalars *sc, double *partials,
+                   unsigned *ticket) {
+    return t == vt::f64 ? launch_cg_init<double>(s, n, b, r, z, p, inv, bs, tol, sc, partials, ticket)
+                        : launch_cg_init<float>(s, n, b, r, z, p, inv, bs, tol, sc, partials, ticket);
+}
+
+template <typename V, int W>
+static hipError_t launch_cg_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                                  const void *val, const void *p, void *q, krylov_scalars *sc,
+                                  double *partials, unsigned *ticket) {
+    int64_t g = (n + (kB / W) - 1) / (kB / W);
+    if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
+    if (g < 1) g = 1;
+    cg_spmv_csr_kernel<V, W><<<(unsigned)g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
+                                                        static_cast<const V *>(p),
+                                                        static_cast<V *>(q), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t launch_cg_csr(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                                const void *val, const void *p, void *q, int w, krylov_scalars *sc,
+                                double *partials, unsigned *ticket) {
+    switch (w) {
+        case 1: return launch_cg_csr_w<V, 1>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 2: return launch_cg_csr_w<V, 2>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 4: return launch_cg_csr_w<V, 4>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 8: return launch_cg_csr_w<V, 8>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 16: return launch_cg_csr_w<V, 16>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 32: return launch_cg_csr_w<V, 32>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        case 64: return launch_cg_csr_w<V, 64>(s, n, rp, col, val, p, q, sc, partials, ticket);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                       const void *val, const void *p, void *q, int w, krylov_scalars *sc,
+                       double *partials, unsigned *ticket) {
+    return t == vt::f64 ? launch_cg_csr<double>(s, n, rp, col, val, p, q, w, sc, partials, ticket)
+                        : launch_cg_csr<float>(s, n, rp, col, val, p, q, w, sc, partials, ticket);
+}
+
+hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
+                 double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    if (t == vt::f64)
+        cg_pq_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(p),
+                                              static_cast<const double *>(q), sc, partials, ticket);
+    else
+        cg_pq_kernel<float><<<g, kB, 0, s>>>(n, static_cast<const float *>(p),
+                                             static_cast<const float *>(q), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t launch_cg_update(hipStream_t s, int64_t n, void *x, void *r, void *z,
+                                   const void *p, const void *q, const void *inv, int bs,
+                                   krylov_scalars *sc, double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    V *X = static_cast<V *>(x), *R = static_cast<V *>(r), *Z = static_cast<V *>(z);
+    const V *P = static_cast<const V *>(p), *Q = static_cast<const V *>(q);
+    const V *I = static_cast<const V *>(inv);
+    switch (bs) {
+        case 0: cg_update_kernel<V, 0><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 1: cg_update_kernel<V, 1><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 2: cg_update_kernel<V, 2><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 4: cg_update_kernel<V, 4><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 8: cg_update_kernel<V, 8><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 16: cg_update_kernel<V, 16><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,
+                     const void *q, const void *inv, int bs, krylov_scalars *sc, double *partials,
+                     unsigned *ticket) {
+    return t == vt::f64
+               ? launch_cg_update<double>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket)
+               : launch_cg_update<float>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket);
+}
+
+hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
+                        const krylov_scalars *sc) {
+    const int g = reduction_blocks(n);
+    if (t == vt::f64)
+        cg_direction_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(z),
+                                                     static_cast<double *>(p), sc);
+    else
+        cg_direction_kernel<float><<<g, kB, 0, s>>>(n, static_cast<const float *>(z),
+                                                    static_cast<float *>(p), sc);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ BiCGSTAB (FP64)
+// Start from r = b - A x: rhat = r, p = v = 0, rho = rhat.r, bb = b.b,
+// rho_old = alpha = omega = 1, so the first direction is p = r.
+__global__ __launch_bounds__(kB) void bicg_init_kernel(int64_t n, const double *__restrict__ b,
+                                                       const double *__restrict__ r,
+                                                       double *__restrict__ rh,
+                                                       double *__restrict__ p,
+                                                       double *__restrict__ v, double tol,
+                                                       krylov_scalars *sc, double *partials,
+                                                       unsigned *ticket) {
+    double a_rr = 0.0, a_bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        const double ri = r[i];
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        a_rr += ri * ri;
+        a_bb += b[i] * b[i];
+    }
+    double vv[2] = {a_rr, a_bb}, out[2];
+    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
+        sc->rho = out[0];
+        sc->rr = out[0];
+        sc->bb = out[1];
+        sc->stop2 = tol * tol * out[1];
+        sc->rho_old = sc->alpha = sc->omega = 1.0;
+        sc->half = 0;
+        if (!std::isfinite(out[0])) sc->done = kBreakdown;
+        else if (out[0] <= sc->stop2) sc->done = kConverged;
+        else if (!(fabs(out[0]) >= 1e-300)) sc->done = kBreakdown;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else {
+            sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+            sc->done = kRunning;
+        }
+    }
+}
+
+// p = r + beta (p - omega v)
+__global__ __launch_bounds__(kB) void bicg_p_kernel(int64_t n, const double *__restrict__ r,
+                                                    const double *__restrict__ v,
+                                                    double *__restrict__ p,
+                                                    const krylov_scalars *sc) {
+    if (sc->done) return;
+    const double beta = sc->beta, omega = sc->omega;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+        p[i] = r[i] + beta * (p[i] - omega * v[i]);
+}
+
+// alpha = rho / (rhat.v)
+__global__ __launch_bounds__(kB) void bicg_alpha_kernel(int64_t n, const double *__restrict__ rh,
+                                                        const double *__restrict__ v,
+                                                        krylov_scalars *sc, double *partials,
+                                                        unsigned *ticket) {
+    if (sc->done) return;
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
+        a += rh[i] * v[i];
+    double vv[1] = {a}, out[1];
+    if (grid_reduce<kB, 1>(vv, partials, ticket, out) && threadIdx.x == 0) {
+        sc->aux = out[0];
+        if (!(fabs(out[0]) >= 1e-300)) sc->done = kBreakdown;
+        else sc->alpha = sc->rho / out[0];
+    }
+}
+
+// s = r - alpha v, with s.s: converging here finishes at the half step.
+__global__ __launch_bounds__(kB) void bicg_s_kernel(int64_t n, const double *__restrict__ r,
+                                                    const double *__restrict__ v,
+                                                    double *__restrict__ s, krylov_scalars *sc,
+                                                    double *partials, unsigned *ticket) {
+    if (sc->done) return;
+    const double alpha = sc->alpha;
+    double a = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        const double si = r[i] - alpha * v[i];
+        s[i] = si;
+        a += si * si;
+    }
+    double vv[1] = {a}, out[1];
+    if (grid_reduce<kB, 1>(vv, partials, ticket, out) && threadIdx.x == 0) {
+        sc->iter += 1;
+        if (!std::isfinite(out[0])) sc->done = kBreakdown;
+        else if (out[0] <= sc->stop2) {
+            sc->half = 1;
+            sc->rr = out[0];
+        }
+    }
+}
+
+// omega = (t.s) / (t.t)
+__global__ __launch_bounds__(kB) void bicg_omega_kernel(int64_t n, const double *__restrict__ t,
+                                                        const double *__restrict__ s,
+                                                        krylov_scalars *sc, double *partials,
+                                                        unsigned *ticket) {
+    if (sc->done || sc->half) return;
+    double a_ts = 0.0, a_tt = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        a_ts += t[i] * s[i];
+        a_tt += t[i] * t[i];
+    }
+    double vv[2] = {a_ts, a_tt}, out[2];
+    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
+        sc->aux = out[1];
+        if (!(out[1] >= 1e-300)) sc->done = kBreakdown;
+        else sc->omega = out[0] / out[1];
+    }
+}
+
+// x += alpha p + omega s; r = s - omega t; then rr and the next rho = rhat.r.
+// At the half step only x += alpha p.
+__global__ __launch_bounds__(kB) void bicg_update_kernel(int64_t n, double *__restrict__ x,
+                                                         double *__restrict__ r,
+                                                         const double *__restrict__ rh,
+                                                         const double *__restrict__ p,
+                                                         const double *__restrict__ s,
+                                                         const double *__restrict__ t,
+                                                         krylov_scalars *sc, double *partials,
+                                                         unsigned *ticket) {
+    if (sc->done) return;
+    const bool half = sc->half != 0;
+    const double alpha = sc->alpha, omega = sc->omega;
+    double a_rr = 0.0, a_rho = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        if (half) {
+            x[i] = x[i] + alpha * p[i];
+        } else {
+            x[i] = x[i] + alpha * p[i] + omega * s[i];
+            const double ri = s[i] - omega * t[i];
+            r[i] = ri;
+            a_rr += ri * ri;
+            a_rho += rh[i] * ri;
+        }
+    }
+    double vv[2] = {a_rr, a_rho}, out[2];
+    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
+        if (half) {
+            sc->done = kConverged;
+            return;
+        }
+        sc->rr = out[0];
+        if (!std::isfinite(out[0])) sc->done = kBreakdown;
+        else if (out[0] <= sc->stop2) sc->done = kConverged;
+        else if (omega == 0.0) sc->done = kBreakdown;
+        else {
+            sc->rho_old = sc->rho;
+            sc->rho = out[1];
+            if (!(fabs(out[1]) >= 1e-300)) sc->done = kBreakdown;
+            else {
+                sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+                if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+            }
+        }
+    }
+}
+
+static inline const double *cd(const void *p) { return static_cast<const double *>(p); }
+static inline double *md(void *p) { return static_cast<double *>(p); }
+
+hipError_t bicg_init(hipStream_t st, int64_t n, const void *b, const void *r, void *rh, void *p,
+                     void *v, double tol, krylov_scalars *sc, double *partials, unsigned *ticket) {
+    bicg_init_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(b), cd(r), md(rh), md(p), md(v), tol,
+                                                        sc, partials, ticket);
+    return hipGetLastError();
+}
+
+hipError_t bicg_p(hipStream_t st, int64_t n, const void *r, const void *v, void *p,
+                  const krylov_scalars *sc) {
+    bicg_p_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(r), cd(v), md(p), sc);
+    return hipGetLastError();
+}
+
+hipError_t bicg_alpha(hipStream_t st, int64_t n, const void *rh, const void *v, krylov_scalars *sc,
+                      double *partials, unsigned *ticket) {
+    bicg_alpha_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(rh), cd(v), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+hipError_t bicg_s(hipStream_t st, int64_t n, const void *r, const void *v, void *s,
+                  krylov_scalars *sc, double *partials, unsigned *ticket) {
+    bicg_s_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(r), cd(v), md(s), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+hipError_t bicg_omega(hipStream_t st, int64_t n, const void *t, const void *s, krylov_scalars *sc,
+                      double *partials, unsigned *ticket) {
+    bicg_omega_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(t), cd(s), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+hipError_t bicg_update(hipStream_t st, int64_t n, void *x, void *r, const void *rh, const void *p,
+                       const void *s, const void *t, krylov_scalars *sc, double *partials,
+                       unsigned *ticket) {
+    bicg_update_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, md(x), md(r), cd(rh), cd(p), cd(s),
+                                                          cd(t), sc, partials, ticket);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ mixed-precision helpers
+// rt = fp32(r / ||r||) with ||r|| read from device memory.
+__global__ void scaled_cast_kernel(int64_t n, const double *__restrict__ r,
+                                   const double *__restrict__ norm, float *__restrict__ rt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) rt[i] = (float)(r[i] / *norm);
+}
+
+hipError_t scaled_cast(hipStream_t s, int64_t n, const double *r, const double *norm, float *rt) {
+    if (n == 0) return hipSuccess;
+    scaled_cast_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, r, norm, rt);
+    return hipGetLastError();
+}
+
+// x += ||r|| * fp64(d)
+__global__ void refine_update_kernel(int64_t n, double *__restrict__ x, const double *__restrict__ norm,
+                                     const float *__restrict__ d) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = x[i] + *norm * (double)d[i];
+}
+
+hipError_t refine_update(hipStream_t s, int64_t n, double *x, const double *norm, const float *d) {
+    if (n == 0) return hipSuccess;
+    refine_update_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, x, norm, d);
+    return hipGetLastError();
+}
+
+template <typename V>
+__global__ void fill_kernel(int64_t n, V *__restrict__ y, V v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = v;
+}
+
+hipError_t fill_zero(hipStream_t s, vt t, int64_t n, void *y) {
+    if (n == 0) return hipSuccess;
+    const unsigned g = (unsigned)((n + 255) / 256);
+    if (t == vt::f64) fill_kernel<double><<<g, 256, 0, s>>>(n, static_cast<double *>(y), 0.0);
+    else fill_kernel<float><<<g, 256, 0, s>>>(n, static_cast<float *>(y), 0.0f);
+    return hipGetLastError();
+}
+
+}  // namespace gko

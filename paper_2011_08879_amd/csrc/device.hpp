@@ -1,0 +1,107 @@
+// Device-side building blocks shared by the kernels: subwarp primitives for
+// 64-wide wavefronts, and deterministic block / grid reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gko {
+
+constexpr int kWave = 64;
+using lane_mask = uint64_t;
+
+// ------------------------------------------------------------------ subwarps
+// Contiguous subwarps of Size lanes (a power of two <= 64) inside a wavefront,
+// as in Sec. 4 (cooperative groups): Rank = tid % Size, LaneOffset =
+// floor((tid % 64) / Size) * Size, Mask = (~0 >> (64 - Size)) << LaneOffset.
+template <int Size>
+struct subwarp {
+    static_assert(Size >= 1 && Size <= kWave && (Size & (Size - 1)) == 0, "power of two");
+    __device__ static int rank() { return threadIdx.x % Size; }
+    __device__ static int lane_offset() { return ((threadIdx.x % kWave) / Size) * Size; }
+    __device__ static lane_mask mask() {
+        return (~lane_mask(0) >> (kWave - Size)) << lane_offset();
+    }
+    __device__ static lane_mask ballot(bool p) {
+        return (__ballot(p) & mask()) >> lane_offset();
+    }
+    __device__ static bool any(bool p) { return (__ballot(p) & mask()) != 0; }
+    __device__ static bool all(bool p) { return (__ballot(p) & mask()) == mask(); }
+
+    // Xor butterfly (Sec. 5 subgroup reduction): every lane of the subwarp
+    // ends with the subwarp sum; the combination order is fixed.
+    template <typename T>
+    __device__ static T reduce_sum(T v) {
+#pragma unroll
+        for (int b = 1; b < Size; b <<= 1) v += __shfl_xor(v, b, Size);
+        return v;
+    }
+};
+
+__device__ inline int popcnt(uint32_t m) { return __popc(m); }
+__device__ inline int popcnt(uint64_t m) { return __popcll(m); }
+
+// ------------------------------------------------------------------ block reduction
+// Sum over a block of BLOCK threads (multiple of 64) with a fixed tree: wave
+// butterfly, then the per-wave sums combined by wave 0.  Result valid in
+// thread 0.  `lds` needs BLOCK/64 slots.
+template <int BLOCK, typename T>
+__device__ inline T block_sum(T v, T *lds) {
+    static_assert(BLOCK % kWave == 0, "block of whole waves");
+    constexpr int NW = BLOCK / kWave;
+    v = subwarp<kWave>::reduce_sum(v);
+    const int w = threadIdx.x / kWave;
+    if ((threadIdx.x % kWave) == 0) lds[w] = v;
+    __syncthreads();
+    T s = T(0);
+    if (threadIdx.x < kWave) {
+        s = (threadIdx.x < NW) ? lds[threadIdx.x] : T(0);
+        s = subwarp<kWave>::reduce_sum(s);
+    }
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------------ grid reduction
+// Two-stage deterministic reduction of NV values per block.  Each block
+// stores its NV partial sums, then takes a ticket; the last block to arrive
+// sums all partials in block order with a fixed tree and gets `true`, with
+// the totals in out[0..NV) (valid in thread 0).  The ticket is reset by the
+// last block, so the counter is ready for the next launch.  Results do not
+// depend on block scheduling.
+__device__ inline double load_coherent(const double *p) {
+    uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT);
+    return __longlong_as_double(static_cast<long long>(bits));
+}
+
+template <int BLOCK, int NV>
+__device__ inline bool grid_reduce(const double (&v)[NV], double *partials, unsigned *ticket,
+                                   double (&out)[NV]) {
+    __shared__ double lds[BLOCK / kWave];
+    __shared__ bool am_last;
+    double bs[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) bs[j] = block_sum<BLOCK>(v[j], lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int j = 0; j < NV; ++j) partials[(size_t)j * gridDim.x + blockIdx.x] = bs[j];
+        __threadfence();
+        unsigned t = atomicAdd(ticket, 1u);
+        am_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!am_last) return false;
+    __threadfence();
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+        double s = 0.0;
+        for (unsigned b = threadIdx.x; b < gridDim.x; b += BLOCK)
+            s += load_coherent(partials + (size_t)j * gridDim.x + b);
+        out[j] = block_sum<BLOCK>(s, lds);
+    }
+    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return true;
+}
+
+}  // namespace gko

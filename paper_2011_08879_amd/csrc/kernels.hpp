@@ -1,0 +1,84 @@
+// Host-side launchers of the HIP kernels.  Plain pointers and sizes only;
+// every launcher enqueues on the given stream and returns the launch status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gko {
+
+enum class vt { f64 = 0, f32 = 1 };  // value type of a kernel instance
+
+inline size_t vsize(vt t) { return t == vt::f64 ? 8 : 4; }
+
+// ------------------------------------------------------------------ SpMV
+// CSR, a subwarp of w lanes per row (w a power of two <= 64).
+int csr_subwarp_width(int64_t n, int64_t nnz);
+hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                    const void *val, const void *x, double alpha, double beta, void *y, int w);
+
+// CSR merge-path: equal (rows + nonzeros) tiles per workgroup.
+int64_t merge_tiles(int64_t n, int64_t nnz);
+hipError_t merge_partition(hipStream_t s, int64_t n, int64_t nnz, const int32_t *rp,
+                           int32_t *part /* 2*(tiles+1) */);
+// carry_row: tiles int32, carry_val: tiles values of type t.
+hipError_t spmv_merge(hipStream_t s, vt t, int64_t n, int64_t nnz, const int32_t *rp,
+                      const int32_t *col, const void *val, const int32_t *part, const void *x,
+                      double alpha, double beta, void *y, int32_t *carry_row, void *carry_val);
+
+// COO: equal nonzero chunks per wavefront.  accumulate: y += alpha A x, rows
+// without entries untouched (used for the HYB tail).
+int64_t coo_chunks(int64_t nnz);
+// head/tail: coo_chunks(nnz) values of type t each.
+hipError_t spmv_coo(hipStream_t s, vt t, int64_t n, int64_t nnz, const int32_t *row,
+                    const int32_t *col, const void *val, const void *x, double alpha, double beta,
+                    void *y, bool accumulate, void *head, void *tail);
+
+// ELL: column-major slots, thread per row.
+hipError_t spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
+                    const void *eval, const void *x, double alpha, double beta, void *y);
+
+// y <- beta * y (beta == 0: y <- 0 without reading y).
+hipError_t scale(hipStream_t s, vt t, int64_t n, double beta, void *y);
+
+// ------------------------------------------------------------------ conversions
+// err: one device int, set nonzero on a violation (bit 1: row_ptr, 2: col range, 4: col order).
+hipError_t validate_csr(hipStream_t s, int64_t n, int64_t m, int64_t nnz, const int32_t *rp,
+                        const int32_t *col, int *err);
+hipError_t narrow_row_ptr(hipStream_t s, int64_t n, const int64_t *rp64, int32_t *rp32, int *err);
+hipError_t csr_rows(hipStream_t s, int64_t n, const int32_t *rp, int32_t *row);
+hipError_t rows_to_ptr(hipStream_t s, int64_t n, int64_t nnz, const int32_t *row, int32_t *rp);
+// maxlen: one device int, must be zero on entry.
+hipError_t max_row_len(hipStream_t s, int64_t n, const int32_t *rp, int *maxlen);
+// hist: maxlen+1 device ints, zero on entry.
+hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist);
+hipError_t csr_to_ell(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                      const void *val, int64_t K, int64_t ld, int32_t *ecol, void *eval);
+// tail_ptr: n+1 offsets of the tail entries of each row (exclusive scan of max(0, len-K)).
+hipError_t tail_lengths(hipStream_t s, int64_t n, const int32_t *rp, int64_t K, int32_t *len);
+hipError_t csr_to_tail(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                       const void *val, int64_t K, const int32_t *tail_ptr, int32_t *trow,
+                       int32_t *tcol, void *tval);
+// lengths of rows stored as ELL (+ optional COO tail given by its row offsets).
+hipError_t hyb_lengths(hipStream_t s, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
+                       const int32_t *tail_ptr, int32_t *len);
+hipError_t hyb_to_csr(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
+                      const void *eval, const int32_t *tail_ptr, const int32_t *tcol,
+                      const void *tval, const int32_t *rp, int32_t *col, void *val);
+// Exclusive scan of n int32 lengths into n+1 offsets; tmp: scan_tmp_elems(n) ints.
+int64_t scan_tmp_elems(int64_t n);
+hipError_t exclusive_scan(hipStream_t s, int64_t n, const int32_t *len, int32_t *out, int32_t *tmp);
+hipError_t cast_values(hipStream_t s, vt from, vt to, int64_t n, const void *src, void *dst);
+
+// ------------------------------------------------------------------ reductions
+constexpr int kRedBlock = 256;
+// Reduction kernels launch at most this many blocks (grid-stride loops
+// beyond), so partial-sum scratch of NV * kMaxReductionBlocks doubles fits
+// every launch.
+constexpr int kMaxReductionBlocks = 2048;
+int reduction_blocks(int64_t n);
+// result: one device double. partials: kMaxReductionBlocks doubles; ticket: zeroed uint.
+hipError_t dot(hipStream_t s, vt t, int64_t n, const void *x, const void *y, double *result,
+               double *partials, unsigned *ticket, bool sqrt_result);
+
+}  // namespace gko

@@ -1,0 +1,56 @@
+// Host-side launchers of the solver step kernels (see blas1.hip, precond.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+#include "solver_state.hpp"
+
+namespace gko {
+
+hipError_t scalars_reset(hipStream_t s, krylov_scalars *sc, int32_t maxit);
+
+// CG / PCG.  bs = 0: no preconditioner (z aliases r); bs in {1,2,4,8,16}:
+// block-Jacobi with explicit inverse blocks `inv` (values of type t).
+hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,
+                   const void *inv, int bs, double tol, krylov_scalars *sc, double *partials,
+                   unsigned *ticket);
+hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                       const void *val, const void *p, void *q, int w, krylov_scalars *sc,
+                       double *partials, unsigned *ticket);
+hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
+                 double *partials, unsigned *ticket);
+hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,
+                     const void *q, const void *inv, int bs, krylov_scalars *sc, double *partials,
+                     unsigned *ticket);
+hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
+                        const krylov_scalars *sc);
+
+// BiCGSTAB (FP64).
+hipError_t bicg_init(hipStream_t st, int64_t n, const void *b, const void *r, void *rh, void *p,
+                     void *v, double tol, krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t bicg_p(hipStream_t st, int64_t n, const void *r, const void *v, void *p,
+                  const krylov_scalars *sc);
+hipError_t bicg_alpha(hipStream_t st, int64_t n, const void *rh, const void *v, krylov_scalars *sc,
+                      double *partials, unsigned *ticket);
+hipError_t bicg_s(hipStream_t st, int64_t n, const void *r, const void *v, void *s,
+                  krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t bicg_omega(hipStream_t st, int64_t n, const void *t, const void *s, krylov_scalars *sc,
+                      double *partials, unsigned *ticket);
+hipError_t bicg_update(hipStream_t st, int64_t n, void *x, void *r, const void *rh, const void *p,
+                       const void *s, const void *t, krylov_scalars *sc, double *partials,
+                       unsigned *ticket);
+
+// Mixed precision helpers.
+hipError_t scaled_cast(hipStream_t s, int64_t n, const double *r, const double *norm, float *rt);
+hipError_t refine_update(hipStream_t s, int64_t n, double *x, const double *norm, const float *d);
+hipError_t fill_zero(hipStream_t s, vt t, int64_t n, void *y);
+
+// Block-Jacobi: explicit FP64 inverses of the bs x bs diagonal blocks
+// (Gauss-Jordan, partial pivoting), one bs*bs row-major slot per block.
+// err: device int, set to 1 on a zero pivot.
+hipError_t bj_invert(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                     const double *val, int bs, double *inv, int *err);
+
+}  // namespace gko

@@ -1,0 +1,246 @@
+// SpMV for matrices stored in CSR: the row-parallel ("classical") kernel with
+// a subwarp per row, and the load-balanced merge-path kernel.
+//
+// Both compute y <- alpha A x + beta y (Sec. 6.1); rows are independent, so
+// the only cross-lane work is the per-row sum.  Memory bound: one streaming
+// pass over col/val (s+4 bytes per entry), row_ptr once, x gathered, y once.
+#include <climits>
+
+#include "device.hpp"
+#include "kernels.hpp"
+
+namespace gko {
+
+// ====================================================================== classical
+// A subwarp of W lanes owns one row: strided loads of col/val (consecutive
+// lanes read consecutive entries, so a wave reads 64/W rows' entries as one
+// contiguous stretch), a gather of x, and a subwarp butterfly sum.  W is a
+// compile-time width chosen at run time from the mean row length, in the
+// spirit of the run-time choice among precompiled subgroup widths in Sec. 5.
+template <typename V, int W, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void spmv_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const V *__restrict__ val,
+                                                         const V *__restrict__ x, V alpha, V beta,
+                                                         V *__restrict__ y) {
+    constexpr int RPB = BLOCK / W;
+    const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / W;
+    if (row >= n) return;  // uniform across the subwarp
+    const int lane = threadIdx.x % W;
+    const int32_t b = rp[row], e = rp[row + 1];
+    V s = V(0);
+    for (int32_t k = b + lane; k < e; k += W) s += val[k] * x[col[k]];
+    s = subwarp<W>::reduce_sum(s);
+    if (lane == 0) y[row] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[row];
+}
+
+int csr_subwarp_width(int64_t n, int64_t nnz) {
+    const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
+    int w = 1;
+    while (w < 64 && w < mean) w <<= 1;
+    return w;
+}
+
+template <typename V, int W>
+static hipError_t launch_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                               const void *val, const void *x, double alpha, double beta, void *y) {
+    constexpr int BLOCK = 256;
+    constexpr int RPB = BLOCK / W;
+    const int64_t grid = (n + RPB - 1) / RPB;
+    spmv_csr_kernel<V, W, BLOCK><<<dim3((unsigned)grid), dim3(BLOCK), 0, s>>>(
+        n, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha, (V)beta,
+        static_cast<V *>(y));
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t launch_csr(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                             const void *val, const void *x, double alpha, double beta, void *y,
+                             int w) {
+    switch (w) {
+        case 1: return launch_csr_w<V, 1>(s, n, rp, col, val, x, alpha, beta, y);
+        case 2: return launch_csr_w<V, 2>(s, n, rp, col, val, x, alpha, beta, y);
+        case 4: return launch_csr_w<V, 4>(s, n, rp, col, val, x, alpha, beta, y);
+        case 8: return launch_csr_w<V, 8>(s, n, rp, col, val, x, alpha, beta, y);
+        case 16: return launch_csr_w<V, 16>(s, n, rp, col, val, x, alpha, beta, y);
+        case 32: return launch_csr_w<V, 32>(s, n, rp, col, val, x, alpha, beta, y);
+        case 64: return launch_csr_w<V, 64>(s, n, rp, col, val, x, alpha, beta, y);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                    const void *val, const void *x, double alpha, double beta, void *y, int w) {
+    if (n == 0) return hipSuccess;
+    return t == vt::f64 ? launch_csr<double>(s, n, rp, col, val, x, alpha, beta, y, w)
+                        : launch_csr<float>(s, n, rp, col, val, x, alpha, beta, y, w);
+}
+
+// ====================================================================== merge-path
+// Merge-based SpMV (Merrill and Garland, SC'16): the sequence of n row ends
+// merged with the nnz entries is cut into equal tiles of TILE items, one per
+// workgroup, so work per workgroup does not depend on row lengths.  Tile
+// starts are found once per matrix by a binary search along each diagonal
+// (merge_partition).  Inside a tile the entries' products are staged in LDS
+// with coalesced loads, each thread walks IPT items of the merge
+// sequentially, and rows that cross thread boundaries are combined by a
+// segmented scan of the threads' carry-outs.  Rows crossing tile boundaries
+// leave a carry per tile, added by a second kernel in ascending tile order,
+// so results are bitwise repeatable.
+constexpr int kMergeBlock = 256;
+constexpr int kMergeIpt = 8;
+constexpr int kMergeTile = kMergeBlock * kMergeIpt;
+
+int64_t merge_tiles(int64_t n, int64_t nnz) { return (n + nnz + kMergeTile - 1) / kMergeTile; }
+
+// Coordinate on the merge path at diagonal d: rows completed i, entries consumed d - i.
+__global__ void merge_partition_kernel(int64_t n, int64_t nnz, const int32_t *__restrict__ rp,
+                                       int32_t *__restrict__ part, int64_t tiles) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w > tiles) return;
+    const int64_t d = (w * kMergeTile < n + nnz) ? w * kMergeTile : n + nnz;
+    int64_t lo = d - nnz > 0 ? d - nnz : 0;
+    int64_t hi = d < n ? d : n;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] <= d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    part[2 * w] = (int32_t)lo;
+    part[2 * w + 1] = (int32_t)(d - lo);
+}
+
+hipError_t merge_partition(hipStream_t s, int64_t n, int64_t nnz, const int32_t *rp, int32_t *part) {
+    const int64_t tiles = merge_tiles(n, nnz);
+    const int64_t grid = (tiles + 1 + 255) / 256;
+    merge_partition_kernel<<<dim3((unsigned)grid), dim3(256), 0, s>>>(n, nnz, rp, part, tiles);
+    return hipGetLastError();
+}
+
+template <typename V>
+__global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const int32_t *__restrict__ part, const V *__restrict__ x, V alpha,
+    V beta, V *__restrict__ y, int32_t *__restrict__ carry_row, V *__restrict__ carry_val) {
+    __shared__ V prods[kMergeTile];
+    __shared__ int32_t rend[kMergeTile + 1];
+    __shared__ int32_t s_row[kMergeBlock];
+    __shared__ V s_val[kMergeBlock];
+
+    const int tid = threadIdx.x;
+    const int64_t w = blockIdx.x;
+    const int32_t i0 = part[2 * w], k0 = part[2 * w + 1];
+    const int32_t i1 = part[2 * w + 2], k1 = part[2 * w + 3];
+    const int nrows = i1 - i0;  // row ends inside this tile
+    const int nk = k1 - k0;     // entries inside this tile
+
+    for (int t = tid; t < nk; t += kMergeBlock) prods[t] = val[k0 + t] * x[col[k0 + t]];
+    for (int t = tid; t <= nrows; t += kMergeBlock)
+        rend[t] = ((int64_t)i0 + t < n) ? rp[i0 + t + 1] - k0 : INT_MAX;
+    __syncthreads();
+
+    // This thread's start on the tile's merge path.
+    const int total = nrows + nk;
+    const int d = tid * kMergeIpt < total ? tid * kMergeIpt : total;
+    int lo = d - nk > 0 ? d - nk : 0;
+    int hi = d < nrows ? d : nrows;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (rend[mid] <= d - mid - 1) lo = mid + 1;
+        else hi = mid;
+    }
+    int i = lo, k = d - lo;
+    const int dend = d + kMergeIpt < total ? d + kMergeIpt : total;
+
+    V acc = V(0);
+    int first_row = -1;
+    V first_val = V(0);
+    // Along the tile's merge path i <= nrows and k < nk whenever an entry is
+    // consumed; the explicit bounds only keep every access in range.
+    for (int step = d; step < dend && i <= nrows; ++step) {
+        if (k < rend[i] && k < nk) {
+            acc += prods[k];
+            ++k;
+        } else {
+            const int64_t r = (int64_t)i0 + i;
+            if (first_row < 0) {
+                first_row = i;  // may continue a row begun by earlier threads
+                first_val = acc;
+            } else if (r < n) {
+                y[r] = (beta == V(0)) ? alpha * acc : alpha * acc + beta * y[r];
+            }
+            acc = V(0);
+            ++i;
+        }
+    }
+
+    // Carry-out of each thread: its partial of the row it stops in.  Inclusive
+    // segmented scan over threads (keys are non-decreasing row indices).
+    s_row[tid] = i;
+    s_val[tid] = acc;
+    __syncthreads();
+    for (int off = 1; off < kMergeBlock; off <<= 1) {
+        V add = V(0);
+        if (tid >= off && s_row[tid - off] == s_row[tid]) add = s_val[tid - off];
+        __syncthreads();
+        s_val[tid] += add;
+        __syncthreads();
+    }
+
+    if (first_row >= 0 && (int64_t)i0 + first_row < n) {
+        // The previous thread stopped in the row this thread emits first.
+        V v = first_val;
+        if (tid > 0) v += s_val[tid - 1];
+        const int64_t r = (int64_t)i0 + first_row;
+        y[r] = (beta == V(0)) ? alpha * v : alpha * v + beta * y[r];
+    }
+    if (tid == kMergeBlock - 1) {
+        const int64_t r = (int64_t)i0 + s_row[tid];
+        carry_row[w] = r < n ? (int32_t)r : -1;
+        carry_val[w] = s_val[tid];
+    }
+}
+
+// Adds tile carries: the first tile of each run of tiles ending inside the
+// same row sums the run in tile order and adds it to y.
+template <typename V>
+__global__ void merge_fixup_kernel(int64_t tiles, const int32_t *__restrict__ carry_row,
+                                   const V *__restrict__ carry_val, V alpha, V *__restrict__ y) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= tiles) return;
+    const int32_t r = carry_row[w];
+    if (r < 0) return;
+    if (w > 0 && carry_row[w - 1] == r) return;
+    V s = carry_val[w];
+    for (int64_t u = w + 1; u < tiles && carry_row[u] == r; ++u) s += carry_val[u];
+    y[r] += alpha * s;
+}
+
+template <typename V>
+static hipError_t launch_merge(hipStream_t s, int64_t n, int64_t nnz, const int32_t *rp,
+                               const int32_t *col, const void *val, const int32_t *part,
+                               const void *x, double alpha, double beta, void *y,
+                               int32_t *carry_row, void *carry_val) {
+    const int64_t tiles = merge_tiles(n, nnz);
+    spmv_merge_kernel<V><<<dim3((unsigned)tiles), dim3(kMergeBlock), 0, s>>>(
+        n, rp, col, static_cast<const V *>(val), part, static_cast<const V *>(x), (V)alpha,
+        (V)beta, static_cast<V *>(y), carry_row, static_cast<V *>(carry_val));
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    merge_fixup_kernel<V><<<dim3((unsigned)((tiles + 255) / 256)), dim3(256), 0, s>>>(
+        tiles, carry_row, static_cast<const V *>(carry_val), (V)alpha, static_cast<V *>(y));
+    return hipGetLastError();
+}
+
+hipError_t spmv_merge(hipStream_t s, vt t, int64_t n, int64_t nnz, const int32_t *rp,
+                      const int32_t *col, const void *val, const int32_t *part, const void *x,
+                      double alpha, double beta, void *y, int32_t *carry_row, void *carry_val) {
+    if (n == 0) return hipSuccess;
+    return t == vt::f64
+               ? launch_merge<double>(s, n, nnz, rp, col, val, part, x, alpha, beta, y, carry_row,
+                                      carry_val)
+               : launch_merge<float>(s, n, nnz, rp, col, val, part, x, alpha, beta, y, carry_row,
+                                     carry_val);
+}
+
+}  // namespace gko

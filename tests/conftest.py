@@ -25,3 +25,13 @@ def gen_mod():
     import gen
     gen.build()
     return gen
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each test on the real stderr before it runs, so a GPU fault that
+    kills the process still leaves the failing case in the log."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write("\n[gpu test] %s\n" % request.node.nodeid)
+        sys.__stderr__.flush()
+    yield

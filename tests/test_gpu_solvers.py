@@ -1,0 +1,190 @@
+"""GPU parity of the Krylov solvers (Sec. 6.2: memory-bound Krylov solvers on
+top of SpMV) against the oracle: CG and PCG with block-Jacobi, BiCGSTAB,
+mixed-precision iterative refinement, dot/norm, and the failure statuses."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2011_08879_amd as g
+    return g
+
+
+@pytest.fixture()
+def ctx(g):
+    c = g.default_context()
+    c.set_solver_opts()      # defaults: FP64, no preconditioner
+    yield c
+    c.set_solver_opts()
+
+
+def kappa_laplace2d(N):
+    return (4 + 4 * math.cos(math.pi / (N + 1))) / (4 - 4 * math.cos(math.pi / (N + 1)))
+
+
+@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "ell", "hybrid"])
+def test_cg_config1_matches_oracle(g, orc, gen_mod, ctx, fmt):
+    N = 64
+    A = gen_mod.laplace2d(N)
+    xs = gen_mod.uniform(2, N * N)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.cg(A, b, tol=1e-10)
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = dev(np.zeros(N * N))
+    info = g.cg(M, dev(b), x, tol=1e-10, maxit=5000)
+    assert info["status"] == g.OK, info
+    xg = host(x)
+    # same recurrence, different rounding: the stop test may trip one step apart
+    assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    true = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+    assert true <= 1e-10
+    kappa = kappa_laplace2d(N)
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * true
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+
+
+def test_cg_check_every_does_not_change_iterates(g, orc, gen_mod, ctx):
+    A = gen_mod.laplace2d(32)
+    b = orc.spmv(A, gen_mod.uniform(2, 1024))
+    M = g.Matrix.from_csr(*A)
+    outs = []
+    for ce in (1, 7, 50):
+        ctx.set_solver_opts(check_every=ce)
+        x = dev(np.zeros(1024))
+        info = g.cg(M, dev(b), x, tol=1e-10)
+        outs.append((info["iterations"], host(x).view(np.int64)))
+    assert outs[0][0] == outs[1][0] == outs[2][0]
+    assert np.array_equal(outs[0][1], outs[1][1]) and np.array_equal(outs[0][1], outs[2][1])
+
+
+def test_pcg_block_jacobi_matches_oracle(g, orc, gen_mod, ctx):
+    N = 24
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    xs = gen_mod.uniform(5, n)
+    b = orc.spmv(A, xs)
+    rc, inv = orc.bj_invert(A, 8)
+    rc, xo, info_o = orc.cg(A, b, tol=1e-10, bj_inv=inv)
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    M = g.Matrix.from_csr(*A)
+    x = dev(np.zeros(n))
+    info = g.cg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK
+    assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    xg = host(x)
+    assert np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b) <= 1e-10
+
+
+def test_pcg_exact_block_preconditioner_one_iteration(g, orc, ctx):
+    rng = np.random.default_rng(9)
+    n, bs = 64, 8
+    rp, col, val = [0], [], []
+    for b0 in range(0, n, bs):
+        G = rng.standard_normal((bs, bs))
+        B = G @ G.T + bs * np.eye(bs)
+        for i in range(bs):
+            col += list(range(b0, b0 + bs))
+            val += list(B[i])
+            rp.append(len(col))
+    A = (np.array(rp, np.int32), np.array(col, np.int32), np.array(val))
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=bs)
+    M = g.Matrix.from_csr(*A)
+    bvec = rng.uniform(-1, 1, n)
+    x = dev(np.zeros(n))
+    info = g.cg(M, dev(bvec), x, tol=1e-12)
+    assert info["status"] == g.OK and info["iterations"] == 1
+
+
+def test_mixed_ir_reaches_fp64_residual(g, orc, gen_mod, ctx):
+    N = 32
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    xs = gen_mod.uniform(5, n)
+    b = orc.spmv(A, xs)
+    rc, inv = orc.bj_invert(A, 8)
+    rc, x64, _ = orc.cg(A, b, tol=1e-10, bj_inv=inv)
+    ctx.set_solver_opts(precision=g.PREC_MIXED_IR, precond=g.PRECOND_BLOCK_JACOBI, block_size=8,
+                        inner_tol=1e-5)
+    M = g.Matrix.from_csr(*A)
+    x = dev(np.zeros(n))
+    info = g.cg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK, info
+    assert 2 <= info["outer_iterations"] <= 6
+    xg = host(x)
+    true = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+    assert true <= 1e-10
+    kappa = (6 + 6 * math.cos(math.pi / (N + 1))) / (6 - 6 * math.cos(math.pi / (N + 1)))
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+    assert np.linalg.norm(xg - x64) / np.linalg.norm(x64) <= 2 * kappa * 1e-10
+    # the oracle's mixed solve takes a comparable number of steps
+    rc, xo, info_o = orc.ir_cg(A, b, tol=1e-10, inner_tol=1e-5, bj_inv=inv)
+    assert abs(info["outer_iterations"] - info_o["outer_iters"]) <= 1
+
+
+def test_bicgstab_convdiff(g, orc, gen_mod, ctx):
+    A = gen_mod.convdiff2d(40, 0.5)
+    xs = gen_mod.uniform(8, 1600)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.bicgstab(A, b, tol=1e-10)
+    for fmt in ["csr", "coo", "hybrid"]:
+        M = g.Matrix.from_csr(*A).convert(fmt)
+        x = dev(np.zeros(1600))
+        info = g.bicgstab(M, dev(b), x, tol=1e-10)
+        assert info["status"] == g.OK, info
+        xg = host(x)
+        assert np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b) <= 1.01e-10
+        # iteration counts are not pinned for BiCGSTAB; they should still be close
+        assert abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 10)
+
+
+def test_solver_statuses(g, gen_mod, ctx):
+    import torch
+    A = gen_mod.laplace1d(20)
+    M = g.Matrix.from_csr(*A)
+    x = dev(np.ones(20))
+    info = g.cg(M, dev(np.zeros(20)), x)
+    assert info["status"] == g.OK and info["iterations"] == 0 and host(x).max() == 0
+    b = np.ones(20)
+    b[3] = np.nan
+    assert g.cg(M, dev(b), dev(np.zeros(20)))["status"] == g.ERR_BREAKDOWN
+    D = g.Matrix.from_csr(np.arange(5, dtype=np.int32), np.arange(4, dtype=np.int32),
+                          np.array([1.0, 2.0, -1.0, 3.0]))
+    assert g.cg(D, dev(np.ones(4)), dev(np.zeros(4)))["status"] == g.ERR_NOT_SPD
+    L = g.Matrix.from_csr(*gen_mod.laplace2d(32))
+    info = g.cg(L, dev(np.ones(1024)), dev(np.zeros(1024)), tol=1e-10, maxit=5)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 5
+    with pytest.raises(g.GkoError):
+        g.cg(L, dev(np.ones(1024)), dev(np.zeros(1024)), tol=-1.0, raise_on_failure=True)
+    # BiCGSTAB breakdown: rhat.v = 0 at the first step
+    B = g.Matrix.from_csr(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.ones(2))
+    assert g.bicgstab(B, dev(np.array([1.0, 0.0])), dev(np.zeros(2)))["status"] == g.ERR_BREAKDOWN
+    # singular diagonal block
+    S = g.Matrix.from_csr(np.array([0, 1, 1, 2], np.int32), np.array([0, 2], np.int32), np.ones(2))
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=4)
+    assert g.cg(S, dev(np.ones(3)), dev(np.zeros(3)))["status"] == g.ERR_BREAKDOWN
+
+
+def test_dot_norm(g, orc, gen_mod):
+    import torch
+    for n in [0, 1, 255, 256, 257, 100000, 3000017]:
+        x = gen_mod.uniform(1, n)
+        y = gen_mod.uniform(2, n)
+        d = float(host(g.dot(dev(x), dev(y))))
+        ref = math.fsum(x * y)
+        assert abs(d - ref) <= 2 * n * 2.0 ** -53 * float(np.abs(x * y).sum()) + 1e-300
+        nr = float(host(g.norm2(dev(x))))
+        assert abs(nr - math.sqrt(math.fsum(x * x))) <= (n + 2) * 2.0 ** -53 * max(nr, 1e-300)
+        d32 = float(host(g.dot(dev(x, torch.float32), dev(y, torch.float32))))
+        x32, y32 = x.astype(np.float32).astype(np.float64), y.astype(np.float32).astype(np.float64)
+        assert abs(d32 - math.fsum(x32 * y32)) <= 2 * n * 2.0 ** -53 * float(np.abs(x32 * y32).sum()) + 1e-300
+    # bitwise repeatable
+    x = dev(gen_mod.uniform(3, 1 << 20))
+    r = [float(host(g.dot(x, x))) for _ in range(3)]
+    assert r[0] == r[1] == r[2]

@@ -1,0 +1,179 @@
+"""GPU parity of the SpMV family and the format conversions against the oracle.
+
+SpMV (Sec. 6.1): every format, FP64 and FP32, on edge cases (empty rows and
+runs of them, nnz = 0, a single dense row, rows much longer than a tile or a
+chunk, rectangular shapes) and on small instances of the workload shapes.
+Conversions are integer bookkeeping and must match the oracle's arrays byte
+for byte."""
+import numpy as np
+import pytest
+
+from gpu_util import assert_spmv_close, dev, host, tiny_cases, workload_cases
+
+pytestmark = pytest.mark.gpu
+
+FORMATS = ["csr", "csr_merge", "coo", "ell", "hybrid"]
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2011_08879_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def cases(gen_mod):
+    c = tiny_cases()
+    c.update(workload_cases(gen_mod))
+    return c
+
+
+def make(g, case, f32=False):
+    n, m, rp, col, val = case
+    import torch
+    return g.Matrix.from_csr(rp, col, val.astype(np.float32) if f32 else val, n_cols=m,
+                             dtype=torch.float32 if f32 else torch.float64)
+
+
+def ell_infeasible(case, vb=8):
+    """The library refuses ELL when padded storage exceeds 4x the CSR storage."""
+    n, m, rp, col, val = case
+    K = int(np.diff(rp).max(initial=0))
+    ld = (n + 63) // 64 * 64
+    return K * ld * (vb + 4) > 4 * (len(col) * (vb + 4) + (n + 1) * 4)
+
+
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_spmv_parity(g, orc, gen_mod, cases, fmt, f32):
+    import torch
+    for name, case in cases.items():
+        n, m, rp, col, val = case
+        A = make(g, case, f32)
+        if fmt == "ell" and ell_infeasible(case, 4 if f32 else 8):
+            with pytest.raises(g.GkoError) as e:
+                A.convert("ell")
+            assert e.value.status == g.ERR_UNSUPPORTED
+            assert A.describe().format == "csr"
+            continue
+        A.convert(fmt)
+        assert A.describe().format == fmt
+        x = gen_mod.uniform(7, m)
+        y0 = gen_mod.uniform(8, n)
+        if f32:
+            vals, x, y0 = (val.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64),
+                           y0.astype(np.float32).astype(np.float64))
+        else:
+            vals = val
+        Ah = (rp, col, vals)
+        tdt = torch.float32 if f32 else torch.float64
+        lens = np.diff(rp)
+        for alpha, beta in [(1.0, 0.0), (1.5, -0.5), (-1.0, 1.0)]:
+            xd = dev(x, tdt)
+            yd = dev(y0, tdt)
+            if beta == 0.0:
+                yd.fill_(float("nan"))   # beta = 0: y must not be read
+            g.spmv(A, alpha, xd, beta, yd)
+            y = host(yd)
+            ref = orc.spmv_dot2(Ah, x, alpha, beta, y0)
+            absy = orc.spmv_absbound(Ah, x, alpha, beta, y0)
+            assert_spmv_close(y, ref, absy, lens, f32, "%s/%s a=%g b=%g" % (name, fmt, alpha, beta))
+        A.close()
+
+
+@pytest.mark.parametrize("fmt", FORMATS)
+def test_spmv_deterministic(g, gen_mod, cases, fmt):
+    import torch
+    case = cases["lognormal_20k"]
+    if fmt == "ell":
+        case = cases["stencil27_14"]
+    n, m = case[0], case[1]
+    A = make(g, case).convert(fmt)
+    x = dev(gen_mod.uniform(3, m))
+    outs = []
+    for _ in range(4):
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        g.spmv(A, 1.0, x, 0.0, y)
+        outs.append(host(y).view(np.int64))
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
+
+
+def test_spmv_rejects_overlap(g, cases):
+    import torch
+    A = make(g, cases["laplace2d_64"])
+    v = torch.zeros(4096 + 10, dtype=torch.float64, device="cuda")
+    with pytest.raises(g.GkoError) as e:
+        g.spmv(A, 1.0, v[:4096], 0.0, v[10:])
+    assert e.value.status == g.ERR_INVALID_ARG
+
+
+def test_create_rejects_malformed(g):
+    import torch
+    rp = np.array([0, 2, 1, 3], np.int32)          # decreasing offsets
+    with pytest.raises(g.GkoError):
+        g.Matrix.from_csr(rp, np.array([0, 1, 2], np.int32), np.ones(3))
+    rp = np.array([0, 2, 3], np.int32)
+    with pytest.raises(g.GkoError):                  # unsorted columns in row 0
+        g.Matrix.from_csr(rp, np.array([1, 0, 1], np.int32), np.ones(3))
+    with pytest.raises(g.GkoError):                  # column out of range
+        g.Matrix.from_csr(rp, np.array([0, 1, 7], np.int32), np.ones(3), n_cols=3)
+    # int64 row offsets are accepted
+    A = g.Matrix.from_csr(np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32), np.ones(2))
+    assert A.describe().nnz == 2
+
+
+def bits(a):
+    return np.ascontiguousarray(a).view(np.int64 if a.dtype == np.float64 else np.int32)
+
+
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_conversions_bit_exact(g, orc, cases, f32):
+    for name, case in cases.items():
+        n, m, rp, col, val = case
+        vals = val.astype(np.float32) if f32 else val
+        A = make(g, case, f32)
+        Ah = (rp, col, vals.astype(np.float64))
+        # COO
+        A.convert("coo")
+        s = A.export_storage()
+        r, c, v = orc.csr_to_coo(Ah)
+        assert np.array_equal(host(s["coo_row"]), r), name
+        assert np.array_equal(host(s["coo_col"]), c), name
+        assert np.array_equal(bits(host(s["coo_val"])), bits(v.astype(vals.dtype))), name
+        # HYB
+        A.convert("hybrid")
+        s = A.export_storage()
+        K, ld, ec, ev, tr, tc, tv = orc.csr_to_hyb(Ah, value_bytes=4 if f32 else 8)
+        assert (s["K"], s["ld"]) == (K, ld), name
+        assert np.array_equal(host(s["ell_col"]), ec), name
+        assert np.array_equal(bits(host(s["ell_val"])), bits(ev.astype(vals.dtype))), name
+        assert np.array_equal(host(s["coo_row"]), tr), name
+        assert np.array_equal(host(s["coo_col"]), tc), name
+        assert np.array_equal(bits(host(s["coo_val"])), bits(tv.astype(vals.dtype))), name
+        # ELL
+        if not ell_infeasible(case, 4 if f32 else 8):
+            A.convert("ell")
+            s = A.export_storage()
+            K, ld, ec, ev = orc.csr_to_ell(Ah)
+            assert (s["K"], s["ld"]) == (K, ld), name
+            assert np.array_equal(host(s["ell_col"]), ec), name
+            assert np.array_equal(bits(host(s["ell_val"])), bits(ev.astype(vals.dtype))), name
+        # merge, and back to CSR from whatever is stored
+        for fmt in ["csr_merge", "coo", "hybrid", "csr"]:
+            A.convert(fmt)
+            erp, ecol, evl = (host(t) for t in A.export_csr())
+            assert np.array_equal(erp, rp) and np.array_equal(ecol, col), (name, fmt)
+            assert np.array_equal(bits(evl), bits(vals)), (name, fmt)
+        d = A.describe()
+        assert d.format == "csr" and d.nnz == len(col) and d.stored_bytes == (n + 1) * 4 + len(col) * (8 if f32 else 12)
+        B = A.clone()
+        assert B.describe() == d
+        A.close()
+        B.close()
+
+
+def test_auto_picks_a_format(g, cases):
+    A = make(g, cases["stencil27_14"])
+    A.convert("auto")
+    assert A.describe().format in ("csr", "csr_merge", "coo", "ell", "hybrid")
