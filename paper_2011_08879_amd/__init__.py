@@ -21,6 +21,11 @@ if not os.path.exists(LIB_PATH):
     raise ImportError("libgko_mi355x.so is not built; run `python -m paper_2011_08879_amd.build` "
                       "(or __graft_entry__.build())")
 
+# torch ships its own HIP runtime (same soname as /opt/rocm's).  Loading torch
+# first makes the library bind to that already-loaded runtime, so streams and
+# device pointers handed over by torch belong to the runtime the library uses.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 # ----------------------------------------------------------------------------- enums
@@ -356,6 +361,7 @@ def norm2(x, ctx: Context | None = None):
 def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):
     st = fn(A.handle, _ptr(b), _ptr(x), tol, maxit)
     info = A.ctx.solve_info()
+    info["status"] = st
     info["status_name"] = status_string(st)
     if st != OK and raise_on_failure:
         raise GkoError(st, last_error())

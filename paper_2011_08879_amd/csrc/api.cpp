@@ -1057,7 +1057,10 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
         c->info.status = st;
         c->info.seconds = now_seconds() - t0;
     });
-    if (call != GKO_OK) return call;
+    if (call != GKO_OK) {
+        if (A) A->ctx->info.status = call;
+        return call;
+    }
     if (st != GKO_OK) g_last_error = std::string("cg: ") + gko_status_string(st);
     return st;
 }
@@ -1116,7 +1119,10 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         c->info.status = st;
         c->info.seconds = now_seconds() - t0;
     });
-    if (call != GKO_OK) return call;
+    if (call != GKO_OK) {
+        if (A) A->ctx->info.status = call;
+        return call;
+    }
     if (st != GKO_OK) g_last_error = std::string("bicgstab: ") + gko_status_string(st);
     return st;
 }

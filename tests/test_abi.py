@@ -20,6 +20,7 @@ def declared():
 
 @pytest.fixture(scope="module")
 def lib():
+    import torch  # noqa: F401  (bind to torch's HIP runtime, as the binding does)
     if not os.path.exists(LIB):
         from paper_2011_08879_amd import build
         build.build()
