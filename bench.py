@@ -119,6 +119,30 @@ def cpu_baseline(inputs, budget_s=12.0):
             "seconds_per_spmv": round(per, 4)}
 
 
+def stream_probe(g, torch, n=1 << 27, reps=10):
+    """Achievable HBM bandwidth: the library's COPY and TRIAD kernels on 1 GiB
+    FP64 arrays (the measured-bandwidth reference the paper takes from
+    BabelStream, Sec. 6).  Mean over reps after one warm-up."""
+    a = torch.rand(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.empty_like(a)
+    out = {"n": n, "bytes_per_array": n * 8}
+    for name, op, nbytes in (("copy", g.STREAM_COPY, 16 * n), ("triad", g.STREAM_TRIAD, 24 * n)):
+        g.stream(op, a, c, b, 0.5)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            g.stream(op, a, c, b, 0.5)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_GB/s"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
+    del a, b, c
+    torch.cuda.empty_cache()
+    return out
+
+
 def run_solvers(g, gen, torch):
     import scipy.sparse as sp
     out = {}
@@ -196,6 +220,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the sweep, copy this many MiB device-to-device (a transfer of "
+                         "known size for scaling hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -286,6 +313,21 @@ def main():
         (value, 100 * value / HBM_PEAK_GBS, ms_per_step))
     for p in per_kernel:
         log("  %-14s %-10s %8.4f ms %8.1f GB/s" % (p["matrix"], p["format"], p["ms"], p["GB/s"]))
+    if args.calib_copy_mib:
+        # one library COPY kernel of known size: reads and writes calib bytes
+        nel = (args.calib_copy_mib << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        g.stream(g.STREAM_COPY, src, dst)
+        torch.cuda.synchronize()
+        result["calib_copy_bytes"] = nel * 8
+        del src, dst
+    result["stream"] = stream_probe(g, torch)
+    log("stream probe: copy %.0f GB/s, triad %.0f GB/s" % (result["stream"]["copy_GB/s"],
+                                                           result["stream"]["triad_GB/s"]))
+    roofline["frac_of_stream_copy"] = round(achieved / result["stream"]["copy_GB/s"], 4)
+    result["config"]["frac_of_stream_copy"] = round(value / result["stream"]["copy_GB/s"], 4)
     for e in mats:
         e["M"].close()
     for M in base.values():

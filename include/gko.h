@@ -156,6 +156,18 @@ gko_status gko_dot(gko_context ctx, gko_dtype dt, int64_t n, const void *x, cons
                    double *result);
 gko_status gko_norm2(gko_context ctx, gko_dtype dt, int64_t n, const void *x, double *result);
 
+/* ---------------------------------------------------------------- bandwidth probe */
+
+/* STREAM-style kernels on FP64 device arrays of n elements, the achievable
+ * bandwidth that the paper measures before its SpMV and solver results
+ * (Sec. 6):  GKO_STREAM_COPY: c[i] = a[i];  GKO_STREAM_TRIAD: c[i] = a[i] + s * b[i]
+ * (multiply and add rounded separately).  b is ignored by COPY.  c must not
+ * overlap a or b.  Asynchronous.  Also serves as a transfer of known size
+ * for scaling hardware byte counters. */
+typedef enum gko_stream_op { GKO_STREAM_COPY = 0, GKO_STREAM_TRIAD = 1 } gko_stream_op;
+gko_status gko_stream(gko_context ctx, gko_stream_op op, int64_t n, const double *a,
+                      const double *b, double s, double *c);
+
 /* ---------------------------------------------------------------- Krylov solvers (Sec. 6.2) */
 
 typedef enum gko_precision { GKO_PREC_FP64 = 0, GKO_PREC_MIXED_IR = 1 } gko_precision;

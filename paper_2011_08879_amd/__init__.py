@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgko_mi355x.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libgko_mi355x.so is not built; run `python -m paper_2011_08879_amd.build` "
+    raise ImportError("libgko_mi355x.so is not built; run `python paper_2011_08879_amd/build.py` "
                       "(or __graft_entry__.build())")
 
 # torch ships its own HIP runtime (same soname as /opt/rocm's).  Loading torch
@@ -81,6 +81,7 @@ _SIGS = {
     "gko_convert": [_vp, _st],
     "gko_dot": [_vp, _st, _i64, _vp, _vp, _vp],
     "gko_norm2": [_vp, _st, _i64, _vp, _vp],
+    "gko_stream": [_vp, _st, _i64, _vp, _vp, _f64, _vp],
     "gko_context_set_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
@@ -356,6 +357,16 @@ def norm2(x, ctx: Context | None = None):
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(_lib.gko_norm2(ctx.handle, _dtype_code(x), x.numel(), _ptr(x), _ptr(out)))
     return out
+
+
+STREAM_COPY, STREAM_TRIAD = 0, 1
+
+
+def stream(op: int, a, c, b=None, s: float = 0.0, ctx: Context | None = None):
+    """Bandwidth probe on float64 device tensors: COPY c = a, TRIAD c = a + s b."""
+    ctx = ctx or default_context()
+    _check(_lib.gko_stream(ctx.handle, op, a.numel(), _ptr(a), _ptr(b), s, _ptr(c)))
+    return c
 
 
 def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):

@@ -1,7 +1,8 @@
 """Build libgko_mi355x.so (the C-ABI library) for gfx950 with hipcc.
 
 Every source under csrc/ is compiled separately (in parallel) and linked into
-one shared library next to this file.  Usage: ``python -m paper_2011_08879_amd.build``.
+one shared library next to this file.  Usage: ``python paper_2011_08879_amd/build.py``
+(run as a file: importing the package loads the library it builds).
 """
 from __future__ import annotations
 

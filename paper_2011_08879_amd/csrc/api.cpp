@@ -345,7 +345,7 @@ int64_t hyb_width_of_csr(gko_matrix A, int64_t maxlen) {
     gko_context c = A->ctx;
     dbuf hist(c, (maxlen + 1) * 4);
     HIPC(hipMemsetAsync(hist.p, 0, (maxlen + 1) * 4, c->stream));
-    HIPC(row_len_hist(c->stream, A->n, A->rp, hist.as<int>()));
+    HIPC(row_len_hist(c->stream, A->n, A->rp, hist.as<int>(), maxlen));
     std::vector<int> h(maxlen + 1);
     HIPC(hipMemcpyAsync(h.data(), hist.p, (maxlen + 1) * 4, hipMemcpyDeviceToHost, c->stream));
     c->sync();
@@ -972,6 +972,17 @@ gko_status gko_norm2(gko_context ctx, gko_dtype dt, int64_t n, const void *x, do
         require(dt == GKO_F64 || dt == GKO_F32, GKO_ERR_INVALID_ARG, "bad dtype");
         HIPC(dot(ctx->stream, dt == GKO_F64 ? vt::f64 : vt::f32, n, x, x, result, ctx->red_partials,
                  ctx->red_ticket, true));
+    });
+}
+
+gko_status gko_stream(gko_context ctx, gko_stream_op op, int64_t n, const double *a,
+                      const double *b, double s, double *c) {
+    return guarded([&] {
+        require(ctx != nullptr, GKO_ERR_INVALID_ARG, "null context");
+        require(op == GKO_STREAM_COPY || op == GKO_STREAM_TRIAD, GKO_ERR_INVALID_ARG, "bad op");
+        require(n >= 0 && (n == 0 || (a && c && (op == GKO_STREAM_COPY || b))), GKO_ERR_INVALID_ARG,
+                "bad arrays");
+        HIPC(stream_op(ctx->stream, (int)op, n, a, b, s, c));
     });
 }
 

@@ -9,6 +9,7 @@
 // always accumulate in FP64, also for FP32 vectors.
 #include <cmath>
 
+#include "csr_rows.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
@@ -139,7 +140,8 @@ __device__ inline void cg_set_alpha(krylov_scalars *sc, double pq) {
     }
 }
 
-// q = A p for CSR with a subwarp of W lanes per row, fused with p.q.
+// q = A p for CSR (a subwarp of W lanes per U rows, as in the plain SpMV),
+// fused with p.q.
 template <typename V, int W>
 __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
@@ -148,18 +150,22 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
                                                          krylov_scalars *sc, double *partials,
                                                          unsigned *ticket) {
     if (sc->done) return;
-    constexpr int RPB = kB / W;
+    constexpr int U = csr_shape<W>::U;
+    constexpr int RPB = kB / W * U;
     const int lane = threadIdx.x % W;
     double acc = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * RPB; base < n; base += (int64_t)gridDim.x * RPB) {
-        const int64_t row = base + threadIdx.x / W;
-        if (row < n) {
-            V s = V(0);
-            for (int32_t k = rp[row] + lane; k < rp[row + 1]; k += W) s += val[k] * p[col[k]];
-            s = subwarp<W>::reduce_sum(s);
-            if (lane == 0) {
-                q[row] = s;
-                acc += (double)p[row] * (double)s;
+    for (int64_t g0 = (int64_t)blockIdx.x * RPB; g0 < n; g0 += (int64_t)gridDim.x * RPB) {
+        const int64_t row0 = g0 + (int64_t)(threadIdx.x / W) * U;
+        if (row0 < n) {  // uniform across the subwarp
+            V s[U];
+            csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, p, s);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t r = row0 + u;
+                if ((W >= U ? lane == u : lane == 0) && r < n) {
+                    q[r] = s[u];
+                    acc += (double)p[r] * (double)s[u];
+                }
             }
         }
     }
@@ -268,7 +274,8 @@ template <typename V, int W>
 static hipError_t launch_cg_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                                   const void *val, const void *p, void *q, krylov_scalars *sc,
                                   double *partials, unsigned *ticket) {
-    int64_t g = (n + (kB / W) - 1) / (kB / W);
+    constexpr int RPB = kB / W * csr_shape<W>::U;
+    int64_t g = (n + RPB - 1) / RPB;
     if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
     if (g < 1) g = 1;
     cg_spmv_csr_kernel<V, W><<<(unsigned)g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),

@@ -113,14 +113,58 @@ hipError_t max_row_len(hipStream_t s, int64_t n, const int32_t *rp, int *maxlen)
     return hipGetLastError();
 }
 
+// Row-length histogram.  Row lengths of structured matrices take few
+// distinct values, so counting straight into global memory serialises on a
+// handful of addresses; each block counts into LDS first (when the bins fit)
+// and adds its nonzero bins once.
+constexpr int kHistLdsBins = 8192;
+
+__global__ void hist_lds_kernel(int64_t n, const int32_t *__restrict__ rp, int *hist, int nbins) {
+    __shared__ int lh[kHistLdsBins];
+    for (int t = threadIdx.x; t < nbins; t += blockDim.x) lh[t] = 0;
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        atomicAdd(&lh[rp[i + 1] - rp[i]], 1);
+    __syncthreads();
+    for (int t = threadIdx.x; t < nbins; t += blockDim.x)
+        if (lh[t]) atomicAdd(hist + t, lh[t]);
+}
+
 __global__ void hist_kernel(int64_t n, const int32_t *__restrict__ rp, int *hist) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) atomicAdd(hist + (rp[i + 1] - rp[i]), 1);
 }
 
-hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist) {
+hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist, int64_t maxlen) {
     if (n == 0) return hipSuccess;
-    hist_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, hist);
+    if (maxlen + 1 <= kHistLdsBins) {
+        const unsigned g = grid_for(n, 256) < 1024 ? grid_for(n, 256) : 1024;
+        hist_lds_kernel<<<g, 256, 0, s>>>(n, rp, hist, (int)(maxlen + 1));
+    } else {
+        hist_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, rp, hist);
+    }
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ STREAM probe
+__global__ void stream_copy_kernel(int64_t n, const double *__restrict__ a, double *__restrict__ c) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = a[i];
+}
+
+__global__ void stream_triad_kernel(int64_t n, const double *__restrict__ a,
+                                    const double *__restrict__ b, double sc, double *__restrict__ c) {
+#pragma clang fp contract(off)
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) c[i] = a[i] + sc * b[i];
+}
+
+hipError_t stream_op(hipStream_t s, int op, int64_t n, const double *a, const double *b, double sc,
+                     double *c) {
+    if (n == 0) return hipSuccess;
+    if (op == 0) stream_copy_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, a, c);
+    else stream_triad_kernel<<<grid_for(n, 256), 256, 0, s>>>(n, a, b, sc, c);
     return hipGetLastError();
 }
 

@@ -1,0 +1,43 @@
+// Row sums of CSR SpMV for a subwarp of W lanes owning U consecutive rows,
+// shared by the plain SpMV and the CG step that fuses p.q into it.
+#pragma once
+
+#include "device.hpp"
+
+namespace gko {
+
+template <int W>
+struct csr_shape {
+    static constexpr int U = W >= 4 ? 4 : 8;  // rows per subwarp
+};
+
+template <typename V, int W, int U>
+__device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
+                                    const int32_t *__restrict__ rp,
+                                    const int32_t *__restrict__ col, const V *__restrict__ val,
+                                    const V *__restrict__ x, V (&s)[U]) {
+    int32_t b[U], e[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool ok = row0 + u < n;
+        b[u] = ok ? rp[row0 + u] : 0;
+        e[u] = ok ? rp[row0 + u + 1] : 0;
+    }
+    int32_t c[U];
+    V v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int32_t k = b[u] + lane;
+        c[u] = k < e[u] ? col[k] : -1;
+        v[u] = k < e[u] ? val[k] : V(0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = c[u] >= 0 ? v[u] * x[c[u]] : V(0);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        for (int32_t k = b[u] + W + lane; k < e[u]; k += W) s[u] += val[k] * x[col[k]];
+#pragma unroll
+    for (int u = 0; u < U; ++u) s[u] = subwarp<W>::reduce_sum(s[u]);
+}
+
+}  // namespace gko

@@ -51,7 +51,10 @@ hipError_t rows_to_ptr(hipStream_t s, int64_t n, int64_t nnz, const int32_t *row
 // maxlen: one device int, must be zero on entry.
 hipError_t max_row_len(hipStream_t s, int64_t n, const int32_t *rp, int *maxlen);
 // hist: maxlen+1 device ints, zero on entry.
-hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist);
+hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist, int64_t maxlen);
+// STREAM probe: op 0 c = a, op 1 c = a + sc * b (two roundings).
+hipError_t stream_op(hipStream_t s, int op, int64_t n, const double *a, const double *b, double sc,
+                     double *c);
 hipError_t csr_to_ell(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
                       const void *val, int64_t K, int64_t ld, int32_t *ecol, void *eval);
 // tail_ptr: n+1 offsets of the tail entries of each row (exclusive scan of max(0, len-K)).

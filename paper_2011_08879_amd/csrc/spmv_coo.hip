@@ -20,6 +20,7 @@ namespace gko {
 constexpr int kCooBlock = 256;
 constexpr int kCooBatches = 16;                  // batches of 64 entries per wave
 constexpr int kCooChunk = kWave * kCooBatches;   // entries per wave
+constexpr int kCooHoist = 4;                     // batches whose loads are issued together
 
 int64_t coo_chunks(int64_t nnz) { return (nnz + kCooChunk - 1) / kCooChunk; }
 
@@ -46,43 +47,64 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
     int32_t carry_row = -1;
     V carry = V(0);
 
-    for (int64_t base = cb; base < ce; base += kWave) {
-        const int64_t k = base + lane;
-        const bool valid = k < ce;
-        const int32_t r = valid ? row[k] : INT_MAX;
-        V p = valid ? val[k] * x[col[k]] : V(0);
-
-        if (!ACC) {
-            // rows without entries between the previous entry and this one
-            int32_t rprev = __shfl_up(r, 1);
-            if (lane == 0) rprev = prev_row;
-            if (valid)
-                for (int32_t e = rprev + 1; e < r; ++e) y[e] = combine(alpha, beta, V(0), y[e], false);
+    for (int64_t base = cb; base < ce; base += kWave * kCooHoist) {
+        // loads of kCooHoist batches first, then their x gathers
+        int32_t rb[kCooHoist], cb_[kCooHoist];
+        V vb[kCooHoist], pb[kCooHoist];
+#pragma unroll
+        for (int j = 0; j < kCooHoist; ++j) {
+            const int64_t k = base + j * kWave + lane;
+            const bool valid = k < ce;
+            rb[j] = valid ? row[k] : INT_MAX;
+            cb_[j] = valid ? col[k] : -1;
+            vb[j] = valid ? val[k] : V(0);
         }
+#pragma unroll
+        for (int j = 0; j < kCooHoist; ++j) pb[j] = cb_[j] >= 0 ? vb[j] * x[cb_[j]] : V(0);
 
 #pragma unroll
-        for (int off = 1; off < kWave; off <<= 1) {
-            const V pu = __shfl_up(p, off);
-            const int32_t ru = __shfl_up(r, off);
-            if (lane >= off && ru == r) p += pu;
-        }
-        if (r == carry_row) p += carry;
+        for (int j = 0; j < kCooHoist; ++j) {
+            const int64_t bbase = base + j * kWave;
+            if (bbase >= ce) break;  // uniform across the wave
+            const int64_t k = bbase + lane;
+            const bool valid = k < ce;
+            const int32_t r = rb[j];
+            V p = pb[j];
 
-        // A lane ends its row's segment when the next entry (in this batch,
-        // or the first of the next batch of this chunk) has another row.
-        const bool more = base + kWave < ce;
-        int32_t rn = __shfl_down(r, 1);
-        if (lane == kWave - 1) rn = more ? row[k + 1] : -2;
-        const bool seg_end = valid && rn != r;
-        if (seg_end) {
-            if (r == first_row && open_start) head[c] = p;
-            else if (r == last_row && open_end) tail[c] = p;
-            else y[r] = combine(alpha, beta, p, ACC || beta != V(0) ? y[r] : V(0), ACC);
+            if (!ACC) {
+                // rows without entries between the previous entry and this one
+                int32_t rprev = __shfl_up(r, 1);
+                if (lane == 0) rprev = prev_row;
+                if (valid)
+                    for (int32_t e = rprev + 1; e < r; ++e) y[e] = combine(alpha, beta, V(0), y[e], false);
+            }
+
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                const V pu = __shfl_up(p, off);
+                const int32_t ru = __shfl_up(r, off);
+                if (lane >= off && ru == r) p += pu;
+            }
+            if (r == carry_row) p += carry;
+
+            // A lane ends its row's segment when the next entry (in this batch,
+            // or the first of the next batch of this chunk) has another row.
+            const bool more = bbase + kWave < ce;
+            const int32_t next_first = (j + 1 < kCooHoist) ? __shfl(rb[(j + 1) % kCooHoist], 0)
+                                                           : ((lane == kWave - 1 && more) ? row[k + 1] : -2);
+            int32_t rn = __shfl_down(r, 1);
+            if (lane == kWave - 1) rn = more ? next_first : -2;
+            const bool seg_end = valid && rn != r;
+            if (seg_end) {
+                if (r == first_row && open_start) head[c] = p;
+                else if (r == last_row && open_end) tail[c] = p;
+                else y[r] = combine(alpha, beta, p, ACC || beta != V(0) ? y[r] : V(0), ACC);
+            }
+            // a row still open at the batch end carries into the next batch
+            carry_row = __shfl(seg_end ? -1 : r, kWave - 1);
+            carry = __shfl(p, kWave - 1);
+            prev_row = __shfl(r, kWave - 1);
         }
-        // a row still open at the batch end carries into the next batch
-        carry_row = __shfl(seg_end ? -1 : r, kWave - 1);
-        carry = __shfl(p, kWave - 1);
-        prev_row = __shfl(r, kWave - 1);
     }
     if (!ACC && ce == nnz)  // rows after the last entry
         for (int64_t e = (int64_t)last_row + 1 + lane; e < n; e += kWave)

@@ -6,32 +6,42 @@
 // pass over col/val (s+4 bytes per entry), row_ptr once, x gathered, y once.
 #include <climits>
 
+#include "csr_rows.hpp"
 #include "device.hpp"
 #include "kernels.hpp"
 
 namespace gko {
 
 // ====================================================================== classical
-// A subwarp of W lanes owns one row: strided loads of col/val (consecutive
-// lanes read consecutive entries, so a wave reads 64/W rows' entries as one
-// contiguous stretch), a gather of x, and a subwarp butterfly sum.  W is a
-// compile-time width chosen at run time from the mean row length, in the
-// spirit of the run-time choice among precompiled subgroup widths in Sec. 5.
+// A subwarp of W lanes owns U consecutive rows: consecutive lanes read
+// consecutive entries, so a wave reads the entries of 64/W * U rows as
+// contiguous stretches.  The loads of all U rows (offsets, then columns and
+// values, then the x gathers) are issued before any is consumed, so each
+// wave keeps U times more bytes in flight than a row-at-a-time loop; rows
+// longer than W continue in a strided loop.  Each row is then summed by a
+// subwarp butterfly.  W is a compile-time width chosen at run time from the
+// mean row length, in the spirit of the run-time choice among precompiled
+// subgroup widths in Sec. 5.
 template <typename V, int W, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void spmv_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const V *__restrict__ x, V alpha, V beta,
                                                          V *__restrict__ y) {
-    constexpr int RPB = BLOCK / W;
-    const int64_t row = (int64_t)blockIdx.x * RPB + threadIdx.x / W;
-    if (row >= n) return;  // uniform across the subwarp
+    constexpr int U = csr_shape<W>::U;
+    constexpr int SPB = BLOCK / W;
     const int lane = threadIdx.x % W;
-    const int32_t b = rp[row], e = rp[row + 1];
-    V s = V(0);
-    for (int32_t k = b + lane; k < e; k += W) s += val[k] * x[col[k]];
-    s = subwarp<W>::reduce_sum(s);
-    if (lane == 0) y[row] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[row];
+    const int64_t row0 = ((int64_t)blockIdx.x * SPB + threadIdx.x / W) * U;
+    if (row0 >= n) return;  // uniform across the subwarp
+    V s[U];
+    csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, x, s);
+    // lane u stores row u (when the subwarp has fewer lanes than rows, lane 0 stores all)
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t r = row0 + u;
+        if ((W >= U ? lane == u : lane == 0) && r < n)
+            y[r] = (beta == V(0)) ? alpha * s[u] : alpha * s[u] + beta * y[r];
+    }
 }
 
 int csr_subwarp_width(int64_t n, int64_t nnz) {
@@ -45,7 +55,7 @@ template <typename V, int W>
 static hipError_t launch_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                                const void *val, const void *x, double alpha, double beta, void *y) {
     constexpr int BLOCK = 256;
-    constexpr int RPB = BLOCK / W;
+    constexpr int RPB = BLOCK / W * csr_shape<W>::U;
     const int64_t grid = (n + RPB - 1) / RPB;
     spmv_csr_kernel<V, W, BLOCK><<<dim3((unsigned)grid), dim3(BLOCK), 0, s>>>(
         n, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha, (V)beta,
@@ -134,7 +144,23 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
     const int nrows = i1 - i0;  // row ends inside this tile
     const int nk = k1 - k0;     // entries inside this tile
 
-    for (int t = tid; t < nk; t += kMergeBlock) prods[t] = val[k0 + t] * x[col[k0 + t]];
+    {
+        // all of this thread's column and value loads first, then the gathers
+        int32_t c[kMergeIpt];
+        V v[kMergeIpt];
+#pragma unroll
+        for (int j = 0; j < kMergeIpt; ++j) {
+            const int t = tid + j * kMergeBlock;
+            const bool ok = t < nk;
+            c[j] = ok ? col[k0 + t] : 0;
+            v[j] = ok ? val[k0 + t] : V(0);
+        }
+#pragma unroll
+        for (int j = 0; j < kMergeIpt; ++j) {
+            const int t = tid + j * kMergeBlock;
+            if (t < nk) prods[t] = v[j] * x[c[j]];
+        }
+    }
     for (int t = tid; t <= nrows; t += kMergeBlock)
         rend[t] = ((int64_t)i0 + t < n) ? rp[i0 + t + 1] - k0 : INT_MAX;
     __syncthreads();

@@ -22,8 +22,8 @@ def declared():
 def lib():
     import torch  # noqa: F401  (bind to torch's HIP runtime, as the binding does)
     if not os.path.exists(LIB):
-        from paper_2011_08879_amd import build
-        build.build()
+        import __graft_entry__
+        __graft_entry__._lib_builder().build()
     return ctypes.CDLL(LIB)
 
 

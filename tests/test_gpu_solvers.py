@@ -188,3 +188,15 @@ def test_dot_norm(g, orc, gen_mod):
     x = dev(gen_mod.uniform(3, 1 << 20))
     r = [float(host(g.dot(x, x))) for _ in range(3)]
     assert r[0] == r[1] == r[2]
+
+
+def test_stream_probe_exact(g, gen_mod):
+    import torch
+    n = 1_000_003
+    a, b = gen_mod.uniform(1, n), gen_mod.uniform(2, n)
+    c = dev(np.full(n, np.nan))
+    g.stream(g.STREAM_COPY, dev(a), c)
+    assert np.array_equal(host(c), a)
+    g.stream(g.STREAM_TRIAD, dev(a), c, dev(b), 0.37)
+    # two roundings (no fused multiply-add), exactly as numpy computes it
+    assert np.array_equal(host(c).view(np.int64), (a + 0.37 * b).view(np.int64))
