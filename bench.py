@@ -37,6 +37,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+METRIC = "SpMV GB/s (% HBM peak); CG s to 1e-10, FP64 vs mixed; batch solves/s"
 
 
 def spmv_bytes(desc, s=8):
@@ -213,31 +214,7 @@ def run_solvers(g, gen, torch):
     return out
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="after the sweep, copy this many MiB device-to-device (a transfer of "
-                         "known size for scaling hardware byte counters)")
-    args = ap.parse_args()
-    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
-
-    import torch
-
-    import gen
-    import paper_2011_08879_amd as g
-
-    if not os.path.exists(gen._LIB):
-        gen.build()
-    torch.cuda.set_device(0)
-    g.default_context()
+def run_sweep(args, g, gen, torch, result):
     mats, skipped, inputs, base = build_sweep(g, gen, torch)
     log("sweep matrices on device: %d SpMV kernels per step" % len(mats))
 
@@ -286,8 +263,8 @@ def main():
                 "kernel": "spmv %s on %s" % (d["format"], d["matrix"]),
                 "alg_bytes_per_launch": d["alg_bytes"]}
 
-    result = {
-        "metric": "SpMV GB/s (% HBM peak); CG s to 1e-10, FP64 vs mixed; batch solves/s",
+    result.update({
+        "metric": METRIC,
         "value": round(value, 1),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -308,7 +285,7 @@ def main():
                    "skipped": skipped},
         "roofline": roofline,
         "per_kernel": per_kernel,
-    }
+    })
     log("sweep: %.1f GB/s aggregate (%.1f%% of 8 TB/s), %.3f ms/step" %
         (value, 100 * value / HBM_PEAK_GBS, ms_per_step))
     for p in per_kernel:
@@ -335,9 +312,46 @@ def main():
     del mats
     torch.cuda.empty_cache()
 
+    return result, inputs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the SpMV sweep (profiling the solvers alone)")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the sweep, copy this many MiB device-to-device (a transfer of "
+                         "known size for scaling hardware byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import gen
+    import paper_2011_08879_amd as g
+
+    if not os.path.exists(gen._LIB):
+        gen.build()
+    torch.cuda.set_device(0)
+    g.default_context()
+    result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+              "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "f64", "data": "synthetic"}
+    inputs = None
+    if not args.no_sweep:
+        result, inputs = run_sweep(args, g, gen, torch, result)
+
     if not args.no_solvers:
         result["solvers"] = run_solvers(g, gen, torch)
-    if not args.no_cpu:
+    if not args.no_cpu and inputs is not None:
         log("cpu baseline (oracle, 1 core) ...")
         result["cpu_baseline"] = cpu_baseline(inputs)
         log("cpu baseline: %.2f GB/s" % result["cpu_baseline"]["value"])

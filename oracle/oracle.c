@@ -447,9 +447,12 @@ done:
  * FP32 block-Jacobi inverse (rounded from the FP64 one); SpMV rows summed in
  * FP32; dot products accumulate FP64 products of the FP32 data in FP64;
  * scalars alpha, beta are FP64 and each vector update is done in FP64 and
- * rounded once to FP32.  Inner stop: ||r_inner|| <= inner_tol ||rt||, or
- * max_inner iterations.  Outer stop: converged, max_outer, or a residual
- * that did not halve (stagnation, -> not converged).
+ * rounded once to FP32.  Inner stop: ||r_inner|| <= tau_k ||rt||, or
+ * max_inner iterations, where step k asks only for the reduction still
+ * missing (with a factor 2 of margin), but never less than inner_tol:
+ *   tau_k = max(inner_tol, 0.5 tol ||b|| / ||r_k||).
+ * Outer stop: converged, max_outer, or a residual that did not halve
+ * (stagnation, -> not converged).
  * out[0] = total inner iterations, out[1] = outer iterations,
  * out[2] = final true relres.
  * ====================================================================== */
@@ -550,8 +553,10 @@ int orc_ir_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         if (outer >= max_outer || !(rnorm <= 0.5 * prev)) { rc = ORC_NOT_CONVERGED; break; }
         prev = rnorm;
         for (int64_t i = 0; i < n; ++i) rt[i] = (float)(r[i] / rnorm);
+        double tau = 0.5 * (tol * bnorm / rnorm);
+        if (tau < inner_tol) tau = inner_tol;
         int st;
-        inner_total += pcg_f32(n, rp, ci, v32, rt, d, inner_tol, max_inner, inv32, bs,
+        inner_total += pcg_f32(n, rp, ci, v32, rt, d, tau, max_inner, inv32, bs,
                                w1, w2, w3, w4, &st);
         if (st == ORC_NOT_SPD || st == ORC_BREAKDOWN) { rc = st; break; }
         for (int64_t i = 0; i < n; ++i) x[i] = x[i] + rnorm * (double)d[i];

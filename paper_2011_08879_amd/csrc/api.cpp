@@ -160,6 +160,8 @@ struct gko_matrix_s {
     int32_t *trow = nullptr, *tcol = nullptr;
     void *tval = nullptr;
     int subwarp = 1;
+    int64_t n_long = 0;             // CSR rows handled by a workgroup each
+    int32_t *long_rows = nullptr;
     void *carry_a = nullptr, *carry_b = nullptr;  // merge / COO carries
     int64_t carry_elems = 0;
     // FP32 copies of the value arrays, made on demand for mixed precision
@@ -191,8 +193,8 @@ struct gko_matrix_s {
     }
     void drop_storage() {
         drop(rp); drop(row); drop(col); drop(val); drop(part); drop(ecol); drop(eval);
-        drop(trow); drop(tcol); drop(tval); drop(carry_a); drop(carry_b);
-        tiles = K = ld = tnnz = carry_elems = 0;
+        drop(trow); drop(tcol); drop(tval); drop(carry_a); drop(carry_b); drop(long_rows);
+        tiles = K = ld = tnnz = carry_elems = n_long = 0;
         drop_caches();
     }
     int64_t stored_bytes() const {
@@ -241,7 +243,8 @@ void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, d
     hipStream_t s = A->ctx->stream;
     switch (A->fmt) {
         case GKO_FMT_CSR:
-            HIPC(spmv_csr(s, v.t, A->n, A->rp, A->col, v.val, x, alpha, beta, y, A->subwarp));
+            HIPC(spmv_csr(s, v.t, A->n, A->rp, A->col, v.val, x, alpha, beta, y, A->subwarp,
+                          A->n_long, A->long_rows));
             break;
         case GKO_FMT_CSR_MERGE:
             HIPC(spmv_merge(s, v.t, A->n, A->nnz, A->rp, A->col, v.val, A->part, x, alpha, beta, y,
@@ -305,12 +308,35 @@ void export_csr_into(gko_matrix A, const values &v, int32_t *rp, int32_t *col, v
     }
 }
 
+int64_t read_int(gko_context c, const int *d);
+
+// Rows too long for a subwarp get a workgroup each (see spmv_csr).
+void refresh_long_rows(gko_matrix A) {
+    A->drop(A->long_rows);
+    A->n_long = 0;
+    if (A->n == 0) return;
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    dbuf flag(c, A->n * 4), pos(c, (A->n + 1) * 4), tmp(c, scan_tmp_elems(A->n) * 4);
+    HIPC(csr_long_flags(s, A->n, A->rp, csr_long_threshold(A->subwarp), flag.as<int32_t>()));
+    HIPC(exclusive_scan(s, A->n, flag.as<int32_t>(), pos.as<int32_t>(), tmp.as<int32_t>()));
+    const int64_t nl = read_int(c, pos.as<int>() + A->n);
+    if (nl > 0) {
+        dbuf rows(c, nl * 4);
+        HIPC(csr_long_scatter(s, A->n, flag.as<int32_t>(), pos.as<int32_t>(), rows.as<int32_t>()));
+        c->sync();
+        A->long_rows = static_cast<int32_t *>(rows.release());
+        A->n_long = nl;
+    }
+}
+
 void to_csr(gko_matrix A) {
     if (A->fmt == GKO_FMT_CSR) return;
     if (A->fmt == GKO_FMT_CSR_MERGE) {
         A->drop(A->part);
         A->tiles = 0;
         A->fmt = GKO_FMT_CSR;
+        refresh_long_rows(A);
         return;
     }
     gko_context c = A->ctx;
@@ -323,6 +349,7 @@ void to_csr(gko_matrix A) {
     A->val = val.release();
     A->fmt = GKO_FMT_CSR;
     A->subwarp = csr_subwarp_width(A->n, A->nnz);
+    refresh_long_rows(A);
 }
 
 int64_t read_int(gko_context c, const int *d) {
@@ -376,6 +403,8 @@ void csr_to_format(gko_matrix A, gko_format fmt) {
         case GKO_FMT_CSR:
             return;
         case GKO_FMT_CSR_MERGE: {
+            A->drop(A->long_rows);
+            A->n_long = 0;
             const int64_t tiles = merge_tiles(A->n, A->nnz);
             dbuf part(c, 2 * (tiles + 1) * 4);
             HIPC(merge_partition(s, A->n, A->nnz, A->rp, part.as<int32_t>()));
@@ -392,6 +421,8 @@ void csr_to_format(gko_matrix A, gko_format fmt) {
             ensure_carries(A, coo_chunks(A->nnz));
             c->sync();
             A->drop(A->rp);
+            A->drop(A->long_rows);
+            A->n_long = 0;
             A->row = static_cast<int32_t *>(row.release());
             A->fmt = GKO_FMT_COO;
             return;
@@ -575,7 +606,7 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
     auto *S = sc.as<krylov_scalars>();
     HIPC(scalars_reset(s, S, maxit));
     void *zz = bs > 0 ? z.p : r.p;
-    const bool fused = A->fmt == GKO_FMT_CSR;
+    const bool fused = A->fmt == GKO_FMT_CSR && A->n_long == 0;
     solve_result res;
     krylov_scalars h{};
     for (;;) {
@@ -651,7 +682,10 @@ mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gk
         prev = rn;
         HIPC(scaled_cast(s, n, r.as<double>(), nrm.as<double>(), rt.as<float>()));
         HIPC(fill_zero(s, vt::f32, n, d.p));
-        solve_result in = cg_core(A, v32, rt.p, d.p, o.inner_tol, o.max_inner,
+        // ask the inner solve only for the reduction still missing (factor 2
+        // of margin), never for less than inner_tol
+        const double tau = std::max(o.inner_tol, 0.5 * (tol * bnorm / rn));
+        solve_result in = cg_core(A, v32, rt.p, d.p, tau, o.max_inner,
                                   bs > 0 ? (const void *)A->bj32 : nullptr, bs, o.check_every, false);
         res.inner += in.iters;
         if (in.flag == kNotSpd || in.flag == kBreakdown) {
@@ -799,6 +833,13 @@ gko_status gko_matrix_create_csr(gko_context ctx, int64_t n_rows, int64_t n_cols
         A->col = static_cast<int32_t *>(col.release());
         A->val = val.release();
         A->subwarp = csr_subwarp_width(n_rows, nnz);
+        try {
+            refresh_long_rows(A);
+        } catch (...) {
+            A->drop_storage();
+            delete A;
+            throw;
+        }
         *out = A;
     });
 }
@@ -838,6 +879,8 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
             B->trow = (int32_t *)copy(A->trow, A->tnnz * 4);
             B->tcol = (int32_t *)copy(A->tcol, A->tnnz * 4);
             B->tval = copy(A->tval, A->tnnz * vb);
+            B->n_long = A->n_long;
+            B->long_rows = (int32_t *)copy(A->long_rows, A->n_long * 4);
             if (A->carry_a) ensure_carries(B, A->carry_elems);
             c->sync();
         } catch (...) {

@@ -7,6 +7,7 @@
 // each deterministic grid reduction updates them in device memory, and every
 // kernel returns immediately once the solver is flagged done.  Reductions
 // always accumulate in FP64, also for FP32 vectors.
+#include <climits>
 #include <cmath>
 
 #include "csr_rows.hpp"
@@ -158,7 +159,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
         const int64_t row0 = g0 + (int64_t)(threadIdx.x / W) * U;
         if (row0 < n) {  // uniform across the subwarp
             V s[U];
-            csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, p, s);
+            csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, p, s, INT_MAX);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t r = row0 + u;

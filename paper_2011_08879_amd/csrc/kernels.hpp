@@ -12,10 +12,18 @@ enum class vt { f64 = 0, f32 = 1 };  // value type of a kernel instance
 inline size_t vsize(vt t) { return t == vt::f64 ? 8 : 4; }
 
 // ------------------------------------------------------------------ SpMV
-// CSR, a subwarp of w lanes per row (w a power of two <= 64).
+// CSR, a subwarp of w lanes per row (w a power of two <= 64).  Rows longer
+// than csr_long_threshold(w) are listed in long_rows (n_long of them) and
+// summed by a workgroup each.
 int csr_subwarp_width(int64_t n, int64_t nnz);
+int32_t csr_long_threshold(int w);
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
-                    const void *val, const void *x, double alpha, double beta, void *y, int w);
+                    const void *val, const void *x, double alpha, double beta, void *y, int w,
+                    int64_t n_long, const int32_t *long_rows);
+// flag[i] = len_i > long_t; rows[pos[i]] = i for flagged rows (pos: exclusive scan of flag).
+hipError_t csr_long_flags(hipStream_t s, int64_t n, const int32_t *rp, int32_t long_t, int32_t *flag);
+hipError_t csr_long_scatter(hipStream_t s, int64_t n, const int32_t *flag, const int32_t *pos,
+                            int32_t *rows);
 
 // CSR merge-path: equal (rows + nonzeros) tiles per workgroup.
 int64_t merge_tiles(int64_t n, int64_t nnz);

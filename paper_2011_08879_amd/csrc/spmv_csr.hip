@@ -27,21 +27,78 @@ __global__ __launch_bounds__(BLOCK) void spmv_csr_kernel(int64_t n, const int32_
                                                          const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const V *__restrict__ x, V alpha, V beta,
-                                                         V *__restrict__ y) {
+                                                         V *__restrict__ y, int32_t long_t) {
     constexpr int U = csr_shape<W>::U;
     constexpr int SPB = BLOCK / W;
     const int lane = threadIdx.x % W;
     const int64_t row0 = ((int64_t)blockIdx.x * SPB + threadIdx.x / W) * U;
     if (row0 >= n) return;  // uniform across the subwarp
     V s[U];
-    csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, x, s);
+    csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, x, s, long_t);
     // lane u stores row u (when the subwarp has fewer lanes than rows, lane 0 stores all)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t r = row0 + u;
-        if ((W >= U ? lane == u : lane == 0) && r < n)
+        if ((W >= U ? lane == u : lane == 0) && r < n && rp[r + 1] - rp[r] <= long_t)
             y[r] = (beta == V(0)) ? alpha * s[u] : alpha * s[u] + beta * y[r];
     }
+}
+
+// Rows longer than the subwarp threshold: one workgroup per row, four loads
+// per thread in flight, a fixed-tree block sum.
+constexpr int kLongBlock = 256;
+
+template <typename V>
+__global__ __launch_bounds__(kLongBlock) void spmv_csr_long_kernel(
+    const int32_t *__restrict__ long_rows, const int32_t *__restrict__ rp,
+    const int32_t *__restrict__ col, const V *__restrict__ val, const V *__restrict__ x, V alpha,
+    V beta, V *__restrict__ y) {
+    __shared__ V lds[kLongBlock / kWave];
+    const int32_t r = long_rows[blockIdx.x];
+    const int32_t b = rp[r], e = rp[r + 1];
+    V s = V(0);
+    for (int32_t k = b + threadIdx.x; k < e; k += 4 * kLongBlock) {
+        int32_t cc[4];
+        V vv[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int32_t kj = k + j * kLongBlock;
+            cc[j] = kj < e ? col[kj] : -1;
+            vv[j] = kj < e ? val[kj] : V(0);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (cc[j] >= 0) s += vv[j] * x[cc[j]];
+    }
+    s = block_sum<kLongBlock>(s, lds);
+    if (threadIdx.x == 0) y[r] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[r];
+}
+
+int32_t csr_long_threshold(int w) { return 32 * w > 512 ? 32 * w : 512; }
+
+__global__ void long_flag_kernel(int64_t n, const int32_t *__restrict__ rp, int32_t long_t,
+                                 int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) flag[i] = rp[i + 1] - rp[i] > long_t;
+}
+
+__global__ void long_scatter_kernel(int64_t n, const int32_t *__restrict__ flag,
+                                    const int32_t *__restrict__ pos, int32_t *__restrict__ rows) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n && flag[i]) rows[pos[i]] = (int32_t)i;
+}
+
+hipError_t csr_long_flags(hipStream_t s, int64_t n, const int32_t *rp, int32_t long_t, int32_t *flag) {
+    if (n == 0) return hipSuccess;
+    long_flag_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, rp, long_t, flag);
+    return hipGetLastError();
+}
+
+hipError_t csr_long_scatter(hipStream_t s, int64_t n, const int32_t *flag, const int32_t *pos,
+                            int32_t *rows) {
+    if (n == 0) return hipSuccess;
+    long_scatter_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(n, flag, pos, rows);
+    return hipGetLastError();
 }
 
 int csr_subwarp_width(int64_t n, int64_t nnz) {
@@ -53,37 +110,53 @@ int csr_subwarp_width(int64_t n, int64_t nnz) {
 
 template <typename V, int W>
 static hipError_t launch_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
-                               const void *val, const void *x, double alpha, double beta, void *y) {
+                               const void *val, const void *x, double alpha, double beta, void *y,
+                               int32_t long_t) {
     constexpr int BLOCK = 256;
     constexpr int RPB = BLOCK / W * csr_shape<W>::U;
     const int64_t grid = (n + RPB - 1) / RPB;
     spmv_csr_kernel<V, W, BLOCK><<<dim3((unsigned)grid), dim3(BLOCK), 0, s>>>(
         n, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha, (V)beta,
-        static_cast<V *>(y));
+        static_cast<V *>(y), long_t);
     return hipGetLastError();
 }
 
 template <typename V>
 static hipError_t launch_csr(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                              const void *val, const void *x, double alpha, double beta, void *y,
-                             int w) {
+                             int w, int32_t long_t) {
     switch (w) {
-        case 1: return launch_csr_w<V, 1>(s, n, rp, col, val, x, alpha, beta, y);
-        case 2: return launch_csr_w<V, 2>(s, n, rp, col, val, x, alpha, beta, y);
-        case 4: return launch_csr_w<V, 4>(s, n, rp, col, val, x, alpha, beta, y);
-        case 8: return launch_csr_w<V, 8>(s, n, rp, col, val, x, alpha, beta, y);
-        case 16: return launch_csr_w<V, 16>(s, n, rp, col, val, x, alpha, beta, y);
-        case 32: return launch_csr_w<V, 32>(s, n, rp, col, val, x, alpha, beta, y);
-        case 64: return launch_csr_w<V, 64>(s, n, rp, col, val, x, alpha, beta, y);
+        case 1: return launch_csr_w<V, 1>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 2: return launch_csr_w<V, 2>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 4: return launch_csr_w<V, 4>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 8: return launch_csr_w<V, 8>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 16: return launch_csr_w<V, 16>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 32: return launch_csr_w<V, 32>(s, n, rp, col, val, x, alpha, beta, y, long_t);
+        case 64: return launch_csr_w<V, 64>(s, n, rp, col, val, x, alpha, beta, y, long_t);
         default: return hipErrorInvalidValue;
     }
 }
 
+template <typename V>
+static hipError_t launch_csr_long(hipStream_t s, int64_t n_long, const int32_t *long_rows,
+                                  const int32_t *rp, const int32_t *col, const void *val,
+                                  const void *x, double alpha, double beta, void *y) {
+    spmv_csr_long_kernel<V><<<dim3((unsigned)n_long), dim3(kLongBlock), 0, s>>>(
+        long_rows, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha,
+        (V)beta, static_cast<V *>(y));
+    return hipGetLastError();
+}
+
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
-                    const void *val, const void *x, double alpha, double beta, void *y, int w) {
+                    const void *val, const void *x, double alpha, double beta, void *y, int w,
+                    int64_t n_long, const int32_t *long_rows) {
     if (n == 0) return hipSuccess;
-    return t == vt::f64 ? launch_csr<double>(s, n, rp, col, val, x, alpha, beta, y, w)
-                        : launch_csr<float>(s, n, rp, col, val, x, alpha, beta, y, w);
+    const int32_t long_t = n_long > 0 ? csr_long_threshold(w) : INT_MAX;
+    hipError_t e = t == vt::f64 ? launch_csr<double>(s, n, rp, col, val, x, alpha, beta, y, w, long_t)
+                                : launch_csr<float>(s, n, rp, col, val, x, alpha, beta, y, w, long_t);
+    if (e != hipSuccess || n_long == 0) return e;
+    return t == vt::f64 ? launch_csr_long<double>(s, n_long, long_rows, rp, col, val, x, alpha, beta, y)
+                        : launch_csr_long<float>(s, n_long, long_rows, rp, col, val, x, alpha, beta, y);
 }
 
 // ====================================================================== merge-path
