@@ -213,6 +213,55 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
  * or t.t below 1e-300, or omega = 0) returns GKO_ERR_BREAKDOWN. */
 gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
+/* ---------------------------------------------------------------- batched CG */
+
+typedef struct gko_batch_s *gko_batch;
+
+/* Create a batch of nsys independent square systems from caller device
+ * arrays, which are copied (the call synchronises the stream):
+ *   row_off[nsys+1] (int64): system i has rows row_off[i] .. row_off[i+1]-1
+ *                            of the concatenated vectors; 1 <= m_i <= 2048.
+ *   nnz_off[nsys+1] (int64): its entries are nnz_off[i] .. nnz_off[i+1]-1.
+ *   row_ptr_local          : m_i + 1 local offsets per system (starting at 0),
+ *                            stored back to back from index row_off[i] + i.
+ *   col_idx (int32)        : local column indices in [0, m_i).
+ *   values                 : FP64 or FP32 (dt).
+ * Systems are queued largest first (by nonzeros) for the solve.  A malformed
+ * system returns GKO_ERR_INVALID_ARG. */
+gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *row_off,
+                                const int64_t *nnz_off, const int32_t *row_ptr_local,
+                                const int32_t *col_idx, const void *values, gko_dtype dt,
+                                gko_batch *out);
+gko_status gko_batch_destroy(gko_batch B);
+
+/* Solve every system by CG from x = 0 in ONE persistent kernel launch: each
+ * workgroup takes systems from an atomic queue and iterates one system at a
+ * time with its vectors in LDS, so no host round trip happens until all are
+ * done.  FP64 batches run FP64 CG; FP32 batches run FP32 CG iterations inside
+ * FP64 iterative refinement (residual, norms and update in FP64).
+ *   b, x            : FP64 device arrays of row_off[nsys] entries (x is output).
+ *   tol             : per-system stop ||b_i - A_i x_i||_2 <= tol ||b_i||_2.
+ *   maxit           : iteration cap per system (inner iterations for FP32).
+ *   iters_out       : device int32[nsys], iterations used.
+ *   relres_out      : device double[nsys], true relative residual at exit.
+ * Synchronous.  Returns GKO_OK if every system converged, else the worst of
+ * GKO_ERR_NOT_CONVERGED, GKO_ERR_BREAKDOWN, GKO_ERR_NOT_SPD (inspect the
+ * per-system outputs). */
+gko_status gko_batch_cg_solve(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                              int32_t *iters_out, double *relres_out);
+
+/* Workgroup size used by gko_batch_cg_solve: 64, 128, 256 or 512 threads. */
+gko_status gko_batch_set_block(gko_batch B, int32_t block);
+gko_status gko_batch_get_block(gko_batch B, int32_t *block);
+
+/* Time one full batched solve for each workgroup size (64, 128, 256, 512) on
+ * the given right-hand sides and keep the fastest for this batch.
+ * times_ms[4] (host) receives the timings; *block_out (host) the choice.
+ * x, iters and relres are scratch outputs as in gko_batch_cg_solve. */
+gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                              int32_t *iters_out, double *relres_out, int32_t *block_out,
+                              float *times_ms);
+
 /* ---------------------------------------------------------------- errors */
 
 /* Message of the last failing call on this thread ("" if none). */

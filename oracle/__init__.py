@@ -80,6 +80,8 @@ def _load():
                               i32, _f64p]
     lib.orc_batch_cg.argtypes = [i64, _i64p, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32,
                                  _i32p, _f64p]
+    lib.orc_batch_ir_cg.argtypes = [i64, _i64p, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32,
+                                    _i32p, _f64p]
     _lib = lib
     return lib
 
@@ -277,4 +279,18 @@ def batch_cg(row_off, nnz_off, rp_local, col, val, b, tol: float = 1e-10, maxit:
     rc = _load().orc_batch_cg(nsys, row_off, nnz_off, np.ascontiguousarray(rp_local, np.int32),
                               np.ascontiguousarray(col, np.int32), _f64(val), _f64(b), x, tol,
                               maxit, it, rr)
+    return rc, x, it, rr
+
+
+def batch_ir_cg(row_off, nnz_off, rp_local, col, val, b, tol: float = 1e-10, max_inner: int = 1000):
+    """Per-system FP64 refinement around FP32 CG.  Returns (status, x, iters, true_relres)."""
+    row_off = np.ascontiguousarray(row_off, np.int64)
+    nnz_off = np.ascontiguousarray(nnz_off, np.int64)
+    nsys = row_off.shape[0] - 1
+    x = np.zeros(int(row_off[-1]))
+    it = np.zeros(nsys, np.int32)
+    rr = np.zeros(nsys)
+    rc = _load().orc_batch_ir_cg(nsys, row_off, nnz_off, np.ascontiguousarray(rp_local, np.int32),
+                                 np.ascontiguousarray(col, np.int32), _f64(val), _f64(b), x, tol,
+                                 max_inner, it, rr)
     return rc, x, it, rr

@@ -597,3 +597,30 @@ int orc_batch_cg(int64_t nsys, const int64_t *row_off, const int64_t *nnz_off,
     }
     return worst;
 }
+
+/* ======================================================================
+ * Batched mixed-precision solve: each system by orc_ir_cg (no
+ * preconditioner), the FP32 inner solves on the system's values rounded to
+ * FP32 and the FP64 residual on the values as given.  For a batch stored in
+ * FP32 the values passed here are those FP32 values, so the outer residual
+ * refines towards the solution of the FP32-stored matrix.
+ * iters[i] = total inner iterations, relres[i] = final true relres.
+ * ====================================================================== */
+int orc_batch_ir_cg(int64_t nsys, const int64_t *row_off, const int64_t *nnz_off,
+                    const int32_t *rp_local, const int32_t *ci, const double *v,
+                    const double *b, double *x, double tol, int32_t max_inner,
+                    int32_t *iters, double *relres) {
+    int worst = ORC_OK;
+    for (int64_t s = 0; s < nsys; ++s) {
+        int64_t m = row_off[s + 1] - row_off[s];
+        const int32_t *rp = rp_local + row_off[s] + s;
+        double out[3];
+        for (int64_t i = 0; i < m; ++i) x[row_off[s] + i] = 0.0;
+        int rc = orc_ir_cg(m, rp, ci + nnz_off[s], v + nnz_off[s], b + row_off[s], x + row_off[s],
+                           tol, 20, 1e-5, max_inner, NULL, 0, out);
+        iters[s] = (int32_t)out[0];
+        relres[s] = out[2];
+        if (rc != ORC_OK && worst == ORC_OK) worst = rc;
+    }
+    return worst;
+}

@@ -86,6 +86,13 @@ _SIGS = {
     "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
     "gko_cg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_batch_create_csr": [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _st, ctypes.POINTER(_vp)],
+    "gko_batch_destroy": [_vp],
+    "gko_batch_cg_solve": [_vp, _vp, _vp, _f64, _i32, _vp, _vp],
+    "gko_batch_set_block": [_vp, _i32],
+    "gko_batch_get_block": [_vp, ctypes.POINTER(_i32)],
+    "gko_batch_autotune": [_vp, _vp, _vp, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
+                           ctypes.POINTER(ctypes.c_float)],
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
 }
 for _name, _args in _SIGS.items():
@@ -387,3 +394,72 @@ def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure
 def bicgstab(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
              raise_on_failure: bool = False):
     return _solve(_lib.gko_bicgstab_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+# ----------------------------------------------------------------------------- batched CG
+class Batch:
+    """Many small independent systems solved by one persistent kernel launch."""
+
+    def __init__(self, row_off, nnz_off, row_ptr_local, col, val, ctx: Context | None = None,
+                 dtype=None):
+        torch = _torch()
+        self.ctx = ctx or default_context()
+        dev = torch.device("cuda", self.ctx.device)
+
+        def d(a, dt):
+            t = a if isinstance(a, torch.Tensor) else torch.from_numpy(np.ascontiguousarray(a))
+            return t.to(device=dev, dtype=dt).contiguous()
+
+        ro, no = d(row_off, torch.int64), d(nnz_off, torch.int64)
+        rp, ci = d(row_ptr_local, torch.int32), d(col, torch.int32)
+        va = d(val, dtype or torch.float64)
+        self.nsys = ro.numel() - 1
+        self.rows = int(ro[-1].item()) if self.nsys > 0 else 0
+        h = _vp()
+        _check(_lib.gko_batch_create_csr(self.ctx.handle, self.nsys, _ptr(ro), _ptr(no), _ptr(rp),
+                                         _ptr(ci), _ptr(va), _dtype_code(va), ctypes.byref(h)))
+        self.handle = h
+
+    @property
+    def block(self) -> int:
+        b = _i32()
+        _check(_lib.gko_batch_get_block(self.handle, ctypes.byref(b)))
+        return b.value
+
+    @block.setter
+    def block(self, v: int):
+        _check(_lib.gko_batch_set_block(self.handle, v))
+
+    def _outs(self):
+        torch = _torch()
+        dev = torch.device("cuda", self.ctx.device)
+        return (torch.empty(self.nsys, dtype=torch.int32, device=dev),
+                torch.empty(self.nsys, dtype=torch.float64, device=dev))
+
+    def solve(self, b, x, tol: float = 1e-10, maxit: int = 1000):
+        """Returns (status, iters[nsys] device tensor, relres[nsys] device tensor)."""
+        it, rr = self._outs()
+        st = _lib.gko_batch_cg_solve(self.handle, _ptr(b), _ptr(x), tol, maxit, _ptr(it), _ptr(rr))
+        if st not in (OK, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NOT_SPD):
+            raise GkoError(st, last_error())
+        return st, it, rr
+
+    def autotune(self, b, x, tol: float = 1e-10, maxit: int = 1000):
+        """Times every workgroup size, keeps the fastest.  Returns (block, {block: ms})."""
+        it, rr = self._outs()
+        blk = _i32()
+        ms = (ctypes.c_float * 4)()
+        _check(_lib.gko_batch_autotune(self.handle, _ptr(b), _ptr(x), tol, maxit, _ptr(it),
+                                       _ptr(rr), ctypes.byref(blk), ms))
+        return blk.value, dict(zip((64, 128, 256, 512), list(ms)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gko_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <numeric>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -14,6 +15,7 @@
 #include <string>
 #include <vector>
 
+#include "batch_kernels.hpp"
 #include "gko.h"
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
@@ -620,6 +622,9 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
                 if (fused) {
                     HIPC(cg_spmv_csr(s, v.t, n, A->rp, A->col, v.val, p.p, q.p, A->subwarp, S,
                                      partials.as<double>(), ticket.as<unsigned>()));
+                } else if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
+                    HIPC(cg_spmv_ell(s, v.t, n, A->K, A->ld, A->ecol, v.eval, p.p, q.p, S,
+                                     partials.as<double>(), ticket.as<unsigned>()));
                 } else {
                     spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
                     HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
@@ -717,10 +722,232 @@ bool overlap(const void *a, size_t na, const void *b, size_t nb) {
 
 }  // namespace
 
+// ====================================================================== batches
+struct gko_batch_s {
+    gko_context ctx = nullptr;
+    gko_dtype dt = GKO_F64;
+    int64_t nsys = 0, rows = 0, nnz = 0, max_m = 0;
+    int64_t *row_off = nullptr, *nnz_off = nullptr;
+    int32_t *rp_local = nullptr, *col = nullptr, *order = nullptr;
+    void *val = nullptr;
+    unsigned *counter = nullptr;
+    int *status = nullptr;
+    int block = 128;
+
+    void free_all() {
+        void *ps[] = {row_off, nnz_off, rp_local, col, order, val, counter, status};
+        for (void *p : ps) ctx->free_bytes(p);
+        row_off = nnz_off = nullptr;
+        rp_local = col = order = nullptr;
+        val = nullptr;
+        counter = nullptr;
+        status = nullptr;
+    }
+};
+
+namespace {
+
+gko_status batch_run(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                     int32_t *iters, double *relres, float *ms) {
+    gko_context c = B->ctx;
+    hipStream_t s = c->stream;
+    batch_args a;
+    a.nsys = B->nsys;
+    a.row_off = B->row_off;
+    a.nnz_off = B->nnz_off;
+    a.rp_local = B->rp_local;
+    a.col = B->col;
+    a.val = B->val;
+    a.order = B->order;
+    a.counter = B->counter;
+    a.b = b;
+    a.x = x;
+    a.tol = tol;
+    a.maxit = maxit;
+    a.iters = iters;
+    a.relres = relres;
+    a.status = B->status;
+    a.max_m = B->max_m;
+    a.block = B->block;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (ms) {
+        HIPC(hipEventCreate(&e0));
+        HIPC(hipEventCreate(&e1));
+        HIPC(hipEventRecord(e0, s));
+    }
+    HIPC(batch_cg(s, B->dt == GKO_F64 ? vt::f64 : vt::f32, a));
+    if (ms) {
+        HIPC(hipEventRecord(e1, s));
+        HIPC(hipEventSynchronize(e1));
+        HIPC(hipEventElapsedTime(ms, e0, e1));
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    const int st = read_int(c, B->status);
+    switch (st) {
+        case 0: return GKO_OK;
+        case kBatchNotSpd: return GKO_ERR_NOT_SPD;
+        case kBatchBreakdown: return GKO_ERR_BREAKDOWN;
+        default: return GKO_ERR_NOT_CONVERGED;
+    }
+}
+
+void check_batch_solve_args(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                            int32_t *iters, double *relres) {
+    require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
+    require(B->nsys == 0 || (b && x && iters && relres), GKO_ERR_INVALID_ARG, "null array");
+    require(tol > 0.0 && std::isfinite(tol), GKO_ERR_INVALID_ARG, "tol must be positive and finite");
+    require(maxit >= 0, GKO_ERR_INVALID_ARG, "maxit must be >= 0");
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
 const char *gko_last_error(void) { return g_last_error.c_str(); }
+
+gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *row_off,
+                                const int64_t *nnz_off, const int32_t *row_ptr_local,
+                                const int32_t *col_idx, const void *values, gko_dtype dt,
+                                gko_batch *out) {
+    return guarded([&] {
+        require(ctx && out, GKO_ERR_INVALID_ARG, "null context or output handle");
+        *out = nullptr;
+        require(nsys >= 0 && nsys < std::numeric_limits<int32_t>::max(), GKO_ERR_INVALID_ARG,
+                "bad system count");
+        require(dt == GKO_F64 || dt == GKO_F32, GKO_ERR_INVALID_ARG, "bad dtype");
+        require(nsys == 0 || (row_off && nnz_off && row_ptr_local), GKO_ERR_INVALID_ARG,
+                "null offsets");
+        hipStream_t s = ctx->stream;
+        std::vector<int64_t> ro(nsys + 1, 0), no(nsys + 1, 0);
+        if (nsys > 0) {
+            HIPC(hipMemcpyAsync(ro.data(), row_off, (nsys + 1) * 8, hipMemcpyDeviceToHost, s));
+            HIPC(hipMemcpyAsync(no.data(), nnz_off, (nsys + 1) * 8, hipMemcpyDeviceToHost, s));
+            ctx->sync();
+        }
+        require(ro[0] == 0 && no[0] == 0, GKO_ERR_INVALID_ARG, "offsets must start at 0");
+        int64_t max_m = 0;
+        std::vector<int64_t> nz(nsys);
+        for (int64_t i = 0; i < nsys; ++i) {
+            const int64_t m = ro[i + 1] - ro[i];
+            nz[i] = no[i + 1] - no[i];
+            require(m >= 1 && m <= kBatchMaxRows, GKO_ERR_INVALID_ARG,
+                    "system " + std::to_string(i) + " has " + std::to_string(m) +
+                        " rows (1.." + std::to_string(kBatchMaxRows) + " supported)");
+            require(nz[i] >= 0, GKO_ERR_INVALID_ARG, "nonzero offsets must not decrease");
+            max_m = std::max(max_m, m);
+        }
+        const int64_t rows = ro[nsys], nnz = no[nsys];
+        require(nnz < std::numeric_limits<int32_t>::max(), GKO_ERR_UNSUPPORTED, "nnz must be below 2^31");
+        require(nnz == 0 || (col_idx && values), GKO_ERR_INVALID_ARG, "null columns or values");
+        // queue order: largest systems first (ties by index)
+        std::vector<int32_t> order(nsys);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int32_t a, int32_t b) { return nz[a] > nz[b]; });
+        auto B = new gko_batch_s();
+        B->ctx = ctx;
+        try {
+            const size_t vb = dt == GKO_F64 ? 8 : 4;
+            B->dt = dt;
+            B->nsys = nsys;
+            B->rows = rows;
+            B->nnz = nnz;
+            B->max_m = max_m;
+            B->row_off = static_cast<int64_t *>(ctx->alloc_bytes((nsys + 1) * 8));
+            B->nnz_off = static_cast<int64_t *>(ctx->alloc_bytes((nsys + 1) * 8));
+            B->rp_local = static_cast<int32_t *>(ctx->alloc_bytes((rows + nsys) * 4));
+            B->col = static_cast<int32_t *>(ctx->alloc_bytes(nnz * 4));
+            B->val = ctx->alloc_bytes(nnz * vb);
+            B->order = static_cast<int32_t *>(ctx->alloc_bytes(nsys * 4));
+            B->counter = static_cast<unsigned *>(ctx->alloc_bytes(8));
+            B->status = static_cast<int *>(ctx->alloc_bytes(8));
+            HIPC(hipMemcpyAsync(B->row_off, ro.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(B->nnz_off, no.data(), (nsys + 1) * 8, hipMemcpyHostToDevice, s));
+            if (nsys > 0) {
+                HIPC(hipMemcpyAsync(B->rp_local, row_ptr_local, (rows + nsys) * 4,
+                                    hipMemcpyDeviceToDevice, s));
+                HIPC(hipMemcpyAsync(B->order, order.data(), nsys * 4, hipMemcpyHostToDevice, s));
+            }
+            if (nnz > 0) {
+                HIPC(hipMemcpyAsync(B->col, col_idx, nnz * 4, hipMemcpyDeviceToDevice, s));
+                HIPC(hipMemcpyAsync(B->val, values, nnz * vb, hipMemcpyDeviceToDevice, s));
+            }
+            HIPC(hipMemsetAsync(B->status, 0, 4, s));
+            HIPC(batch_validate(s, nsys, B->row_off, B->nnz_off, B->rp_local, B->col, B->status));
+            if (read_int(ctx, B->status))
+                fail(GKO_ERR_INVALID_ARG, "malformed system (offsets or column indices)");
+            B->block = max_m <= 256 ? 64 : 128;
+        } catch (...) {
+            B->free_all();
+            delete B;
+            throw;
+        }
+        *out = B;
+    });
+}
+
+gko_status gko_batch_destroy(gko_batch B) {
+    return guarded([&] {
+        if (!B) return;
+        B->free_all();
+        delete B;
+    });
+}
+
+gko_status gko_batch_set_block(gko_batch B, int32_t block) {
+    return guarded([&] {
+        require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
+        require(block == 64 || block == 128 || block == 256 || block == 512, GKO_ERR_INVALID_ARG,
+                "block must be 64, 128, 256 or 512");
+        B->block = block;
+    });
+}
+
+gko_status gko_batch_get_block(gko_batch B, int32_t *block) {
+    return guarded([&] {
+        require(B && block, GKO_ERR_INVALID_ARG, "null batch or output");
+        *block = B->block;
+    });
+}
+
+gko_status gko_batch_cg_solve(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                              int32_t *iters_out, double *relres_out) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_batch_solve_args(B, b, x, tol, maxit, iters_out, relres_out);
+        if (B->nsys == 0) return;
+        st = batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);
+    });
+    if (call != GKO_OK) return call;
+    if (st != GKO_OK) g_last_error = std::string("batch cg: ") + gko_status_string(st);
+    return st;
+}
+
+gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
+                              int32_t *iters_out, double *relres_out, int32_t *block_out,
+                              float *times_ms) {
+    return guarded([&] {
+        check_batch_solve_args(B, b, x, tol, maxit, iters_out, relres_out);
+        const int cand[4] = {64, 128, 256, 512};
+        int best = B->block;
+        float best_ms = std::numeric_limits<float>::infinity();
+        for (int j = 0; j < 4; ++j) {
+            B->block = cand[j];
+            float ms = 0.f;
+            (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);  // warm-up
+            (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, &ms);
+            if (times_ms) times_ms[j] = ms;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = cand[j];
+            }
+        }
+        B->block = best;
+        if (block_out) *block_out = best;
+    });
+}
 
 const char *gko_status_string(gko_status s) {
     switch (s) {

@@ -1,0 +1,284 @@
+// Batched CG: thousands of small independent SPD systems in one persistent
+// launch.  Every workgroup loops: take the next system from an atomic work
+// queue (systems ordered by decreasing nonzeros, so the longest jobs start
+// first), solve it to its own tolerance with the iteration vectors in LDS,
+// write x, the iteration count and the true residual, and take the next.
+// The matrix of a system (a few tens of KB) is read from global memory and
+// stays in the L1/L2 caches across its iterations; each workgroup exits once
+// the queue runs dry, so every wave reaches the end.
+//
+// FP64 batches run plain CG (Hestenes-Stiefel).  FP32 batches store the
+// matrix in FP32 and run FP32 CG iterations inside FP64 iterative
+// refinement: the residual b - A x, its norm and the update x += |r| d are
+// FP64, each inner solve asks for tau_k = max(1e-5, tol |b| / (2 |r_k|)).
+#include <cmath>
+
+#include "batch_kernels.hpp"
+#include "device.hpp"
+
+namespace gko {
+
+// Sum over the workgroup with a fixed tree; every thread gets the total.
+template <int T>
+__device__ inline double wg_sum(double v, double *red) {
+    v = subwarp<kWave>::reduce_sum(v);
+    if constexpr (T == kWave) {
+        return v;
+    } else {
+        constexpr int NW = T / kWave;
+        const int w = threadIdx.x / kWave;
+        if ((threadIdx.x % kWave) == 0) red[w] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) s += red[j];
+        __syncthreads();
+        return s;
+    }
+}
+
+template <int T>
+__device__ inline void wg_sync() {
+    __syncthreads();
+}
+
+struct sys_view {
+    int32_t m;
+    const int32_t *rp;
+    const int32_t *col;
+    int64_t row0;
+};
+
+// q = A p over this thread's rows (rows tid, tid+T, ...), returns sum of p_i q_i.
+template <typename VA, typename VV, int T>
+__device__ inline double spmv_rows(const sys_view &S, const VA *__restrict__ val, const VV *p,
+                                   VV *q) {
+    double pq = 0.0;
+    for (int i = threadIdx.x; i < S.m; i += T) {
+        VV s = VV(0);
+        for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (VV)val[k] * p[S.col[k]];
+        q[i] = s;
+        pq += (double)p[i] * (double)s;
+    }
+    return pq;
+}
+
+// Plain CG on A x = rhs from x = 0, vectors x, r, p, q in LDS (type VV),
+// dots in FP64.  Returns iterations; *flag = 1 not SPD, 2 breakdown.
+template <typename VA, typename VV, int T>
+__device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val, VV *x, VV *r, VV *p,
+                                VV *q, double rhs_norm2, double stop2, int maxit, double *red,
+                                int *flag) {
+    double rr = rhs_norm2;
+    int it = 0;
+    *flag = 0;
+    while (it < maxit && rr > stop2) {
+        const double pq = wg_sum<T>(spmv_rows<VA, VV, T>(S, val, p, q), red);
+        ++it;
+        if (!(pq > 0.0)) {
+            *flag = std::isnan(pq) ? 2 : 1;
+            break;
+        }
+        const double alpha = rr / pq;
+        double loc = 0.0;
+        for (int i = threadIdx.x; i < S.m; i += T) {
+            x[i] = (VV)((double)x[i] + alpha * (double)p[i]);
+            const VV ri = (VV)((double)r[i] - alpha * (double)q[i]);
+            r[i] = ri;
+            loc += (double)ri * (double)ri;
+        }
+        const double rr_new = wg_sum<T>(loc, red);
+        if (!std::isfinite(rr_new)) {
+            *flag = 2;
+            break;
+        }
+        const double beta = rr_new / rr;
+        rr = rr_new;
+        for (int i = threadIdx.x; i < S.m; i += T) p[i] = (VV)((double)r[i] + beta * (double)p[i]);
+        wg_sync<T>();
+    }
+    return it;
+}
+
+template <typename VA, int T>
+__global__ __launch_bounds__(T) void batch_cg_kernel(
+    int64_t nsys, const int64_t *__restrict__ row_off, const int64_t *__restrict__ nnz_off,
+    const int32_t *__restrict__ rp_local, const int32_t *__restrict__ col,
+    const VA *__restrict__ val, const int32_t *__restrict__ order, unsigned *counter,
+    const double *__restrict__ b, double *__restrict__ xout, double tol, int32_t maxit,
+    int32_t *__restrict__ iters, double *__restrict__ relres, int *status) {
+    extern __shared__ double lds[];
+    __shared__ double red[T / kWave];
+    __shared__ unsigned s_next;
+    constexpr bool kRefine = sizeof(VA) == 4;  // FP32 storage: FP32 CG inside FP64 refinement
+    for (;;) {
+        if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
+        __syncthreads();
+        const unsigned qi = s_next;
+        __syncthreads();
+        if (qi >= nsys) break;  // uniform: the queue is empty
+        const int32_t sid = order[qi];
+        sys_view S;
+        S.row0 = row_off[sid];
+        S.m = (int32_t)(row_off[sid + 1] - S.row0);
+        S.rp = rp_local + S.row0 + sid;
+        S.col = col + nnz_off[sid];
+        const VA *A = val + nnz_off[sid];
+        const double *bs = b + S.row0;
+        double bb = 0.0;
+        for (int i = threadIdx.x; i < S.m; i += T) bb += bs[i] * bs[i];
+        bb = wg_sum<T>(bb, red);
+        const double bnorm = sqrt(bb);
+        int its = 0, flag = 0;
+        double *x64 = lds;            // m doubles
+        if constexpr (!kRefine) {
+            double *r = x64 + S.m, *p = r + S.m, *q = p + S.m;
+            for (int i = threadIdx.x; i < S.m; i += T) {
+                x64[i] = 0.0;
+                r[i] = bs[i];
+                p[i] = bs[i];
+            }
+            wg_sync<T>();
+            its = cg_in_lds<VA, double, T>(S, A, x64, r, p, q, bb, tol * tol * bb, maxit, red, &flag);
+        } else {
+            double *r64 = x64 + S.m;
+            float *d = reinterpret_cast<float *>(r64 + S.m);
+            float *r = d + S.m, *p = r + S.m, *q = p + S.m;
+            for (int i = threadIdx.x; i < S.m; i += T) {
+                x64[i] = 0.0;
+                r64[i] = bs[i];
+            }
+            wg_sync<T>();
+            double rn = bnorm, prev = INFINITY;
+            for (int outer = 0; outer < 20; ++outer) {
+                if (!(rn > tol * bnorm) || !(rn <= 0.5 * prev)) break;
+                prev = rn;
+                double tau = 0.5 * (tol * bnorm / rn);
+                if (tau < 1e-5) tau = 1e-5;
+                double rt2 = 0.0;
+                for (int i = threadIdx.x; i < S.m; i += T) {
+                    const float ri = (float)(r64[i] / rn);
+                    d[i] = 0.0f;
+                    r[i] = ri;
+                    p[i] = ri;
+                    rt2 += (double)ri * (double)ri;
+                }
+                rt2 = wg_sum<T>(rt2, red);
+                its += cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
+                                               maxit - its, red, &flag);
+                if (flag) break;
+                // x += |r| d, then the FP64 residual b - A x
+                for (int i = threadIdx.x; i < S.m; i += T) x64[i] = x64[i] + rn * (double)d[i];
+                wg_sync<T>();
+                double loc = 0.0;
+                for (int i = threadIdx.x; i < S.m; i += T) {
+                    double s = 0.0;
+                    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * x64[S.col[k]];
+                    const double ri = bs[i] - s;
+                    r64[i] = ri;
+                    loc += ri * ri;
+                }
+                rn = sqrt(wg_sum<T>(loc, red));
+                if (its >= maxit) break;
+            }
+        }
+        // true residual of the final x (FP64), x to global memory
+        wg_sync<T>();
+        double loc = 0.0;
+        for (int i = threadIdx.x; i < S.m; i += T) {
+            double s = 0.0;
+            for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * x64[S.col[k]];
+            const double ri = bs[i] - s;
+            loc += ri * ri;
+            xout[S.row0 + i] = x64[i];
+        }
+        const double tr = sqrt(wg_sum<T>(loc, red));
+        if (threadIdx.x == 0) {
+            iters[sid] = its;
+            relres[sid] = bnorm > 0.0 ? tr / bnorm : 0.0;
+            const int st = flag == 1 ? kBatchNotSpd
+                         : flag == 2 ? kBatchBreakdown
+                         : (bnorm > 0.0 && !(tr <= tol * bnorm)) ? kBatchNotConverged : 0;
+            if (st) atomicMax(status, st);
+        }
+        __syncthreads();
+    }
+}
+
+// Structure check, one workgroup per system: local offsets start at 0, do
+// not decrease, end at the system's nonzero count; columns in [0, m).
+__global__ void batch_validate_kernel(int64_t nsys, const int64_t *__restrict__ row_off,
+                                      const int64_t *__restrict__ nnz_off,
+                                      const int32_t *__restrict__ rp_local,
+                                      const int32_t *__restrict__ col, int *err) {
+    const int64_t sid = blockIdx.x;
+    if (sid >= nsys) return;
+    const int64_t m = row_off[sid + 1] - row_off[sid];
+    const int64_t nz = nnz_off[sid + 1] - nnz_off[sid];
+    const int32_t *rp = rp_local + row_off[sid] + sid;
+    const int32_t *c = col + nnz_off[sid];
+    int bad = 0;
+    if (threadIdx.x == 0 && (rp[0] != 0 || (int64_t)rp[m] != nz)) bad = 1;
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+        if (rp[i + 1] < rp[i]) bad = 1;
+        else
+            for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
+                if (c[k] < 0 || c[k] >= m) bad = 1;
+    }
+    if (bad) atomicOr(err, 1);
+}
+
+hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
+                          const int64_t *nnz_off, const int32_t *rp_local, const int32_t *col,
+                          int *err) {
+    if (nsys == 0) return hipSuccess;
+    batch_validate_kernel<<<(unsigned)nsys, 256, 0, s>>>(nsys, row_off, nnz_off, rp_local, col, err);
+    return hipGetLastError();
+}
+
+__global__ void batch_reset_kernel(unsigned *counter, int *status) {
+    *counter = 0u;
+    *status = 0;
+}
+
+size_t batch_lds_bytes(vt t, int64_t max_m) {
+    return (size_t)max_m * (t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4);
+}
+
+template <typename VA, int T>
+static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m);
+    int dev = 0, cus = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T>, T, lds);
+    if (e != hipSuccess) return e;
+    if (per_cu < 1) return hipErrorInvalidConfiguration;
+    int64_t grid = (int64_t)cus * per_cu;
+    if (grid > a.nsys) grid = a.nsys;
+    if (grid < 1) grid = 1;
+    batch_reset_kernel<<<1, 1, 0, s>>>(a.counter, a.status);
+    batch_cg_kernel<VA, T><<<(unsigned)grid, T, lds, s>>>(
+        a.nsys, a.row_off, a.nnz_off, a.rp_local, a.col, static_cast<const VA *>(a.val), a.order,
+        a.counter, a.b, a.x, a.tol, a.maxit, a.iters, a.relres, a.status);
+    return hipGetLastError();
+}
+
+template <typename VA>
+static hipError_t launch_batch_v(hipStream_t s, const batch_args &a) {
+    switch (a.block) {
+        case 64: return launch_batch_t<VA, 64>(s, a);
+        case 128: return launch_batch_t<VA, 128>(s, a);
+        case 256: return launch_batch_t<VA, 256>(s, a);
+        case 512: return launch_batch_t<VA, 512>(s, a);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a) {
+    if (a.nsys == 0) return hipSuccess;
+    return t == vt::f64 ? launch_batch_v<double>(s, a) : launch_batch_v<float>(s, a);
+}
+
+}  // namespace gko

@@ -1,0 +1,46 @@
+// Host-side launcher of the persistent batched CG kernel (batch_cg.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hpp"
+
+namespace gko {
+
+// Per-batch outcome, the worst over all systems (atomicMax).
+constexpr int kBatchNotConverged = 1;
+constexpr int kBatchBreakdown = 2;
+constexpr int kBatchNotSpd = 3;
+
+// Largest system the kernel takes (rows): its iteration vectors live in LDS.
+constexpr int64_t kBatchMaxRows = 2048;
+
+struct batch_args {
+    int64_t nsys;
+    const int64_t *row_off;   // nsys+1
+    const int64_t *nnz_off;   // nsys+1
+    const int32_t *rp_local;  // row_off[nsys] + nsys local row offsets
+    const int32_t *col;       // local column indices
+    const void *val;          // values (FP64 or FP32)
+    const int32_t *order;     // system ids, largest first
+    unsigned *counter;        // work-queue head (reset by the launcher)
+    const double *b;
+    double *x;
+    double tol;
+    int32_t maxit;
+    int32_t *iters;
+    double *relres;
+    int *status;
+    int64_t max_m;
+    int block;                // workgroup size: 64, 128, 256 or 512
+};
+
+size_t batch_lds_bytes(vt t, int64_t max_m);
+// err: device int set to 1 on a malformed system.
+hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
+                          const int64_t *nnz_off, const int32_t *rp_local, const int32_t *col,
+                          int *err);
+hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a);
+
+}  // namespace gko

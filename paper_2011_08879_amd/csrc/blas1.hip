@@ -174,6 +174,54 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
     if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
 }
 
+// q = A p for ELL (thread per row, column-major slots, padding last),
+// fused with p.q.
+template <typename V>
+__global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, int64_t ld,
+                                                         const int32_t *__restrict__ ecol,
+                                                         const V *__restrict__ eval,
+                                                         const V *__restrict__ p, V *__restrict__ q,
+                                                         krylov_scalars *sc, double *partials,
+                                                         unsigned *ticket) {
+    if (sc->done) return;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        V s = V(0);
+        for (int64_t j = 0; j < K; j += 4) {
+            int32_t c[4];
+            V v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                c[u] = j + u < K ? ecol[(j + u) * ld + i] : -1;
+                v[u] = j + u < K ? eval[(j + u) * ld + i] : V(0);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (c[u] >= 0) s += v[u] * p[c[u]];
+            if (c[3] < 0) break;
+        }
+        q[i] = s;
+        acc += (double)p[i] * (double)s;
+    }
+    double v[1] = {acc}, out[1];
+    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+}
+
+hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
+                       const void *eval, const void *p, void *q, krylov_scalars *sc,
+                       double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    if (t == vt::f64)
+        cg_spmv_ell_kernel<double><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const double *>(eval),
+                                                    static_cast<const double *>(p),
+                                                    static_cast<double *>(q), sc, partials, ticket);
+    else
+        cg_spmv_ell_kernel<float><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const float *>(eval),
+                                                   static_cast<const float *>(p),
+                                                   static_cast<float *>(q), sc, partials, ticket);
+    return hipGetLastError();
+}
+
 // p.q after a SpMV done by a format's own kernel.
 template <typename V>
 __global__ __launch_bounds__(kB) void cg_pq_kernel(int64_t n, const V *__restrict__ p,

@@ -8,7 +8,7 @@ namespace gko {
 
 template <int W>
 struct csr_shape {
-    static constexpr int U = W >= 4 ? 4 : 8;  // rows per subwarp
+    static constexpr int U = W >= 16 ? 4 : 8;  // rows per subwarp
 };
 
 // Rows longer than long_t are left out (their sum is 0 here): a separate

@@ -250,3 +250,20 @@ def test_batch_cg_closed_form_bounds(orc, gen_mod):
         # identical to a standalone solve of the same system
         rc1, x1, info = orc.cg(B.system(i), b[r0:r1], tol=1e-10)
         assert info["iters"] == iters[i] and np.array_equal(x1, x[r0:r1])
+
+
+def test_batch_ir_cg_fp32_storage(orc, gen_mod):
+    """Refinement around FP32 CG reaches 1e-10 on every system of an FP32-stored batch."""
+    B = gen_mod.batch_systems(30, master_seed=6)
+    vals = B.val.astype(np.float32).astype(np.float64)
+    b = np.empty_like(B.xstar)
+    for i in range(B.nsys):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        rp, c, _ = B.system(i)
+        k0, k1 = int(B.nnz_off[i]), int(B.nnz_off[i + 1])
+        b[r0:r1] = orc.spmv((rp, c, vals[k0:k1]), B.xstar[r0:r1])
+    rc, x, it, rr = orc.batch_ir_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, b, tol=1e-10)
+    assert rc == orc.OK and np.all(rr <= 1e-10)
+    rc64, x64, it64, rr64 = orc.batch_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, b, tol=1e-10)
+    # the refined solution agrees with the FP64 solve of the same (FP32-valued) systems
+    assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 81 * 2e-10
