@@ -1,0 +1,116 @@
+"""Parity at the full sizes the bench times, in the same launch configurations.
+
+* SpMV sweep: the 27-point stencil on 128^3 (n = 2,097,152, nnz = 55,742,968) and
+  the lognormal random matrix (n = 10^6, longest row 10,000), every format the
+  bench runs; all rows are checked against the oracle (the serial C oracle
+  handles these sizes in well under a second per SpMV).
+* Solvers: block-Jacobi PCG on the 3D 7-point Poisson 256^3 in FP64 and mixed
+  precision, in the format the library's AUTO choice picks, checked by the
+  oracle's true residual and the manufactured-solution error bound.
+* Batched CG: the 10,000-system batch, FP64 and FP32 storage, per-system true
+  residuals from the oracle.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import assert_spmv_close, dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2011_08879_amd as g
+    return g
+
+
+@pytest.fixture(scope="module")
+def sweep(gen_mod):
+    return {"stencil27_128": gen_mod.stencil27(128),
+            "lognormal_1M": gen_mod.random_lognormal(4, 1_000_000, mean=16.0, sigma=1.56,
+                                                     max_len=10000)}
+
+
+@pytest.mark.parametrize("name,fmt", [("stencil27_128", f) for f in
+                                      ("csr", "csr_merge", "coo", "ell", "hybrid")] +
+                         [("lognormal_1M", f) for f in ("csr", "csr_merge", "coo", "hybrid")])
+def test_sweep_spmv_full_size(g, orc, gen_mod, sweep, name, fmt):
+    import torch
+    A = sweep[name]
+    n = len(A[0]) - 1
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = gen_mod.uniform(3 if name.startswith("st") else 5, n)
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g.spmv(M, 1.0, dev(x), 0.0, y)
+    ref = orc.spmv_dot2(A, x)
+    absy = orc.spmv_absbound(A, x)
+    assert_spmv_close(host(y), ref, absy, np.diff(A[0]), False, "%s/%s" % (name, fmt))
+    M.close()
+
+
+def test_lognormal_ell_refused(g, sweep):
+    M = g.Matrix.from_csr(*sweep["lognormal_1M"])
+    with pytest.raises(g.GkoError) as e:
+        M.convert("ell")
+    assert e.value.status == g.ERR_UNSUPPORTED and M.describe().format == "csr"
+
+
+@pytest.fixture(scope="module")
+def poisson(gen_mod, orc):
+    N = 256
+    A = gen_mod.laplace3d(N)
+    xs = gen_mod.uniform(5, N ** 3)
+    b = orc.spmv(A, xs)
+    return A, xs, b
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_poisson256_pcg_full_size(g, orc, poisson, mixed):
+    A, xs, b = poisson
+    N = 256
+    ctx = g.default_context()
+    ctx.set_solver_opts(precision=g.PREC_MIXED_IR if mixed else g.PREC_FP64,
+                        precond=g.PRECOND_BLOCK_JACOBI, block_size=8, inner_tol=1e-5)
+    try:
+        M = g.Matrix.from_csr(*A)
+        M.convert("auto")
+        x = dev(np.zeros(N ** 3))
+        info = g.cg(M, dev(b), x, tol=1e-10, maxit=20000)
+        assert info["status"] == g.OK, info
+        xg = host(x)
+        true = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+        assert true <= 1e-10
+        kappa = (6 + 6 * math.cos(math.pi / (N + 1))) / (6 - 6 * math.cos(math.pi / (N + 1)))
+        assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * true
+    finally:
+        ctx.set_solver_opts()
+
+
+@pytest.mark.parametrize("f32", [False, True], ids=["fp64", "fp32"])
+def test_batch_10k_full_size(g, orc, gen_mod, f32):
+    import torch
+    B = gen_mod.batch_systems(10000, master_seed=6)
+    vals = B.val.astype(np.float32).astype(np.float64) if f32 else B.val
+    b = np.empty_like(B.xstar)
+    for i in range(B.nsys):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        k0, k1 = int(B.nnz_off[i]), int(B.nnz_off[i + 1])
+        b[r0:r1] = orc.spmv((B.system(i)[0], B.system(i)[1], vals[k0:k1]), B.xstar[r0:r1])
+    G = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col,
+                B.val.astype(np.float32) if f32 else B.val,
+                dtype=torch.float32 if f32 else torch.float64)
+    x = dev(np.zeros(B.xstar.shape))
+    blk, _ = G.autotune(dev(b), x)
+    st, it, rr = G.solve(dev(b), x, tol=1e-10)
+    assert st == g.OK
+    xg = host(x)
+    for i in range(B.nsys):
+        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+        k0, k1 = int(B.nnz_off[i]), int(B.nnz_off[i + 1])
+        r = b[r0:r1] - orc.spmv((B.system(i)[0], B.system(i)[1], vals[k0:k1]), xg[r0:r1])
+        assert np.linalg.norm(r) <= 1e-10 * np.linalg.norm(b[r0:r1]), i
+    if not f32:
+        rc, xo, it_o, rr_o = orc.batch_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, b, tol=1e-10)
+        assert np.all(np.abs(host(it) - it_o) <= 2)
