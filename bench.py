@@ -59,6 +59,32 @@ def csr_bytes(n, m, nnz, s=8):
     return nnz * (s + 4) + (n + 1) * 4 + m * s + n * s
 
 
+def kernel_source_hash():
+    """sha256 over the HIP sources: counters taken on other sources do not apply."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2011_08879_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic(key):
+    """HBM bytes per launch of one sweep SpMV from the committed rocprofv3 counter
+    summary (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale, both scaled by a
+    1 GiB copy of known size), or None when the kernels changed since."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        t = json.load(fh)
+    if t.get("source_sha256") != kernel_source_hash() or key not in t.get("kernels", {}):
+        return None
+    return t["kernels"][key]["traffic_bytes"]
+
+
 def log(msg):
     sys.stderr.write("[bench] %s\n" % msg)
     sys.stderr.flush()
@@ -305,7 +331,8 @@ def run_sweep(args, g, gen, torch, result):
     d = per_kernel[dom]
     achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic("%s/%s" % (d["matrix"], d["format"])),
                 "kernel": "spmv %s on %s" % (d["format"], d["matrix"]),
                 "alg_bytes_per_launch": d["alg_bytes"]}
 
