@@ -82,6 +82,11 @@ def _load():
                                  _i32p, _f64p]
     lib.orc_batch_ir_cg.argtypes = [i64, _i64p, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32,
                                     _i32p, _f64p]
+    lib.orc_features.argtypes = [i64, i64, _i32p, _i32p, _f64p]
+    lib.orc_mlp_forward.argtypes = [i64, _f64p, _f64p, _f64p]
+    lib.orc_mlp_loss_grad.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_mlp_loss_grad.restype = f64
+    lib.orc_adam_step.argtypes = [i64, _f64p, _f64p, _f64p, _f64p, i64, f64, f64, f64, f64]
     _lib = lib
     return lib
 
@@ -294,3 +299,40 @@ def batch_ir_cg(row_off, nnz_off, rp_local, col, val, b, tol: float = 1e-10, max
                                  np.ascontiguousarray(col, np.int32), _f64(val), _f64(b), x, tol,
                                  max_inner, it, rr)
     return rc, x, it, rr
+
+
+# --------------------------------------------------------------------------- selector
+N_FEATURES = 32
+MLP_SHAPES = [(64, 32), (64,), (64, 64), (64,), (5, 64), (5,)]
+N_PARAMS = 6597
+
+
+def features(A, n_cols: int | None = None) -> np.ndarray:
+    """The 32 structural features (FP64), see selector.c for the list."""
+    rp, col, _ = _csr(A)
+    n = rp.shape[0] - 1
+    f = np.zeros(N_FEATURES)
+    _load().orc_features(n, n if n_cols is None else n_cols, rp, col, f)
+    return f
+
+
+def mlp_forward(P, X) -> np.ndarray:
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 32)
+    out = np.zeros((X.shape[0], 5))
+    _load().orc_mlp_forward(X.shape[0], _f64(P), X, out)
+    return out
+
+
+def mlp_loss_grad(P, X, Y, M):
+    """Masked mean-squared loss and its gradient w.r.t. the 6597 parameters."""
+    X = np.ascontiguousarray(X, np.float64).reshape(-1, 32)
+    Y = np.ascontiguousarray(Y, np.float64).reshape(-1, 5)
+    M = np.ascontiguousarray(M, np.float64).reshape(-1, 5)
+    G = np.zeros(N_PARAMS)
+    loss = _load().orc_mlp_loss_grad(X.shape[0], _f64(P), X, Y, M, G)
+    return float(loss), G
+
+
+def adam_step(P, G, m, v, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """In place: the t-th Adam update of P, m, v (t >= 1)."""
+    _load().orc_adam_step(P.shape[0], P, _f64(G), m, v, t, lr, b1, b2, eps)
