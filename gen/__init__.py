@@ -240,3 +240,46 @@ def batch_systems(nsys: int, master_seed: int = 6, m_lo: int = 32, m_hi: int = 1
     xs = np.empty(int(row_off[-1]), dtype=np.float64)
     lib.gen_batch_fill(master_seed, nsys, m_lo, m_hi, row_off, nnz_off, rp, col, val, xs)
     return BatchSystems(m, pat, shift, row_off, nnz_off, rp, col, val, xs)
+
+
+# --------------------------------------------------------------------------- selector corpus
+CORPUS_FAMILIES = ("banded", "stencil", "uniform", "powerlaw", "blockdiag")
+
+
+def corpus_spec(i: int, seed: int = 7, n_lo: float = 1e4, n_hi: float = 1e6) -> dict:
+    """Recipe of corpus matrix i: family i mod 5; n log-uniform in [n_lo, n_hi];
+    target mean row length U[4, 64]; family parameters from stream (seed*2^20 + i, 0)."""
+    u = uniform((seed << 20) + i, 6, 0.0, 1.0)
+    fam = CORPUS_FAMILIES[i % 5]
+    n = int(round(10 ** (math.log10(n_lo) + (math.log10(n_hi) - math.log10(n_lo)) * u[0])))
+    mean = 4.0 + 60.0 * u[1]
+    spec = {"index": i, "family": fam, "n": n, "mean": mean, "seed": (seed << 20) + i}
+    if fam == "banded":
+        spec["bandwidth"] = 1 + int(u[2] * 64)
+    elif fam == "stencil":
+        spec["stencil"] = ("2d5", "2d9", "3d7", "3d27")[int(u[2] * 4) % 4]
+    elif fam == "powerlaw":
+        spec["sigma"] = 0.5 + 1.5 * u[3]
+    return spec
+
+
+def corpus_matrix(spec: dict):
+    """CSR triple of a corpus recipe."""
+    fam, n, mean, s = spec["family"], spec["n"], spec["mean"], spec["seed"]
+    lo, hi = max(1, int(mean / 2)), max(1, int(1.5 * mean))
+    if fam == "banded":
+        return banded(s, n, spec["bandwidth"], lo, hi)
+    if fam == "stencil":
+        kind = spec["stencil"]
+        if kind.startswith("2d"):
+            N = max(2, int(round(math.sqrt(n))))
+            return grid(N, N, kind="star" if kind == "2d5" else "box")
+        N = max(2, int(round(n ** (1.0 / 3.0))))
+        return grid(N, N, N, kind="star" if kind == "3d7" else "box")
+    if fam == "uniform":
+        return uniform_random(s, n, lo, hi)
+    if fam == "powerlaw":
+        return random_lognormal(s, n, mean=mean, sigma=spec["sigma"], max_len=min(n, 10000))
+    if fam == "blockdiag":
+        return blockdiag(s, n, 4, 64)
+    raise ValueError(fam)

@@ -59,7 +59,8 @@ typedef enum gko_itype { GKO_I32 = 0, GKO_I64 = 1 } gko_itype;
  *  HYBRID    : ELL of width K* plus a COO tail holding the rest, where K*
  *              minimises n*K*(s+4) + (s+8)*tail(K) bytes (s = value size),
  *              ties to the smaller K.
- *  AUTO      : (gko_convert only) pick the fastest by timing every format. */
+ *  AUTO      : (gko_convert only) the context's selector model if one is set
+ *              (gko_context_set_selector), else the fastest by timing. */
 typedef enum gko_format {
     GKO_FMT_CSR = 0,
     GKO_FMT_CSR_MERGE = 1,
@@ -143,8 +144,9 @@ gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void
 /* Convert A's storage in place to fmt; the logical matrix is unchanged.
  * Converting between any two formats is bit-exact.  ELL is refused with
  * GKO_ERR_UNSUPPORTED (A unchanged) when its padded storage would exceed 4x
- * the CSR storage.  GKO_FMT_AUTO times one SpMV in every feasible format and
- * keeps the fastest.  Synchronises the stream. */
+ * the CSR storage.  GKO_FMT_AUTO asks the context's selector model, or
+ * without one times one SpMV in every feasible format and keeps the fastest.
+ * Synchronises the stream. */
 gko_status gko_convert(gko_matrix A, gko_format fmt);
 
 /* ---------------------------------------------------------------- reductions */
@@ -261,6 +263,70 @@ gko_status gko_batch_get_block(gko_batch B, int32_t *block);
 gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
                               int32_t *iters_out, double *relres_out, int32_t *block_out,
                               float *times_ms);
+
+/* ---------------------------------------------------------------- format selector */
+
+/* 32 structural features of A, in this order (FP32, host array):
+ *  0 log10 n     1 log10 nnz     2 mean row length   3 std of row lengths
+ *  4 cv          5 min length    6 max length        7/8/9 p50/p90/p99 length
+ * 10 max/mean   11 frac empty rows   12 frac rows of length <= 4
+ * 13 ELL padding n*max/nnz   14 HYB width / mean   15 HYB tail / nnz
+ * 16 Gini of row lengths     17 entropy of the row-length distribution
+ * 18 share of nnz in the longest ceil(n/100) rows
+ * 19 log10 CSR working set (12 nnz + 4(n+1) + 8 n_cols + 8 n bytes)  20 that / 2^28
+ * 21 n_cols / n   22 mean |i-j| / n_cols   23 max |i-j| / n_cols   24 frac i == j
+ * 25 frac |i-j| <= 1   26 frac |i-j| <= 64   27 log10(1 + mean in-row column gap)
+ * 28 frac of in-row gaps equal to 1   29 64-byte x segments touched per entry
+ * 30 frac of entries whose transpose is stored (square only)
+ * 31 log10(1 + mean column span of nonempty rows)
+ * Percentile p: smallest L with #rows(len <= L) >= ceil(p n).  Synchronous. */
+gko_status gko_matrix_features(gko_matrix A, float *features);
+
+/* Exhaustive autotune: time one SpMV of a clone of A in every format
+ * (CSR, CSR_MERGE, COO, ELL, HYBRID order; mean of 5 after 2 warm-ups;
+ * infinity when a format is infeasible).  A is not changed.  *best (host)
+ * receives the fastest, times_ms[5] (host, may be NULL) the timings. */
+gko_status gko_autotune_format(gko_matrix A, gko_format *best, float *times_ms);
+
+/* The selector network: an MLP 32 -> 64 -> 64 -> 5 (ReLU, ReLU, linear) on
+ * z-scored features, FP32.  Output f predicts ln(t_f / t_best) for the five
+ * formats in the order above; the selected format is the argmin among the
+ * feasible ones.  Parameters (6597 floats): W1[64][32], b1[64], W2[64][64],
+ * b2[64], W3[5][64], b3[5], row-major (out x in). */
+typedef struct gko_mlp_s *gko_mlp;
+
+/* Create from initial parameters (host array of 6597 floats); normalisation
+ * starts as mean 0, std 1; Adam state at zero. */
+gko_status gko_mlp_create(gko_context ctx, const float *params, gko_mlp *out);
+gko_status gko_mlp_destroy(gko_mlp M);
+/* Copy parameters (6597) and normalisation (mean[32] then std[32]) to host;
+ * either pointer may be NULL. */
+gko_status gko_mlp_get_params(gko_mlp M, float *params, float *norm);
+/* Per-feature mean and std (floored at 1e-6) of n samples X (device, n x 32). */
+gko_status gko_mlp_fit_normalization(gko_mlp M, int64_t n, const float *X);
+/* out (device, n x 5) <- network(X) for n samples X (device, n x 32). */
+gko_status gko_mlp_forward(gko_mlp M, int64_t n, const float *X, float *out);
+/* Masked mean squared loss L = sum mask (out - Y)^2 / sum mask over n samples
+ * (X: n x 32, Y and mask: n x 5, device) and its gradient.  grad: device
+ * float[6597], loss: device double.  The backward pass uses relu'(0) = 0. */
+gko_status gko_mlp_loss_grad(gko_mlp M, int64_t n, const float *X, const float *Y,
+                             const float *mask, float *grad, double *loss);
+/* steps full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
+ * rate lr) on the GPU; the Adam state persists across calls.  loss_history
+ * (device float[steps], may be NULL) receives the loss before each step. */
+gko_status gko_mlp_train(gko_mlp M, int64_t n, const float *X, const float *Y, const float *mask,
+                         int32_t steps, float lr, float *loss_history);
+/* Save / load parameters and normalisation (binary: magic "GKOMLP1", version,
+ * parameter count, arch string, norm[64], params[6597]; little endian). */
+gko_status gko_mlp_save(gko_mlp M, const char *path);
+gko_status gko_mlp_load(gko_context ctx, const char *path, gko_mlp *out);
+
+/* Predicted-fastest feasible format of A; scores[5] (host, may be NULL)
+ * receive the network outputs.  A is not changed. */
+gko_status gko_select_format(gko_matrix A, gko_mlp model, gko_format *out, float *scores);
+/* Model used by gko_convert(A, GKO_FMT_AUTO) on this context (NULL: time all
+ * formats instead).  The context does not own the model. */
+gko_status gko_context_set_selector(gko_context ctx, gko_mlp model);
 
 /* ---------------------------------------------------------------- errors */
 

@@ -86,6 +86,19 @@ _SIGS = {
     "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
     "gko_cg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_matrix_features": [_vp, ctypes.POINTER(ctypes.c_float)],
+    "gko_autotune_format": [_vp, ctypes.POINTER(_st), ctypes.POINTER(ctypes.c_float)],
+    "gko_select_format": [_vp, _vp, ctypes.POINTER(_st), ctypes.POINTER(ctypes.c_float)],
+    "gko_context_set_selector": [_vp, _vp],
+    "gko_mlp_create": [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(_vp)],
+    "gko_mlp_destroy": [_vp],
+    "gko_mlp_get_params": [_vp, ctypes.POINTER(ctypes.c_float), ctypes.POINTER(ctypes.c_float)],
+    "gko_mlp_fit_normalization": [_vp, _i64, _vp],
+    "gko_mlp_forward": [_vp, _i64, _vp, _vp],
+    "gko_mlp_loss_grad": [_vp, _i64, _vp, _vp, _vp, _vp, _vp],
+    "gko_mlp_train": [_vp, _i64, _vp, _vp, _vp, _i32, ctypes.c_float, _vp],
+    "gko_mlp_save": [_vp, ctypes.c_char_p],
+    "gko_mlp_load": [_vp, ctypes.c_char_p, ctypes.POINTER(_vp)],
     "gko_batch_create_csr": [_vp, _i64, _vp, _vp, _vp, _vp, _vp, _st, ctypes.POINTER(_vp)],
     "gko_batch_destroy": [_vp],
     "gko_batch_cg_solve": [_vp, _vp, _vp, _f64, _i32, _vp, _vp],
@@ -463,3 +476,110 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ----------------------------------------------------------------------------- selector
+N_FEATURES = 32
+N_PARAMS = 6597
+SELECTOR_FORMATS = ("csr", "csr_merge", "coo", "ell", "hybrid")
+
+
+def _fbuf(n):
+    return (ctypes.c_float * n)()
+
+
+def features(A: Matrix) -> np.ndarray:
+    """The 32 structural features of A (float32, host)."""
+    f = _fbuf(N_FEATURES)
+    _check(_lib.gko_matrix_features(A.handle, f))
+    return np.frombuffer(f, dtype=np.float32).copy()
+
+
+def autotune_format(A: Matrix):
+    """Time every format on clones of A.  Returns (best name, float32[5] ms; inf = infeasible)."""
+    best = _st()
+    ms = _fbuf(5)
+    _check(_lib.gko_autotune_format(A.handle, ctypes.byref(best), ms))
+    return FORMAT_NAMES[best.value], np.frombuffer(ms, dtype=np.float32).copy()
+
+
+class Mlp:
+    """The selector network (32 -> 64 -> 64 -> 5), parameters and Adam state on the GPU."""
+
+    def __init__(self, params=None, ctx: Context | None = None, handle=None):
+        self.ctx = ctx or default_context()
+        if handle is not None:
+            self.handle = handle
+            return
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.size != N_PARAMS:
+            raise ValueError("expected %d parameters" % N_PARAMS)
+        h = _vp()
+        _check(_lib.gko_mlp_create(self.ctx.handle, p.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                   ctypes.byref(h)))
+        self.handle = h
+
+    @classmethod
+    def load(cls, path: str, ctx: Context | None = None) -> "Mlp":
+        ctx = ctx or default_context()
+        h = _vp()
+        _check(_lib.gko_mlp_load(ctx.handle, path.encode(), ctypes.byref(h)))
+        return cls(ctx=ctx, handle=h)
+
+    def save(self, path: str):
+        _check(_lib.gko_mlp_save(self.handle, path.encode()))
+
+    def params(self):
+        p, n = _fbuf(N_PARAMS), _fbuf(2 * N_FEATURES)
+        _check(_lib.gko_mlp_get_params(self.handle, p, n))
+        return (np.frombuffer(p, dtype=np.float32).copy(),
+                np.frombuffer(n, dtype=np.float32).copy().reshape(2, N_FEATURES))
+
+    def fit_normalization(self, X):
+        _check(_lib.gko_mlp_fit_normalization(self.handle, X.shape[0], _ptr(X)))
+
+    def forward(self, X):
+        torch = _torch()
+        out = torch.empty((X.shape[0], 5), dtype=torch.float32, device=X.device)
+        _check(_lib.gko_mlp_forward(self.handle, X.shape[0], _ptr(X), _ptr(out)))
+        return out
+
+    def loss_grad(self, X, Y, M):
+        torch = _torch()
+        g = torch.empty(N_PARAMS, dtype=torch.float32, device=X.device)
+        loss = torch.empty((), dtype=torch.float64, device=X.device)
+        _check(_lib.gko_mlp_loss_grad(self.handle, X.shape[0], _ptr(X), _ptr(Y), _ptr(M), _ptr(g),
+                                      _ptr(loss)))
+        return loss, g
+
+    def train(self, X, Y, M, steps: int, lr: float = 1e-3):
+        """Full-batch Adam steps on the GPU; returns the loss before each step (device)."""
+        torch = _torch()
+        hist = torch.empty(steps, dtype=torch.float32, device=X.device)
+        _check(_lib.gko_mlp_train(self.handle, X.shape[0], _ptr(X), _ptr(Y), _ptr(M), steps, lr,
+                                  _ptr(hist)))
+        return hist
+
+    def select(self, A: Matrix):
+        """(format name, float32[5] scores) predicted for A."""
+        f = _st()
+        sc = _fbuf(5)
+        _check(_lib.gko_select_format(A.handle, self.handle, ctypes.byref(f), sc))
+        return FORMAT_NAMES[f.value], np.frombuffer(sc, dtype=np.float32).copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.gko_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def set_selector(model: Mlp | None, ctx: Context | None = None):
+    """Make gko_convert(A, 'auto') on this context ask model (None: time every format)."""
+    ctx = ctx or default_context()
+    _check(_lib.gko_context_set_selector(ctx.handle, None if model is None else model.handle))

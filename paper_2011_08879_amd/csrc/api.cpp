@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <fstream>
 #include <limits>
 #include <stdexcept>
 #include <string>
@@ -17,6 +18,7 @@
 
 #include "batch_kernels.hpp"
 #include "gko.h"
+#include "selector_kernels.hpp"
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
 
@@ -88,6 +90,7 @@ struct gko_context_s {
     gko_solve_info info{};
     double *red_partials = nullptr;  // scratch of gko_dot / gko_norm2
     unsigned *red_ticket = nullptr;
+    struct gko_mlp_s *selector = nullptr;  // used by gko_convert(AUTO) when set
 
     void *alloc_bytes(size_t bytes) {
         if (bytes == 0) bytes = 8;
@@ -802,6 +805,259 @@ void check_batch_solve_args(gko_batch B, const double *b, double *x, double tol,
 
 }  // namespace
 
+// ====================================================================== selector
+struct gko_mlp_s {
+    gko_context ctx = nullptr;
+    float *params = nullptr;  // kMlpParams
+    float *norm = nullptr;    // mean[32], std[32]
+    float *adam_m = nullptr, *adam_v = nullptr;
+    int *step = nullptr;
+    float *grads = nullptr;
+    double *lossp = nullptr, *msum = nullptr;
+    unsigned *ticket = nullptr;
+
+    void free_all() {
+        void *ps[] = {params, norm, adam_m, adam_v, step, grads, lossp, msum, ticket};
+        for (void *p : ps) ctx->free_bytes(p);
+    }
+    mlp_work work() const { return {msum, grads, lossp, ticket, adam_m, adam_v, step}; }
+};
+
+namespace {
+
+constexpr char kMlpMagic[8] = {'G', 'K', 'O', 'M', 'L', 'P', '1', '\0'};
+
+gko_mlp new_mlp(gko_context ctx, const float *params_host, const float *norm_host) {
+    auto M = new gko_mlp_s();
+    M->ctx = ctx;
+    try {
+        hipStream_t s = ctx->stream;
+        M->params = static_cast<float *>(ctx->alloc_bytes(kMlpParams * 4));
+        M->norm = static_cast<float *>(ctx->alloc_bytes(2 * kMlpIn * 4));
+        M->adam_m = static_cast<float *>(ctx->alloc_bytes(kMlpParams * 4));
+        M->adam_v = static_cast<float *>(ctx->alloc_bytes(kMlpParams * 4));
+        M->step = static_cast<int *>(ctx->alloc_bytes(8));
+        M->grads = static_cast<float *>(ctx->alloc_bytes((size_t)kMlpMaxBlocks * kMlpParams * 4));
+        M->lossp = static_cast<double *>(ctx->alloc_bytes(kMlpMaxBlocks * 8));
+        M->msum = static_cast<double *>(ctx->alloc_bytes(8));
+        M->ticket = static_cast<unsigned *>(ctx->alloc_bytes(8));
+        std::vector<float> norm(2 * kMlpIn, 0.0f);
+        if (norm_host) std::copy(norm_host, norm_host + 2 * kMlpIn, norm.begin());
+        else std::fill(norm.begin() + kMlpIn, norm.end(), 1.0f);
+        HIPC(hipMemcpyAsync(M->params, params_host, kMlpParams * 4, hipMemcpyHostToDevice, s));
+        HIPC(hipMemcpyAsync(M->norm, norm.data(), 2 * kMlpIn * 4, hipMemcpyHostToDevice, s));
+        HIPC(hipMemsetAsync(M->adam_m, 0, kMlpParams * 4, s));
+        HIPC(hipMemsetAsync(M->adam_v, 0, kMlpParams * 4, s));
+        HIPC(hipMemsetAsync(M->step, 0, 8, s));
+        HIPC(hipMemsetAsync(M->ticket, 0, 8, s));
+        ctx->sync();
+    } catch (...) {
+        M->free_all();
+        delete M;
+        throw;
+    }
+    return M;
+}
+
+// The 32 features from the row-length histogram and the entry counters; the
+// same definitions as listed in the header (row-length statistics exact from
+// integer counts, ratios and logarithms in FP64, rounded to FP32 at the end).
+void finish_features(int64_t n, int64_t m, int64_t nnz, const std::vector<int> &h,
+                     const unsigned long long *c, float *out) {
+    const int64_t maxl = (int64_t)h.size() - 1;
+    const double dn = (double)n, dnz = nnz > 0 ? (double)nnz : 1.0, dm = m > 0 ? (double)m : 1.0;
+    const double mean = n > 0 ? (double)nnz / dn : 0.0;
+    int64_t minl = 0;
+    while (minl < maxl && h[minl] == 0) ++minl;
+    double var = 0.0;
+    for (int64_t L = 0; L <= maxl; ++L) var += (double)h[L] * ((double)L - mean) * ((double)L - mean);
+    const double sd = n > 0 ? std::sqrt(var / dn) : 0.0;
+    auto pct = [&](int64_t P) {  // smallest L with #rows(len <= L) >= ceil(P n / 100)
+        const int64_t need = (n * P + 99) / 100;
+        int64_t cum = 0;
+        for (int64_t L = 0; L <= maxl; ++L) {
+            cum += h[L];
+            if (cum >= need && need > 0) return (double)L;
+        }
+        return (double)(need > 0 ? maxl : 0);
+    };
+    __int128 wsum = 0;
+    int64_t rank = 0;
+    for (int64_t L = 0; L <= maxl; ++L) {
+        const int64_t cnt = h[L];
+        wsum += (__int128)L * ((__int128)cnt * rank + (__int128)cnt * (cnt + 1) / 2);
+        rank += cnt;
+    }
+    const double gini = (n > 0 && nnz > 0) ? 2.0 * (double)wsum / (dn * (double)nnz) -
+                                                 (double)(n + 1) / dn : 0.0;
+    double ent = 0.0;
+    for (int64_t L = 0; L <= maxl; ++L)
+        if (h[L] > 0) {
+            const double p = (double)h[L] / dn;
+            ent -= p * std::log(p);
+        }
+    int64_t left = (n + 99) / 100, topnnz = 0;
+    for (int64_t L = maxl; L >= 0 && left > 0; --L) {
+        const int64_t take = std::min<int64_t>(left, h[L]);
+        topnnz += take * L;
+        left -= take;
+    }
+    // HYB width (FP64 values) and its tail, from the same histogram
+    int64_t rows_gt = 0, ent_gt = 0, best = 0, best_cost = -1, tail_best = 0;
+    std::vector<int64_t> tail(maxl + 1);
+    for (int64_t K = maxl; K >= 0; --K) {
+        tail[K] = ent_gt - K * rows_gt;
+        rows_gt += h[K];
+        ent_gt += (int64_t)h[K] * K;
+    }
+    for (int64_t K = 0; K <= maxl; ++K) {
+        const int64_t cost = n * K * 12 + 16 * tail[K];
+        if (best_cost < 0 || cost < best_cost) {
+            best_cost = cost;
+            best = K;
+            tail_best = tail[K];
+        }
+    }
+    const double ws = 12.0 * (double)nnz + 4.0 * (double)(n + 1) + 8.0 * (double)m + 8.0 * dn;
+    const double pairs = (double)c[6];
+    double f[kNumFeatures];
+    f[0] = n > 0 ? std::log10(dn) : 0.0;
+    f[1] = std::log10(nnz > 0 ? (double)nnz : 1.0);
+    f[2] = mean;
+    f[3] = sd;
+    f[4] = mean > 0 ? sd / mean : 0.0;
+    f[5] = (double)minl;
+    f[6] = (double)maxl;
+    f[7] = pct(50);
+    f[8] = pct(90);
+    f[9] = pct(99);
+    f[10] = mean > 0 ? (double)maxl / mean : 0.0;
+    f[11] = n > 0 ? (double)h[0] / dn : 0.0;
+    int64_t le4 = 0;
+    for (int64_t L = 0; L <= std::min<int64_t>(4, maxl); ++L) le4 += h[L];
+    f[12] = n > 0 ? (double)le4 / dn : 0.0;
+    f[13] = nnz > 0 ? dn * (double)maxl / (double)nnz : 1.0;
+    f[14] = mean > 0 ? (double)best / mean : 0.0;
+    f[15] = (double)tail_best / dnz;
+    f[16] = gini;
+    f[17] = ent;
+    f[18] = (double)topnnz / dnz;
+    f[19] = std::log10(ws);
+    f[20] = ws / 268435456.0;
+    f[21] = n > 0 ? (double)m / dn : 0.0;
+    f[22] = (double)c[0] / dnz / dm;
+    f[23] = (double)c[1] / dm;
+    f[24] = (double)c[2] / dnz;
+    f[25] = (double)c[3] / dnz;
+    f[26] = (double)c[4] / dnz;
+    f[27] = std::log10(1.0 + (pairs > 0 ? (double)c[5] / pairs : 0.0));
+    f[28] = pairs > 0 ? (double)c[7] / pairs : 0.0;
+    f[29] = (double)c[8] / dnz;
+    f[30] = n == m ? (double)c[9] / dnz : 0.0;
+    f[31] = std::log10(1.0 + (c[11] > 0 ? (double)c[10] / (double)c[11] : 0.0));
+    for (int j = 0; j < kNumFeatures; ++j) out[j] = (float)f[j];
+}
+
+// Features of A into host memory (32 floats).
+void matrix_features(gko_matrix A, float *out) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    dbuf rpb, colb, valb;
+    const int32_t *rp = A->rp, *col = A->col;
+    if (!(A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE)) {
+        rpb = dbuf(c, (A->n + 1) * 4);
+        colb = dbuf(c, A->nnz * 4);
+        valb = dbuf(c, A->nnz * A->vs());
+        export_csr_into(A, own_values(A), rpb.as<int32_t>(), colb.as<int32_t>(), valb.p);
+        rp = rpb.as<int32_t>();
+        col = colb.as<int32_t>();
+    }
+    dbuf ml(c, 4);
+    HIPC(hipMemsetAsync(ml.p, 0, 4, s));
+    HIPC(max_row_len(s, A->n, rp, ml.as<int>()));
+    const int64_t maxl = read_int(c, ml.as<int>());
+    dbuf hist(c, (maxl + 1) * 4), cnt(c, kFeatCounters * 8);
+    HIPC(hipMemsetAsync(hist.p, 0, (maxl + 1) * 4, s));
+    HIPC(hipMemsetAsync(cnt.p, 0, kFeatCounters * 8, s));
+    HIPC(row_len_hist(s, A->n, rp, hist.as<int>(), maxl));
+    HIPC(feature_counts(s, A->n, A->m, rp, col, cnt.as<unsigned long long>()));
+    std::vector<int> h(maxl + 1);
+    unsigned long long cc[kFeatCounters];
+    HIPC(hipMemcpyAsync(h.data(), hist.p, (maxl + 1) * 4, hipMemcpyDeviceToHost, s));
+    HIPC(hipMemcpyAsync(cc, cnt.p, kFeatCounters * 8, hipMemcpyDeviceToHost, s));
+    c->sync();
+    if (A->n == 0) h.assign(1, 0);
+    finish_features(A->n, A->m, A->nnz, h, cc, out);
+}
+
+const gko_format kAllFormats[5] = {GKO_FMT_CSR, GKO_FMT_CSR_MERGE, GKO_FMT_COO, GKO_FMT_ELL,
+                                   GKO_FMT_HYBRID};
+
+// Mean SpMV time of a clone of A in every format (infinity when infeasible);
+// A itself is not changed.
+void time_formats(gko_matrix A, float *ms_out, int reps) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    const size_t vb = A->vs();
+    dbuf x(c, std::max<int64_t>(A->m, 1) * vb), y(c, std::max<int64_t>(A->n, 1) * vb);
+    HIPC(fill_zero(s, A->type(), A->m, x.p));
+    hipEvent_t e0, e1;
+    HIPC(hipEventCreate(&e0));
+    HIPC(hipEventCreate(&e1));
+    try {
+        for (int f = 0; f < 5; ++f) {
+            gko_matrix B = nullptr;
+            if (gko_matrix_clone(A, &B) != GKO_OK) fail(GKO_ERR_ALLOC, g_last_error);
+            try {
+                convert_to(B, kAllFormats[f]);
+            } catch (const api_error &e) {
+                gko_matrix_destroy(B);
+                if (e.status != GKO_ERR_UNSUPPORTED) throw;
+                ms_out[f] = std::numeric_limits<float>::infinity();
+                continue;
+            }
+            spmv_dispatch(B, own_values(B), 1.0, x.p, 0.0, y.p);
+            spmv_dispatch(B, own_values(B), 1.0, x.p, 0.0, y.p);
+            HIPC(hipEventRecord(e0, s));
+            for (int r = 0; r < reps; ++r) spmv_dispatch(B, own_values(B), 1.0, x.p, 0.0, y.p);
+            HIPC(hipEventRecord(e1, s));
+            HIPC(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIPC(hipEventElapsedTime(&ms, e0, e1));
+            ms_out[f] = ms / reps;
+            gko_matrix_destroy(B);
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+}
+
+gko_format select_with(gko_matrix A, gko_mlp model, float *scores) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    float feat[kNumFeatures], sc[kMlpOut];
+    matrix_features(A, feat);
+    dbuf fd(c, kNumFeatures * 4), od(c, kMlpOut * 4);
+    HIPC(hipMemcpyAsync(fd.p, feat, kNumFeatures * 4, hipMemcpyHostToDevice, s));
+    HIPC(mlp_forward(s, 1, fd.as<float>(), model->params, model->norm, od.as<float>()));
+    HIPC(hipMemcpyAsync(sc, od.p, kMlpOut * 4, hipMemcpyDeviceToHost, s));
+    c->sync();
+    const bool ell_ok = ell_feasible(A, (int64_t)feat[6]);
+    int best = -1;
+    for (int f = 0; f < kMlpOut; ++f) {
+        if (scores) scores[f] = sc[f];
+        if (kAllFormats[f] == GKO_FMT_ELL && !ell_ok) continue;
+        if (best < 0 || sc[f] < sc[best]) best = f;
+    }
+    return kAllFormats[best];
+}
+
+}  // namespace
+
 // ====================================================================== C ABI
 extern "C" {
 
@@ -1183,41 +1439,16 @@ gko_status gko_convert(gko_matrix A, gko_format fmt) {
         require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
         require(fmt >= GKO_FMT_CSR && fmt <= GKO_FMT_AUTO, GKO_ERR_INVALID_ARG, "unknown format");
         if (fmt == GKO_FMT_AUTO) {
-            // time one SpMV per feasible format on a scratch x / y, keep the fastest
-            gko_context c = A->ctx;
-            hipStream_t s = c->stream;
-            const size_t vb = A->vs();
-            dbuf x(c, std::max<int64_t>(A->m, 1) * vb), y(c, std::max<int64_t>(A->n, 1) * vb);
-            HIPC(fill_zero(s, A->type(), A->m, x.p));
-            hipEvent_t e0, e1;
-            HIPC(hipEventCreate(&e0));
-            HIPC(hipEventCreate(&e1));
-            gko_format best = A->fmt;
-            float best_ms = std::numeric_limits<float>::infinity();
-            const gko_format cand[5] = {GKO_FMT_CSR, GKO_FMT_CSR_MERGE, GKO_FMT_COO, GKO_FMT_ELL,
-                                        GKO_FMT_HYBRID};
-            for (gko_format f : cand) {
-                try {
-                    convert_to(A, f);
-                } catch (const api_error &e) {
-                    if (e.status == GKO_ERR_UNSUPPORTED) continue;
-                    throw;
-                }
-                spmv_dispatch(A, own_values(A), 1.0, x.p, 0.0, y.p);  // warm-up
-                HIPC(hipEventRecord(e0, s));
-                for (int r = 0; r < 5; ++r) spmv_dispatch(A, own_values(A), 1.0, x.p, 0.0, y.p);
-                HIPC(hipEventRecord(e1, s));
-                HIPC(hipEventSynchronize(e1));
-                float ms = 0.f;
-                HIPC(hipEventElapsedTime(&ms, e0, e1));
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = f;
-                }
+            if (A->ctx->selector) {
+                convert_to(A, select_with(A, A->ctx->selector, nullptr));
+            } else {
+                float ms[5];
+                time_formats(A, ms, 5);
+                int best = 0;
+                for (int f = 1; f < 5; ++f)
+                    if (ms[f] < ms[best]) best = f;
+                convert_to(A, kAllFormats[best]);
             }
-            (void)hipEventDestroy(e0);
-            (void)hipEventDestroy(e1);
-            convert_to(A, best);
             return;
         }
         convert_to(A, fmt);
@@ -1253,6 +1484,152 @@ gko_status gko_stream(gko_context ctx, gko_stream_op op, int64_t n, const double
         require(n >= 0 && (n == 0 || (a && c && (op == GKO_STREAM_COPY || b))), GKO_ERR_INVALID_ARG,
                 "bad arrays");
         HIPC(stream_op(ctx->stream, (int)op, n, a, b, s, c));
+    });
+}
+
+gko_status gko_matrix_features(gko_matrix A, float *features) {
+    return guarded([&] {
+        require(A && features, GKO_ERR_INVALID_ARG, "null matrix or output");
+        matrix_features(A, features);
+    });
+}
+
+gko_status gko_autotune_format(gko_matrix A, gko_format *best, float *times_ms) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        float ms[5];
+        time_formats(A, ms, 5);
+        int b = 0;
+        for (int f = 0; f < 5; ++f) {
+            if (times_ms) times_ms[f] = ms[f];
+            if (ms[f] < ms[b]) b = f;
+        }
+        if (best) *best = kAllFormats[b];
+    });
+}
+
+gko_status gko_select_format(gko_matrix A, gko_mlp model, gko_format *out, float *scores) {
+    return guarded([&] {
+        require(A && model && out, GKO_ERR_INVALID_ARG, "null matrix, model or output");
+        require(model->ctx == A->ctx, GKO_ERR_INVALID_ARG, "model and matrix belong to different contexts");
+        *out = select_with(A, model, scores);
+    });
+}
+
+gko_status gko_context_set_selector(gko_context ctx, gko_mlp model) {
+    return guarded([&] {
+        require(ctx != nullptr, GKO_ERR_INVALID_ARG, "null context");
+        require(!model || model->ctx == ctx, GKO_ERR_INVALID_ARG, "model from another context");
+        ctx->selector = model;
+    });
+}
+
+gko_status gko_mlp_create(gko_context ctx, const float *params, gko_mlp *out) {
+    return guarded([&] {
+        require(ctx && params && out, GKO_ERR_INVALID_ARG, "null context, params or output");
+        *out = new_mlp(ctx, params, nullptr);
+    });
+}
+
+gko_status gko_mlp_destroy(gko_mlp M) {
+    return guarded([&] {
+        if (!M) return;
+        if (M->ctx->selector == M) M->ctx->selector = nullptr;
+        M->free_all();
+        delete M;
+    });
+}
+
+gko_status gko_mlp_get_params(gko_mlp M, float *params, float *norm) {
+    return guarded([&] {
+        require(M != nullptr, GKO_ERR_INVALID_ARG, "null model");
+        hipStream_t s = M->ctx->stream;
+        if (params) HIPC(hipMemcpyAsync(params, M->params, kMlpParams * 4, hipMemcpyDeviceToHost, s));
+        if (norm) HIPC(hipMemcpyAsync(norm, M->norm, 2 * kMlpIn * 4, hipMemcpyDeviceToHost, s));
+        M->ctx->sync();
+    });
+}
+
+gko_status gko_mlp_fit_normalization(gko_mlp M, int64_t n, const float *X) {
+    return guarded([&] {
+        require(M && (n == 0 || X) && n >= 0, GKO_ERR_INVALID_ARG, "bad arguments");
+        HIPC(mlp_norm_fit(M->ctx->stream, n, X, M->norm));
+    });
+}
+
+gko_status gko_mlp_forward(gko_mlp M, int64_t n, const float *X, float *out) {
+    return guarded([&] {
+        require(M && n >= 0 && (n == 0 || (X && out)), GKO_ERR_INVALID_ARG, "bad arguments");
+        HIPC(mlp_forward(M->ctx->stream, n, X, M->params, M->norm, out));
+    });
+}
+
+gko_status gko_mlp_loss_grad(gko_mlp M, int64_t n, const float *X, const float *Y, const float *mask,
+                             float *grad, double *loss) {
+    return guarded([&] {
+        require(M && n > 0 && X && Y && mask && grad && loss, GKO_ERR_INVALID_ARG, "bad arguments");
+        hipStream_t s = M->ctx->stream;
+        HIPC(mlp_mask_sum(s, n * kMlpOut, mask, M->msum));
+        HIPC(mlp_grad(s, M->work(), n, X, Y, mask, M->params, M->norm, grad, loss, false, 0.f, nullptr));
+    });
+}
+
+gko_status gko_mlp_train(gko_mlp M, int64_t n, const float *X, const float *Y, const float *mask,
+                         int32_t steps, float lr, float *loss_history) {
+    return guarded([&] {
+        require(M && n > 0 && X && Y && mask && steps >= 0 && lr > 0.f, GKO_ERR_INVALID_ARG,
+                "bad arguments");
+        hipStream_t s = M->ctx->stream;
+        HIPC(mlp_mask_sum(s, n * kMlpOut, mask, M->msum));
+        int step0 = read_int(M->ctx, M->step);
+        float *hist = loss_history;
+        for (int32_t k = 0; k < steps; ++k)
+            HIPC(mlp_grad(s, M->work(), n, X, Y, mask, M->params, M->norm, nullptr, nullptr, true, lr,
+                          hist ? hist - step0 : nullptr));
+        M->ctx->sync();
+    });
+}
+
+gko_status gko_mlp_save(gko_mlp M, const char *path) {
+    return guarded([&] {
+        require(M && path, GKO_ERR_INVALID_ARG, "null model or path");
+        std::vector<float> p(kMlpParams), nrm(2 * kMlpIn);
+        HIPC(hipMemcpyAsync(p.data(), M->params, kMlpParams * 4, hipMemcpyDeviceToHost, M->ctx->stream));
+        HIPC(hipMemcpyAsync(nrm.data(), M->norm, 2 * kMlpIn * 4, hipMemcpyDeviceToHost, M->ctx->stream));
+        M->ctx->sync();
+        std::ofstream f(path, std::ios::binary);
+        require((bool)f, GKO_ERR_INVALID_ARG, std::string("cannot write ") + path);
+        const int32_t version = 1, np = kMlpParams;
+        char arch[16] = "gfx950";
+        f.write(kMlpMagic, 8);
+        f.write(reinterpret_cast<const char *>(&version), 4);
+        f.write(reinterpret_cast<const char *>(&np), 4);
+        f.write(arch, 16);
+        f.write(reinterpret_cast<const char *>(nrm.data()), nrm.size() * 4);
+        f.write(reinterpret_cast<const char *>(p.data()), p.size() * 4);
+        require((bool)f, GKO_ERR_INVALID_ARG, std::string("write failed: ") + path);
+    });
+}
+
+gko_status gko_mlp_load(gko_context ctx, const char *path, gko_mlp *out) {
+    return guarded([&] {
+        require(ctx && path && out, GKO_ERR_INVALID_ARG, "null context, path or output");
+        *out = nullptr;
+        std::ifstream f(path, std::ios::binary);
+        require((bool)f, GKO_ERR_INVALID_ARG, std::string("cannot read ") + path);
+        char magic[8], arch[16];
+        int32_t version = 0, np = 0;
+        f.read(magic, 8);
+        f.read(reinterpret_cast<char *>(&version), 4);
+        f.read(reinterpret_cast<char *>(&np), 4);
+        f.read(arch, 16);
+        require((bool)f && std::memcmp(magic, kMlpMagic, 8) == 0 && version == 1 && np == kMlpParams,
+                GKO_ERR_INVALID_ARG, "not a model file of this library");
+        std::vector<float> nrm(2 * kMlpIn), p(kMlpParams);
+        f.read(reinterpret_cast<char *>(nrm.data()), nrm.size() * 4);
+        f.read(reinterpret_cast<char *>(p.data()), p.size() * 4);
+        require((bool)f, GKO_ERR_INVALID_ARG, "truncated model file");
+        *out = new_mlp(ctx, p.data(), nrm.data());
     });
 }
 
