@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
+    ap.add_argument("--selector-matrices", type=int, default=400,
+                    help="corpus size of the learned-selector leg (0 skips it)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the SpMV sweep (profiling the solvers alone)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
@@ -424,6 +426,17 @@ def main():
 
     if not args.no_solvers:
         result["solvers"] = run_solvers(g, gen, torch)
+    if args.selector_matrices > 0:
+        import paper_2011_08879_amd.selector as sel
+        t0 = time.time()
+        res, model = sel.run(n_matrices=args.selector_matrices, n_lo=1e4, n_hi=1e6, steps=3000,
+                             lr=3e-3, workers=8, log=log)
+        res["wall_s"] = round(time.time() - t0, 1)
+        result["selector"] = res
+        log("selector (%d matrices): test regret %.3f (CSR alone %.3f), gain vs CSR %.3f" %
+            (args.selector_matrices, res["test"]["regret_total"], res["test"]["csr_regret_total"],
+             res["test"]["gain_vs_csr_total"]))
+        model.close()
     if not args.no_cpu and inputs is not None:
         log("cpu baseline (oracle, 1 core) ...")
         result["cpu_baseline"] = cpu_baseline(inputs)

@@ -340,10 +340,14 @@ __global__ void mask_sum_kernel(int64_t count, const float *__restrict__ M, doub
 // Per-feature mean and standard deviation (population), std floored at 1e-6.
 __global__ void norm_fit_kernel(int64_t n, const float *__restrict__ X, float *__restrict__ norm) {
     __shared__ double red[256 / kWave];
+    __shared__ double s_mean;
     for (int k = 0; k < NI; ++k) {
         double s = 0.0;
         for (int64_t i = threadIdx.x; i < n; i += 256) s += (double)X[i * NI + k];
-        const double mean = block_sum<256>(s, red) / (double)(n > 0 ? n : 1);
+        s = block_sum<256>(s, red);   // valid in thread 0
+        if (threadIdx.x == 0) s_mean = s / (double)(n > 0 ? n : 1);
+        __syncthreads();
+        const double mean = s_mean;
         double v = 0.0;
         for (int64_t i = threadIdx.x; i < n; i += 256) {
             const double d = (double)X[i * NI + k] - mean;
@@ -355,6 +359,7 @@ __global__ void norm_fit_kernel(int64_t n, const float *__restrict__ X, float *_
             const double sd = sqrt(var);
             norm[NI + k] = (float)(sd > 1e-6 ? sd : 1e-6);
         }
+        __syncthreads();   // s_mean is rewritten for the next feature
     }
 }
 
