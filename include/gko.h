@@ -183,6 +183,10 @@ typedef struct gko_solver_opts {
     double inner_tol;    /* MIXED_IR: inner relative tolerance (default 1e-5) */
     int32_t max_inner;   /* MIXED_IR: inner iteration cap per outer step (default 1000) */
     int32_t max_outer;   /* MIXED_IR: outer step cap (default 20) */
+    int32_t single_workgroup; /* 1 (default): FP64 unpreconditioned CG on a CSR matrix whose
+                                 direction vector fits in one workgroup's LDS (n up to 8192 on
+                                 gfx950) runs as one launch on one workgroup; 0: always the
+                                 multi-kernel path.  Same steps and stopping test either way. */
 } gko_solver_opts;
 
 typedef struct gko_solve_info {

@@ -54,7 +54,7 @@ class _MatrixDesc(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("precond", _i32), ("block_size", _i32),
                 ("check_every", _i32), ("inner_tol", _f64), ("max_inner", _i32),
-                ("max_outer", _i32)]
+                ("max_outer", _i32), ("single_workgroup", _i32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -200,8 +200,9 @@ class Context:
 
     def set_solver_opts(self, precision: int = PREC_FP64, precond: int = PRECOND_NONE,
                         block_size: int = 8, check_every: int = 16, inner_tol: float = 1e-5,
-                        max_inner: int = 1000, max_outer: int = 20):
-        o = SolverOpts(precision, precond, block_size, check_every, inner_tol, max_inner, max_outer)
+                        max_inner: int = 1000, max_outer: int = 20, single_workgroup: int = 1):
+        o = SolverOpts(precision, precond, block_size, check_every, inner_tol, max_inner, max_outer,
+                       single_workgroup)
         _check(_lib.gko_context_set_solver_opts(self.handle, ctypes.byref(o)))
 
     def solver_opts(self) -> dict:

@@ -74,6 +74,7 @@ gko_solver_opts default_opts() {
     o.inner_tol = 1e-5;
     o.max_inner = 1000;
     o.max_outer = 20;
+    o.single_workgroup = 1;
     return o;
 }
 
@@ -91,6 +92,7 @@ struct gko_context_s {
     double *red_partials = nullptr;  // scratch of gko_dot / gko_norm2
     unsigned *red_ticket = nullptr;
     struct gko_mlp_s *selector = nullptr;  // used by gko_convert(AUTO) when set
+    int64_t small_cg_rows = -1;            // single-workgroup CG limit, queried once
 
     void *alloc_bytes(size_t bytes) {
         if (bytes == 0) bytes = 8;
@@ -1646,6 +1648,8 @@ gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *o
         require(o->check_every >= 1, GKO_ERR_INVALID_ARG, "check_every must be >= 1");
         require(o->inner_tol > 0.0 && o->inner_tol < 1.0, GKO_ERR_INVALID_ARG, "inner_tol in (0,1)");
         require(o->max_inner >= 1 && o->max_outer >= 1, GKO_ERR_INVALID_ARG, "iteration caps >= 1");
+        require(o->single_workgroup == 0 || o->single_workgroup == 1, GKO_ERR_INVALID_ARG,
+                "single_workgroup must be 0 or 1");
         ctx->opts = *o;
     });
 }
@@ -1674,6 +1678,27 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
         c->info = gko_solve_info{};
         const gko_solver_opts o = c->opts;
         const int64_t n = A->n;
+        if (c->small_cg_rows < 0) c->small_cg_rows = small_cg_max_rows();
+        const bool single = o.single_workgroup && o.precision == GKO_PREC_FP64 &&
+                            o.precond == GKO_PRECOND_NONE && n > 0 && n <= c->small_cg_rows &&
+                            (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE);
+        if (single) {
+            dbuf res(c, sizeof(small_cg_result));
+            HIPC(small_cg(c->stream, n, A->rp, A->col, static_cast<const double *>(A->val),
+                          static_cast<const double *>(b), static_cast<double *>(x), tol, maxit,
+                          res.as<small_cg_result>()));
+            small_cg_result h{};
+            HIPC(hipMemcpyAsync(&h, res.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+            c->sync();
+            st = h.bb == 0.0 ? GKO_OK : flag_status(h.flag);
+            c->info.iterations = h.iters;
+            c->info.restarts = h.restarts;
+            c->info.rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+            c->info.true_rel_residual = h.bb > 0 ? std::sqrt(h.tr2 / h.bb) : 0.0;
+            c->info.status = st;
+            c->info.seconds = now_seconds() - t0;
+            return;
+        }
         // ||b|| decides the trivial cases before any iteration
             dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
         HIPC(hipMemsetAsync(ticket.p, 0, 8, c->stream));

@@ -31,8 +31,8 @@ __device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int32_t k = b[u] + lane;
-        c[u] = k < e[u] ? col[k] : -1;
-        v[u] = k < e[u] ? val[k] : V(0);
+        c[u] = k < e[u] ? load_stream(col + k) : -1;
+        v[u] = k < e[u] ? load_stream(val + k) : V(0);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) s[u] = c[u] >= 0 ? v[u] * x[c[u]] : V(0);
@@ -45,8 +45,8 @@ __device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int32_t kj = k + j * W;
-                cc[j] = kj < e[u] ? col[kj] : -1;
-                vv[j] = kj < e[u] ? val[kj] : V(0);
+                cc[j] = kj < e[u] ? load_stream(col + kj) : -1;
+                vv[j] = kj < e[u] ? load_stream(val + kj) : V(0);
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j)

@@ -10,6 +10,14 @@ namespace gko {
 constexpr int kWave = 64;
 using lane_mask = uint64_t;
 
+// Load of a matrix stream (values, indices) that is read once per product:
+// the non-temporal hint lets the caches drop these lines first, so the
+// gathered vector x keeps its place in L2.
+template <typename T>
+__device__ __forceinline__ T load_stream(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
 // ------------------------------------------------------------------ subwarps
 // Contiguous subwarps of Size lanes (a power of two <= 64) inside a wavefront,
 // as in Sec. 4 (cooperative groups): Rank = tid % Size, LaneOffset =
@@ -37,6 +45,58 @@ struct subwarp {
         return v;
     }
 };
+
+
+// ------------------------------------------------------------------ wave scans
+// Inclusive segmented sum over the 64 lanes of a wavefront whose keys do not
+// decrease with the lane index: afterwards each lane holds the sum of the
+// values of all lanes at or below it with the same key.  Hillis-Steele steps
+// over DPP lane moves (no LDS): row shifts by 1, 2, 4, 8 inside each row of
+// 16 lanes, then the broadcast of lane 15 of each row into the next row and
+// of lane 31 into rows 2 and 3.  A lane without a source reads key -7, which
+// no row index equals, so it adds nothing.  The combination order is fixed.
+namespace dpp {
+constexpr int kRowShr1 = 0x111, kRowShr2 = 0x112, kRowShr4 = 0x114, kRowShr8 = 0x118;
+constexpr int kRowBcast15 = 0x142, kRowBcast31 = 0x143;
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int move(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(double &p, int key) {
+    const int k = move<CTRL, ROWS>(-7, key);
+    const int lo = move<CTRL, ROWS>(0, __double2loint(p));
+    const int hi = move<CTRL, ROWS>(0, __double2hiint(p));
+    if (k == key) p += __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void seg_step(float &p, int key) {
+    const int k = move<CTRL, ROWS>(-7, key);
+    const int v = move<CTRL, ROWS>(0, __float_as_int(p));
+    if (k == key) p += __int_as_float(v);
+}
+}  // namespace dpp
+
+template <typename T>
+__device__ __forceinline__ void wave_segmented_scan(T &p, int key) {
+    dpp::seg_step<dpp::kRowShr1, 0xf>(p, key);
+    dpp::seg_step<dpp::kRowShr2, 0xf>(p, key);
+    dpp::seg_step<dpp::kRowShr4, 0xf>(p, key);
+    dpp::seg_step<dpp::kRowShr8, 0xf>(p, key);
+    dpp::seg_step<dpp::kRowBcast15, 0xa>(p, key);  // rows 1 and 3
+    dpp::seg_step<dpp::kRowBcast31, 0xc>(p, key);  // rows 2 and 3
+}
+
+// Value of lane l (uniform across the wave) without an LDS round trip.
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_value(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
 
 __device__ inline int popcnt(uint32_t m) { return __popc(m); }
 __device__ inline int popcnt(uint64_t m) { return __popcll(m); }

@@ -11,6 +11,23 @@ namespace gko {
 
 hipError_t scalars_reset(hipStream_t s, krylov_scalars *sc, int32_t maxit);
 
+// Single-workgroup CG for small FP64 CSR systems (small_cg.hip): the whole
+// solve in one launch.  x: initial guess in, solution out.
+struct small_cg_result {
+    double bb;         // b.b
+    double rr;         // recursive r.r at exit
+    double tr2;        // true ||b - A x||^2 at exit
+    int32_t iters;     // iterations over all restarts
+    int32_t flag;      // solver_flag
+    int32_t restarts;  // true-residual restarts
+    int32_t pad;
+};
+// Largest n the device's LDS allows (0 when the device cannot be queried).
+int64_t small_cg_max_rows();
+hipError_t small_cg(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
+                    const double *val, const double *b, double *x, double tol, int32_t maxit,
+                    small_cg_result *out);
+
 // CG / PCG.  bs = 0: no preconditioner (z aliases r); bs in {1,2,4,8,16}:
 // block-Jacobi with explicit inverse blocks `inv` (values of type t).
 hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,

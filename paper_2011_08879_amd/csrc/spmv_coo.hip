@@ -4,8 +4,10 @@
 // the paper's solvers use it (Sec. 6.2).  Each wavefront owns an equal chunk
 // of entries, so the work split ignores row lengths.  Within a chunk the
 // wave takes 64 entries at a time with coalesced loads and combines products
-// of equal row by a segmented inclusive scan over the lanes (keys are sorted,
-// so a shuffle partner with the same key means every lane between has it).
+// of equal row by a segmented inclusive scan over the lanes, done with DPP
+// lane moves (keys are sorted, so a partner lane with the same key means
+// every lane between has it); the values the next batch needs from lane 63
+// are read with readlane, so a batch touches no LDS.
 // Rows wholly inside a chunk are written directly; a row cut by a chunk
 // boundary leaves partials (head of the next chunk, tail of this one) that a
 // second kernel adds in ascending chunk order.  Results are bitwise
@@ -55,9 +57,9 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
         for (int j = 0; j < kCooHoist; ++j) {
             const int64_t k = base + j * kWave + lane;
             const bool valid = k < ce;
-            rb[j] = valid ? row[k] : INT_MAX;
-            cb_[j] = valid ? col[k] : -1;
-            vb[j] = valid ? val[k] : V(0);
+            rb[j] = valid ? load_stream(row + k) : INT_MAX;
+            cb_[j] = valid ? load_stream(col + k) : -1;
+            vb[j] = valid ? load_stream(val + k) : V(0);
         }
 #pragma unroll
         for (int j = 0; j < kCooHoist; ++j) pb[j] = cb_[j] >= 0 ? vb[j] * x[cb_[j]] : V(0);
@@ -79,18 +81,13 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
                     for (int32_t e = rprev + 1; e < r; ++e) y[e] = combine(alpha, beta, V(0), y[e], false);
             }
 
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-                const V pu = __shfl_up(p, off);
-                const int32_t ru = __shfl_up(r, off);
-                if (lane >= off && ru == r) p += pu;
-            }
+            wave_segmented_scan(p, r);
             if (r == carry_row) p += carry;
 
             // A lane ends its row's segment when the next entry (in this batch,
             // or the first of the next batch of this chunk) has another row.
             const bool more = bbase + kWave < ce;
-            const int32_t next_first = (j + 1 < kCooHoist) ? __shfl(rb[(j + 1) % kCooHoist], 0)
+            const int32_t next_first = (j + 1 < kCooHoist) ? lane_value(rb[(j + 1) % kCooHoist], 0)
                                                            : ((lane == kWave - 1 && more) ? row[k + 1] : -2);
             int32_t rn = __shfl_down(r, 1);
             if (lane == kWave - 1) rn = more ? next_first : -2;
@@ -101,9 +98,9 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
                 else y[r] = combine(alpha, beta, p, ACC || beta != V(0) ? y[r] : V(0), ACC);
             }
             // a row still open at the batch end carries into the next batch
-            carry_row = __shfl(seg_end ? -1 : r, kWave - 1);
-            carry = __shfl(p, kWave - 1);
-            prev_row = __shfl(r, kWave - 1);
+            carry_row = lane_value(seg_end ? -1 : r, kWave - 1);
+            carry = lane_value(p, kWave - 1);
+            prev_row = lane_value(r, kWave - 1);
         }
     }
     if (!ACC && ce == nnz)  // rows after the last entry

@@ -63,8 +63,8 @@ __global__ __launch_bounds__(kLongBlock) void spmv_csr_long_kernel(
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int32_t kj = k + j * kLongBlock;
-            cc[j] = kj < e ? col[kj] : -1;
-            vv[j] = kj < e ? val[kj] : V(0);
+            cc[j] = kj < e ? load_stream(col + kj) : -1;
+            vv[j] = kj < e ? load_stream(val + kj) : V(0);
         }
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -167,11 +167,15 @@ hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int
 // (merge_partition).  Inside a tile the entries' products are staged in LDS
 // with coalesced loads, each thread walks IPT items of the merge
 // sequentially, and rows that cross thread boundaries are combined by a
-// segmented scan of the threads' carry-outs.  Rows crossing tile boundaries
+// segmented scan of the threads' carry-outs (a DPP scan inside each wave,
+// then the wave totals).  Small tiles (4 items per thread) keep many
+// workgroups resident, so loads of some overlap the walks of others.  The
+// staged products are padded by one slot per 8, so the threads' walks, which
+// start about IPT entries apart, fall into different LDS banks.  Rows crossing tile boundaries
 // leave a carry per tile, added by a second kernel in ascending tile order,
 // so results are bitwise repeatable.
 constexpr int kMergeBlock = 256;
-constexpr int kMergeIpt = 8;
+constexpr int kMergeIpt = 4;
 constexpr int kMergeTile = kMergeBlock * kMergeIpt;
 
 int64_t merge_tiles(int64_t n, int64_t nnz) { return (n + nnz + kMergeTile - 1) / kMergeTile; }
@@ -205,7 +209,7 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const int32_t *__restrict__ part, const V *__restrict__ x, V alpha,
     V beta, V *__restrict__ y, int32_t *__restrict__ carry_row, V *__restrict__ carry_val) {
-    __shared__ V prods[kMergeTile];
+    __shared__ V prods[kMergeTile + kMergeTile / 8];  // entry t at t + t / 8
     __shared__ int32_t rend[kMergeTile + 1];
     __shared__ int32_t s_row[kMergeBlock];
     __shared__ V s_val[kMergeBlock];
@@ -225,13 +229,13 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
         for (int j = 0; j < kMergeIpt; ++j) {
             const int t = tid + j * kMergeBlock;
             const bool ok = t < nk;
-            c[j] = ok ? col[k0 + t] : 0;
-            v[j] = ok ? val[k0 + t] : V(0);
+            c[j] = ok ? load_stream(col + k0 + t) : 0;
+            v[j] = ok ? load_stream(val + k0 + t) : V(0);
         }
 #pragma unroll
         for (int j = 0; j < kMergeIpt; ++j) {
             const int t = tid + j * kMergeBlock;
-            if (t < nk) prods[t] = v[j] * x[c[j]];
+            if (t < nk) prods[t + (t >> 3)] = v[j] * x[c[j]];
         }
     }
     for (int t = tid; t <= nrows; t += kMergeBlock)
@@ -258,7 +262,7 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
     // consumed; the explicit bounds only keep every access in range.
     for (int step = d; step < dend && i <= nrows; ++step) {
         if (k < rend[i] && k < nk) {
-            acc += prods[k];
+            acc += prods[k + (k >> 3)];
             ++k;
         } else {
             const int64_t r = (int64_t)i0 + i;
@@ -274,15 +278,27 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
     }
 
     // Carry-out of each thread: its partial of the row it stops in.  Inclusive
-    // segmented scan over threads (keys are non-decreasing row indices).
-    s_row[tid] = i;
-    s_val[tid] = acc;
-    __syncthreads();
-    for (int off = 1; off < kMergeBlock; off <<= 1) {
-        V add = V(0);
-        if (tid >= off && s_row[tid - off] == s_row[tid]) add = s_val[tid - off];
+    // segmented scan over threads (keys are non-decreasing row indices): a
+    // wave scan, then each thread adds the totals of the preceding waves that
+    // end in its row, nearest first, stopping at a wave that starts in
+    // another row.
+    {
+        __shared__ int32_t w_first[kMergeBlock / kWave], w_last[kMergeBlock / kWave];
+        __shared__ V w_tot[kMergeBlock / kWave];
+        V sv = acc;
+        const int sr = i;
+        wave_segmented_scan(sv, sr);
+        const int wv = tid / kWave, ln = tid % kWave;
+        if (ln == kWave - 1) { w_last[wv] = sr; w_tot[wv] = sv; }
+        if (ln == 0) w_first[wv] = sr;
         __syncthreads();
-        s_val[tid] += add;
+        for (int q = wv - 1; q >= 0; --q) {
+            if (w_last[q] != sr) break;
+            sv += w_tot[q];
+            if (w_first[q] != sr) break;
+        }
+        s_row[tid] = sr;
+        s_val[tid] = sv;
         __syncthreads();
     }
 

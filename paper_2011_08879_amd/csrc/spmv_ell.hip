@@ -24,10 +24,10 @@ __global__ __launch_bounds__(kEllBlock) void spmv_ell_kernel(int64_t n, int64_t 
     int64_t j = 0;
     // four slots per step, loads issued before use
     for (; j + 4 <= K; j += 4) {
-        const int32_t c0 = c[(j + 0) * ld], c1 = c[(j + 1) * ld];
-        const int32_t c2 = c[(j + 2) * ld], c3 = c[(j + 3) * ld];
-        const V v0 = v[(j + 0) * ld], v1 = v[(j + 1) * ld];
-        const V v2 = v[(j + 2) * ld], v3 = v[(j + 3) * ld];
+        const int32_t c0 = load_stream(c + (j + 0) * ld), c1 = load_stream(c + (j + 1) * ld);
+        const int32_t c2 = load_stream(c + (j + 2) * ld), c3 = load_stream(c + (j + 3) * ld);
+        const V v0 = load_stream(v + (j + 0) * ld), v1 = load_stream(v + (j + 1) * ld);
+        const V v2 = load_stream(v + (j + 2) * ld), v3 = load_stream(v + (j + 3) * ld);
         if (c0 >= 0) s += v0 * x[c0];
         if (c1 >= 0) s += v1 * x[c1];
         if (c2 >= 0) s += v2 * x[c2];

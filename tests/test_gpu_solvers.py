@@ -29,13 +29,17 @@ def kappa_laplace2d(N):
     return (4 + 4 * math.cos(math.pi / (N + 1))) / (4 - 4 * math.cos(math.pi / (N + 1)))
 
 
-@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "ell", "hybrid"])
-def test_cg_config1_matches_oracle(g, orc, gen_mod, ctx, fmt):
+@pytest.mark.parametrize("fmt,single", [("csr", 1), ("csr", 0), ("csr_merge", 1), ("coo", 1),
+                                        ("ell", 1), ("hybrid", 1)])
+def test_cg_config1_matches_oracle(g, orc, gen_mod, ctx, fmt, single):
+    """single = 1: CSR systems this small run on one workgroup in one launch;
+    single = 0 and the other formats: the multi-kernel path."""
     N = 64
     A = gen_mod.laplace2d(N)
     xs = gen_mod.uniform(2, N * N)
     b = orc.spmv(A, xs)
     rc, xo, info_o = orc.cg(A, b, tol=1e-10)
+    ctx.set_solver_opts(single_workgroup=single)
     M = g.Matrix.from_csr(*A).convert(fmt)
     x = dev(np.zeros(N * N))
     info = g.cg(M, dev(b), x, tol=1e-10, maxit=5000)
@@ -56,7 +60,7 @@ def test_cg_check_every_does_not_change_iterates(g, orc, gen_mod, ctx):
     M = g.Matrix.from_csr(*A)
     outs = []
     for ce in (1, 7, 50):
-        ctx.set_solver_opts(check_every=ce)
+        ctx.set_solver_opts(check_every=ce, single_workgroup=0)
         x = dev(np.zeros(1024))
         info = g.cg(M, dev(b), x, tol=1e-10)
         outs.append((info["iterations"], host(x).view(np.int64)))
@@ -144,8 +148,9 @@ def test_bicgstab_convdiff(g, orc, gen_mod, ctx):
         assert abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 10)
 
 
-def test_solver_statuses(g, gen_mod, ctx):
-    import torch
+@pytest.mark.parametrize("single", [1, 0])
+def test_solver_statuses(g, gen_mod, ctx, single):
+    ctx.set_solver_opts(single_workgroup=single)
     A = gen_mod.laplace1d(20)
     M = g.Matrix.from_csr(*A)
     x = dev(np.ones(20))
@@ -169,6 +174,46 @@ def test_solver_statuses(g, gen_mod, ctx):
     S = g.Matrix.from_csr(np.array([0, 1, 1, 2], np.int32), np.array([0, 2], np.int32), np.ones(2))
     ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=4)
     assert g.cg(S, dev(np.ones(3)), dev(np.zeros(3)))["status"] == g.ERR_BREAKDOWN
+
+
+def test_single_workgroup_cg_size_limits(g, orc, gen_mod, ctx):
+    """The largest 2D Laplacian the one-workgroup path takes (90^2 = 8100 rows,
+    8 rows per thread) and one just above it (91^2, multi-kernel path) both
+    meet the oracle; the two paths agree on the iteration count within the
+    rounding slack of the stopping test."""
+    for N in (90, 91):
+        A = gen_mod.laplace2d(N)
+        n = N * N
+        b = orc.spmv(A, gen_mod.uniform(2, n))
+        rc, xo, info_o = orc.cg(A, b, tol=1e-10)
+        M = g.Matrix.from_csr(*A)
+        for single in (1, 0):
+            ctx.set_solver_opts(single_workgroup=single)
+            x = dev(np.zeros(n))
+            info = g.cg(M, dev(b), x, tol=1e-10, maxit=5000)
+            assert info["status"] == g.OK, (N, single, info)
+            assert abs(info["iterations"] - info_o["iters"]) <= 2, (N, single, info, info_o)
+            xg = host(x)
+            assert np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b) <= 1e-10
+            assert info["true_rel_residual"] <= 1e-10
+
+
+def test_single_workgroup_cg_nonzero_guess_and_repeatable(g, orc, gen_mod, ctx):
+    """x on entry is the initial guess; two identical solves agree bitwise."""
+    A = gen_mod.laplace2d(40)
+    n = 1600
+    b = orc.spmv(A, gen_mod.uniform(2, n))
+    x0 = gen_mod.uniform(11, n)
+    rc, xo, info_o = orc.cg(A, b, tol=1e-10, x0=x0)
+    M = g.Matrix.from_csr(*A)
+    outs = []
+    for _ in range(2):
+        x = dev(x0.copy())
+        info = g.cg(M, dev(b), x, tol=1e-10)
+        assert info["status"] == g.OK
+        assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+        outs.append(host(x).view(np.int64))
+    assert np.array_equal(outs[0], outs[1])
 
 
 def test_dot_norm(g, orc, gen_mod):
