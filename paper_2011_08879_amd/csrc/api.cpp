@@ -167,6 +167,7 @@ struct gko_matrix_s {
     int32_t *trow = nullptr, *tcol = nullptr;
     void *tval = nullptr;
     int subwarp = 1;
+    int64_t max_len = -1;           // longest row (a property of the matrix), -1 until needed
     int64_t n_long = 0;             // CSR rows handled by a workgroup each
     int32_t *long_rows = nullptr;
     void *carry_a = nullptr, *carry_b = nullptr;  // merge / COO carries
@@ -556,14 +557,18 @@ void ensure_block_jacobi(gko_matrix A, int bs, bool need32) {
         }
         if (read_int(c, err.as<int>()))
             fail(GKO_ERR_BREAKDOWN, "block-Jacobi: a diagonal block is singular");
-        A->bj64 = inv.as<double>();
-        inv.release();
+        const int64_t packed = nb * (bs * (bs + 1) / 2);
+        dbuf up(c, packed * 8);
+        HIPC(bj_pack_upper(s, nb, bs, inv.as<double>(), up.as<double>()));
+        c->sync();  // the full inverse is freed on return
+        A->bj64 = up.as<double>();
+        up.release();
         A->bj_bs = bs;
     }
     if (need32 && !A->bj32) {
-        const int64_t nb = (A->n + bs - 1) / bs;
-        A->bj32 = static_cast<float *>(c->alloc_bytes(nb * bs * bs * 4));
-        HIPC(cast_values(s, vt::f64, vt::f32, nb * bs * bs, A->bj64, A->bj32));
+        const int64_t packed = (A->n + bs - 1) / bs * (bs * (bs + 1) / 2);
+        A->bj32 = static_cast<float *>(c->alloc_bytes(packed * 4));
+        HIPC(cast_values(s, vt::f64, vt::f32, packed, A->bj64, A->bj32));
     }
 }
 
@@ -1347,6 +1352,7 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
         try {
             B->ctx = c; B->fmt = A->fmt; B->dt = A->dt; B->n = A->n; B->m = A->m; B->nnz = A->nnz;
             B->tiles = A->tiles; B->K = A->K; B->ld = A->ld; B->tnnz = A->tnnz; B->subwarp = A->subwarp;
+            B->max_len = A->max_len;
             auto copy = [&](const void *src, size_t bytes) -> void * {
                 if (!src) return nullptr;
                 void *d = c->alloc_bytes(bytes);
@@ -1683,8 +1689,9 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
                             o.precond == GKO_PRECOND_NONE && n > 0 && n <= c->small_cg_rows &&
                             (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE);
         if (single) {
+            if (A->max_len < 0) A->max_len = max_len_of_csr(A);
             dbuf res(c, sizeof(small_cg_result));
-            HIPC(small_cg(c->stream, n, A->rp, A->col, static_cast<const double *>(A->val),
+            HIPC(small_cg(c->stream, n, A->max_len, A->rp, A->col, static_cast<const double *>(A->val),
                           static_cast<const double *>(b), static_cast<double *>(x), tol, maxit,
                           res.as<small_cg_result>()));
             small_cg_result h{};

@@ -70,24 +70,35 @@ hipError_t scalars_reset(hipStream_t s, krylov_scalars *sc, int32_t maxit) {
 }
 
 // ------------------------------------------------------------------ block-Jacobi apply
-// z_i = sum_j D_b^{-1}[i mod bs][j] r_{b*bs + j} for the tile of 256 rows
-// starting at `base`; the tile's inverse blocks (256*BS values, contiguous
-// because BS divides 256) and residuals are staged in LDS with coalesced
-// loads.  Slots of a short last block beyond n are zero in `inv`.
+// z_i = sum_j D_b^{-1}[i mod bs][j] r_{b*bs + j}, j ascending, for the tile
+// of 256 rows starting at `base`, with entry (i, j) of a symmetric inverse
+// block read from its packed upper triangle (the (min, max) entry).  The
+// tile's packed blocks (contiguous because BS divides 256) and residuals are
+// staged in LDS with coalesced loads.  Slots of a short last block beyond n
+// are zero in `inv`.
+template <int BS>
+constexpr int bj_packed() { return BS * (BS + 1) / 2; }
+
 template <typename V, int BS>
 __device__ inline V bj_tile_apply(int64_t n, int64_t base, V ri, const V *__restrict__ inv,
                                   V *r_lds, V *inv_lds) {
+    constexpr int P = bj_packed<BS>();
     const int tid = threadIdx.x;
     r_lds[tid] = ri;
     const int64_t nb = (n + BS - 1) / BS;
-    const int64_t off = base * BS;  // (base / BS) * BS * BS
-    for (int t = tid; t < kB * BS; t += kB)
-        inv_lds[t] = (off + t < nb * BS * BS) ? inv[off + t] : V(0);
+    const int64_t off = (base / BS) * P;
+    for (int t = tid; t < (kB / BS) * P; t += kB)
+        inv_lds[t] = (off + t < nb * P) ? inv[off + t] : V(0);
     __syncthreads();
     V z = V(0);
-    const int b0 = (tid / BS) * BS;
+    const int i = tid % BS, b0 = tid - i;
+    const V *D = inv_lds + (tid / BS) * P;
+    const int row_i = i * BS - i * (i - 1) / 2 - i;  // packed (i, j) = row_i + j, j >= i
 #pragma unroll
-    for (int j = 0; j < BS; ++j) z += inv_lds[tid * BS + j] * r_lds[b0 + j];
+    for (int j = 0; j < BS; ++j) {
+        const int idx = j >= i ? row_i + j : j * BS - j * (j - 1) / 2 - j + i;
+        z += D[idx] * r_lds[b0 + j];
+    }
     __syncthreads();
     return z;
 }
@@ -102,7 +113,7 @@ __global__ __launch_bounds__(kB) void cg_init_kernel(int64_t n, const V *__restr
                                                      double tol, krylov_scalars *sc,
                                                      double *partials, unsigned *ticket) {
     __shared__ V r_lds[BS > 0 ? kB : 1];
-    __shared__ V inv_lds[BS > 0 ? kB * BS : 1];
+    __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
     double a_rz = 0.0, a_rr = 0.0, a_bb = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
         const int64_t i = base + threadIdx.x;
@@ -245,7 +256,7 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict_
                                                        krylov_scalars *sc, double *partials,
                                                        unsigned *ticket) {
     __shared__ V r_lds[BS > 0 ? kB : 1];
-    __shared__ V inv_lds[BS > 0 ? kB * BS : 1];
+    __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
     if (sc->done) return;
     const double alpha = sc->alpha;
     double a_rz = 0.0, a_rr = 0.0;

@@ -103,6 +103,29 @@ static hipError_t launch_bj(hipStream_t s, int64_t n, const int32_t *rp, const i
     return hipGetLastError();
 }
 
+// Upper triangle of each inverse block, row by row: entry (i, j), j >= i,
+// of block k goes to k P + i bs - i (i - 1) / 2 + (j - i), P = bs (bs + 1) / 2.
+__global__ void bj_pack_kernel(int64_t nb, int bs, const double *__restrict__ full,
+                               double *__restrict__ packed) {
+    const int P = bs * (bs + 1) / 2;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nb * P) return;
+    const int64_t k = g / P;
+    int t = (int)(g % P), i = 0;
+    while (t >= bs - i) {
+        t -= bs - i;
+        ++i;
+    }
+    packed[g] = full[k * bs * bs + (int64_t)i * bs + i + t];
+}
+
+hipError_t bj_pack_upper(hipStream_t s, int64_t nb, int bs, const double *full, double *packed) {
+    const int64_t total = nb * (int64_t)(bs * (bs + 1) / 2);
+    if (total == 0) return hipSuccess;
+    bj_pack_kernel<<<(unsigned)((total + 255) / 256), 256, 0, s>>>(nb, bs, full, packed);
+    return hipGetLastError();
+}
+
 hipError_t bj_invert(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                      const double *val, int bs, double *inv, int *err) {
     if (n == 0) return hipSuccess;

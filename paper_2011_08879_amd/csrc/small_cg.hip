@@ -5,7 +5,10 @@
 // 0.7 MB per iteration.  Here the whole solve is one launch on one compute
 // unit.  Thread t owns rows t, t+T, t+2T, ...; the solution, residual and
 // A p of its rows stay in registers, and only the direction p (gathered by
-// the product) lives in LDS.  An iteration costs three workgroup barriers.
+// the product) lives in LDS.  When every row has at most L entries, a
+// thread also keeps its rows' column indices and values in registers
+// (padded with zero values), so an iteration reads no global memory at all.
+// An iteration costs three workgroup barriers.
 //
 // The steps are those of the multi-kernel path (Hestenes-Stiefel CG,
 // unpreconditioned): stop when r.r <= tol^2 b.b, recompute the true residual
@@ -45,23 +48,62 @@ struct wg_reducer {
     }
 };
 
-// s_j = (A v)_i for the thread's rows i = tid + j T, v in LDS.
-template <int T, int R>
+// The thread's rows held in registers: L slots per row, unused slots with
+// value 0 and the row's own index as column (a harmless in-range read).
+// Columns are below 2^16 here (n <= 8192), so two share a register.
+template <int R, int L>
+struct row_cache {
+    static constexpr int LP = L > 0 ? (L + 1) / 2 : 1;
+    uint32_t c[R][LP];
+    double v[R][L > 0 ? L : 1];
+    __device__ int32_t col(int j, int q) const { return (c[j][q / 2] >> (16 * (q & 1))) & 0xffffu; }
+};
+
+template <int T, int R, int L>
+__device__ inline void load_rows(int32_t n, const int32_t *__restrict__ rp,
+                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                 row_cache<R, L> &rc) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int32_t i = threadIdx.x + j * T;
+        const int32_t b = i < n ? rp[i] : 0, e = i < n ? rp[i + 1] : 0;
+#pragma unroll
+        for (int q = 0; q < row_cache<R, L>::LP; ++q) rc.c[j][q] = 0u;
+#pragma unroll
+        for (int q = 0; q < L; ++q) {
+            const bool ok = b + q < e;
+            const uint32_t cq = (uint32_t)(ok ? col[b + q] : (i < n ? i : 0));
+            rc.c[j][q / 2] |= cq << (16 * (q & 1));
+            rc.v[j][q] = ok ? val[b + q] : 0.0;
+        }
+    }
+}
+
+// s_j = (A v)_i for the thread's rows i = tid + j T, v in LDS; entries in
+// ascending order, from registers (L > 0) or from global memory.
+template <int T, int R, int L>
 __device__ inline void rows_product(int32_t n, const int32_t *__restrict__ rp,
                                     const int32_t *__restrict__ col,
-                                    const double *__restrict__ val, const double *v,
-                                    double (&s)[R]) {
+                                    const double *__restrict__ val, const row_cache<R, L> &rc,
+                                    const double *v, double (&s)[R]) {
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int32_t i = threadIdx.x + j * T;
         double a = 0.0;
-        if (i < n)
+        if constexpr (L > 0) {
+#pragma unroll
+            for (int q = 0; q < L; ++q) a += rc.v[j][q] * v[rc.col(j, q)];
+            // one row's gathers in flight at a time: keeps the register
+            // budget for the cached rows
+            __builtin_amdgcn_sched_barrier(0);
+        } else if (i < n) {
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k) a += val[k] * v[col[k]];
+        }
         s[j] = a;
     }
 }
 
-template <int T, int R>
+template <int T, int R, int L>
 __global__ __launch_bounds__(T) void small_cg_kernel(int32_t n, const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
                                                      const double *__restrict__ val,
@@ -72,14 +114,16 @@ __global__ __launch_bounds__(T) void small_cg_kernel(int32_t n, const int32_t *_
     __shared__ double slots[2][T / kWave];
     wg_reducer<T> sum{slots};
 
-    double xr[R], rr[R], br[R], q[R];
+    row_cache<R, L> rc;
+    if constexpr (L > 0) load_rows<T, R, L>(n, rp, col, val, rc);
+    double xr[R], rr[R], q[R];
     double loc = 0.0;
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int32_t i = threadIdx.x + j * T;
-        br[j] = i < n ? b[i] : 0.0;
+        const double bi = i < n ? b[i] : 0.0;
         xr[j] = i < n ? x[i] : 0.0;
-        loc += br[j] * br[j];
+        loc += bi * bi;
     }
     const double bb = sum(loc);
     const double stop2 = tol * tol * bb;
@@ -95,12 +139,12 @@ __global__ __launch_bounds__(T) void small_cg_kernel(int32_t n, const int32_t *_
             if (i < n) p[i] = xr[j];
         }
         __syncthreads();
-        rows_product<T, R>(n, rp, col, val, p, q);
+        rows_product<T, R, L>(n, rp, col, val, rc, p, q);
         double l = 0.0;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             const int32_t i = threadIdx.x + j * T;
-            rr[j] = i < n ? br[j] - q[j] : 0.0;
+            rr[j] = i < n ? b[i] - q[j] : 0.0;
             l += rr[j] * rr[j];
         }
         return sum(l);
@@ -127,7 +171,7 @@ __global__ __launch_bounds__(T) void small_cg_kernel(int32_t n, const int32_t *_
             }
             __syncthreads();
             while (rho > stop2 && it < maxit) {
-                rows_product<T, R>(n, rp, col, val, p, q);
+                rows_product<T, R, L>(n, rp, col, val, rc, p, q);
                 double l = 0.0;
 #pragma unroll
                 for (int j = 0; j < R; ++j) {
@@ -210,13 +254,24 @@ __global__ __launch_bounds__(T) void small_cg_kernel(int32_t n, const int32_t *_
     }
 }
 
-template <int R>
+template <int R, int L>
 hipError_t launch_small(hipStream_t s, int32_t n, const int32_t *rp, const int32_t *col,
                         const double *val, const double *b, double *x, double tol, int32_t maxit,
                         small_cg_result *out) {
-    small_cg_kernel<kSmallT, R><<<1, kSmallT, (size_t)n * sizeof(double), s>>>(
+    small_cg_kernel<kSmallT, R, L><<<1, kSmallT, (size_t)n * sizeof(double), s>>>(
         n, rp, col, val, b, x, tol, maxit, out);
     return hipGetLastError();
+}
+
+// R rows per thread; rows of at most LMAX entries are kept in registers
+// (LMAX is what fits the register budget of a 1024-thread workgroup next to
+// R), longer ones are read from memory every iteration.
+template <int R, int LMAX>
+hipError_t launch_small_r(hipStream_t s, int32_t n, int64_t max_len, const int32_t *rp,
+                          const int32_t *col, const double *val, const double *b, double *x,
+                          double tol, int32_t maxit, small_cg_result *out) {
+    if (max_len <= LMAX) return launch_small<R, LMAX>(s, n, rp, col, val, b, x, tol, maxit, out);
+    return launch_small<R, 0>(s, n, rp, col, val, b, x, tol, maxit, out);
 }
 
 }  // namespace
@@ -232,15 +287,18 @@ int64_t small_cg_max_rows() {
     return by_lds < by_regs ? by_lds : by_regs;
 }
 
-hipError_t small_cg(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
-                    const double *val, const double *b, double *x, double tol, int32_t maxit,
-                    small_cg_result *out) {
+hipError_t small_cg(hipStream_t s, int64_t n, int64_t max_len, const int32_t *rp,
+                    const int32_t *col, const double *val, const double *b, double *x, double tol,
+                    int32_t maxit, small_cg_result *out) {
     if (n <= 0 || n > small_cg_max_rows()) return hipErrorInvalidValue;
     const int32_t m = (int32_t)n;
-    if (n <= kSmallT) return launch_small<1>(s, m, rp, col, val, b, x, tol, maxit, out);
-    if (n <= 2 * kSmallT) return launch_small<2>(s, m, rp, col, val, b, x, tol, maxit, out);
-    if (n <= 4 * kSmallT) return launch_small<4>(s, m, rp, col, val, b, x, tol, maxit, out);
-    return launch_small<8>(s, m, rp, col, val, b, x, tol, maxit, out);
+    if (n <= kSmallT)
+        return launch_small_r<1, 16>(s, m, max_len, rp, col, val, b, x, tol, maxit, out);
+    if (n <= 2 * kSmallT)
+        return launch_small_r<2, 8>(s, m, max_len, rp, col, val, b, x, tol, maxit, out);
+    if (n <= 4 * kSmallT)
+        return launch_small_r<4, 5>(s, m, max_len, rp, col, val, b, x, tol, maxit, out);
+    return launch_small_r<8, 3>(s, m, max_len, rp, col, val, b, x, tol, maxit, out);
 }
 
 }  // namespace gko

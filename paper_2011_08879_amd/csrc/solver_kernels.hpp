@@ -24,12 +24,14 @@ struct small_cg_result {
 };
 // Largest n the device's LDS allows (0 when the device cannot be queried).
 int64_t small_cg_max_rows();
-hipError_t small_cg(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
-                    const double *val, const double *b, double *x, double tol, int32_t maxit,
-                    small_cg_result *out);
+// max_len: longest row; rows up to a small bound are kept in registers.
+hipError_t small_cg(hipStream_t s, int64_t n, int64_t max_len, const int32_t *rp,
+                    const int32_t *col, const double *val, const double *b, double *x, double tol,
+                    int32_t maxit, small_cg_result *out);
 
 // CG / PCG.  bs = 0: no preconditioner (z aliases r); bs in {1,2,4,8,16}:
-// block-Jacobi with explicit inverse blocks `inv` (values of type t).
+// block-Jacobi with the packed upper triangles `inv` of the explicit inverse
+// blocks (values of type t, bj_pack_upper layout).
 hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,
                    const void *inv, int bs, double tol, krylov_scalars *sc, double *partials,
                    unsigned *ticket);
@@ -72,5 +74,9 @@ hipError_t fill_zero(hipStream_t s, vt t, int64_t n, void *y);
 // err: device int, set to 1 on a zero pivot.
 hipError_t bj_invert(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                      const double *val, int bs, double *inv, int *err);
+// The solvers apply the upper triangles of the inverse blocks: the inverse
+// of a symmetric block is symmetric, so z = D^-1 r reads bs (bs + 1) / 2
+// values per block instead of bs^2 (row by row, see precond.hip).
+hipError_t bj_pack_upper(hipStream_t s, int64_t nb, int bs, const double *full, double *packed);
 
 }  // namespace gko

@@ -245,3 +245,11 @@ def test_stream_probe_exact(g, gen_mod):
     g.stream(g.STREAM_TRIAD, dev(a), c, dev(b), 0.37)
     # two roundings (no fused multiply-add), exactly as numpy computes it
     assert np.array_equal(host(c).view(np.int64), (a + 0.37 * b).view(np.int64))
+    # arrays off the 16-byte grid take the one-element-per-thread kernels
+    ad, cd = dev(a), dev(np.full(n, np.nan))
+    g.stream(g.STREAM_COPY, ad[1:], cd[1:])
+    assert np.array_equal(host(cd)[1:], a[1:]) and np.isnan(host(cd)[0])
+    for m in (1, 2, 3):
+        c = dev(np.full(m, np.nan))
+        g.stream(g.STREAM_COPY, dev(a[:m]), c)
+        assert np.array_equal(host(c), a[:m])
