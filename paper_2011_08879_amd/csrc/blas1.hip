@@ -27,31 +27,176 @@ int reduction_blocks(int64_t n) {
     return (int)g;
 }
 
+// ------------------------------------------------------------------ finishing operations
+// What the totals of each reduction update, applied once per launch (by the
+// last block or by the finalize kernel).  skip() repeats the early-exit test
+// of the kernel whose partials are being summed.
+struct dot_op {
+    double *result;
+    bool sq;
+    __device__ bool skip() const { return false; }
+    __device__ void operator()(const double *o) const { *result = sq ? sqrt(o[0]) : o[0]; }
+};
+
+// CG start: totals r.z, r.r, b.b.
+struct cg_init_op {
+    krylov_scalars *sc;
+    double tol;
+    __device__ bool skip() const { return false; }
+    __device__ void operator()(const double *o) const {
+        sc->rho = o[0];
+        sc->rr = o[1];
+        sc->bb = o[2];
+        sc->stop2 = tol * tol * o[2];
+        if (!std::isfinite(o[1]) || !std::isfinite(o[0])) sc->done = kBreakdown;
+        else if (o[1] <= sc->stop2) sc->done = kConverged;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else sc->done = kRunning;
+    }
+};
+
+// alpha = rho / p.q; p.q <= 0 means A is not SPD.
+struct cg_alpha_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        const double pq = o[0];
+        sc->aux = pq;
+        if (!(pq > 0.0)) {
+            sc->done = std::isnan(pq) ? kBreakdown : kNotSpd;
+            sc->iter += 1;
+        } else {
+            sc->alpha = sc->rho / pq;
+        }
+    }
+};
+
+// After the update: totals r.z, r.r; convergence test, then beta.
+struct cg_update_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        sc->iter += 1;
+        sc->rr = o[1];
+        if (!std::isfinite(o[1]) || !std::isfinite(o[0])) {
+            sc->done = kBreakdown;
+        } else if (o[1] <= sc->stop2) {
+            sc->done = kConverged;
+        } else {
+            sc->beta = o[0] / sc->rho;
+            sc->rho = o[0];
+            if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        }
+    }
+};
+
+// BiCGSTAB start: totals r.r, b.b.
+struct bicg_init_op {
+    krylov_scalars *sc;
+    double tol;
+    __device__ bool skip() const { return false; }
+    __device__ void operator()(const double *o) const {
+        sc->rho = o[0];
+        sc->rr = o[0];
+        sc->bb = o[1];
+        sc->stop2 = tol * tol * o[1];
+        sc->rho_old = sc->alpha = sc->omega = 1.0;
+        sc->half = 0;
+        if (!std::isfinite(o[0])) sc->done = kBreakdown;
+        else if (o[0] <= sc->stop2) sc->done = kConverged;
+        else if (!(fabs(o[0]) >= 1e-300)) sc->done = kBreakdown;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else {
+            sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+            sc->done = kRunning;
+        }
+    }
+};
+
+// alpha = rho / (rhat.v)
+struct bicg_alpha_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        sc->aux = o[0];
+        if (!(fabs(o[0]) >= 1e-300)) sc->done = kBreakdown;
+        else sc->alpha = sc->rho / o[0];
+    }
+};
+
+// s.s: converging here finishes at the half step.
+struct bicg_s_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        sc->iter += 1;
+        if (!std::isfinite(o[0])) sc->done = kBreakdown;
+        else if (o[0] <= sc->stop2) {
+            sc->half = 1;
+            sc->rr = o[0];
+        }
+    }
+};
+
+// omega = (t.s) / (t.t)
+struct bicg_omega_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0 || sc->half != 0; }
+    __device__ void operator()(const double *o) const {
+        sc->aux = o[1];
+        if (!(o[1] >= 1e-300)) sc->done = kBreakdown;
+        else sc->omega = o[0] / o[1];
+    }
+};
+
+// After the update: totals r.r and the next rho = rhat.r.
+struct bicg_update_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        if (sc->half) {
+            sc->done = kConverged;
+            return;
+        }
+        sc->rr = o[0];
+        if (!std::isfinite(o[0])) sc->done = kBreakdown;
+        else if (o[0] <= sc->stop2) sc->done = kConverged;
+        else if (sc->omega == 0.0) sc->done = kBreakdown;
+        else {
+            sc->rho_old = sc->rho;
+            sc->rho = o[1];
+            if (!(fabs(o[1]) >= 1e-300)) sc->done = kBreakdown;
+            else {
+                sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
+                if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+            }
+        }
+    }
+};
+
 // ------------------------------------------------------------------ dot / norm
 template <typename V>
 __global__ __launch_bounds__(kB) void dot_kernel(int64_t n, const V *__restrict__ x,
-                                                 const V *__restrict__ y, double *result,
-                                                 double *partials, unsigned *ticket, bool sq) {
+                                                 const V *__restrict__ y, red_args ra, dot_op op) {
     double s = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
         s += (double)x[i] * (double)y[i];
-    double v[1] = {s}, out[1];
-    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0)
-        *result = sq ? sqrt(out[0]) : out[0];
+    double v[1] = {s};
+    grid_sum_apply<kB, 1>(v, ra, op);
 }
 
 hipError_t dot(hipStream_t s, vt t, int64_t n, const void *x, const void *y, double *result,
                double *partials, unsigned *ticket, bool sqrt_result) {
     const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    const dot_op op{result, sqrt_result};
     if (t == vt::f64)
         dot_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(x),
-                                            static_cast<const double *>(y), result, partials,
-                                            ticket, sqrt_result);
+                                            static_cast<const double *>(y), ra, op);
     else
         dot_kernel<float><<<g, kB, 0, s>>>(n, static_cast<const float *>(x),
-                                           static_cast<const float *>(y), result, partials, ticket,
-                                           sqrt_result);
-    return hipGetLastError();
+                                           static_cast<const float *>(y), ra, op);
+    return red_finish<1>(s, g, ra, op);
 }
 
 // ------------------------------------------------------------------ scalars
@@ -111,7 +256,7 @@ __global__ __launch_bounds__(kB) void cg_init_kernel(int64_t n, const V *__restr
                                                      const V *__restrict__ r, V *__restrict__ z,
                                                      V *__restrict__ p, const V *__restrict__ inv,
                                                      double tol, krylov_scalars *sc,
-                                                     double *partials, unsigned *ticket) {
+                                                     red_args ra) {
     __shared__ V r_lds[BS > 0 ? kB : 1];
     __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
     double a_rz = 0.0, a_rr = 0.0, a_bb = 0.0;
@@ -129,27 +274,8 @@ __global__ __launch_bounds__(kB) void cg_init_kernel(int64_t n, const V *__restr
             a_bb += bi * bi;
         }
     }
-    double v[3] = {a_rz, a_rr, a_bb}, out[3];
-    if (grid_reduce<kB, 3>(v, partials, ticket, out) && threadIdx.x == 0) {
-        sc->rho = out[0];
-        sc->rr = out[1];
-        sc->bb = out[2];
-        sc->stop2 = tol * tol * out[2];
-        if (!std::isfinite(out[1]) || !std::isfinite(out[0])) sc->done = kBreakdown;
-        else if (out[1] <= sc->stop2) sc->done = kConverged;
-        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
-        else sc->done = kRunning;
-    }
-}
-
-__device__ inline void cg_set_alpha(krylov_scalars *sc, double pq) {
-    sc->aux = pq;
-    if (!(pq > 0.0)) {
-        sc->done = std::isnan(pq) ? kBreakdown : kNotSpd;
-        sc->iter += 1;
-    } else {
-        sc->alpha = sc->rho / pq;
-    }
+    double v[3] = {a_rz, a_rr, a_bb};
+    grid_sum_apply<kB, 3>(v, ra, cg_init_op{sc, tol});
 }
 
 // q = A p for CSR (a subwarp of W lanes per U rows, as in the plain SpMV),
@@ -159,8 +285,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
                                                          const int32_t *__restrict__ col,
                                                          const V *__restrict__ val,
                                                          const V *__restrict__ p, V *__restrict__ q,
-                                                         krylov_scalars *sc, double *partials,
-                                                         unsigned *ticket) {
+                                                         krylov_scalars *sc, red_args ra) {
     if (sc->done) return;
     constexpr int U = csr_shape<W>::U;
     constexpr int RPB = kB / W * U;
@@ -181,8 +306,8 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
             }
         }
     }
-    double v[1] = {acc}, out[1];
-    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+    double v[1] = {acc};
+    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
 }
 
 // q = A p for ELL (thread per row, column-major slots, padding last),
@@ -192,8 +317,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, i
                                                          const int32_t *__restrict__ ecol,
                                                          const V *__restrict__ eval,
                                                          const V *__restrict__ p, V *__restrict__ q,
-                                                         krylov_scalars *sc, double *partials,
-                                                         unsigned *ticket) {
+                                                         krylov_scalars *sc, red_args ra) {
     if (sc->done) return;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
@@ -214,36 +338,37 @@ __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, i
         q[i] = s;
         acc += (double)p[i] * (double)s;
     }
-    double v[1] = {acc}, out[1];
-    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+    double v[1] = {acc};
+    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
 }
 
 hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                        const void *eval, const void *p, void *q, krylov_scalars *sc,
                        double *partials, unsigned *ticket) {
     const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_spmv_ell_kernel<double><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const double *>(eval),
                                                     static_cast<const double *>(p),
-                                                    static_cast<double *>(q), sc, partials, ticket);
+                                                    static_cast<double *>(q), sc, ra);
     else
         cg_spmv_ell_kernel<float><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const float *>(eval),
                                                    static_cast<const float *>(p),
-                                                   static_cast<float *>(q), sc, partials, ticket);
-    return hipGetLastError();
+                                                   static_cast<float *>(q), sc, ra);
+    return red_finish<1>(s, g, ra, cg_alpha_op{sc});
 }
 
 // p.q after a SpMV done by a format's own kernel.
 template <typename V>
 __global__ __launch_bounds__(kB) void cg_pq_kernel(int64_t n, const V *__restrict__ p,
                                                    const V *__restrict__ q, krylov_scalars *sc,
-                                                   double *partials, unsigned *ticket) {
+                                                   red_args ra) {
     if (sc->done) return;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
         acc += (double)p[i] * (double)q[i];
-    double v[1] = {acc}, out[1];
-    if (grid_reduce<kB, 1>(v, partials, ticket, out) && threadIdx.x == 0) cg_set_alpha(sc, out[0]);
+    double v[1] = {acc};
+    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
 }
 
 // x += alpha p; r -= alpha q; z = M^-1 r; rho' = r.z; rr = r.r; then beta.
@@ -253,8 +378,7 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict_
                                                        const V *__restrict__ p,
                                                        const V *__restrict__ q,
                                                        const V *__restrict__ inv,
-                                                       krylov_scalars *sc, double *partials,
-                                                       unsigned *ticket) {
+                                                       krylov_scalars *sc, red_args ra) {
     __shared__ V r_lds[BS > 0 ? kB : 1];
     __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
     if (sc->done) return;
@@ -276,20 +400,8 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict_
             a_rr += (double)ri * (double)ri;
         }
     }
-    double v[2] = {a_rz, a_rr}, out[2];
-    if (grid_reduce<kB, 2>(v, partials, ticket, out) && threadIdx.x == 0) {
-        sc->iter += 1;
-        sc->rr = out[1];
-        if (!std::isfinite(out[1]) || !std::isfinite(out[0])) {
-            sc->done = kBreakdown;
-        } else if (out[1] <= sc->stop2) {
-            sc->done = kConverged;
-        } else {
-            sc->beta = out[0] / sc->rho;
-            sc->rho = out[0];
-            if (sc->iter >= sc->maxit) sc->done = kMaxIter;
-        }
-    }
+    double v[2] = {a_rz, a_rr};
+    grid_sum_apply<kB, 2>(v, ra, cg_update_op{sc});
 }
 
 // p = z + beta p  (z = r without a preconditioner).
@@ -308,19 +420,20 @@ static hipError_t launch_cg_init(hipStream_t s, int64_t n, const void *b, const 
                                  void *p, const void *inv, int bs, double tol, krylov_scalars *sc,
                                  double *partials, unsigned *ticket) {
     const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
     const V *B = static_cast<const V *>(b), *R = static_cast<const V *>(r);
     V *Z = static_cast<V *>(z), *P = static_cast<V *>(p);
     const V *I = static_cast<const V *>(inv);
     switch (bs) {
-        case 0: cg_init_kernel<V, 0><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
-        case 1: cg_init_kernel<V, 1><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
-        case 2: cg_init_kernel<V, 2><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
-        case 4: cg_init_kernel<V, 4><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
-        case 8: cg_init_kernel<V, 8><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
-        case 16: cg_init_kernel<V, 16><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, partials, ticket); break;
+        case 0: cg_init_kernel<V, 0><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
+        case 1: cg_init_kernel<V, 1><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
+        case 2: cg_init_kernel<V, 2><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
+        case 4: cg_init_kernel<V, 4><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
+        case 8: cg_init_kernel<V, 8><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
+        case 16: cg_init_kernel<V, 16><<<g, kB, 0, s>>>(n, B, R, Z, P, I, tol, sc, ra); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return red_finish<3>(s, g, ra, cg_init_op{sc, tol});
 }
 
 hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,
@@ -338,10 +451,11 @@ static hipError_t launch_cg_csr_w(hipStream_t s, int64_t n, const int32_t *rp, c
     int64_t g = (n + RPB - 1) / RPB;
     if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
     if (g < 1) g = 1;
+    const red_args ra = red_for((int)g, partials, ticket);
     cg_spmv_csr_kernel<V, W><<<(unsigned)g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
                                                         static_cast<const V *>(p),
-                                                        static_cast<V *>(q), sc, partials, ticket);
-    return hipGetLastError();
+                                                        static_cast<V *>(q), sc, ra);
+    return red_finish<1>(s, (int)g, ra, cg_alpha_op{sc});
 }
 
 template <typename V>
@@ -370,13 +484,14 @@ hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const 
 hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
                  double *partials, unsigned *ticket) {
     const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_pq_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(p),
-                                              static_cast<const double *>(q), sc, partials, ticket);
+                                              static_cast<const double *>(q), sc, ra);
     else
         cg_pq_kernel<float><<<g, kB, 0, s>>>(n, static_cast<const float *>(p),
-                                             static_cast<const float *>(q), sc, partials, ticket);
-    return hipGetLastError();
+                                             static_cast<const float *>(q), sc, ra);
+    return red_finish<1>(s, g, ra, cg_alpha_op{sc});
 }
 
 template <typename V>
@@ -384,19 +499,20 @@ static hipError_t launch_cg_update(hipStream_t s, int64_t n, void *x, void *r, v
                                    const void *p, const void *q, const void *inv, int bs,
                                    krylov_scalars *sc, double *partials, unsigned *ticket) {
     const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
     V *X = static_cast<V *>(x), *R = static_cast<V *>(r), *Z = static_cast<V *>(z);
     const V *P = static_cast<const V *>(p), *Q = static_cast<const V *>(q);
     const V *I = static_cast<const V *>(inv);
     switch (bs) {
-        case 0: cg_update_kernel<V, 0><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
-        case 1: cg_update_kernel<V, 1><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
-        case 2: cg_update_kernel<V, 2><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
-        case 4: cg_update_kernel<V, 4><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
-        case 8: cg_update_kernel<V, 8><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
-        case 16: cg_update_kernel<V, 16><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, partials, ticket); break;
+        case 0: cg_update_kernel<V, 0><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 1: cg_update_kernel<V, 1><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 2: cg_update_kernel<V, 2><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 4: cg_update_kernel<V, 4><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 8: cg_update_kernel<V, 8><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 16: cg_update_kernel<V, 16><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
+    return red_finish<2>(s, g, ra, cg_update_op{sc});
 }
 
 hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,
@@ -427,8 +543,7 @@ __global__ __launch_bounds__(kB) void bicg_init_kernel(int64_t n, const double *
                                                        double *__restrict__ rh,
                                                        double *__restrict__ p,
                                                        double *__restrict__ v, double tol,
-                                                       krylov_scalars *sc, double *partials,
-                                                       unsigned *ticket) {
+                                                       krylov_scalars *sc, red_args ra) {
     double a_rr = 0.0, a_bb = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
         const double ri = r[i];
@@ -438,23 +553,8 @@ __global__ __launch_bounds__(kB) void bicg_init_kernel(int64_t n, const double *
         a_rr += ri * ri;
         a_bb += b[i] * b[i];
     }
-    double vv[2] = {a_rr, a_bb}, out[2];
-    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
-        sc->rho = out[0];
-        sc->rr = out[0];
-        sc->bb = out[1];
-        sc->stop2 = tol * tol * out[1];
-        sc->rho_old = sc->alpha = sc->omega = 1.0;
-        sc->half = 0;
-        if (!std::isfinite(out[0])) sc->done = kBreakdown;
-        else if (out[0] <= sc->stop2) sc->done = kConverged;
-        else if (!(fabs(out[0]) >= 1e-300)) sc->done = kBreakdown;
-        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
-        else {
-            sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
-            sc->done = kRunning;
-        }
-    }
+    double vv[2] = {a_rr, a_bb};
+    grid_sum_apply<kB, 2>(vv, ra, bicg_init_op{sc, tol});
 }
 
 // p = r + beta (p - omega v)
@@ -471,25 +571,20 @@ __global__ __launch_bounds__(kB) void bicg_p_kernel(int64_t n, const double *__r
 // alpha = rho / (rhat.v)
 __global__ __launch_bounds__(kB) void bicg_alpha_kernel(int64_t n, const double *__restrict__ rh,
                                                         const double *__restrict__ v,
-                                                        krylov_scalars *sc, double *partials,
-                                                        unsigned *ticket) {
+                                                        krylov_scalars *sc, red_args ra) {
     if (sc->done) return;
     double a = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB)
         a += rh[i] * v[i];
-    double vv[1] = {a}, out[1];
-    if (grid_reduce<kB, 1>(vv, partials, ticket, out) && threadIdx.x == 0) {
-        sc->aux = out[0];
-        if (!(fabs(out[0]) >= 1e-300)) sc->done = kBreakdown;
-        else sc->alpha = sc->rho / out[0];
-    }
+    double vv[1] = {a};
+    grid_sum_apply<kB, 1>(vv, ra, bicg_alpha_op{sc});
 }
 
 // s = r - alpha v, with s.s: converging here finishes at the half step.
 __global__ __launch_bounds__(kB) void bicg_s_kernel(int64_t n, const double *__restrict__ r,
                                                     const double *__restrict__ v,
                                                     double *__restrict__ s, krylov_scalars *sc,
-                                                    double *partials, unsigned *ticket) {
+                                                    red_args ra) {
     if (sc->done) return;
     const double alpha = sc->alpha;
     double a = 0.0;
@@ -498,34 +593,22 @@ __global__ __launch_bounds__(kB) void bicg_s_kernel(int64_t n, const double *__r
         s[i] = si;
         a += si * si;
     }
-    double vv[1] = {a}, out[1];
-    if (grid_reduce<kB, 1>(vv, partials, ticket, out) && threadIdx.x == 0) {
-        sc->iter += 1;
-        if (!std::isfinite(out[0])) sc->done = kBreakdown;
-        else if (out[0] <= sc->stop2) {
-            sc->half = 1;
-            sc->rr = out[0];
-        }
-    }
+    double vv[1] = {a};
+    grid_sum_apply<kB, 1>(vv, ra, bicg_s_op{sc});
 }
 
 // omega = (t.s) / (t.t)
 __global__ __launch_bounds__(kB) void bicg_omega_kernel(int64_t n, const double *__restrict__ t,
                                                         const double *__restrict__ s,
-                                                        krylov_scalars *sc, double *partials,
-                                                        unsigned *ticket) {
+                                                        krylov_scalars *sc, red_args ra) {
     if (sc->done || sc->half) return;
     double a_ts = 0.0, a_tt = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
         a_ts += t[i] * s[i];
         a_tt += t[i] * t[i];
     }
-    double vv[2] = {a_ts, a_tt}, out[2];
-    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
-        sc->aux = out[1];
-        if (!(out[1] >= 1e-300)) sc->done = kBreakdown;
-        else sc->omega = out[0] / out[1];
-    }
+    double vv[2] = {a_ts, a_tt};
+    grid_sum_apply<kB, 2>(vv, ra, bicg_omega_op{sc});
 }
 
 // x += alpha p + omega s; r = s - omega t; then rr and the next rho = rhat.r.
@@ -536,8 +619,7 @@ __global__ __launch_bounds__(kB) void bicg_update_kernel(int64_t n, double *__re
                                                          const double *__restrict__ p,
                                                          const double *__restrict__ s,
                                                          const double *__restrict__ t,
-                                                         krylov_scalars *sc, double *partials,
-                                                         unsigned *ticket) {
+                                                         krylov_scalars *sc, red_args ra) {
     if (sc->done) return;
     const bool half = sc->half != 0;
     const double alpha = sc->alpha, omega = sc->omega;
@@ -553,26 +635,8 @@ __global__ __launch_bounds__(kB) void bicg_update_kernel(int64_t n, double *__re
             a_rho += rh[i] * ri;
         }
     }
-    double vv[2] = {a_rr, a_rho}, out[2];
-    if (grid_reduce<kB, 2>(vv, partials, ticket, out) && threadIdx.x == 0) {
-        if (half) {
-            sc->done = kConverged;
-            return;
-        }
-        sc->rr = out[0];
-        if (!std::isfinite(out[0])) sc->done = kBreakdown;
-        else if (out[0] <= sc->stop2) sc->done = kConverged;
-        else if (omega == 0.0) sc->done = kBreakdown;
-        else {
-            sc->rho_old = sc->rho;
-            sc->rho = out[1];
-            if (!(fabs(out[1]) >= 1e-300)) sc->done = kBreakdown;
-            else {
-                sc->beta = (sc->rho / sc->rho_old) * (sc->alpha / sc->omega);
-                if (sc->iter >= sc->maxit) sc->done = kMaxIter;
-            }
-        }
-    }
+    double vv[2] = {a_rr, a_rho};
+    grid_sum_apply<kB, 2>(vv, ra, bicg_update_op{sc});
 }
 
 static inline const double *cd(const void *p) { return static_cast<const double *>(p); }
@@ -580,9 +644,11 @@ static inline double *md(void *p) { return static_cast<double *>(p); }
 
 hipError_t bicg_init(hipStream_t st, int64_t n, const void *b, const void *r, void *rh, void *p,
                      void *v, double tol, krylov_scalars *sc, double *partials, unsigned *ticket) {
-    bicg_init_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(b), cd(r), md(rh), md(p), md(v), tol,
-                                                        sc, partials, ticket);
-    return hipGetLastError();
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    bicg_init_kernel<<<g, kB, 0, st>>>(n, cd(b), cd(r), md(rh), md(p), md(v), tol,
+                                                        sc, ra);
+    return red_finish<2>(st, g, ra, bicg_init_op{sc, tol});
 }
 
 hipError_t bicg_p(hipStream_t st, int64_t n, const void *r, const void *v, void *p,
@@ -593,28 +659,35 @@ hipError_t bicg_p(hipStream_t st, int64_t n, const void *r, const void *v, void 
 
 hipError_t bicg_alpha(hipStream_t st, int64_t n, const void *rh, const void *v, krylov_scalars *sc,
                       double *partials, unsigned *ticket) {
-    bicg_alpha_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(rh), cd(v), sc, partials, ticket);
-    return hipGetLastError();
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    bicg_alpha_kernel<<<g, kB, 0, st>>>(n, cd(rh), cd(v), sc, ra);
+    return red_finish<1>(st, g, ra, bicg_alpha_op{sc});
 }
 
 hipError_t bicg_s(hipStream_t st, int64_t n, const void *r, const void *v, void *s,
                   krylov_scalars *sc, double *partials, unsigned *ticket) {
-    bicg_s_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(r), cd(v), md(s), sc, partials, ticket);
-    return hipGetLastError();
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    bicg_s_kernel<<<g, kB, 0, st>>>(n, cd(r), cd(v), md(s), sc, ra);
+    return red_finish<1>(st, g, ra, bicg_s_op{sc});
 }
 
 hipError_t bicg_omega(hipStream_t st, int64_t n, const void *t, const void *s, krylov_scalars *sc,
                       double *partials, unsigned *ticket) {
-    bicg_omega_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(t), cd(s), sc, partials, ticket);
-    return hipGetLastError();
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    bicg_omega_kernel<<<g, kB, 0, st>>>(n, cd(t), cd(s), sc, ra);
+    return red_finish<2>(st, g, ra, bicg_omega_op{sc});
 }
 
 hipError_t bicg_update(hipStream_t st, int64_t n, void *x, void *r, const void *rh, const void *p,
-                       const void *s, const void *t, krylov_scalars *sc, double *partials,
-                       unsigned *ticket) {
-    bicg_update_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, md(x), md(r), cd(rh), cd(p), cd(s),
-                                                          cd(t), sc, partials, ticket);
-    return hipGetLastError();
+                       const void *s, const void *t, krylov_scalars *sc, double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    bicg_update_kernel<<<g, kB, 0, st>>>(n, md(x), md(r), cd(rh), cd(p), cd(s),
+                                                          cd(t), sc, ra);
+    return red_finish<2>(st, g, ra, bicg_update_op{sc});
 }
 
 // ------------------------------------------------------------------ mixed-precision helpers

@@ -123,45 +123,111 @@ __device__ inline T block_sum(T v, T *lds) {
 }
 
 // ------------------------------------------------------------------ grid reduction
-// Two-stage deterministic reduction of NV values per block.  Each block
-// stores its NV partial sums, then takes a ticket; the last block to arrive
-// sums all partials in block order with a fixed tree and gets `true`, with
-// the totals in out[0..NV) (valid in thread 0).  The ticket is reset by the
-// last block, so the counter is ready for the next launch.  Results do not
-// depend on block scheduling.
+// Deterministic grid-wide sums of NV values per thread, finished once by an
+// operation `op` on the totals (thread 0).  Every block first forms its NV
+// block sums with a fixed tree and stores them as partials[j * grid + block].
+// The partials are then summed in block order with a fixed tree, in one of
+// two ways chosen by the grid size alone, so results never depend on block
+// scheduling:
+//  * small grids: the block that takes the last ticket sums the partials and
+//    applies op in the same launch (a release fence per block, an acquire
+//    fence in the last one);
+//  * large grids: a one-workgroup finalize kernel launched right after sums
+//    them and applies op.  On MI355X a per-block release fence writes back
+//    the XCD's dirty L2 lines, which for a few thousand blocks that store
+//    vectors costs more than the extra launch (measured: 2048 blocks of an
+//    x+y kernel with its z.z reduction, 164 us with fences against 87 us
+//    with the finalize kernel).
+constexpr int kTicketMaxBlocks = 64;
+
+struct red_args {
+    double *partials;  // NV * grid doubles
+    unsigned *ticket;  // zeroed; null: the partials go to a finalize kernel
+};
+
 __device__ inline double load_coherent(const double *p) {
     uint64_t bits = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
                                       __HIP_MEMORY_SCOPE_AGENT);
     return __longlong_as_double(static_cast<long long>(bits));
 }
 
-template <int BLOCK, int NV>
-__device__ inline bool grid_reduce(const double (&v)[NV], double *partials, unsigned *ticket,
-                                   double (&out)[NV]) {
+// Sum of partials[j * g + b] over b < g in a fixed order (strided per
+// thread, four loads in flight, then the block tree); valid in thread 0.
+template <int BLOCK, bool COHERENT>
+__device__ inline double sum_partials(const double *pj, unsigned g, double *lds) {
+    double s = 0.0;
+    unsigned b = threadIdx.x;
+    for (; b + 3 * BLOCK < g; b += 4 * BLOCK) {
+        double t[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t[u] = COHERENT ? load_coherent(pj + b + u * BLOCK) : pj[b + u * BLOCK];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) s += t[u];
+    }
+    for (; b < g; b += BLOCK) s += COHERENT ? load_coherent(pj + b) : pj[b];
+    return block_sum<BLOCK>(s, lds);
+}
+
+template <int BLOCK, int NV, typename Op>
+__device__ inline void grid_sum_apply(const double (&v)[NV], const red_args &ra, const Op &op) {
     __shared__ double lds[BLOCK / kWave];
     __shared__ bool am_last;
     double bs[NV];
 #pragma unroll
     for (int j = 0; j < NV; ++j) bs[j] = block_sum<BLOCK>(v[j], lds);
+    if (!ra.ticket) {
+        if (threadIdx.x == 0)
+#pragma unroll
+            for (int j = 0; j < NV; ++j) ra.partials[(size_t)j * gridDim.x + blockIdx.x] = bs[j];
+        return;
+    }
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int j = 0; j < NV; ++j) partials[(size_t)j * gridDim.x + blockIdx.x] = bs[j];
-        __threadfence();
-        unsigned t = atomicAdd(ticket, 1u);
-        am_last = (t == gridDim.x - 1);
+        for (int j = 0; j < NV; ++j) ra.partials[(size_t)j * gridDim.x + blockIdx.x] = bs[j];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        am_last = atomicAdd(ra.ticket, 1u) == gridDim.x - 1;
     }
     __syncthreads();
-    if (!am_last) return false;
-    __threadfence();
+    if (!am_last) return;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    double out[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) {
-        double s = 0.0;
-        for (unsigned b = threadIdx.x; b < gridDim.x; b += BLOCK)
-            s += load_coherent(partials + (size_t)j * gridDim.x + b);
-        out[j] = block_sum<BLOCK>(s, lds);
+    for (int j = 0; j < NV; ++j)
+        out[j] = sum_partials<BLOCK, true>(ra.partials + (size_t)j * gridDim.x, gridDim.x, lds);
+    if (threadIdx.x == 0) {
+        __hip_atomic_store(ra.ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        op(out);
     }
-    if (threadIdx.x == 0) __hip_atomic_store(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return true;
+}
+
+constexpr int kFinalizeBlock = 1024;
+
+// The finalize kernel of a large grid: g blocks stored their partials.
+// op.skip() repeats the early-exit test of the kernel that produced them.
+template <int NV, typename Op>
+__global__ __launch_bounds__(kFinalizeBlock) void finalize_kernel(unsigned g, const double *partials,
+                                                                  Op op) {
+    __shared__ double lds[kFinalizeBlock / kWave];
+    if (op.skip()) return;
+    double out[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j)
+        out[j] = sum_partials<kFinalizeBlock, false>(partials + (size_t)j * g, g, lds);
+    if (threadIdx.x == 0) op(out);
+}
+
+// Host side: the reduction mode for a grid of g blocks, and the finalize
+// launch that follows the reducing kernel when the grid is large.
+inline red_args red_for(int g, double *partials, unsigned *ticket) {
+    return red_args{partials, g <= kTicketMaxBlocks ? ticket : nullptr};
+}
+
+template <int NV, typename Op>
+inline hipError_t red_finish(hipStream_t s, int g, const red_args &ra, const Op &op) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ra.ticket) return e;
+    finalize_kernel<NV, Op><<<1, kFinalizeBlock, 0, s>>>((unsigned)g, ra.partials, op);
+    return hipGetLastError();
 }
 
 }  // namespace gko
