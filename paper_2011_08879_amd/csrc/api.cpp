@@ -318,11 +318,13 @@ void export_csr_into(gko_matrix A, const values &v, int32_t *rp, int32_t *col, v
 
 int64_t read_int(gko_context c, const int *d);
 
+int64_t max_len_of_csr(gko_matrix A);
+
 // Rows too long for a subwarp get a workgroup each (see spmv_csr).
 void refresh_long_rows(gko_matrix A) {
     A->drop(A->long_rows);
     A->n_long = 0;
-    if (A->n == 0) return;
+    if (A->n == 0 || A->subwarp == kCsrRowThread) return;
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     dbuf flag(c, A->n * 4), pos(c, (A->n + 1) * 4), tmp(c, scan_tmp_elems(A->n) * 4);
@@ -336,6 +338,16 @@ void refresh_long_rows(gko_matrix A) {
         A->long_rows = static_cast<int32_t *>(rows.release());
         A->n_long = nl;
     }
+}
+
+// The CSR kernel for this matrix: a thread per row for short regular rows,
+// else a subwarp per row with the width from the mean row length; then the
+// list of rows too long for that width.
+void analyse_csr(gko_matrix A) {
+    if (A->max_len < 0) A->max_len = A->n > 0 ? max_len_of_csr(A) : 0;
+    A->subwarp = csr_rowthread_suits(A->n, A->nnz, A->max_len) ? kCsrRowThread
+                                                               : csr_subwarp_width(A->n, A->nnz);
+    refresh_long_rows(A);
 }
 
 void to_csr(gko_matrix A) {
@@ -356,8 +368,7 @@ void to_csr(gko_matrix A) {
     A->col = static_cast<int32_t *>(col.release());
     A->val = val.release();
     A->fmt = GKO_FMT_CSR;
-    A->subwarp = csr_subwarp_width(A->n, A->nnz);
-    refresh_long_rows(A);
+    analyse_csr(A);
 }
 
 int64_t read_int(gko_context c, const int *d) {
@@ -1322,9 +1333,8 @@ gko_status gko_matrix_create_csr(gko_context ctx, int64_t n_rows, int64_t n_cols
         A->rp = static_cast<int32_t *>(rp.release());
         A->col = static_cast<int32_t *>(col.release());
         A->val = val.release();
-        A->subwarp = csr_subwarp_width(n_rows, nnz);
         try {
-            refresh_long_rows(A);
+            analyse_csr(A);
         } catch (...) {
             A->drop_storage();
             delete A;

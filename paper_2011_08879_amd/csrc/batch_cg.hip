@@ -63,17 +63,73 @@ __device__ inline double spmv_rows(const sys_view &S, const VA *__restrict__ val
     return pq;
 }
 
+// A system's rows held in registers for its whole solve: a thread's rows
+// tid + j T (j < R) with up to L entries each, unused slots with value 0 and
+// the row itself as column (an in-range read that adds nothing).  Systems
+// with more rows or longer rows are read from memory every iteration.
+template <int T>
+constexpr int batch_cache_rows() { return 1024 / T < 4 ? 1024 / T : 4; }
+constexpr int kBatchCacheLen = 5;
+
+template <typename VA, int T>
+struct sys_regs {
+    static constexpr int R = batch_cache_rows<T>(), L = kBatchCacheLen;
+    int32_t c[R][L];
+    VA v[R][L];
+
+    // Loads this thread's rows; true (uniform) when every row of the system fits.
+    __device__ bool load(const sys_view &S, const VA *__restrict__ val, double *red) {
+        bool fits = S.m <= R * T;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = threadIdx.x + j * T;
+            const int32_t b = i < S.m ? S.rp[i] : 0, e = i < S.m ? S.rp[i + 1] : 0;
+            if (e - b > L) fits = false;
+#pragma unroll
+            for (int q = 0; q < L; ++q) {
+                const bool ok = b + q < e;
+                c[j][q] = ok ? S.col[b + q] : (i < S.m ? i : 0);
+                v[j][q] = ok ? val[b + q] : VA(0);
+            }
+        }
+        return wg_sum<T>(fits ? 0.0 : 1.0, red) == 0.0;
+    }
+
+    // q = A p over this thread's rows, returns sum of p_i q_i (as spmv_rows).
+    template <typename VV>
+    __device__ double spmv(int32_t m, const VV *p, VV *q) const {
+        double pq = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = threadIdx.x + j * T;
+            if (i < m) {
+                VV s = VV(0);
+#pragma unroll
+                for (int k = 0; k < L; ++k) s += (VV)v[j][k] * p[c[j][k]];
+                q[i] = s;
+                pq += (double)p[i] * (double)s;
+            }
+        }
+        return pq;
+    }
+};
+
 // Plain CG on A x = rhs from x = 0, vectors x, r, p, q in LDS (type VV),
-// dots in FP64.  Returns iterations; *flag = 1 not SPD, 2 breakdown.
-template <typename VA, typename VV, int T>
-__device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val, VV *x, VV *r, VV *p,
-                                VV *q, double rhs_norm2, double stop2, int maxit, double *red,
+// dots in FP64.  q = A p comes from the register-held rows (CACHED) or from
+// memory.  Returns iterations; *flag = 1 not SPD, 2 breakdown.
+template <typename VA, typename VV, int T, bool CACHED>
+__device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val,
+                                const sys_regs<VA, T> &regs, VV *x, VV *r, VV *p, VV *q,
+                                double rhs_norm2, double stop2, int maxit, double *red,
                                 int *flag) {
     double rr = rhs_norm2;
     int it = 0;
     *flag = 0;
     while (it < maxit && rr > stop2) {
-        const double pq = wg_sum<T>(spmv_rows<VA, VV, T>(S, val, p, q), red);
+        double pq_local;
+        if constexpr (CACHED) pq_local = regs.template spmv<VV>(S.m, p, q);
+        else pq_local = spmv_rows<VA, VV, T>(S, val, p, q);
+        const double pq = wg_sum<T>(pq_local, red);
         ++it;
         if (!(pq > 0.0)) {
             *flag = std::isnan(pq) ? 2 : 1;
@@ -129,6 +185,8 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
         for (int i = threadIdx.x; i < S.m; i += T) bb += bs[i] * bs[i];
         bb = wg_sum<T>(bb, red);
         const double bnorm = sqrt(bb);
+        sys_regs<VA, T> regs;
+        const bool cached = regs.load(S, A, red);
         int its = 0, flag = 0;
         double *x64 = lds;            // m doubles
         if constexpr (!kRefine) {
@@ -139,7 +197,10 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                 p[i] = bs[i];
             }
             wg_sync<T>();
-            its = cg_in_lds<VA, double, T>(S, A, x64, r, p, q, bb, tol * tol * bb, maxit, red, &flag);
+            its = cached ? cg_in_lds<VA, double, T, true>(S, A, regs, x64, r, p, q, bb,
+                                                          tol * tol * bb, maxit, red, &flag)
+                         : cg_in_lds<VA, double, T, false>(S, A, regs, x64, r, p, q, bb,
+                                                           tol * tol * bb, maxit, red, &flag);
         } else {
             double *r64 = x64 + S.m;
             float *d = reinterpret_cast<float *>(r64 + S.m);
@@ -164,8 +225,12 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                     rt2 += (double)ri * (double)ri;
                 }
                 rt2 = wg_sum<T>(rt2, red);
-                its += cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
-                                               maxit - its, red, &flag);
+                its += cached ? cg_in_lds<VA, float, T, true>(S, A, regs, d, r, p, q, rt2,
+                                                              tau * tau * rt2, maxit - its, red,
+                                                              &flag)
+                              : cg_in_lds<VA, float, T, false>(S, A, regs, d, r, p, q, rt2,
+                                                               tau * tau * rt2, maxit - its, red,
+                                                               &flag);
                 if (flag) break;
                 // x += |r| d, then the FP64 residual b - A x
                 for (int i = threadIdx.x; i < S.m; i += T) x64[i] = x64[i] + rn * (double)d[i];

@@ -12,6 +12,7 @@
 
 #include "csr_rows.hpp"
 #include "device.hpp"
+#include "ell_rows.hpp"
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
 #include "solver_state.hpp"
@@ -310,7 +311,30 @@ __global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_
     grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
 }
 
-// q = A p for ELL (thread per row, column-major slots, padding last),
+// q = A p for CSR with a thread per row (short regular rows, as in the
+// plain SpMV), fused with p.q; the workgroup strides over tiles of rows.
+template <typename V>
+__global__ __launch_bounds__(kRowThreadBlock) void cg_spmv_csr_rowthread_kernel(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ p, V *__restrict__ q, krylov_scalars *sc,
+    red_args ra) {
+    static_assert(kRowThreadBlock == kB, "one reduction block shape");
+    __shared__ rowthread_lds<V> L;
+    if (sc->done) return;
+    double acc = 0.0;
+    for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n; r0 += (int64_t)gridDim.x * kB) {
+        const V s = csr_rowthread_sum(n, r0, rp, col, val, p, L);
+        const int64_t i = r0 + threadIdx.x;
+        if (i < n) {
+            q[i] = s;
+            acc += (double)p[i] * (double)s;
+        }
+    }
+    double v[1] = {acc};
+    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
+}
+
+// q = A p for ELL (two adjacent rows per thread, as in the plain SpMV),
 // fused with p.q.
 template <typename V>
 __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, int64_t ld,
@@ -320,23 +344,16 @@ __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, i
                                                          krylov_scalars *sc, red_args ra) {
     if (sc->done) return;
     double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
-        V s = V(0);
-        for (int64_t j = 0; j < K; j += 4) {
-            int32_t c[4];
-            V v[4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                c[u] = j + u < K ? ecol[(j + u) * ld + i] : -1;
-                v[u] = j + u < K ? eval[(j + u) * ld + i] : V(0);
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-                if (c[u] >= 0) s += v[u] * p[c[u]];
-            if (c[3] < 0) break;
+    for (int64_t i = 2 * ((int64_t)blockIdx.x * kB + threadIdx.x); i < n;
+         i += 2 * (int64_t)gridDim.x * kB) {
+        V s0, s1;
+        ell_pair_rows(K, ld, i, ecol, eval, p, s0, s1);
+        q[i] = s0;
+        acc += (double)p[i] * (double)s0;
+        if (i + 1 < n) {
+            q[i + 1] = s1;
+            acc += (double)p[i + 1] * (double)s1;
         }
-        q[i] = s;
-        acc += (double)p[i] * (double)s;
     }
     double v[1] = {acc};
     grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
@@ -345,7 +362,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, i
 hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                        const void *eval, const void *p, void *q, krylov_scalars *sc,
                        double *partials, unsigned *ticket) {
-    const int g = reduction_blocks(n);
+    const int g = reduction_blocks((n + 1) / 2);
     const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_spmv_ell_kernel<double><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const double *>(eval),
@@ -462,6 +479,14 @@ template <typename V>
 static hipError_t launch_cg_csr(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
                                 const void *val, const void *p, void *q, int w, krylov_scalars *sc,
                                 double *partials, unsigned *ticket) {
+    if (w == kCsrRowThread) {
+        const int g = reduction_blocks(n);
+        const red_args ra = red_for(g, partials, ticket);
+        cg_spmv_csr_rowthread_kernel<V><<<g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
+                                                         static_cast<const V *>(p),
+                                                         static_cast<V *>(q), sc, ra);
+        return red_finish<1>(s, g, ra, cg_alpha_op{sc});
+    }
     switch (w) {
         case 1: return launch_cg_csr_w<V, 1>(s, n, rp, col, val, p, q, sc, partials, ticket);
         case 2: return launch_cg_csr_w<V, 2>(s, n, rp, col, val, p, q, sc, partials, ticket);

@@ -56,4 +56,67 @@ __device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
     for (int u = 0; u < U; ++u) s[u] = subwarp<W>::reduce_sum(s[u]);
 }
 
+// Row-per-thread CSR for matrices whose rows are short and of similar
+// length: a workgroup of T threads owns T consecutive rows, stages their
+// entries (one contiguous range) through LDS in chunks of C with coalesced
+// loads, and each thread walks its own row's entries in the chunk.  The x
+// gathers of neighbouring threads then hit neighbouring columns for banded
+// and stencil patterns (as in ELL), unlike a subwarp per row, whose lanes
+// gather along one row.  Returns the thread's row sum (0 for rows >= n).
+// Measured on the 27-point stencil: 235 us with a 32-lane subwarp per row,
+// 171 us row-per-thread.
+constexpr int kRowThreadBlock = 256;
+constexpr int kRowThreadChunk = 2048;
+
+template <typename V>
+struct rowthread_lds {
+    int32_t col[kRowThreadChunk];
+    V val[kRowThreadChunk];
+};
+
+template <typename V>
+__device__ inline V csr_rowthread_sum(int64_t n, int64_t r0, const int32_t *__restrict__ rp,
+                                      const int32_t *__restrict__ col, const V *__restrict__ val,
+                                      const V *__restrict__ x, rowthread_lds<V> &L) {
+    constexpr int T = kRowThreadBlock, C = kRowThreadChunk;
+    const int64_t i = r0 + threadIdx.x;
+    const int64_t rl = r0 + T < n ? r0 + T : n;
+    const int32_t kb = rp[r0], ke = rp[rl];
+    const int32_t b = i < n ? rp[i] : ke, e = i < n ? rp[i + 1] : ke;
+    V s = V(0);
+    for (int32_t c0 = kb; c0 < ke; c0 += C) {
+        const int32_t cn = ke - c0 < C ? ke - c0 : C;
+        int32_t cc[C / T];
+        V vv[C / T];
+#pragma unroll
+        for (int j = 0; j < C / T; ++j) {
+            const int t = threadIdx.x + j * T;
+            cc[j] = t < cn ? load_stream(col + c0 + t) : 0;
+            vv[j] = t < cn ? load_stream(val + c0 + t) : V(0);
+        }
+#pragma unroll
+        for (int j = 0; j < C / T; ++j) {
+            const int t = threadIdx.x + j * T;
+            if (t < cn) {
+                L.col[t] = cc[j];
+                L.val[t] = vv[j];
+            }
+        }
+        __syncthreads();
+        const int32_t lo = (b > c0 ? b : c0) - c0;
+        const int32_t hi = (e < c0 + cn ? e : c0 + cn) - c0;
+        int32_t k = lo;
+        for (; k + 4 <= hi; k += 4) {  // four gathers in flight, summed in order
+            const V x0 = x[L.col[k]], x1 = x[L.col[k + 1]], x2 = x[L.col[k + 2]], x3 = x[L.col[k + 3]];
+            s += L.val[k] * x0;
+            s += L.val[k + 1] * x1;
+            s += L.val[k + 2] * x2;
+            s += L.val[k + 3] * x3;
+        }
+        for (; k < hi; ++k) s += L.val[k] * x[L.col[k]];
+        __syncthreads();
+    }
+    return s;
+}
+
 }  // namespace gko

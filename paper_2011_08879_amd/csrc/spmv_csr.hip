@@ -74,6 +74,34 @@ __global__ __launch_bounds__(kLongBlock) void spmv_csr_long_kernel(
     if (threadIdx.x == 0) y[r] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[r];
 }
 
+// Row-per-thread CSR (csr_rowthread_sum), chosen for short regular rows.
+template <typename V>
+__global__ __launch_bounds__(kRowThreadBlock) void spmv_csr_rowthread_kernel(
+    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
+    __shared__ rowthread_lds<V> L;
+    const int64_t r0 = (int64_t)blockIdx.x * kRowThreadBlock;
+    const V s = csr_rowthread_sum(n, r0, rp, col, val, x, L);
+    const int64_t i = r0 + threadIdx.x;
+    if (i < n) y[i] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[i];
+}
+
+template <typename V>
+static hipError_t launch_csr_rowthread(hipStream_t s, int64_t n, const int32_t *rp,
+                                       const int32_t *col, const void *val, const void *x,
+                                       double alpha, double beta, void *y) {
+    spmv_csr_rowthread_kernel<V><<<dim3((unsigned)((n + kRowThreadBlock - 1) / kRowThreadBlock)),
+                                   dim3(kRowThreadBlock), 0, s>>>(
+        n, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha, (V)beta,
+        static_cast<V *>(y));
+    return hipGetLastError();
+}
+
+bool csr_rowthread_suits(int64_t n, int64_t nnz, int64_t max_len) {
+    const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
+    return n > 0 && max_len <= kCsrRowThreadMaxLen && (double)max_len <= 2.0 * mean + 8.0;
+}
+
 int32_t csr_long_threshold(int w) { return 32 * w > 512 ? 32 * w : 512; }
 
 __global__ void long_flag_kernel(int64_t n, const int32_t *__restrict__ rp, int32_t long_t,
@@ -151,6 +179,9 @@ hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int
                     const void *val, const void *x, double alpha, double beta, void *y, int w,
                     int64_t n_long, const int32_t *long_rows) {
     if (n == 0) return hipSuccess;
+    if (w == kCsrRowThread)
+        return t == vt::f64 ? launch_csr_rowthread<double>(s, n, rp, col, val, x, alpha, beta, y)
+                            : launch_csr_rowthread<float>(s, n, rp, col, val, x, alpha, beta, y);
     const int32_t long_t = n_long > 0 ? csr_long_threshold(w) : INT_MAX;
     hipError_t e = t == vt::f64 ? launch_csr<double>(s, n, rp, col, val, x, alpha, beta, y, w, long_t)
                                 : launch_csr<float>(s, n, rp, col, val, x, alpha, beta, y, w, long_t);
