@@ -340,13 +340,12 @@ void refresh_long_rows(gko_matrix A) {
     }
 }
 
-// The CSR kernel for this matrix: a thread per row for short regular rows,
-// else a subwarp per row with the width from the mean row length; then the
-// list of rows too long for that width.
+// The CSR kernel for this matrix (csr_kernel_width: a thread per row for
+// short rows, else a subwarp per row), then the list of rows too long for
+// that subwarp width.
 void analyse_csr(gko_matrix A) {
     if (A->max_len < 0) A->max_len = A->n > 0 ? max_len_of_csr(A) : 0;
-    A->subwarp = csr_rowthread_suits(A->n, A->nnz, A->max_len) ? kCsrRowThread
-                                                               : csr_subwarp_width(A->n, A->nnz);
+    A->subwarp = csr_kernel_width(A->n, A->nnz, A->max_len);
     refresh_long_rows(A);
 }
 

@@ -56,8 +56,8 @@ __device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
     for (int u = 0; u < U; ++u) s[u] = subwarp<W>::reduce_sum(s[u]);
 }
 
-// Row-per-thread CSR for matrices whose rows are short and of similar
-// length: a workgroup of T threads owns T consecutive rows, stages their
+// Row-per-thread CSR for matrices with short rows (see csr_kernel_width):
+// a workgroup of T threads owns T consecutive rows, stages their
 // entries (one contiguous range) through LDS in chunks of C with coalesced
 // loads, and each thread walks its own row's entries in the chunk.  The x
 // gathers of neighbouring threads then hit neighbouring columns for banded

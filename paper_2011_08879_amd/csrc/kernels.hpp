@@ -16,11 +16,13 @@ inline size_t vsize(vt t) { return t == vt::f64 ? 8 : 4; }
 // than csr_long_threshold(w) are listed in long_rows (n_long of them) and
 // summed by a workgroup each.  w = kCsrRowThread: a thread per row with the
 // entries staged through LDS (for short rows of similar length, see
-// csr_rowthread_suits; no long rows then).
+// csr_kernel_width; no long rows then).
 constexpr int kCsrRowThread = 0;
-constexpr int64_t kCsrRowThreadMaxLen = 64;
+constexpr int64_t kCsrRowThreadMaxLen = 256;
+// Power of two >= the mean row length, at most 64.
 int csr_subwarp_width(int64_t n, int64_t nnz);
-bool csr_rowthread_suits(int64_t n, int64_t nnz, int64_t max_len);
+// The kernel for a matrix: kCsrRowThread or a subwarp width.
+int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len);
 int32_t csr_long_threshold(int w);
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
                     const void *val, const void *x, double alpha, double beta, void *y, int w,

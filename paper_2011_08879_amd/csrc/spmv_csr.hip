@@ -97,9 +97,25 @@ static hipError_t launch_csr_rowthread(hipStream_t s, int64_t n, const int32_t *
     return hipGetLastError();
 }
 
-bool csr_rowthread_suits(int64_t n, int64_t nnz, int64_t max_len) {
+// The CSR kernel for a matrix, from its mean and longest row (measured on
+// MI355X over 2D/3D stencils, banded, block-diagonal, uniform and lognormal
+// random patterns, n = 0.5-4M):
+//  * rows of at most 48 entries on average and 256 at most: a thread per row
+//    (2D Laplacian 92 -> 34 us, banded mean 32 173 -> 107 us, banded mean 48
+//    216 -> 173 us, lognormal rows with sigma 0.5 201 -> 180 us against the
+//    subwarp kernel);
+//  * longer rows that are regular (longest <= 4 x mean): a subwarp of about
+//    mean/4 lanes, four entries per lane (banded mean 64: 156 us with 64
+//    lanes, 150 us a thread per row, 120 us with 16 lanes; block-diagonal
+//    mean 70: 164, 159, 130 us);
+//  * otherwise a subwarp of about mean lanes plus the long-row kernel
+//    (lognormal rows with sigma 1.56: 223 us; a thread per row 910 us).
+int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len) {
     const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
-    return n > 0 && max_len <= kCsrRowThreadMaxLen && (double)max_len <= 2.0 * mean + 8.0;
+    if (n > 0 && max_len <= kCsrRowThreadMaxLen && mean <= 48.0) return kCsrRowThread;
+    const int w = csr_subwarp_width(n, nnz);
+    if ((double)max_len <= 4.0 * mean) return w >= 4 ? w / 4 : 1;
+    return w;
 }
 
 int32_t csr_long_threshold(int w) { return 32 * w > 512 ? 32 * w : 512; }
