@@ -21,7 +21,7 @@ namespace gko {
 // Sum over the workgroup with a fixed tree; every thread gets the total.
 template <int T>
 __device__ inline double wg_sum(double v, double *red) {
-    v = subwarp<kWave>::reduce_sum(v);
+    v = wave_total(v);
     if constexpr (T == kWave) {
         return v;
     } else {

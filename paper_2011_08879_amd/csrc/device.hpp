@@ -47,6 +47,16 @@ struct subwarp {
 };
 
 
+// Value of lane l (uniform across the wave) without an LDS round trip.
+__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ double lane_value(double v, int l) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ float lane_value(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+
 // ------------------------------------------------------------------ wave scans
 // Inclusive segmented sum over the 64 lanes of a wavefront whose keys do not
 // decrease with the lane index: afterwards each lane holds the sum of the
@@ -76,7 +86,35 @@ __device__ __forceinline__ void seg_step(float &p, int key) {
     const int v = move<CTRL, ROWS>(0, __float_as_int(p));
     if (k == key) p += __int_as_float(v);
 }
+
+// v plus v of the DPP source lane (0 where there is none).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double add_moved(double v) {
+    const int lo = move<CTRL, ROWS>(0, __double2loint(v));
+    const int hi = move<CTRL, ROWS>(0, __double2hiint(v));
+    return v + __hiloint2double(hi, lo);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float add_moved(float v) {
+    return v + __int_as_float(move<CTRL, ROWS>(0, __float_as_int(v)));
+}
 }  // namespace dpp
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane: the
+// DPP inclusive scan (row shifts, then the broadcasts of lanes 15 and 31)
+// leaves the total in lane 63, which readlane broadcasts.  DPP moves are
+// VALU operations, so this chain is much shorter than an LDS-crossbar
+// butterfly; the summation order is fixed.
+template <typename T>
+__device__ __forceinline__ T wave_total(T v) {
+    v = dpp::add_moved<dpp::kRowShr1, 0xf>(v);
+    v = dpp::add_moved<dpp::kRowShr2, 0xf>(v);
+    v = dpp::add_moved<dpp::kRowShr4, 0xf>(v);
+    v = dpp::add_moved<dpp::kRowShr8, 0xf>(v);
+    v = dpp::add_moved<dpp::kRowBcast15, 0xa>(v);
+    v = dpp::add_moved<dpp::kRowBcast31, 0xc>(v);
+    return lane_value(v, kWave - 1);
+}
 
 template <typename T>
 __device__ __forceinline__ void wave_segmented_scan(T &p, int key) {
@@ -88,35 +126,27 @@ __device__ __forceinline__ void wave_segmented_scan(T &p, int key) {
     dpp::seg_step<dpp::kRowBcast31, 0xc>(p, key);  // rows 2 and 3
 }
 
-// Value of lane l (uniform across the wave) without an LDS round trip.
-__device__ __forceinline__ int lane_value(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
-__device__ __forceinline__ double lane_value(double v, int l) {
-    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
-                            __builtin_amdgcn_readlane(__double2loint(v), l));
-}
-__device__ __forceinline__ float lane_value(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 
 __device__ inline int popcnt(uint32_t m) { return __popc(m); }
 __device__ inline int popcnt(uint64_t m) { return __popcll(m); }
 
 // ------------------------------------------------------------------ block reduction
 // Sum over a block of BLOCK threads (multiple of 64) with a fixed tree: wave
-// butterfly, then the per-wave sums combined by wave 0.  Result valid in
+// totals (wave_total), then the per-wave sums combined by wave 0.  Every
+// thread of the block must call it.  Result valid in
 // thread 0.  `lds` needs BLOCK/64 slots.
 template <int BLOCK, typename T>
 __device__ inline T block_sum(T v, T *lds) {
     static_assert(BLOCK % kWave == 0, "block of whole waves");
     constexpr int NW = BLOCK / kWave;
-    v = subwarp<kWave>::reduce_sum(v);
+    v = wave_total(v);
     const int w = threadIdx.x / kWave;
     if ((threadIdx.x % kWave) == 0) lds[w] = v;
     __syncthreads();
     T s = T(0);
     if (threadIdx.x < kWave) {
         s = (threadIdx.x < NW) ? lds[threadIdx.x] : T(0);
-        s = subwarp<kWave>::reduce_sum(s);
+        s = wave_total(s);
     }
     __syncthreads();
     return s;

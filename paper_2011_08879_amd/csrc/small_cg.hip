@@ -36,7 +36,7 @@ struct wg_reducer {
     int parity = 0;
     __device__ double operator()(double v) {
         constexpr int NW = T / kWave;
-        v = subwarp<kWave>::reduce_sum(v);
+        v = wave_total(v);
         double *red = slots[parity];
         parity ^= 1;
         if ((threadIdx.x % kWave) == 0) red[threadIdx.x / kWave] = v;
