@@ -324,7 +324,9 @@ int64_t max_len_of_csr(gko_matrix A);
 void refresh_long_rows(gko_matrix A) {
     A->drop(A->long_rows);
     A->n_long = 0;
-    if (A->n == 0 || A->subwarp == kCsrRowThread) return;
+    if (A->n == 0) return;
+    if (A->max_len < 0) A->max_len = max_len_of_csr(A);
+    if (!csr_has_long_rows(A->n, A->nnz, A->max_len, A->subwarp)) return;
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     dbuf flag(c, A->n * 4), pos(c, (A->n + 1) * 4), tmp(c, scan_tmp_elems(A->n) * 4);

@@ -23,6 +23,9 @@ constexpr int64_t kCsrRowThreadMaxLen = 256;
 int csr_subwarp_width(int64_t n, int64_t nnz);
 // The kernel for a matrix: kCsrRowThread or a subwarp width.
 int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len);
+// Whether rows longer than csr_long_threshold(w) get the workgroup-per-row
+// kernel: only for irregular rows (longest > 4 x mean).
+bool csr_has_long_rows(int64_t n, int64_t nnz, int64_t max_len, int w);
 int32_t csr_long_threshold(int w);
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
                     const void *val, const void *x, double alpha, double beta, void *y, int w,
