@@ -224,10 +224,10 @@ hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int
 // with coalesced loads, each thread walks IPT items of the merge
 // sequentially, and rows that cross thread boundaries are combined by a
 // segmented scan of the threads' carry-outs (a DPP scan inside each wave,
-// then the wave totals).  Small tiles (4 items per thread) keep many
-// workgroups resident, so loads of some overlap the walks of others.  The
-// staged products are padded by one slot per 8, so the threads' walks, which
-// start about IPT entries apart, fall into different LDS banks.  Rows crossing tile boundaries
+// then the wave totals).  Tiles of 4 items per thread measured best (2048
+// items 301 us, 1024 236 us, 512 275 us on the stencil, one workgroup per
+// tile).  The staged products are padded by one slot per 8, so the threads'
+// walks, which start about IPT entries apart, fall into different LDS banks.  Rows crossing tile boundaries
 // leave a carry per tile, added by a second kernel in ascending tile order,
 // so results are bitwise repeatable.
 constexpr int kMergeBlock = 256;
@@ -260,87 +260,116 @@ hipError_t merge_partition(hipStream_t s, int64_t n, int64_t nnz, const int32_t 
     return hipGetLastError();
 }
 
+
+// What a workgroup fetches for one tile before it needs it: the tile's start
+// on the merge path, its column indices and values (four per thread,
+// coalesced) and its row ends.
+template <typename V>
+struct merge_tile_in {
+    int32_t i0, k0, nrows, nk;
+    int32_t c[kMergeIpt];
+    V v[kMergeIpt];
+    int32_t re[kMergeIpt + 1];
+};
+
+template <typename V>
+__device__ inline void merge_fetch(int64_t w, int64_t n, const int32_t *__restrict__ rp,
+                                   const int32_t *__restrict__ col, const V *__restrict__ val,
+                                   const int32_t *__restrict__ part, merge_tile_in<V> &T) {
+    const int tid = threadIdx.x;
+    T.i0 = part[2 * w];
+    T.k0 = part[2 * w + 1];
+    T.nrows = part[2 * w + 2] - T.i0;
+    T.nk = part[2 * w + 3] - T.k0;
+#pragma unroll
+    for (int j = 0; j < kMergeIpt; ++j) {
+        const int t = tid + j * kMergeBlock;
+        const bool ok = t < T.nk;
+        T.c[j] = ok ? load_stream(col + T.k0 + t) : 0;
+        T.v[j] = ok ? load_stream(val + T.k0 + t) : V(0);
+    }
+#pragma unroll
+    for (int j = 0; j <= kMergeIpt; ++j) {
+        const int t = tid + j * kMergeBlock;
+        T.re[j] = (t <= T.nrows && (int64_t)T.i0 + t < n) ? rp[T.i0 + t + 1] - T.k0 : INT_MAX;
+    }
+}
+
+// Persistent: as many workgroups as fit on the chip at once, each taking
+// tiles w, w + grid, ...  While a workgroup walks tile w in LDS, the loads of
+// its next tile are already in flight (the x gathers of tile w were issued
+// first), so memory traffic does not stop during the LDS phase.  27-point
+// stencil: 231 us with one workgroup per tile, 188 us persistent.
 template <typename V>
 __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
-    int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    int64_t n, int64_t tiles, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const int32_t *__restrict__ part, const V *__restrict__ x, V alpha,
     V beta, V *__restrict__ y, int32_t *__restrict__ carry_row, V *__restrict__ carry_val) {
     __shared__ V prods[kMergeTile + kMergeTile / 8];  // entry t at t + t / 8
     __shared__ int32_t rend[kMergeTile + 1];
     __shared__ int32_t s_row[kMergeBlock];
     __shared__ V s_val[kMergeBlock];
+    __shared__ int32_t w_first[kMergeBlock / kWave], w_last[kMergeBlock / kWave];
+    __shared__ V w_tot[kMergeBlock / kWave];
 
     const int tid = threadIdx.x;
-    const int64_t w = blockIdx.x;
-    const int32_t i0 = part[2 * w], k0 = part[2 * w + 1];
-    const int32_t i1 = part[2 * w + 2], k1 = part[2 * w + 3];
-    const int nrows = i1 - i0;  // row ends inside this tile
-    const int nk = k1 - k0;     // entries inside this tile
-
-    {
-        // all of this thread's column and value loads first, then the gathers
-        int32_t c[kMergeIpt];
-        V v[kMergeIpt];
+    int64_t w = blockIdx.x;
+    if (w >= tiles) return;
+    merge_tile_in<V> cur;
+    merge_fetch(w, n, rp, col, val, part, cur);
+    for (; w < tiles; w += gridDim.x) {
+        V pr[kMergeIpt];
 #pragma unroll
         for (int j = 0; j < kMergeIpt; ++j) {
             const int t = tid + j * kMergeBlock;
-            const bool ok = t < nk;
-            c[j] = ok ? load_stream(col + k0 + t) : 0;
-            v[j] = ok ? load_stream(val + k0 + t) : V(0);
+            pr[j] = t < cur.nk ? cur.v[j] * x[cur.c[j]] : V(0);
         }
+        const bool more = w + gridDim.x < tiles;
+        merge_tile_in<V> nxt;
+        if (more) merge_fetch(w + gridDim.x, n, rp, col, val, part, nxt);
+        const int32_t i0 = cur.i0, nrows = cur.nrows, nk = cur.nk;
 #pragma unroll
         for (int j = 0; j < kMergeIpt; ++j) {
             const int t = tid + j * kMergeBlock;
-            if (t < nk) prods[t + (t >> 3)] = v[j] * x[c[j]];
+            if (t < nk) prods[t + (t >> 3)] = pr[j];
         }
-    }
-    for (int t = tid; t <= nrows; t += kMergeBlock)
-        rend[t] = ((int64_t)i0 + t < n) ? rp[i0 + t + 1] - k0 : INT_MAX;
-    __syncthreads();
+#pragma unroll
+        for (int j = 0; j <= kMergeIpt; ++j) {
+            const int t = tid + j * kMergeBlock;
+            if (t <= nrows) rend[t] = cur.re[j];
+        }
+        __syncthreads();
 
-    // This thread's start on the tile's merge path.
-    const int total = nrows + nk;
-    const int d = tid * kMergeIpt < total ? tid * kMergeIpt : total;
-    int lo = d - nk > 0 ? d - nk : 0;
-    int hi = d < nrows ? d : nrows;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (rend[mid] <= d - mid - 1) lo = mid + 1;
-        else hi = mid;
-    }
-    int i = lo, k = d - lo;
-    const int dend = d + kMergeIpt < total ? d + kMergeIpt : total;
-
-    V acc = V(0);
-    int first_row = -1;
-    V first_val = V(0);
-    // Along the tile's merge path i <= nrows and k < nk whenever an entry is
-    // consumed; the explicit bounds only keep every access in range.
-    for (int step = d; step < dend && i <= nrows; ++step) {
-        if (k < rend[i] && k < nk) {
-            acc += prods[k + (k >> 3)];
-            ++k;
-        } else {
-            const int64_t r = (int64_t)i0 + i;
-            if (first_row < 0) {
-                first_row = i;  // may continue a row begun by earlier threads
-                first_val = acc;
-            } else if (r < n) {
-                y[r] = (beta == V(0)) ? alpha * acc : alpha * acc + beta * y[r];
+        const int total = nrows + nk;
+        const int d = tid * kMergeIpt < total ? tid * kMergeIpt : total;
+        int lo = d - nk > 0 ? d - nk : 0;
+        int hi = d < nrows ? d : nrows;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rend[mid] <= d - mid - 1) lo = mid + 1;
+            else hi = mid;
+        }
+        int i = lo, k = d - lo;
+        const int dend = d + kMergeIpt < total ? d + kMergeIpt : total;
+        V acc = V(0);
+        int first_row = -1;
+        V first_val = V(0);
+        for (int step = d; step < dend && i <= nrows; ++step) {
+            if (k < rend[i] && k < nk) {
+                acc += prods[k + (k >> 3)];
+                ++k;
+            } else {
+                const int64_t r = (int64_t)i0 + i;
+                if (first_row < 0) {
+                    first_row = i;
+                    first_val = acc;
+                } else if (r < n) {
+                    y[r] = (beta == V(0)) ? alpha * acc : alpha * acc + beta * y[r];
+                }
+                acc = V(0);
+                ++i;
             }
-            acc = V(0);
-            ++i;
         }
-    }
-
-    // Carry-out of each thread: its partial of the row it stops in.  Inclusive
-    // segmented scan over threads (keys are non-decreasing row indices): a
-    // wave scan, then each thread adds the totals of the preceding waves that
-    // end in its row, nearest first, stopping at a wave that starts in
-    // another row.
-    {
-        __shared__ int32_t w_first[kMergeBlock / kWave], w_last[kMergeBlock / kWave];
-        __shared__ V w_tot[kMergeBlock / kWave];
         V sv = acc;
         const int sr = i;
         wave_segmented_scan(sv, sr);
@@ -356,19 +385,18 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
         s_row[tid] = sr;
         s_val[tid] = sv;
         __syncthreads();
-    }
-
-    if (first_row >= 0 && (int64_t)i0 + first_row < n) {
-        // The previous thread stopped in the row this thread emits first.
-        V v = first_val;
-        if (tid > 0) v += s_val[tid - 1];
-        const int64_t r = (int64_t)i0 + first_row;
-        y[r] = (beta == V(0)) ? alpha * v : alpha * v + beta * y[r];
-    }
-    if (tid == kMergeBlock - 1) {
-        const int64_t r = (int64_t)i0 + s_row[tid];
-        carry_row[w] = r < n ? (int32_t)r : -1;
-        carry_val[w] = s_val[tid];
+        if (first_row >= 0 && (int64_t)i0 + first_row < n) {
+            V v = first_val;
+            if (tid > 0) v += s_val[tid - 1];
+            const int64_t r = (int64_t)i0 + first_row;
+            y[r] = (beta == V(0)) ? alpha * v : alpha * v + beta * y[r];
+        }
+        if (tid == kMergeBlock - 1) {
+            const int64_t r = (int64_t)i0 + s_row[tid];
+            carry_row[w] = r < n ? (int32_t)r : -1;
+            carry_val[w] = s_val[tid];
+        }
+        if (more) cur = nxt;
     }
 }
 
@@ -393,8 +421,22 @@ static hipError_t launch_merge(hipStream_t s, int64_t n, int64_t nnz, const int3
                                const void *x, double alpha, double beta, void *y,
                                int32_t *carry_row, void *carry_val) {
     const int64_t tiles = merge_tiles(n, nnz);
-    spmv_merge_kernel<V><<<dim3((unsigned)tiles), dim3(kMergeBlock), 0, s>>>(
-        n, rp, col, static_cast<const V *>(val), part, static_cast<const V *>(x), (V)alpha,
+    // workgroups that fit on the device at once, per device
+    static int resident_of[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    int &resident = resident_of[dev];
+    if (!resident) {
+        int cus = 0, per = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, spmv_merge_kernel<V>, kMergeBlock, 0) !=
+                hipSuccess)
+            return hipErrorInvalidValue;
+        resident = cus * (per > 0 ? per : 1);
+    }
+    const int64_t grid = tiles < resident ? tiles : resident;
+    spmv_merge_kernel<V><<<dim3((unsigned)grid), dim3(kMergeBlock), 0, s>>>(
+        n, tiles, rp, col, static_cast<const V *>(val), part, static_cast<const V *>(x), (V)alpha,
         (V)beta, static_cast<V *>(y), carry_row, static_cast<V *>(carry_val));
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
