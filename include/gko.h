@@ -118,6 +118,10 @@ typedef struct gko_matrix_desc {
     int64_t ell_ld;        /* ELL / HYBRID: leading dimension, else 0 */
     int64_t coo_nnz;       /* COO: nnz; HYBRID: tail entries; else 0 */
     int64_t stored_bytes;  /* bytes of device storage held by the handle */
+    int32_t csr_kernel;    /* CSR: 0 = a thread per row (entries staged through LDS), else the
+                              lanes of the subwarp per row; other formats: -1 */
+    int32_t max_row_len;   /* longest row (-1 where not yet computed) */
+    int64_t csr_long_rows; /* CSR: rows handed to the workgroup-per-row kernel, else 0 */
 } gko_matrix_desc;
 gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out);
 

@@ -48,7 +48,8 @@ _st = ctypes.c_int
 class _MatrixDesc(ctypes.Structure):
     _fields_ = [("format", _i32), ("dtype", _i32), ("n_rows", _i64), ("n_cols", _i64),
                 ("nnz", _i64), ("ell_width", _i64), ("ell_ld", _i64), ("coo_nnz", _i64),
-                ("stored_bytes", _i64)]
+                ("stored_bytes", _i64), ("csr_kernel", _i32), ("max_row_len", _i32),
+                ("csr_long_rows", _i64)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -249,6 +250,9 @@ class Desc:
     ell_ld: int
     coo_nnz: int
     stored_bytes: int
+    csr_kernel: int      # CSR: 0 thread per row, else subwarp lanes; -1 otherwise
+    max_row_len: int
+    csr_long_rows: int
 
 
 class Matrix:
@@ -289,7 +293,8 @@ class Matrix:
         d = _MatrixDesc()
         _check(_lib.gko_matrix_describe(self.handle, ctypes.byref(d)))
         return Desc(FORMAT_NAMES[d.format], "f64" if d.dtype == F64 else "f32", d.n_rows,
-                    d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes)
+                    d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes,
+                    d.csr_kernel, d.max_row_len, d.csr_long_rows)
 
     @property
     def shape(self):

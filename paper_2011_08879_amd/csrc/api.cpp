@@ -1406,6 +1406,9 @@ gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out) {
         out->ell_ld = (A->fmt == GKO_FMT_ELL || A->fmt == GKO_FMT_HYBRID) ? A->ld : 0;
         out->coo_nnz = A->fmt == GKO_FMT_COO ? A->nnz : (A->fmt == GKO_FMT_HYBRID ? A->tnnz : 0);
         out->stored_bytes = A->stored_bytes();
+        out->csr_kernel = A->fmt == GKO_FMT_CSR ? A->subwarp : -1;
+        out->max_row_len = (int32_t)A->max_len;
+        out->csr_long_rows = A->fmt == GKO_FMT_CSR ? A->n_long : 0;
     });
 }
 

@@ -177,3 +177,40 @@ def test_auto_picks_a_format(g, cases):
     A = make(g, cases["stencil27_14"])
     A.convert("auto")
     assert A.describe().format in ("csr", "csr_merge", "coo", "ell", "hybrid")
+
+
+def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
+    """The CSR kernel follows the row-length rule (a thread per row for short
+    rows; a quarter-mean subwarp for long regular rows; a mean-width subwarp
+    plus the workgroup-per-row kernel for irregular rows), and each of these
+    paths meets the SpMV bound against the oracle."""
+    rng = np.random.default_rng(21)
+    lens = list(rng.integers(1, 4, 700))
+    lens[350] = 300
+    rp = np.zeros(701, np.int32)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(700, size=l, replace=False)) for l in lens]).astype(np.int32)
+    cases = {
+        "laplace2d": (gen_mod.laplace2d(40), 0, False),
+        "banded_mean64": (gen_mod.banded(12, 3000, 64, 48, 80), 16, False),
+        "banded_mean40": (gen_mod.banded(19, 3000, 40, 32, 48), 0, False),
+        "lognormal": (gen_mod.random_lognormal(4, 20000, max_len=3000), 16, True),
+        "one_long_row": ((rp, col, rng.uniform(-1, 1, len(col))), 4, True),
+    }
+    for name, (A, kernel, has_long) in cases.items():
+        M = g.Matrix.from_csr(*A)
+        d = M.describe()
+        lens = np.diff(A[0])
+        assert d.csr_kernel == kernel, (name, d)
+        assert d.max_row_len == lens.max(), (name, d)
+        assert (d.csr_long_rows > 0) == has_long, (name, d)
+        if has_long:
+            assert d.csr_long_rows == int((lens > max(4 * kernel, 64)).sum()), (name, d)
+        n = len(A[0]) - 1
+        x = gen_mod.uniform(7, n)
+        y = dev(np.full(n, np.nan))
+        g.spmv(M, 1.0, dev(x), 0.0, y)
+        ref = orc.spmv_dot2(A, x, 1.0, 0.0, np.zeros(n))
+        absy = orc.spmv_absbound(A, x, 1.0, 0.0, np.zeros(n))
+        assert_spmv_close(host(y), ref, absy, lens, False, name)
+        M.close()
