@@ -253,3 +253,29 @@ def test_stream_probe_exact(g, gen_mod):
         c = dev(np.full(m, np.nan))
         g.stream(g.STREAM_COPY, dev(a[:m]), c)
         assert np.array_equal(host(c), a[:m])
+
+
+def test_solver_statuses_large_grids(g, gen_mod, ctx):
+    """The failure statuses also come out right when the reductions finish in
+    the separate finalize kernel (grids of more than 64 blocks)."""
+    ctx.set_solver_opts(single_workgroup=0)
+    n = 200_000
+    L = g.Matrix.from_csr(*gen_mod.laplace2d(448))   # 200,704 rows
+    m = L.describe().n_rows
+    b = np.ones(m)
+    b[12345] = np.nan
+    assert g.cg(L, dev(b), dev(np.zeros(m)))["status"] == g.ERR_BREAKDOWN
+    info = g.cg(L, dev(np.ones(m)), dev(np.zeros(m)), tol=1e-10, maxit=7)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 7
+    d = np.ones(n)
+    d[n // 2] = -1.0
+    D = g.Matrix.from_csr(np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    rhs = np.zeros(n)
+    rhs[n // 2] = 1.0
+    assert g.cg(D, dev(rhs), dev(np.zeros(n)))["status"] == g.ERR_NOT_SPD
+    # BiCGSTAB on the same diagonal converges (it does not need SPD)
+    info = g.bicgstab(D, dev(rhs), dev(np.zeros(n)), tol=1e-12)
+    assert info["status"] == g.OK, info
+    x = dev(np.zeros(m))
+    info = g.cg(L, dev(np.ones(m)), x, tol=1e-8)
+    assert info["status"] == g.OK and info["true_rel_residual"] <= 1e-8
