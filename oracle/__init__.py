@@ -68,6 +68,10 @@ def _load():
     lib.orc_coo_to_csr.argtypes = [i64, i64, _i32p, _i32p, _f64p, _i32p, _i32p, _f64p]
     lib.orc_hyb_to_csr.argtypes = [i64, i32, i64, _i32p, _f64p, i64, _i32p, _i32p, _f64p,
                                    _i32p, _i32p, _f64p]
+    lib.orc_sellp_layout.argtypes = [i64, _i32p, i32, _i32p, _i64p]
+    lib.orc_sellp_layout.restype = i64
+    lib.orc_csr_to_sellp.argtypes = [i64, _i32p, _i32p, _f64p, i32, _i32p, _i64p, _i32p, _f64p]
+    lib.orc_sellp_to_csr.argtypes = [i64, i32, _i32p, _i64p, _i32p, _f64p, _i32p, _i32p, _f64p]
     lib.orc_dot.argtypes = [i64, _f64p, _f64p]
     lib.orc_dot.restype = f64
     lib.orc_norm2.argtypes = [i64, _f64p]
@@ -201,6 +205,33 @@ def hyb_to_csr(n: int, K: int, ld: int, ecol, evals, trow=None, tcol=None, tval=
     nnz = int((ecol >= 0).sum()) + trow.shape[0]
     rp, c, v = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz, np.float64)
     _load().orc_hyb_to_csr(n, K, ld, ecol, evals, trow.shape[0], trow, tcol, tval, rp, c, v)
+    return rp, c, v
+
+
+SELLP_SLICE = 64   # rows per SELL-P slice (one wavefront)
+
+
+def csr_to_sellp(A, C: int = SELLP_SLICE):
+    """SELL-P (sliced ELL, padding per slice): returns (widths, sets, col, val)."""
+    rp, col, val = _csr(A)
+    n = rp.shape[0] - 1
+    ns = (n + C - 1) // C
+    lib = _load()
+    widths, sets = np.empty(ns, np.int32), np.empty(ns + 1, np.int64)
+    slots = int(lib.orc_sellp_layout(n, rp, C, widths, sets))
+    sc, sv = np.empty(slots, np.int32), np.empty(slots, np.float64)
+    lib.orc_csr_to_sellp(n, rp, col, val, C, widths, sets, sc, sv)
+    return widths, sets, sc, sv
+
+
+def sellp_to_csr(n: int, widths, sets, scol, sval, C: int = SELLP_SLICE):
+    widths = np.ascontiguousarray(widths, np.int32)
+    sets = np.ascontiguousarray(sets, np.int64)
+    scol = np.ascontiguousarray(scol, np.int32)
+    sval = _f64(sval)
+    nnz = int((scol >= 0).sum())
+    rp, c, v = np.empty(n + 1, np.int32), np.empty(nnz, np.int32), np.empty(nnz, np.float64)
+    _load().orc_sellp_to_csr(n, C, widths, sets, scol, sval, rp, c, v)
     return rp, c, v
 
 

@@ -206,6 +206,61 @@ void orc_hyb_to_csr(int64_t n, int32_t K, int64_t ld, const int32_t *ecol, const
     }
 }
 
+/* SELL-P, the sliced ELL format with padding (Anzt, Tomov and Dongarra,
+ * "Implementing a sparse matrix vector product for the SELL-C/SELL-C-sigma
+ * formats on NVIDIA GPUs", 2014), without row sorting and with stride
+ * factor 1: rows are grouped in slices of C consecutive rows; slice s is
+ * padded to its own width w_s (its longest row) and stored column-major
+ * inside the slice.  Slot (j, r) of slice s -- the j-th entry of row
+ * i = s*C + r -- is at sets[s] + j*C + r, with sets[0] = 0 and
+ * sets[s+1] = sets[s] + w_s*C.  Padding (and rows i >= n of the last slice)
+ * is col = -1, val = +0.0.  Returns the number of slots, sets[nslices]. */
+int64_t orc_sellp_layout(int64_t n, const int32_t *rp, int32_t C, int32_t *widths, int64_t *sets) {
+    const int64_t ns = (n + C - 1) / C;
+    sets[0] = 0;
+    for (int64_t s = 0; s < ns; ++s) {
+        int32_t w = 0;
+        for (int64_t i = s * C; i < (s + 1) * C && i < n; ++i)
+            if (rp[i + 1] - rp[i] > w) w = rp[i + 1] - rp[i];
+        widths[s] = w;
+        sets[s + 1] = sets[s] + (int64_t)w * C;
+    }
+    return sets[ns];
+}
+
+void orc_csr_to_sellp(int64_t n, const int32_t *rp, const int32_t *ci, const double *v, int32_t C,
+                      const int32_t *widths, const int64_t *sets, int32_t *scol, double *sval) {
+    const int64_t ns = (n + C - 1) / C;
+    for (int64_t s = 0; s < ns; ++s)
+        for (int64_t j = 0; j < widths[s]; ++j)
+            for (int64_t r = 0; r < C; ++r) {
+                const int64_t i = s * C + r, slot = sets[s] + j * C + r;
+                const int64_t len = i < n ? rp[i + 1] - rp[i] : 0;
+                if (j < len) {
+                    scol[slot] = ci[rp[i] + j];
+                    sval[slot] = v[rp[i] + j];
+                } else {
+                    scol[slot] = -1;
+                    sval[slot] = 0.0;
+                }
+            }
+}
+
+/* SELL-P back to CSR: padding dropped, entries of a row in slot order. */
+void orc_sellp_to_csr(int64_t n, int32_t C, const int32_t *widths, const int64_t *sets,
+                      const int32_t *scol, const double *sval, int32_t *rp, int32_t *ci, double *v) {
+    int64_t k = 0;
+    rp[0] = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t s = i / C, r = i % C;
+        for (int64_t j = 0; j < widths[s]; ++j) {
+            const int64_t slot = sets[s] + j * C + r;
+            if (scol[slot] >= 0) { ci[k] = scol[slot]; v[k] = sval[slot]; ++k; }
+        }
+        rp[i + 1] = (int32_t)k;
+    }
+}
+
 /* ======================================================================
  * Dot products and norms: serial ascending sums.
  * ====================================================================== */

@@ -1,9 +1,11 @@
-"""Pins for the oracle's format conversions (CSR <-> COO / ELL / HYB).
+"""Pins for the oracle's format conversions (CSR <-> COO / ELL / HYB / SELL-P).
 
 Layouts are this library's definitions (the paper names the formats' role in
 Sec. 6.1 but not their layout): COO row-major triplets; ELL column-major with
 leading dimension n rounded up to 64 and padding col = -1, val = +0.0; HYB an
-ELL part of width K* (the byte-minimising split) plus a row-major COO tail.
+ELL part of width K* (the byte-minimising split) plus a row-major COO tail;
+SELL-P slices of C rows, each padded to its own width and column-major
+inside the slice (Anzt, Tomov and Dongarra 2014, unsorted, stride factor 1).
 Pinned by a hand-worked example, brute force and round-trip identities.
 """
 import numpy as np
@@ -128,3 +130,72 @@ def test_formats_give_same_spmv(orc, gen_mod):
     np.add.at(yh, tr, tv * x[tc])
     absy = orc.spmv_absbound(A, x)
     assert np.all(np.abs(yh - y) <= 1e-14 * absy.max())
+
+
+# --------------------------------------------------------------------------- SELL-P
+def test_hand_example_sellp(orc):
+    # slices of C = 2 rows: {0,1} width 2, {2,3} width 3, {4, pad row} width 1
+    w, sets, sc, sv = orc.csr_to_sellp(A5, 2)
+    assert list(w) == [2, 3, 1]
+    assert list(sets) == [0, 4, 10, 12]
+    # slot (j, r) of slice s at sets[s] + j*C + r
+    assert list(sc) == [0, -1, 2, -1,  1, 0, -1, 1, -1, 3,  3, -1]
+    assert list(sv) == [1.0, 0.0, 2.0, 0.0,  3.0, 4.0, 0.0, 5.0, 0.0, 6.0,  7.0, 0.0]
+    assert np.all(bits(sv[sc < 0]) == 0)                                # +0.0 padding
+
+
+def sellp_layout_bruteforce(rp, C):
+    lens = np.diff(rp).astype(np.int64)
+    n = len(lens)
+    ns = (n + C - 1) // C
+    padded = np.zeros(ns * C, np.int64)
+    padded[:n] = lens
+    w = padded.reshape(ns, C).max(axis=1) if ns else np.zeros(0, np.int64)
+    return w, np.concatenate([[0], np.cumsum(w * C)])
+
+
+@pytest.mark.parametrize("C", [1, 2, 7, 64])
+def test_sellp_layout_and_roundtrip(orc, gen_mod, C):
+    for name, A in matrices(gen_mod):
+        rp, ci, va = A
+        n = len(rp) - 1
+        w, sets, sc, sv = orc.csr_to_sellp(A, C)
+        bw, bsets = sellp_layout_bruteforce(rp, C)
+        assert np.array_equal(w, bw) and np.array_equal(sets, bsets), name
+        assert len(sc) == sets[-1] and int((sc >= 0).sum()) == len(ci), name
+        assert np.all(bits(sv[sc < 0]) == 0), name
+        back = orc.sellp_to_csr(n, w, sets, sc, sv, C)
+        assert np.array_equal(back[0], rp) and np.array_equal(back[1], ci), name
+        assert np.array_equal(bits(back[2]), bits(va)), name
+
+
+def test_sellp_special_cases(orc, gen_mod):
+    A = gen_mod.random_lognormal(31, 500, mean=6.0, sigma=1.0, max_len=80)
+    rp, ci, va = A
+    # C = 1: every slice is one row without padding, so SELL-P is CSR itself
+    w, sets, sc, sv = orc.csr_to_sellp(A, 1)
+    assert np.array_equal(sets, rp.astype(np.int64))
+    assert np.array_equal(sc, ci) and np.array_equal(bits(sv), bits(va))
+    # n <= C: one slice, which is ELL with leading dimension C
+    B = gen_mod.uniform_random(32, 50, 0, 9)
+    w, sets, sc, sv = orc.csr_to_sellp(B, 64)
+    K, ld, ec, ev = orc.csr_to_ell(B)
+    assert (len(w), int(w[0]), ld) == (1, K, 64)
+    assert np.array_equal(sc, ec) and np.array_equal(bits(sv), bits(ev))
+
+
+def test_sellp_spmv_from_layout(orc, gen_mod):
+    """y computed from the SELL-P arrays (plain numpy) equals CSR's product."""
+    A = gen_mod.random_lognormal(33, 900, mean=5.0, sigma=1.0, max_len=120)
+    n = len(A[0]) - 1
+    x = gen_mod.uniform(34, n)
+    C = 64
+    w, sets, sc, sv = orc.csr_to_sellp(A, C)
+    y = np.zeros(len(w) * C)
+    for s in range(len(w)):
+        blk_c = sc[sets[s]:sets[s + 1]].reshape(w[s], C)
+        blk_v = sv[sets[s]:sets[s + 1]].reshape(w[s], C)
+        y[s * C:(s + 1) * C] = np.where(blk_c >= 0, blk_v * x[np.maximum(blk_c, 0)], 0.0).sum(axis=0)
+    ref = orc.spmv(A, x)
+    assert np.all(np.abs(y[:n] - ref) <= 1e-14 * orc.spmv_absbound(A, x).max())
+    assert np.all(y[n:] == 0.0)
