@@ -52,6 +52,8 @@ def spmv_bytes(desc, s=8):
     if f == "hybrid":
         b = n * desc.ell_width * (s + 4) + desc.coo_nnz * (s + 8) + m * s + n * s
         return b + (n * s if desc.coo_nnz else 0)
+    if f == "sellp":
+        return desc.sellp_slots * (s + 4) + (desc.sellp_slices + 1) * 8 + m * s + n * s
     raise ValueError(f)
 
 
@@ -385,6 +387,7 @@ def run_sweep(args, g, gen, torch, result):
                                                            result["stream"]["triad_GB/s"]))
     roofline["frac_of_stream_copy"] = round(achieved / result["stream"]["copy_GB/s"], 4)
     result["config"]["frac_of_stream_copy"] = round(value / result["stream"]["copy_GB/s"], 4)
+    result["sellp"] = run_sellp(args, g, torch, base, mats, per_kernel)
     for e in mats:
         e["M"].close()
     for M in base.values():
@@ -393,6 +396,45 @@ def run_sweep(args, g, gen, torch, result):
     torch.cuda.empty_cache()
 
     return result, inputs
+
+
+def run_sellp(args, g, torch, base, mats, per_kernel):
+    """SELL-P (sliced ELL, 64-row slices, not sorted) on the sweep matrices, next to
+    ELL on the same matrix; outside the sweep aggregate, whose formats are fixed."""
+    out = {}
+    ell_ms = {p["matrix"]: p["ms"] for p in per_kernel if p["format"] == "ell"}
+    for name, M0 in base.items():
+        try:
+            M = M0.clone().convert("sellp")
+        except g.GkoError as e:
+            assert e.status == g.ERR_UNSUPPORTED
+            out[name] = {"skipped": "unsupported: SELL-P slots above 4x the CSR storage"}
+            continue
+        d = M.describe()
+        x = next(e["x"] for e in mats if e["matrix"] == name)
+        y = torch.empty(d.n_rows, dtype=torch.float64, device="cuda")
+        for _ in range(args.warmup):
+            g.spmv(M, 1.0, x, 0.0, y)
+        reps = max(args.steps, 10)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(reps):
+            g.spmv(M, 1.0, x, 0.0, y)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / reps
+        nb = spmv_bytes(d)
+        out[name] = {"ms": round(ms, 5), "GB/s": round(nb / (ms * 1e-3) / 1e9, 1),
+                     "frac_hbm_peak": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "alg_bytes": int(nb), "slots": d.sellp_slots,
+                     "padding_ratio": round(d.sellp_slots / max(d.nnz, 1), 4)}
+        if name in ell_ms:
+            out[name]["ell_ms_in_sweep"] = ell_ms[name]
+        log("sellp %-14s %8.4f ms %8.1f GB/s (slots/nnz %.4f)" %
+            (name, ms, out[name]["GB/s"], out[name]["padding_ratio"]))
+        M.close()
+    return out
 
 
 def main():

@@ -60,14 +60,24 @@ typedef enum gko_itype { GKO_I32 = 0, GKO_I64 = 1 } gko_itype;
  *              minimises n*K*(s+4) + (s+8)*tail(K) bytes (s = value size),
  *              ties to the smaller K.
  *  AUTO      : (gko_convert only) the context's selector model if one is set
- *              (gko_context_set_selector), else the fastest by timing. */
+ *              (gko_context_set_selector), else the fastest by timing of the
+ *              five formats above.
+ *  SELLP     : sliced ELL with padding (Anzt, Tomov and Dongarra 2014), not
+ *              sorted, stride factor 1: slices of 64 consecutive rows, slice s
+ *              padded to its own longest row w_s and column-major inside the
+ *              slice.  Entry j of row i = 64 s + r is slot sets[s] + 64 j + r,
+ *              sets[0] = 0, sets[s+1] = sets[s] + 64 w_s; padding (and rows
+ *              >= n_rows of the last slice) is col = -1, val = +0.0.  Not a
+ *              choice of AUTO or the selector, whose model scores the five
+ *              formats of Sec. 6.1. */
 typedef enum gko_format {
     GKO_FMT_CSR = 0,
     GKO_FMT_CSR_MERGE = 1,
     GKO_FMT_COO = 2,
     GKO_FMT_ELL = 3,
     GKO_FMT_HYBRID = 4,
-    GKO_FMT_AUTO = 5
+    GKO_FMT_AUTO = 5,
+    GKO_FMT_SELLP = 6
 } gko_format;
 
 typedef struct gko_context_s *gko_context;
@@ -122,6 +132,9 @@ typedef struct gko_matrix_desc {
                               lanes of the subwarp per row; other formats: -1 */
     int32_t max_row_len;   /* longest row (-1 where not yet computed) */
     int64_t csr_long_rows; /* CSR: rows handed to the workgroup-per-row kernel, else 0 */
+    int64_t sellp_slices;  /* SELLP: ceil(n_rows / sellp_slice), else 0 */
+    int64_t sellp_slots;   /* SELLP: sets[sellp_slices], slots incl. padding, else 0 */
+    int32_t sellp_slice;   /* SELLP: rows per slice (64), else 0 */
 } gko_matrix_desc;
 gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out);
 
@@ -136,6 +149,14 @@ gko_status gko_matrix_export_csr(gko_matrix A, int32_t *row_ptr, int32_t *col_id
  *   coo_row/coo_col/coo_val : coo_nnz          (COO; HYBRID tail) */
 gko_status gko_matrix_export_storage(gko_matrix A, int32_t *ell_col, void *ell_val,
                                      int32_t *coo_row, int32_t *coo_col, void *coo_val);
+/* Export the SELL-P arrays of a matrix stored as SELLP (else
+ * GKO_ERR_INVALID_ARG) into caller device buffers; NULL skips an array.
+ *   slice_sets   : sellp_slices + 1 int64 slot offsets
+ *   slice_widths : sellp_slices int32 widths
+ *   col / val    : sellp_slots columns (int32) / values (the matrix dtype)
+ * Synchronises the stream. */
+gko_status gko_matrix_export_sellp(gko_matrix A, int64_t *slice_sets, int32_t *slice_widths,
+                                   int32_t *col, void *val);
 
 /* ---------------------------------------------------------------- SpMV (Sec. 6.1) */
 
@@ -146,9 +167,9 @@ gko_status gko_matrix_export_storage(gko_matrix A, int32_t *ell_col, void *ell_v
 gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void *y);
 
 /* Convert A's storage in place to fmt; the logical matrix is unchanged.
- * Converting between any two formats is bit-exact.  ELL is refused with
- * GKO_ERR_UNSUPPORTED (A unchanged) when its padded storage would exceed 4x
- * the CSR storage.  GKO_FMT_AUTO asks the context's selector model, or
+ * Converting between any two formats is bit-exact.  ELL and SELLP are
+ * refused with GKO_ERR_UNSUPPORTED (A unchanged) when their padded slots
+ * would exceed 4x the CSR storage.  GKO_FMT_AUTO asks the context's selector model, or
  * without one times one SpMV in every feasible format and keeps the fastest.
  * Synchronises the stream. */
 gko_status gko_convert(gko_matrix A, gko_format fmt);

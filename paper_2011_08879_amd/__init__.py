@@ -33,7 +33,7 @@ OK, ERR_INVALID_ARG, ERR_DIM_MISMATCH, ERR_UNSUPPORTED, ERR_ALLOC, ERR_HIP = 0, 
 ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_NOT_SPD = 6, 7, 8
 F64, F32 = 0, 1
 I32, I64 = 0, 1
-FORMATS = {"csr": 0, "csr_merge": 1, "coo": 2, "ell": 3, "hybrid": 4, "auto": 5}
+FORMATS = {"csr": 0, "csr_merge": 1, "coo": 2, "ell": 3, "hybrid": 4, "auto": 5, "sellp": 6}
 FORMAT_NAMES = {v: k for k, v in FORMATS.items()}
 PREC_FP64, PREC_MIXED_IR = 0, 1
 PRECOND_NONE, PRECOND_BLOCK_JACOBI = 0, 1
@@ -49,7 +49,8 @@ class _MatrixDesc(ctypes.Structure):
     _fields_ = [("format", _i32), ("dtype", _i32), ("n_rows", _i64), ("n_cols", _i64),
                 ("nnz", _i64), ("ell_width", _i64), ("ell_ld", _i64), ("coo_nnz", _i64),
                 ("stored_bytes", _i64), ("csr_kernel", _i32), ("max_row_len", _i32),
-                ("csr_long_rows", _i64)]
+                ("csr_long_rows", _i64), ("sellp_slices", _i64), ("sellp_slots", _i64),
+                ("sellp_slice", _i32)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -78,6 +79,7 @@ _SIGS = {
     "gko_matrix_describe": [_vp, ctypes.POINTER(_MatrixDesc)],
     "gko_matrix_export_csr": [_vp, _vp, _vp, _vp],
     "gko_matrix_export_storage": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "gko_matrix_export_sellp": [_vp, _vp, _vp, _vp, _vp],
     "gko_spmv": [_vp, _f64, _vp, _f64, _vp],
     "gko_convert": [_vp, _st],
     "gko_dot": [_vp, _st, _i64, _vp, _vp, _vp],
@@ -253,6 +255,9 @@ class Desc:
     csr_kernel: int      # CSR: 0 thread per row, else subwarp lanes; -1 otherwise
     max_row_len: int
     csr_long_rows: int
+    sellp_slices: int    # SELLP: number of slices, else 0
+    sellp_slots: int     # SELLP: slots including padding, else 0
+    sellp_slice: int     # SELLP: rows per slice, else 0
 
 
 class Matrix:
@@ -294,7 +299,8 @@ class Matrix:
         _check(_lib.gko_matrix_describe(self.handle, ctypes.byref(d)))
         return Desc(FORMAT_NAMES[d.format], "f64" if d.dtype == F64 else "f32", d.n_rows,
                     d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes,
-                    d.csr_kernel, d.max_row_len, d.csr_long_rows)
+                    d.csr_kernel, d.max_row_len, d.csr_long_rows, d.sellp_slices, d.sellp_slots,
+                    d.sellp_slice)
 
     @property
     def shape(self):
@@ -344,6 +350,19 @@ class Matrix:
         _check(_lib.gko_matrix_export_storage(self.handle, _ptr(ec), _ptr(ev), _ptr(cr), _ptr(cc),
                                               _ptr(cv)))
         return out
+
+    def export_sellp(self) -> dict:
+        """Raw SELL-P arrays: slice offsets (int64), widths, slot columns and values."""
+        torch = _torch()
+        d = self.describe()
+        dev = torch.device("cuda", self.ctx.device)
+        sets = torch.empty(d.sellp_slices + 1, dtype=torch.int64, device=dev)
+        widths = torch.empty(d.sellp_slices, dtype=torch.int32, device=dev)
+        col = torch.empty(d.sellp_slots, dtype=torch.int32, device=dev)
+        val = torch.empty(d.sellp_slots, dtype=self.torch_dtype, device=dev)
+        _check(_lib.gko_matrix_export_sellp(self.handle, _ptr(sets), _ptr(widths), _ptr(col),
+                                            _ptr(val)))
+        return dict(sets=sets, widths=widths, col=col, val=val, slice=d.sellp_slice)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -161,8 +161,11 @@ struct gko_matrix_s {
     int32_t *part = nullptr;  // CSR_MERGE partition, 2 * (tiles + 1)
     int64_t tiles = 0;
     int64_t K = 0, ld = 0;    // ELL, HYBRID
-    int32_t *ecol = nullptr;
+    int32_t *ecol = nullptr;  // ELL / HYBRID slots; SELLP: the slice slots
     void *eval = nullptr;
+    int64_t slots = 0;        // SELLP: slots of all slices (sets[slices])
+    int64_t *sset = nullptr;  // SELLP: slices + 1 slot offsets
+    int32_t *swidth = nullptr;  // SELLP: width of each slice
     int64_t tnnz = 0;         // HYBRID tail
     int32_t *trow = nullptr, *tcol = nullptr;
     void *tval = nullptr;
@@ -181,6 +184,9 @@ struct gko_matrix_s {
 
     vt type() const { return dt == GKO_F64 ? vt::f64 : vt::f32; }
     size_t vs() const { return vsize(type()); }
+    int64_t slices() const { return (n + kSellpSlice - 1) / kSellpSlice; }
+    // elements of ecol / eval
+    int64_t ell_elems() const { return fmt == GKO_FMT_SELLP ? slots : K * ld; }
 
     void drop(void *&p) {
         ctx->free_bytes(p);
@@ -202,7 +208,8 @@ struct gko_matrix_s {
     void drop_storage() {
         drop(rp); drop(row); drop(col); drop(val); drop(part); drop(ecol); drop(eval);
         drop(trow); drop(tcol); drop(tval); drop(carry_a); drop(carry_b); drop(long_rows);
-        tiles = K = ld = tnnz = carry_elems = n_long = 0;
+        drop(sset); drop(swidth);
+        tiles = K = ld = tnnz = carry_elems = n_long = slots = 0;
         drop_caches();
     }
     int64_t stored_bytes() const {
@@ -213,6 +220,7 @@ struct gko_matrix_s {
             case GKO_FMT_COO: return nnz * (8 + s);
             case GKO_FMT_ELL: return K * ld * (4 + s);
             case GKO_FMT_HYBRID: return K * ld * (4 + s) + tnnz * (8 + s);
+            case GKO_FMT_SELLP: return slots * (4 + s) + (slices() + 1) * 8 + slices() * 4;
             default: return 0;
         }
     }
@@ -271,6 +279,9 @@ void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, d
                 HIPC(spmv_coo(s, v.t, A->n, A->tnnz, A->trow, A->tcol, v.tval, x, alpha, 1.0, y,
                               true, A->carry_a, A->carry_b));
             break;
+        case GKO_FMT_SELLP:
+            HIPC(spmv_sellp(s, v.t, A->n, A->sset, A->ecol, v.eval, x, alpha, beta, y));
+            break;
         default:
             fail(GKO_ERR_INVALID_ARG, "matrix has no storage format");
     }
@@ -308,6 +319,15 @@ void export_csr_into(gko_matrix A, const values &v, int32_t *rp, int32_t *col, v
             HIPC(exclusive_scan(s, A->n, len.as<int32_t>(), rp, tmp.as<int32_t>()));
             HIPC(hyb_to_csr(s, v.t, A->n, A->K, A->ld, A->ecol, v.eval, tptr.as<int32_t>(), A->tcol,
                             v.tval, rp, col, val));
+            c->sync();
+            break;
+        }
+        case GKO_FMT_SELLP: {
+            dbuf len(c, std::max<int64_t>(A->n, 1) * 4);
+            dbuf tmp(c, scan_tmp_elems(A->n) * 4);
+            HIPC(sellp_lengths(s, A->n, A->sset, A->ecol, len.as<int32_t>()));
+            HIPC(exclusive_scan(s, A->n, len.as<int32_t>(), rp, tmp.as<int32_t>()));
+            HIPC(sellp_to_csr(s, v.t, A->n, A->sset, A->ecol, v.eval, rp, col, val));
             c->sync();
             break;
         }
@@ -416,6 +436,28 @@ int64_t hyb_width_of_csr(gko_matrix A, int64_t maxlen) {
     return best;
 }
 
+// SELL-P layout of the rows given by the offsets rp (device): slice widths
+// from the device, slot offsets summed on the host in int64.
+struct sellp_layout {
+    std::vector<int32_t> widths;
+    std::vector<int64_t> sets;
+};
+
+sellp_layout sellp_layout_of(gko_matrix A, const int32_t *rp) {
+    gko_context c = A->ctx;
+    const int64_t ns = A->slices();
+    sellp_layout L;
+    L.widths.assign(ns, 0);
+    L.sets.assign(ns + 1, 0);
+    if (ns == 0) return L;
+    dbuf w(c, ns * 4);
+    HIPC(sellp_widths(c->stream, A->n, rp, w.as<int32_t>()));
+    HIPC(hipMemcpyAsync(L.widths.data(), w.p, ns * 4, hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    for (int64_t k = 0; k < ns; ++k) L.sets[k + 1] = L.sets[k] + (int64_t)L.widths[k] * kSellpSlice;
+    return L;
+}
+
 void csr_to_format(gko_matrix A, gko_format fmt) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
@@ -489,6 +531,25 @@ void csr_to_format(gko_matrix A, gko_format fmt) {
             A->fmt = fmt;
             return;
         }
+        case GKO_FMT_SELLP: {
+            const sellp_layout L = sellp_layout_of(A, A->rp);
+            const int64_t ns = A->slices();
+            dbuf sets(c, (ns + 1) * 8), widths(c, std::max<int64_t>(ns, 1) * 4);
+            dbuf scol(c, L.sets[ns] * 4), sval(c, L.sets[ns] * A->vs());
+            HIPC(hipMemcpyAsync(sets.p, L.sets.data(), (ns + 1) * 8, hipMemcpyHostToDevice, s));
+            HIPC(hipMemcpyAsync(widths.p, L.widths.data(), ns * 4, hipMemcpyHostToDevice, s));
+            HIPC(csr_to_sellp(s, A->type(), A->n, A->rp, A->col, A->val, sets.as<int64_t>(),
+                              scol.as<int32_t>(), sval.p));
+            c->sync();
+            A->drop_storage();
+            A->slots = L.sets[ns];
+            A->sset = static_cast<int64_t *>(sets.release());
+            A->swidth = static_cast<int32_t *>(widths.release());
+            A->ecol = static_cast<int32_t *>(scol.release());
+            A->eval = sval.release();
+            A->fmt = GKO_FMT_SELLP;
+            return;
+        }
         default:
             fail(GKO_ERR_INVALID_ARG, "unknown format");
     }
@@ -513,6 +574,27 @@ int64_t max_len_any(gko_matrix A) {
     return read_int(c, ml.as<int>());
 }
 
+// SELL-P is refused, like ELL, when its padded slots would take more than
+// 4x the CSR storage.
+void check_sellp_feasible(gko_matrix A) {
+    int64_t slots = 0;
+    if (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE) {
+        slots = sellp_layout_of(A, A->rp).sets.back();
+    } else {
+        gko_context c = A->ctx;
+        dbuf rp(c, (A->n + 1) * 4), col(c, A->nnz * 4), val(c, A->nnz * A->vs());
+        export_csr_into(A, own_values(A), rp.as<int32_t>(), col.as<int32_t>(), val.p);
+        slots = sellp_layout_of(A, rp.as<int32_t>()).sets.back();
+    }
+    const int64_t s = (int64_t)A->vs();
+    const double sellp = (double)slots * (double)(s + 4);
+    const double csr = (double)A->nnz * (double)(s + 4) + (double)(A->n + 1) * 4.0;
+    if (sellp > 4.0 * csr)
+        fail(GKO_ERR_UNSUPPORTED, "SELL-P storage would exceed 4x the CSR storage (" +
+                                      std::to_string(slots) + " slots for " +
+                                      std::to_string(A->nnz) + " nonzeros)");
+}
+
 void convert_to(gko_matrix A, gko_format fmt) {
     if (fmt == A->fmt) return;
     if (fmt == GKO_FMT_ELL) {
@@ -521,6 +603,7 @@ void convert_to(gko_matrix A, gko_format fmt) {
             fail(GKO_ERR_UNSUPPORTED, "ELL storage would exceed 4x the CSR storage (max row length " +
                                           std::to_string(maxlen) + ")");
     }
+    if (fmt == GKO_FMT_SELLP) check_sellp_feasible(A);
     A->drop_caches();
     to_csr(A);
     csr_to_format(A, fmt);
@@ -536,8 +619,8 @@ values f32_values(gko_matrix A) {
         HIPC(cast_values(s, vt::f64, vt::f32, A->nnz, A->val, A->val32));
     }
     if (A->eval && !A->eval32) {
-        A->eval32 = c->alloc_bytes(A->K * A->ld * 4);
-        HIPC(cast_values(s, vt::f64, vt::f32, A->K * A->ld, A->eval, A->eval32));
+        A->eval32 = c->alloc_bytes(A->ell_elems() * 4);
+        HIPC(cast_values(s, vt::f64, vt::f32, A->ell_elems(), A->eval, A->eval32));
     }
     if (A->tval && !A->tval32) {
         A->tval32 = c->alloc_bytes(A->tnnz * 4);
@@ -647,6 +730,9 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
                 } else if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
                     HIPC(cg_spmv_ell(s, v.t, n, A->K, A->ld, A->ecol, v.eval, p.p, q.p, S,
                                      partials.as<double>(), ticket.as<unsigned>()));
+                } else if (A->fmt == GKO_FMT_SELLP) {
+                    HIPC(cg_spmv_sellp(s, v.t, n, A->sset, A->ecol, v.eval, p.p, q.p, S,
+                                       partials.as<double>(), ticket.as<unsigned>()));
                 } else {
                     spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
                     HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
@@ -1364,6 +1450,7 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
             B->ctx = c; B->fmt = A->fmt; B->dt = A->dt; B->n = A->n; B->m = A->m; B->nnz = A->nnz;
             B->tiles = A->tiles; B->K = A->K; B->ld = A->ld; B->tnnz = A->tnnz; B->subwarp = A->subwarp;
             B->max_len = A->max_len;
+            B->slots = A->slots;
             auto copy = [&](const void *src, size_t bytes) -> void * {
                 if (!src) return nullptr;
                 void *d = c->alloc_bytes(bytes);
@@ -1376,8 +1463,10 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
             B->col = (int32_t *)copy(A->col, A->nnz * 4);
             B->val = copy(A->val, A->nnz * vb);
             B->part = (int32_t *)copy(A->part, 2 * (A->tiles + 1) * 4);
-            B->ecol = (int32_t *)copy(A->ecol, A->K * A->ld * 4);
-            B->eval = copy(A->eval, A->K * A->ld * vb);
+            B->ecol = (int32_t *)copy(A->ecol, A->ell_elems() * 4);
+            B->eval = copy(A->eval, A->ell_elems() * vb);
+            B->sset = (int64_t *)copy(A->sset, (A->slices() + 1) * 8);
+            B->swidth = (int32_t *)copy(A->swidth, A->slices() * 4);
             B->trow = (int32_t *)copy(A->trow, A->tnnz * 4);
             B->tcol = (int32_t *)copy(A->tcol, A->tnnz * 4);
             B->tval = copy(A->tval, A->tnnz * vb);
@@ -1409,6 +1498,10 @@ gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out) {
         out->csr_kernel = A->fmt == GKO_FMT_CSR ? A->subwarp : -1;
         out->max_row_len = (int32_t)A->max_len;
         out->csr_long_rows = A->fmt == GKO_FMT_CSR ? A->n_long : 0;
+        const bool sellp = A->fmt == GKO_FMT_SELLP;
+        out->sellp_slice = sellp ? kSellpSlice : 0;
+        out->sellp_slices = sellp ? A->slices() : 0;
+        out->sellp_slots = sellp ? A->slots : 0;
     });
 }
 
@@ -1445,6 +1538,24 @@ gko_status gko_matrix_export_storage(gko_matrix A, int32_t *ell_col, void *ell_v
     });
 }
 
+gko_status gko_matrix_export_sellp(gko_matrix A, int64_t *slice_sets, int32_t *slice_widths,
+                                   int32_t *col, void *val) {
+    return guarded([&] {
+        require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
+        require(A->fmt == GKO_FMT_SELLP, GKO_ERR_INVALID_ARG, "matrix is not stored as SELL-P");
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const int64_t ns = A->slices();
+        if (slice_sets)
+            HIPC(hipMemcpyAsync(slice_sets, A->sset, (ns + 1) * 8, hipMemcpyDeviceToDevice, s));
+        if (slice_widths)
+            HIPC(hipMemcpyAsync(slice_widths, A->swidth, ns * 4, hipMemcpyDeviceToDevice, s));
+        if (col) HIPC(hipMemcpyAsync(col, A->ecol, A->slots * 4, hipMemcpyDeviceToDevice, s));
+        if (val) HIPC(hipMemcpyAsync(val, A->eval, A->slots * A->vs(), hipMemcpyDeviceToDevice, s));
+        c->sync();
+    });
+}
+
 gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void *y) {
     return guarded([&] {
         require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
@@ -1459,7 +1570,7 @@ gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void
 gko_status gko_convert(gko_matrix A, gko_format fmt) {
     return guarded([&] {
         require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
-        require(fmt >= GKO_FMT_CSR && fmt <= GKO_FMT_AUTO, GKO_ERR_INVALID_ARG, "unknown format");
+        require(fmt >= GKO_FMT_CSR && fmt <= GKO_FMT_SELLP, GKO_ERR_INVALID_ARG, "unknown format");
         if (fmt == GKO_FMT_AUTO) {
             if (A->ctx->selector) {
                 convert_to(A, select_with(A, A->ctx->selector, nullptr));

@@ -3,6 +3,7 @@
 #pragma once
 
 #include "device.hpp"
+#include "kernels.hpp"
 
 namespace gko {
 
@@ -43,6 +44,19 @@ __device__ inline void ell_pair_rows(int64_t K, int64_t ld, int64_t i,
         }
         if (cc[3].x < 0 && cc[3].y < 0) break;
     }
+}
+
+// SELL-P: a slice is an ELL block of its own width with leading dimension
+// kSellpSlice, so the row pair (i, i+1) (i even) is read as in ELL from the
+// slice's base.  The pair never straddles two slices (kSellpSlice is even).
+template <typename V>
+__device__ inline void sellp_pair_rows(int64_t i, const int64_t *__restrict__ sets,
+                                       const int32_t *__restrict__ scol,
+                                       const V *__restrict__ sval, const V *__restrict__ x, V &s0,
+                                       V &s1) {
+    const int64_t sl = i / kSellpSlice;
+    const int64_t base = sets[sl], w = (sets[sl + 1] - base) / kSellpSlice;
+    ell_pair_rows(w, (int64_t)kSellpSlice, i - sl * kSellpSlice, scol + base, sval + base, x, s0, s1);
 }
 
 }  // namespace gko

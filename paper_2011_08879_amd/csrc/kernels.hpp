@@ -56,6 +56,15 @@ hipError_t spmv_coo(hipStream_t s, vt t, int64_t n, int64_t nnz, const int32_t *
 hipError_t spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                     const void *eval, const void *x, double alpha, double beta, void *y);
 
+// SELL-P (sliced ELL with padding): rows in slices of kSellpSlice, slice s
+// padded to its own longest row w_s and stored column-major inside the
+// slice; slot (j, r) of slice s -- entry j of row s*kSellpSlice + r -- is at
+// sets[s] + j*kSellpSlice + r, sets[s+1] = sets[s] + w_s*kSellpSlice.
+// Padding (and rows >= n of the last slice): col = -1, val = +0.0.
+constexpr int kSellpSlice = 64;
+hipError_t spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
+                      const void *sval, const void *x, double alpha, double beta, void *y);
+
 // y <- beta * y (beta == 0: y <- 0 without reading y).
 hipError_t scale(hipStream_t s, vt t, int64_t n, double beta, void *y);
 
@@ -86,6 +95,15 @@ hipError_t hyb_lengths(hipStream_t s, int64_t n, int64_t K, int64_t ld, const in
 hipError_t hyb_to_csr(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                       const void *eval, const int32_t *tail_ptr, const int32_t *tcol,
                       const void *tval, const int32_t *rp, int32_t *col, void *val);
+// SELL-P conversions: widths[s] = longest row of slice s; the slot arrays
+// from CSR given sets; row lengths and CSR arrays back from the slots.
+hipError_t sellp_widths(hipStream_t s, int64_t n, const int32_t *rp, int32_t *widths);
+hipError_t csr_to_sellp(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
+                        const void *val, const int64_t *sets, int32_t *scol, void *sval);
+hipError_t sellp_lengths(hipStream_t s, int64_t n, const int64_t *sets, const int32_t *scol,
+                         int32_t *len);
+hipError_t sellp_to_csr(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
+                        const void *sval, const int32_t *rp, int32_t *col, void *val);
 // Exclusive scan of n int32 lengths into n+1 offsets; tmp: scan_tmp_elems(n) ints.
 int64_t scan_tmp_elems(int64_t n);
 hipError_t exclusive_scan(hipStream_t s, int64_t n, const int32_t *len, int32_t *out, int32_t *tmp);

@@ -41,6 +41,9 @@ hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const 
 hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                        const void *eval, const void *p, void *q, krylov_scalars *sc,
                        double *partials, unsigned *ticket);
+hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
+                         const void *sval, const void *p, void *q, krylov_scalars *sc,
+                         double *partials, unsigned *ticket);
 hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
                  double *partials, unsigned *ticket);
 hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,

@@ -34,7 +34,7 @@ def sweep(gen_mod):
 
 
 @pytest.mark.parametrize("name,fmt", [("stencil27_128", f) for f in
-                                      ("csr", "csr_merge", "coo", "ell", "hybrid")] +
+                                      ("csr", "csr_merge", "coo", "ell", "hybrid", "sellp")] +
                          [("lognormal_1M", f) for f in ("csr", "csr_merge", "coo", "hybrid")])
 def test_sweep_spmv_full_size(g, orc, gen_mod, sweep, name, fmt):
     import torch
@@ -50,10 +50,13 @@ def test_sweep_spmv_full_size(g, orc, gen_mod, sweep, name, fmt):
     M.close()
 
 
-def test_lognormal_ell_refused(g, sweep):
+@pytest.mark.parametrize("fmt", ["ell", "sellp"])
+def test_lognormal_padded_formats_refused(g, sweep, fmt):
+    """Independent lognormal row lengths: ELL pads to 88x and unsorted SELL-P
+    slices to 15x the nonzeros, both above the 4x storage limit."""
     M = g.Matrix.from_csr(*sweep["lognormal_1M"])
     with pytest.raises(g.GkoError) as e:
-        M.convert("ell")
+        M.convert(fmt)
     assert e.value.status == g.ERR_UNSUPPORTED and M.describe().format == "csr"
 
 

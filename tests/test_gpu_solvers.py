@@ -30,7 +30,7 @@ def kappa_laplace2d(N):
 
 
 @pytest.mark.parametrize("fmt,single", [("csr", 1), ("csr", 0), ("csr_merge", 1), ("coo", 1),
-                                        ("ell", 1), ("hybrid", 1)])
+                                        ("ell", 1), ("hybrid", 1), ("sellp", 1)])
 def test_cg_config1_matches_oracle(g, orc, gen_mod, ctx, fmt, single):
     """single = 1: CSR systems this small run on one workgroup in one launch;
     single = 0 and the other formats: the multi-kernel path."""

@@ -12,7 +12,7 @@ from gpu_util import assert_spmv_close, dev, host, tiny_cases, workload_cases
 
 pytestmark = pytest.mark.gpu
 
-FORMATS = ["csr", "csr_merge", "coo", "ell", "hybrid"]
+FORMATS = ["csr", "csr_merge", "coo", "ell", "hybrid", "sellp"]
 
 
 @pytest.fixture(scope="module")
@@ -43,6 +43,22 @@ def ell_infeasible(case, vb=8):
     return K * ld * (vb + 4) > 4 * (len(col) * (vb + 4) + (n + 1) * 4)
 
 
+def sellp_infeasible(case, vb=8):
+    """SELL-P is refused by the same rule: padded slots above 4x the CSR storage."""
+    n, m, rp, col, val = case
+    lens = np.diff(rp).astype(np.int64)
+    ns = (n + 63) // 64
+    padded = np.zeros(ns * 64, np.int64)
+    padded[:n] = lens
+    slots = int(padded.reshape(ns, 64).max(axis=1).sum()) * 64 if ns else 0
+    return slots * (vb + 4) > 4 * (len(col) * (vb + 4) + (n + 1) * 4)
+
+
+def infeasible(fmt, case, vb=8):
+    return ((fmt == "ell" and ell_infeasible(case, vb)) or
+            (fmt == "sellp" and sellp_infeasible(case, vb)))
+
+
 @pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
 @pytest.mark.parametrize("fmt", FORMATS)
 def test_spmv_parity(g, orc, gen_mod, cases, fmt, f32):
@@ -50,9 +66,9 @@ def test_spmv_parity(g, orc, gen_mod, cases, fmt, f32):
     for name, case in cases.items():
         n, m, rp, col, val = case
         A = make(g, case, f32)
-        if fmt == "ell" and ell_infeasible(case, 4 if f32 else 8):
+        if infeasible(fmt, case, 4 if f32 else 8):
             with pytest.raises(g.GkoError) as e:
-                A.convert("ell")
+                A.convert(fmt)
             assert e.value.status == g.ERR_UNSUPPORTED
             assert A.describe().format == "csr"
             continue
@@ -85,7 +101,7 @@ def test_spmv_parity(g, orc, gen_mod, cases, fmt, f32):
 def test_spmv_deterministic(g, gen_mod, cases, fmt):
     import torch
     case = cases["lognormal_20k"]
-    if fmt == "ell":
+    if fmt in ("ell", "sellp"):
         case = cases["stencil27_14"]
     n, m = case[0], case[1]
     A = make(g, case).convert(fmt)
@@ -159,8 +175,28 @@ def test_conversions_bit_exact(g, orc, cases, f32):
             assert (s["K"], s["ld"]) == (K, ld), name
             assert np.array_equal(host(s["ell_col"]), ec), name
             assert np.array_equal(bits(host(s["ell_val"])), bits(ev.astype(vals.dtype))), name
+        # SELL-P
+        if not sellp_infeasible(case, 4 if f32 else 8):
+            A.convert("sellp")
+            d = A.describe()
+            s = A.export_sellp()
+            w, sets, sc, sv = orc.csr_to_sellp(Ah)
+            assert (s["slice"], d.sellp_slices, d.sellp_slots) == (64, len(w), sets[-1]), name
+            assert np.array_equal(host(s["sets"]), sets), name
+            assert np.array_equal(host(s["widths"]), w), name
+            assert np.array_equal(host(s["col"]), sc), name
+            assert np.array_equal(bits(host(s["val"])), bits(sv.astype(vals.dtype))), name
+            vb = 4 if f32 else 8
+            assert d.stored_bytes == sets[-1] * (vb + 4) + (len(w) + 1) * 8 + len(w) * 4, name
+            B = A.clone()
+            assert B.describe() == d
+            sb = B.export_sellp()
+            assert np.array_equal(host(sb["col"]), sc), name
+            B.close()
         # merge, and back to CSR from whatever is stored
-        for fmt in ["csr_merge", "coo", "hybrid", "csr"]:
+        for fmt in ["csr_merge", "coo", "hybrid", "sellp", "csr"]:
+            if fmt == "sellp" and sellp_infeasible(case, 4 if f32 else 8):
+                continue
             A.convert(fmt)
             erp, ecol, evl = (host(t) for t in A.export_csr())
             assert np.array_equal(erp, rp) and np.array_equal(ecol, col), (name, fmt)
@@ -177,6 +213,36 @@ def test_auto_picks_a_format(g, cases):
     A = make(g, cases["stencil27_14"])
     A.convert("auto")
     assert A.describe().format in ("csr", "csr_merge", "coo", "ell", "hybrid")
+
+
+def test_sellp_pads_per_slice(g, orc):
+    """One long row makes ELL pad every row to it; SELL-P pads only its slice."""
+    rng = np.random.default_rng(77)
+    n = 3000
+    lens = rng.integers(1, 9, n)
+    lens[1234] = 100
+    rp = np.zeros(n + 1, np.int32)
+    rp[1:] = np.cumsum(lens)
+    col = np.concatenate([np.sort(rng.choice(n, size=l, replace=False)) for l in lens]).astype(np.int32)
+    val = rng.uniform(-1, 1, len(col))
+    case = (n, n, rp, col, val)
+    assert ell_infeasible(case) and not sellp_infeasible(case)
+    A = make(g, case)
+    with pytest.raises(g.GkoError):
+        A.convert("ell")
+    A.convert("sellp")
+    d = A.describe()
+    w, sets, sc, sv = orc.csr_to_sellp((rp, col, val))
+    assert d.sellp_slots == sets[-1] and d.sellp_slots < 3 * len(col)   # ELL: 22x
+    # SELL-P to every other format and back is bit-exact
+    for fmt in ["coo", "sellp", "hybrid", "sellp", "csr_merge", "sellp"]:
+        A.convert(fmt)
+    s = A.export_sellp()
+    assert np.array_equal(host(s["col"]), sc) and np.array_equal(bits(host(s["val"])), bits(sv))
+    with pytest.raises(g.GkoError) as e:     # not stored as SELL-P
+        A.convert("csr")
+        A.export_sellp()
+    assert e.value.status == g.ERR_INVALID_ARG
 
 
 def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
