@@ -375,25 +375,21 @@ hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, co
     return red_finish<1>(s, g, ra, cg_alpha_op{sc});
 }
 
-// The same for SELL-P: rows 2t, 2t+1 read from their slice.
+// The same for SELL-P: a row per thread, a slice per wavefront (the
+// grid-stride step is a multiple of the slice size).
 template <typename V>
 __global__ __launch_bounds__(kB) void cg_spmv_sellp_kernel(int64_t n, const int64_t *__restrict__ sets,
                                                            const int32_t *__restrict__ scol,
                                                            const V *__restrict__ sval,
                                                            const V *__restrict__ p, V *__restrict__ q,
                                                            krylov_scalars *sc, red_args ra) {
+    static_assert(kB % kSellpSlice == 0, "whole slices per workgroup");
     if (sc->done) return;
     double acc = 0.0;
-    for (int64_t i = 2 * ((int64_t)blockIdx.x * kB + threadIdx.x); i < n;
-         i += 2 * (int64_t)gridDim.x * kB) {
-        V s0, s1;
-        sellp_pair_rows(i, sets, scol, sval, p, s0, s1);
+    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
+        const V s0 = sellp_row(i, sets, scol, sval, p);
         q[i] = s0;
         acc += (double)p[i] * (double)s0;
-        if (i + 1 < n) {
-            q[i + 1] = s1;
-            acc += (double)p[i + 1] * (double)s1;
-        }
     }
     double v[1] = {acc};
     grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
@@ -402,7 +398,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_sellp_kernel(int64_t n, const int6
 hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
                          const void *sval, const void *p, void *q, krylov_scalars *sc,
                          double *partials, unsigned *ticket) {
-    const int g = reduction_blocks((n + 1) / 2);
+    const int g = reduction_blocks(n);
     const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_spmv_sellp_kernel<double><<<g, kB, 0, s>>>(n, sets, scol, static_cast<const double *>(sval),

@@ -4,9 +4,9 @@
 // consecutive rows to that slice's longest row, instead of padding every row
 // to the longest row of the matrix as ELL does: irregular matrices store far
 // fewer padding slots, while the column-major slots inside a slice keep the
-// coalesced, reduction-free access of ELL.  A slice of 64 rows is 32 threads
-// (two rows each, 8- and 16-byte loads) and a workgroup of 256 threads
-// covers 8 slices.  No row sorting, stride factor 1.
+// coalesced, reduction-free access of ELL.  A slice of 64 rows is one
+// wavefront (a row per thread) and a workgroup of 256 threads covers 4
+// slices.  No row sorting, stride factor 1.
 #include "device.hpp"
 #include "ell_rows.hpp"
 #include "kernels.hpp"
@@ -16,8 +16,6 @@ namespace gko {
 namespace {
 
 constexpr int kSellpBlock = 256;
-constexpr int kSellpPairsPerSlice = kSellpSlice / 2;
-static_assert(kSellpSlice % 2 == 0, "row pairs must not straddle slices");
 
 inline unsigned blocks_for(int64_t n, int block) { return (unsigned)((n + block - 1) / block); }
 
@@ -28,18 +26,16 @@ __global__ __launch_bounds__(kSellpBlock) void spmv_sellp_kernel(int64_t n,
                                                                  const V *__restrict__ sval,
                                                                  const V *__restrict__ x, V alpha,
                                                                  V beta, V *__restrict__ y) {
-    const int64_t i = 2 * ((int64_t)blockIdx.x * kSellpBlock + threadIdx.x);
+    const int64_t i = (int64_t)blockIdx.x * kSellpBlock + threadIdx.x;
     if (i >= n) return;
-    V s0, s1;
-    sellp_pair_rows(i, sets, scol, sval, x, s0, s1);
+    const V s0 = sellp_row(i, sets, scol, sval, x);
     y[i] = (beta == V(0)) ? alpha * s0 : alpha * s0 + beta * y[i];
-    if (i + 1 < n) y[i + 1] = (beta == V(0)) ? alpha * s1 : alpha * s1 + beta * y[i + 1];
 }
 
 template <typename V>
 hipError_t launch_sellp(hipStream_t s, int64_t n, const int64_t *sets, const int32_t *scol,
                         const void *sval, const void *x, double alpha, double beta, void *y) {
-    spmv_sellp_kernel<V><<<blocks_for((n + 1) / 2, kSellpBlock), kSellpBlock, 0, s>>>(
+    spmv_sellp_kernel<V><<<blocks_for(n, kSellpBlock), kSellpBlock, 0, s>>>(
         n, sets, scol, static_cast<const V *>(sval), static_cast<const V *>(x), (V)alpha,
         (V)beta, static_cast<V *>(y));
     return hipGetLastError();
