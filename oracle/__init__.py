@@ -334,8 +334,9 @@ def batch_ir_cg(row_off, nnz_off, rp_local, col, val, b, tol: float = 1e-10, max
 
 # --------------------------------------------------------------------------- selector
 N_FEATURES = 32
-MLP_SHAPES = [(64, 32), (64,), (64, 64), (64,), (5, 64), (5,)]
-N_PARAMS = 6597
+N_CLASSES = 6      # SpMV formats scored: CSR, CSR merge, COO, ELL, HYB, SELL-P
+MLP_SHAPES = [(64, 32), (64,), (64, 64), (64,), (N_CLASSES, 64), (N_CLASSES,)]
+N_PARAMS = 6662
 
 
 def features(A, n_cols: int | None = None) -> np.ndarray:
@@ -349,16 +350,16 @@ def features(A, n_cols: int | None = None) -> np.ndarray:
 
 def mlp_forward(P, X) -> np.ndarray:
     X = np.ascontiguousarray(X, np.float64).reshape(-1, 32)
-    out = np.zeros((X.shape[0], 5))
+    out = np.zeros((X.shape[0], N_CLASSES))
     _load().orc_mlp_forward(X.shape[0], _f64(P), X, out)
     return out
 
 
 def mlp_loss_grad(P, X, Y, M):
-    """Masked mean-squared loss and its gradient w.r.t. the 6597 parameters."""
+    """Masked mean-squared loss and its gradient w.r.t. the 6662 parameters."""
     X = np.ascontiguousarray(X, np.float64).reshape(-1, 32)
-    Y = np.ascontiguousarray(Y, np.float64).reshape(-1, 5)
-    M = np.ascontiguousarray(M, np.float64).reshape(-1, 5)
+    Y = np.ascontiguousarray(Y, np.float64).reshape(-1, N_CLASSES)
+    M = np.ascontiguousarray(M, np.float64).reshape(-1, N_CLASSES)
     G = np.zeros(N_PARAMS)
     loss = _load().orc_mlp_loss_grad(X.shape[0], _f64(P), X, Y, M, G)
     return float(loss), G

@@ -2,7 +2,7 @@
  * ORACLE -- test infrastructure, not part of the product.
  *
  * Serial FP64 reference of the learned format selector's arithmetic: the 32
- * structural features of a CSR matrix and the MLP 32 -> 64 -> 64 -> 5
+ * structural features of a CSR matrix and the MLP 32 -> 64 -> 64 -> 6
  * (ReLU, ReLU, linear) with its masked mean-squared loss, the backward pass
  * and Adam (Kingma and Ba, ICLR 2015).  The paper has no selector; the
  * definitions are this library's (listed with the features below).
@@ -37,7 +37,9 @@ static int has_entry(const int32_t *rp, const int32_t *ci, int64_t row, int32_t 
  * 12 frac rows len<=4  13 ELL pad n*max/nnz   14 Kh / mean (Kh = HYB width) 15 HYB tail / nnz
  * 16 Gini of lengths   17 entropy of the length distribution (natural log)
  * 18 frac of nnz in the top ceil(n/100) longest rows
- * 19 log10 CSR working set 12 nnz + 4(n+1) + 8 m + 8 n   20 working set / 2^28
+ * 19 log10 CSR working set 12 nnz + 4(n+1) + 8 m + 8 n
+ * 20 SELL-P padding: slots of 64-row slices (64 x the slice's longest row,
+ *    summed over slices) / nnz
  * 21 m / n             22 mean |i-j| / m      23 max |i-j| / m     24 frac i == j
  * 25 frac |i-j| <= 1   26 frac |i-j| <= 64
  * 27 log10(1 + mean gap between consecutive columns of a row)
@@ -113,6 +115,13 @@ void orc_features(int64_t n, int64_t m, const int32_t *rp, const int32_t *ci, do
     }
     double dn = (double)n, dnz = nnz > 0 ? (double)nnz : 1.0, dm = m > 0 ? (double)m : 1.0;
     double ws = 12.0 * (double)nnz + 4.0 * (double)(n + 1) + 8.0 * (double)m + 8.0 * dn;
+    int64_t sellp = 0;
+    for (int64_t s0 = 0; s0 < n; s0 += 64) {
+        int64_t w = 0;
+        for (int64_t i = s0; i < s0 + 64 && i < n; ++i)
+            if (rp[i + 1] - rp[i] > w) w = rp[i + 1] - rp[i];
+        sellp += 64 * w;
+    }
     f[0] = n > 0 ? log10(dn) : 0.0;
     f[1] = log10(nnz > 0 ? (double)nnz : 1.0);
     f[2] = mean;
@@ -133,7 +142,7 @@ void orc_features(int64_t n, int64_t m, const int32_t *rp, const int32_t *ci, do
     f[17] = ent;
     f[18] = (double)topnnz / dnz;
     f[19] = log10(ws);
-    f[20] = ws / 268435456.0;
+    f[20] = nnz > 0 ? (double)sellp / (double)nnz : 1.0;
     f[21] = n > 0 ? (double)m / dn : 0.0;
     f[22] = (double)sabs / dnz / dm;
     f[23] = (double)mabs / dm;
@@ -148,15 +157,16 @@ void orc_features(int64_t n, int64_t m, const int32_t *rp, const int32_t *ci, do
 }
 
 /* ======================================================================
- * MLP 32 -> 64 -> 64 -> 5.  Parameters (6597), in order: W1[64][32], b1[64],
- * W2[64][64], b2[64], W3[5][64], b3[5] (row-major, out x in).
+ * MLP 32 -> 64 -> 64 -> 6 (one output per SpMV format: CSR, CSR merge, COO,
+ * ELL, HYB, SELL-P).  Parameters (6662), in order: W1[64][32], b1[64],
+ * W2[64][64], b2[64], W3[6][64], b3[6] (row-major, out x in).
  *   h1 = relu(W1 x + b1), h2 = relu(W2 h1 + b2), o = W3 h2 + b3
  * Loss over a batch: L = sum_{s,f} mask[s][f] (o[s][f] - y[s][f])^2 / sum mask.
  * relu'(0) = 0.
  * ====================================================================== */
 #define NI 32
 #define NH 64
-#define NO 5
+#define NO 6
 #define NPARAM (NH * NI + NH + NH * NH + NH + NO * NH + NO)
 
 static void mlp_forward1(const double *P, const double *x, double *h1, double *h2, double *o) {

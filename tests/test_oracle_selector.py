@@ -13,7 +13,7 @@ def test_features_tridiagonal_by_hand(orc, gen_mod):
             10: 3 / 2.8, 11: 0.0, 12: 1.0, 13: 30 / 28, 14: 3 / 2.8,   # K* = 3: 360 B < 368 B
             15: 0.0, 16: 2 / 35,            # sum |l_i - l_j| = 32 over ordered pairs
             17: -(0.2 * math.log(0.2) + 0.8 * math.log(0.8)), 18: 3 / 28,
-            19: math.log10(12 * 28 + 4 * 11 + 80 + 80), 20: 540 / 2 ** 28, 21: 1.0,
+            19: math.log10(12 * 28 + 4 * 11 + 80 + 80), 20: 64 * 3 / 28, 21: 1.0,   # one slice
             22: 18 / 28 / 10, 23: 0.1, 24: 10 / 28, 25: 1.0, 26: 1.0, 27: math.log10(2),
             28: 1.0, 29: 12 / 28,           # rows 7 and 8 straddle the column-8 boundary
             30: 1.0, 31: math.log10(1 + 28 / 10)}
@@ -27,6 +27,7 @@ def test_features_identity_and_rectangular(orc):
     f = orc.features(I)
     assert f[2] == 1 and f[3] == 0 and f[16] == 0 and f[17] == 0 and f[24] == 1
     assert f[27] == 0 and f[28] == 0 and f[29] == 1 and f[30] == 1 and f[18] == 1 / 100
+    assert f[20] == 128 / 100      # two 64-row slices of width 1
     # 3 x 5 with an empty row: rows {0: [1, 4]}, {1: []}, {2: [0, 1, 2]}
     A = (np.array([0, 2, 2, 5], np.int32), np.array([1, 4, 0, 1, 2], np.int32), np.ones(5))
     f = orc.features(A, n_cols=5)
@@ -34,6 +35,19 @@ def test_features_identity_and_rectangular(orc):
     assert f[22] == (1 + 4 + 2 + 1 + 0) / 5 / 5 and f[23] == 4 / 5
     assert abs(f[27] - math.log10(1 + (3 + 1 + 1) / 3)) < 1e-15 and f[28] == 2 / 3
     assert abs(f[31] - math.log10(1 + (4 + 3) / 2)) < 1e-15
+    assert f[20] == 64 * 3 / 5
+    # no entries: every padding ratio is 1 by convention
+    f = orc.features((np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0)))
+    assert f[13] == 1.0 and f[20] == 1.0
+
+
+def test_sellp_padding_feature_matches_layout(orc, gen_mod):
+    """Feature 20 against the slot count of the (separately pinned) SELL-P layout."""
+    for A in (gen_mod.random_lognormal(41, 5000, mean=8.0, sigma=1.2, max_len=500),
+              gen_mod.banded(42, 3001, 30, 1, 40), gen_mod.blockdiag(43, 2000, 4, 40),
+              gen_mod.stencil27(9)):
+        w, sets, sc, sv = orc.csr_to_sellp(A, 64)
+        assert orc.features(A)[20] == sets[-1] / len(A[1])
 
 
 def init_params(seed):
@@ -49,16 +63,16 @@ def init_params(seed):
 
 
 def orc_shapes():
-    return [(64, 32), (64,), (64, 64), (64,), (5, 64), (5,)]
+    return [(64, 32), (64,), (64, 64), (64,), (6, 64), (6,)]
 
 
 def test_mlp_gradient_matches_central_differences(orc):
     rng = np.random.default_rng(3)
     P = init_params(1)
-    assert P.size == orc.N_PARAMS == 6597
+    assert P.size == orc.N_PARAMS == 6662 and orc.N_CLASSES == 6
     X = rng.standard_normal((40, 32))
-    Y = rng.standard_normal((40, 5))
-    M = (rng.random((40, 5)) > 0.2).astype(float)
+    Y = rng.standard_normal((40, 6))
+    M = (rng.random((40, 6)) > 0.2).astype(float)
     loss, G = orc.mlp_loss_grad(P, X, Y, M)
     h = 1e-6
     for i in rng.choice(P.size, 60, replace=False):
@@ -70,16 +84,18 @@ def test_mlp_gradient_matches_central_differences(orc):
 
 
 def test_mlp_forward_by_hand(orc):
-    # W1 = [I_32; 0], W2 = I_64, W3 picks units 0..4, biases 0: o = relu(x)[0:5]
+    # W1 = [I_32; 0], W2 = I_64, W3 picks units 0..5 (unit 5 twice), b3 set:
+    # o = relu(x)[0:6] * (1, 1, 1, 1, 1, 2) + b3
     W1 = np.zeros((64, 32))
     W1[:32, :32] = np.eye(32)
-    W3 = np.zeros((5, 64))
-    W3[np.arange(5), np.arange(5)] = 1.0
-    P = np.concatenate([W1.ravel(), np.zeros(64), np.eye(64).ravel(), np.zeros(64), W3.ravel(),
-                        np.array([0.0, 1.0, 0.0, 0.0, -2.0])])
+    W3 = np.zeros((6, 64))
+    W3[np.arange(6), np.arange(6)] = 1.0
+    W3[5, 5] = 2.0
+    b3 = np.array([0.0, 1.0, 0.0, 0.0, -2.0, 0.5])
+    P = np.concatenate([W1.ravel(), np.zeros(64), np.eye(64).ravel(), np.zeros(64), W3.ravel(), b3])
     x = np.linspace(-2, 2, 32)
     o = orc.mlp_forward(P, x[None])[0]
-    assert np.array_equal(o, np.maximum(x[:5], 0) + np.array([0, 1, 0, 0, -2]))
+    assert np.array_equal(o, np.maximum(x[:6], 0) * np.array([1, 1, 1, 1, 1, 2]) + b3)
 
 
 def test_adam_first_step_closed_form_and_training_decreases(orc):
@@ -93,8 +109,8 @@ def test_adam_first_step_closed_form_and_training_decreases(orc):
     rng = np.random.default_rng(5)
     P = init_params(2)
     X = rng.standard_normal((64, 32))
-    Y = np.tanh(X[:, :5]) + 0.1
-    M = np.ones((64, 5))
+    Y = np.tanh(X[:, :6]) + 0.1
+    M = np.ones((64, 6))
     m, v = np.zeros_like(P), np.zeros_like(P)
     losses = []
     for t in range(1, 201):
