@@ -302,7 +302,8 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
  * 13 ELL padding n*max/nnz   14 HYB width / mean   15 HYB tail / nnz
  * 16 Gini of row lengths     17 entropy of the row-length distribution
  * 18 share of nnz in the longest ceil(n/100) rows
- * 19 log10 CSR working set (12 nnz + 4(n+1) + 8 n_cols + 8 n bytes)  20 that / 2^28
+ * 19 log10 CSR working set (12 nnz + 4(n+1) + 8 n_cols + 8 n bytes)
+ * 20 SELL-P padding: slots of the 64-row slices / nnz (1 when nnz = 0)
  * 21 n_cols / n   22 mean |i-j| / n_cols   23 max |i-j| / n_cols   24 frac i == j
  * 25 frac |i-j| <= 1   26 frac |i-j| <= 64   27 log10(1 + mean in-row column gap)
  * 28 frac of in-row gaps equal to 1   29 64-byte x segments touched per entry
@@ -311,33 +312,38 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
  * Percentile p: smallest L with #rows(len <= L) >= ceil(p n).  Synchronous. */
 gko_status gko_matrix_features(gko_matrix A, float *features);
 
-/* Exhaustive autotune: time one SpMV of a clone of A in every format
- * (CSR, CSR_MERGE, COO, ELL, HYBRID order; mean of 5 after 2 warm-ups;
- * infinity when a format is infeasible).  A is not changed.  *best (host)
- * receives the fastest, times_ms[5] (host, may be NULL) the timings. */
+/* The SpMV formats the autotuner times and the selector scores, in this
+ * order: CSR, CSR_MERGE, COO, ELL, HYBRID, SELLP. */
+#define GKO_SELECTOR_CLASSES 6
+
+/* Exhaustive autotune: time one SpMV of a clone of A in every format of the
+ * GKO_SELECTOR_CLASSES list (mean of 5 after 2 warm-ups; infinity when a
+ * format is infeasible).  A is not changed.  *best (host) receives the
+ * fastest, times_ms[GKO_SELECTOR_CLASSES] (host, may be NULL) the timings. */
 gko_status gko_autotune_format(gko_matrix A, gko_format *best, float *times_ms);
 
-/* The selector network: an MLP 32 -> 64 -> 64 -> 5 (ReLU, ReLU, linear) on
- * z-scored features, FP32.  Output f predicts ln(t_f / t_best) for the five
+/* The selector network: an MLP 32 -> 64 -> 64 -> 6 (ReLU, ReLU, linear) on
+ * z-scored features, FP32.  Output f predicts ln(t_f / t_best) for the six
  * formats in the order above; the selected format is the argmin among the
- * feasible ones.  Parameters (6597 floats): W1[64][32], b1[64], W2[64][64],
- * b2[64], W3[5][64], b3[5], row-major (out x in). */
+ * feasible ones (ELL and SELLP within the 4x storage limit).  Parameters
+ * (6662 floats): W1[64][32], b1[64], W2[64][64], b2[64], W3[6][64], b3[6],
+ * row-major (out x in). */
 typedef struct gko_mlp_s *gko_mlp;
 
-/* Create from initial parameters (host array of 6597 floats); normalisation
+/* Create from initial parameters (host array of 6662 floats); normalisation
  * starts as mean 0, std 1; Adam state at zero. */
 gko_status gko_mlp_create(gko_context ctx, const float *params, gko_mlp *out);
 gko_status gko_mlp_destroy(gko_mlp M);
-/* Copy parameters (6597) and normalisation (mean[32] then std[32]) to host;
+/* Copy parameters (6662) and normalisation (mean[32] then std[32]) to host;
  * either pointer may be NULL. */
 gko_status gko_mlp_get_params(gko_mlp M, float *params, float *norm);
 /* Per-feature mean and std (floored at 1e-6) of n samples X (device, n x 32). */
 gko_status gko_mlp_fit_normalization(gko_mlp M, int64_t n, const float *X);
-/* out (device, n x 5) <- network(X) for n samples X (device, n x 32). */
+/* out (device, n x 6) <- network(X) for n samples X (device, n x 32). */
 gko_status gko_mlp_forward(gko_mlp M, int64_t n, const float *X, float *out);
 /* Masked mean squared loss L = sum mask (out - Y)^2 / sum mask over n samples
- * (X: n x 32, Y and mask: n x 5, device) and its gradient.  grad: device
- * float[6597], loss: device double.  The backward pass uses relu'(0) = 0. */
+ * (X: n x 32, Y and mask: n x 6, device) and its gradient.  grad: device
+ * float[6662], loss: device double.  The backward pass uses relu'(0) = 0. */
 gko_status gko_mlp_loss_grad(gko_mlp M, int64_t n, const float *X, const float *Y,
                              const float *mask, float *grad, double *loss);
 /* steps full-batch Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning
@@ -346,11 +352,12 @@ gko_status gko_mlp_loss_grad(gko_mlp M, int64_t n, const float *X, const float *
 gko_status gko_mlp_train(gko_mlp M, int64_t n, const float *X, const float *Y, const float *mask,
                          int32_t steps, float lr, float *loss_history);
 /* Save / load parameters and normalisation (binary: magic "GKOMLP1", version,
- * parameter count, arch string, norm[64], params[6597]; little endian). */
+ * parameter count, arch string, norm[64], params[6662]; little endian).
+ * Loading refuses a file whose parameter count differs. */
 gko_status gko_mlp_save(gko_mlp M, const char *path);
 gko_status gko_mlp_load(gko_context ctx, const char *path, gko_mlp *out);
 
-/* Predicted-fastest feasible format of A; scores[5] (host, may be NULL)
+/* Predicted-fastest feasible format of A; scores[6] (host, may be NULL)
  * receive the network outputs.  A is not changed. */
 gko_status gko_select_format(gko_matrix A, gko_mlp model, gko_format *out, float *scores);
 /* Model used by gko_convert(A, GKO_FMT_AUTO) on this context (NULL: time all

@@ -505,8 +505,9 @@ class Batch:
 
 # ----------------------------------------------------------------------------- selector
 N_FEATURES = 32
-N_PARAMS = 6597
-SELECTOR_FORMATS = ("csr", "csr_merge", "coo", "ell", "hybrid")
+SELECTOR_FORMATS = ("csr", "csr_merge", "coo", "ell", "hybrid", "sellp")   # output order
+N_CLASSES = len(SELECTOR_FORMATS)
+N_PARAMS = 64 * 32 + 64 + 64 * 64 + 64 + N_CLASSES * 64 + N_CLASSES   # 6662
 
 
 def _fbuf(n):
@@ -521,15 +522,15 @@ def features(A: Matrix) -> np.ndarray:
 
 
 def autotune_format(A: Matrix):
-    """Time every format on clones of A.  Returns (best name, float32[5] ms; inf = infeasible)."""
+    """Time every format on clones of A.  Returns (best name, float32[6] ms; inf = infeasible)."""
     best = _st()
-    ms = _fbuf(5)
+    ms = _fbuf(N_CLASSES)
     _check(_lib.gko_autotune_format(A.handle, ctypes.byref(best), ms))
     return FORMAT_NAMES[best.value], np.frombuffer(ms, dtype=np.float32).copy()
 
 
 class Mlp:
-    """The selector network (32 -> 64 -> 64 -> 5), parameters and Adam state on the GPU."""
+    """The selector network (32 -> 64 -> 64 -> 6), parameters and Adam state on the GPU."""
 
     def __init__(self, params=None, ctx: Context | None = None, handle=None):
         self.ctx = ctx or default_context()
@@ -565,7 +566,7 @@ class Mlp:
 
     def forward(self, X):
         torch = _torch()
-        out = torch.empty((X.shape[0], 5), dtype=torch.float32, device=X.device)
+        out = torch.empty((X.shape[0], N_CLASSES), dtype=torch.float32, device=X.device)
         _check(_lib.gko_mlp_forward(self.handle, X.shape[0], _ptr(X), _ptr(out)))
         return out
 
@@ -586,9 +587,9 @@ class Mlp:
         return hist
 
     def select(self, A: Matrix):
-        """(format name, float32[5] scores) predicted for A."""
+        """(format name, float32[6] scores) predicted for A."""
         f = _st()
-        sc = _fbuf(5)
+        sc = _fbuf(N_CLASSES)
         _check(_lib.gko_select_format(A.handle, self.handle, ctypes.byref(f), sc))
         return FORMAT_NAMES[f.value], np.frombuffer(sc, dtype=np.float32).copy()
 

@@ -576,6 +576,13 @@ int64_t max_len_any(gko_matrix A) {
 
 // SELL-P is refused, like ELL, when its padded slots would take more than
 // 4x the CSR storage.
+bool sellp_feasible(gko_matrix A, int64_t slots) {
+    const int64_t s = (int64_t)A->vs();
+    const double sellp = (double)slots * (double)(s + 4);
+    const double csr = (double)A->nnz * (double)(s + 4) + (double)(A->n + 1) * 4.0;
+    return sellp <= 4.0 * csr;
+}
+
 void check_sellp_feasible(gko_matrix A) {
     int64_t slots = 0;
     if (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE) {
@@ -586,10 +593,7 @@ void check_sellp_feasible(gko_matrix A) {
         export_csr_into(A, own_values(A), rp.as<int32_t>(), col.as<int32_t>(), val.p);
         slots = sellp_layout_of(A, rp.as<int32_t>()).sets.back();
     }
-    const int64_t s = (int64_t)A->vs();
-    const double sellp = (double)slots * (double)(s + 4);
-    const double csr = (double)A->nnz * (double)(s + 4) + (double)(A->n + 1) * 4.0;
-    if (sellp > 4.0 * csr)
+    if (!sellp_feasible(A, slots))
         fail(GKO_ERR_UNSUPPORTED, "SELL-P storage would exceed 4x the CSR storage (" +
                                       std::to_string(slots) + " slots for " +
                                       std::to_string(A->nnz) + " nonzeros)");
@@ -968,7 +972,7 @@ gko_mlp new_mlp(gko_context ctx, const float *params_host, const float *norm_hos
 // same definitions as listed in the header (row-length statistics exact from
 // integer counts, ratios and logarithms in FP64, rounded to FP32 at the end).
 void finish_features(int64_t n, int64_t m, int64_t nnz, const std::vector<int> &h,
-                     const unsigned long long *c, float *out) {
+                     const unsigned long long *c, int64_t sellp_slots, float *out) {
     const int64_t maxl = (int64_t)h.size() - 1;
     const double dn = (double)n, dnz = nnz > 0 ? (double)nnz : 1.0, dm = m > 0 ? (double)m : 1.0;
     const double mean = n > 0 ? (double)nnz / dn : 0.0;
@@ -1048,7 +1052,7 @@ void finish_features(int64_t n, int64_t m, int64_t nnz, const std::vector<int> &
     f[17] = ent;
     f[18] = (double)topnnz / dnz;
     f[19] = std::log10(ws);
-    f[20] = ws / 268435456.0;
+    f[20] = nnz > 0 ? (double)sellp_slots / (double)nnz : 1.0;
     f[21] = n > 0 ? (double)m / dn : 0.0;
     f[22] = (double)c[0] / dnz / dm;
     f[23] = (double)c[1] / dm;
@@ -1063,8 +1067,8 @@ void finish_features(int64_t n, int64_t m, int64_t nnz, const std::vector<int> &
     for (int j = 0; j < kNumFeatures; ++j) out[j] = (float)f[j];
 }
 
-// Features of A into host memory (32 floats).
-void matrix_features(gko_matrix A, float *out) {
+// Features of A into host memory (32 floats); returns the SELL-P slot count.
+int64_t matrix_features(gko_matrix A, float *out) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     dbuf rpb, colb, valb;
@@ -1092,11 +1096,14 @@ void matrix_features(gko_matrix A, float *out) {
     HIPC(hipMemcpyAsync(cc, cnt.p, kFeatCounters * 8, hipMemcpyDeviceToHost, s));
     c->sync();
     if (A->n == 0) h.assign(1, 0);
-    finish_features(A->n, A->m, A->nnz, h, cc, out);
+    const int64_t slots = sellp_layout_of(A, rp).sets.back();
+    finish_features(A->n, A->m, A->nnz, h, cc, slots, out);
+    return slots;
 }
 
-const gko_format kAllFormats[5] = {GKO_FMT_CSR, GKO_FMT_CSR_MERGE, GKO_FMT_COO, GKO_FMT_ELL,
-                                   GKO_FMT_HYBRID};
+// The formats the autotuner times and the selector scores, in output order.
+const gko_format kAllFormats[kMlpOut] = {GKO_FMT_CSR, GKO_FMT_CSR_MERGE, GKO_FMT_COO,
+                                         GKO_FMT_ELL, GKO_FMT_HYBRID, GKO_FMT_SELLP};
 
 // Mean SpMV time of a clone of A in every format (infinity when infeasible);
 // A itself is not changed.
@@ -1110,7 +1117,7 @@ void time_formats(gko_matrix A, float *ms_out, int reps) {
     HIPC(hipEventCreate(&e0));
     HIPC(hipEventCreate(&e1));
     try {
-        for (int f = 0; f < 5; ++f) {
+        for (int f = 0; f < kMlpOut; ++f) {
             gko_matrix B = nullptr;
             if (gko_matrix_clone(A, &B) != GKO_OK) fail(GKO_ERR_ALLOC, g_last_error);
             try {
@@ -1145,17 +1152,19 @@ gko_format select_with(gko_matrix A, gko_mlp model, float *scores) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     float feat[kNumFeatures], sc[kMlpOut];
-    matrix_features(A, feat);
+    const int64_t slots = matrix_features(A, feat);
     dbuf fd(c, kNumFeatures * 4), od(c, kMlpOut * 4);
     HIPC(hipMemcpyAsync(fd.p, feat, kNumFeatures * 4, hipMemcpyHostToDevice, s));
     HIPC(mlp_forward(s, 1, fd.as<float>(), model->params, model->norm, od.as<float>()));
     HIPC(hipMemcpyAsync(sc, od.p, kMlpOut * 4, hipMemcpyDeviceToHost, s));
     c->sync();
     const bool ell_ok = ell_feasible(A, (int64_t)feat[6]);
+    const bool sellp_ok = sellp_feasible(A, slots);
     int best = -1;
     for (int f = 0; f < kMlpOut; ++f) {
         if (scores) scores[f] = sc[f];
         if (kAllFormats[f] == GKO_FMT_ELL && !ell_ok) continue;
+        if (kAllFormats[f] == GKO_FMT_SELLP && !sellp_ok) continue;
         if (best < 0 || sc[f] < sc[best]) best = f;
     }
     return kAllFormats[best];
@@ -1575,10 +1584,10 @@ gko_status gko_convert(gko_matrix A, gko_format fmt) {
             if (A->ctx->selector) {
                 convert_to(A, select_with(A, A->ctx->selector, nullptr));
             } else {
-                float ms[5];
+                float ms[kMlpOut];
                 time_formats(A, ms, 5);
                 int best = 0;
-                for (int f = 1; f < 5; ++f)
+                for (int f = 1; f < kMlpOut; ++f)
                     if (ms[f] < ms[best]) best = f;
                 convert_to(A, kAllFormats[best]);
             }
@@ -1630,10 +1639,10 @@ gko_status gko_matrix_features(gko_matrix A, float *features) {
 gko_status gko_autotune_format(gko_matrix A, gko_format *best, float *times_ms) {
     return guarded([&] {
         require(A != nullptr, GKO_ERR_INVALID_ARG, "null matrix");
-        float ms[5];
+        float ms[kMlpOut];
         time_formats(A, ms, 5);
         int b = 0;
-        for (int f = 0; f < 5; ++f) {
+        for (int f = 0; f < kMlpOut; ++f) {
             if (times_ms) times_ms[f] = ms[f];
             if (ms[f] < ms[b]) b = f;
         }

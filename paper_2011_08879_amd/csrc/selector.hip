@@ -1,5 +1,5 @@
 // Learned format selector: structural features of a CSR matrix and a small
-// MLP (32 -> 64 -> 64 -> 5, ReLU) trained with Adam, all in FP32 on the
+// MLP (32 -> 64 -> 64 -> 6, ReLU) trained with Adam, all in FP32 on the
 // vector ALUs (the network is far too small for matrix cores to matter).
 //
 // Features: the row-length statistics come from the row-length histogram;

@@ -8,9 +8,10 @@ namespace gko {
 
 constexpr int kFeatCounters = 12;
 constexpr int kNumFeatures = 32;
-constexpr int kMlpIn = 32, kMlpHidden = 64, kMlpOut = 5;
+// One output per SpMV format scored: CSR, CSR merge, COO, ELL, HYB, SELL-P.
+constexpr int kMlpIn = 32, kMlpHidden = 64, kMlpOut = 6;
 constexpr int kMlpParams = kMlpHidden * kMlpIn + kMlpHidden + kMlpHidden * kMlpHidden + kMlpHidden +
-                           kMlpOut * kMlpHidden + kMlpOut;  // 6597
+                           kMlpOut * kMlpHidden + kMlpOut;  // 6662
 constexpr int kMlpMaxBlocks = 128;
 
 // Exact integer counters over the entries (see selector.hip); cnt: 12 zeroed uint64.

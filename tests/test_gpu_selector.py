@@ -51,10 +51,12 @@ def test_mlp_forward_and_gradient_match_oracle(g, orc):
     import torch
     rng = np.random.default_rng(3)
     P = params(1)
-    P[6597 - 5 - 320 - 64:6597 - 5 - 320] = rng.uniform(-0.1, 0.1, 64)   # nonzero b2
+    assert P.size == g.N_PARAMS == orc.N_PARAMS and g.N_CLASSES == orc.N_CLASSES == 6
+    b2 = 64 * 32 + 64 + 64 * 64
+    P[b2:b2 + 64] = rng.uniform(-0.1, 0.1, 64)   # nonzero b2
     X = rng.standard_normal((300, 32)).astype(np.float32)
-    Y = rng.standard_normal((300, 5)).astype(np.float32)
-    M = (rng.random((300, 5)) > 0.25).astype(np.float32)
+    Y = rng.standard_normal((300, g.N_CLASSES)).astype(np.float32)
+    M = (rng.random((300, g.N_CLASSES)) > 0.25).astype(np.float32)
     model = g.Mlp(P)
     out = host(model.forward(dev(X)))
     ref = orc.mlp_forward(P.astype(np.float64), X.astype(np.float64))
@@ -75,8 +77,8 @@ def test_mlp_adam_steps_match_oracle(g, orc):
     rng = np.random.default_rng(4)
     P = params(2)
     X = rng.standard_normal((100, 32)).astype(np.float32)
-    Y = np.tanh(X[:, :5]).astype(np.float32)
-    M = np.ones((100, 5), np.float32)
+    Y = np.tanh(X[:, :g.N_CLASSES]).astype(np.float32)
+    M = np.ones((100, g.N_CLASSES), np.float32)
     model = g.Mlp(P)
     hist = host(model.train(dev(X), dev(Y), dev(M), 5, 1e-3))
     Pg, _ = model.params()
@@ -95,8 +97,8 @@ def test_mlp_training_decreases_and_persists(g, tmp_path):
     import torch
     rng = np.random.default_rng(5)
     X = rng.standard_normal((400, 32)).astype(np.float32) * 3 + 1
-    Y = np.stack([np.abs(X[:, k]) for k in range(5)], 1).astype(np.float32)
-    M = np.ones((400, 5), np.float32)
+    Y = np.stack([np.abs(X[:, k]) for k in range(g.N_CLASSES)], 1).astype(np.float32)
+    M = np.ones((400, g.N_CLASSES), np.float32)
     model = g.Mlp(params(3))
     model.fit_normalization(dev(X))
     _, norm = model.params()
@@ -109,21 +111,29 @@ def test_mlp_training_decreases_and_persists(g, tmp_path):
     assert np.array_equal(host(other.forward(dev(X))), host(model.forward(dev(X))))
 
 
-def test_autotune_select_and_auto_convert(g, gen_mod):
-    A = g.Matrix.from_csr(*gen_mod.random_lognormal(4, 20000, max_len=5000))
+def test_autotune_select_and_auto_convert(g, orc, gen_mod):
+    Ah = gen_mod.random_lognormal(4, 20000, max_len=5000)
+    w, sets, _, _ = orc.csr_to_sellp(Ah)
+    assert sets[-1] * 12 > 4 * (len(Ah[1]) * 12 + len(Ah[0]) * 4)   # SELL-P infeasible too
+    A = g.Matrix.from_csr(*Ah)
     best, ms = g.autotune_format(A)
-    assert np.isinf(ms[3]) and np.all(np.isfinite(ms[[0, 1, 2, 4]]))   # ELL infeasible
+    assert g.SELECTOR_FORMATS[3] == "ell" and g.SELECTOR_FORMATS[5] == "sellp"
+    assert np.isinf(ms[3]) and np.isinf(ms[5]) and np.all(np.isfinite(ms[[0, 1, 2, 4]]))
     assert best == g.SELECTOR_FORMATS[int(np.argmin(ms))]
     assert A.describe().format == "csr"                             # A untouched
     model = g.Mlp(params(4))
     fmt, scores = model.select(A)
-    assert fmt in g.SELECTOR_FORMATS and fmt != "ell" and scores.shape == (5,)
+    assert fmt in g.SELECTOR_FORMATS and fmt not in ("ell", "sellp") and scores.shape == (6,)
     g.set_selector(model)
     try:
         A.convert("auto")
         assert A.describe().format == fmt
     finally:
         g.set_selector(None)
+    # a regular matrix: every format feasible and timed
+    S = g.Matrix.from_csr(*gen_mod.stencil27(24))
+    best, ms = g.autotune_format(S)
+    assert np.all(np.isfinite(ms)) and best == g.SELECTOR_FORMATS[int(np.argmin(ms))]
 
 
 def test_small_corpus_training_beats_fixed_csr(g):
