@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-OK, NOT_CONVERGED, BREAKDOWN, NOT_SPD = 0, 6, 7, 8
+OK, BAD, NOT_CONVERGED, BREAKDOWN, NOT_SPD = 0, 1, 6, 7, 8
 
 _i32p = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
 _i64p = np.ctypeslib.ndpointer(dtype=np.int64, flags="C_CONTIGUOUS")
@@ -72,6 +72,8 @@ def _load():
     lib.orc_sellp_layout.restype = i64
     lib.orc_csr_to_sellp.argtypes = [i64, _i32p, _i32p, _f64p, i32, _i32p, _i64p, _i32p, _f64p]
     lib.orc_sellp_to_csr.argtypes = [i64, i32, _i32p, _i64p, _i32p, _f64p, _i32p, _i32p, _f64p]
+    lib.orc_cgs.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, _f64p]
+    lib.orc_gmres.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, i32, _f64p]
     lib.orc_dot.argtypes = [i64, _f64p, _f64p]
     lib.orc_dot.restype = f64
     lib.orc_norm2.argtypes = [i64, _f64p]
@@ -79,6 +81,7 @@ def _load():
     lib.orc_bj_invert.argtypes = [i64, _i32p, _i32p, _f64p, i32, _f64p]
     lib.orc_bj_apply.argtypes = [i64, i32, _f64p, _f64p, _f64p]
     lib.orc_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, vp, i32, _f64p]
+    lib.orc_fcg.argtypes = lib.orc_cg.argtypes
     lib.orc_bicgstab.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, _f64p]
     lib.orc_ir_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, f64, i32, vp,
                               i32, _f64p]
@@ -288,6 +291,39 @@ def bicgstab(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000):
     out = np.zeros(3)
     rc = _load().orc_bicgstab(n, rp, col, val, _f64(b), x, tol, maxit, out)
     return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2]}
+
+
+def fcg(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, bj_inv=None, bs: int = 8):
+    """Flexible (P)CG, Polak-Ribiere beta.  Returns (status, x, info) as cg()."""
+    rp, col, val = _csr(A)
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    out = np.zeros(4)
+    inv = None if bj_inv is None else _f64(np.asarray(bj_inv).reshape(-1))
+    rc = _load().orc_fcg(n, rp, col, val, _f64(b), x, tol, maxit,
+                         None if inv is None else inv.ctypes.data, bs, out)
+    return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2],
+                   "restarts": int(out[3])}
+
+
+def cgs(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000):
+    rp, col, val = _csr(A)
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    out = np.zeros(3)
+    rc = _load().orc_cgs(n, rp, col, val, _f64(b), x, tol, maxit, out)
+    return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2]}
+
+
+def gmres(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, m: int = 30):
+    """Restarted GMRES(m).  info = {iters (Arnoldi steps), relres, true_relres, cycles}."""
+    rp, col, val = _csr(A)
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    out = np.zeros(4)
+    rc = _load().orc_gmres(n, rp, col, val, _f64(b), x, tol, maxit, m, out)
+    return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2],
+                   "cycles": int(out[3])}
 
 
 def ir_cg(A, b, x0=None, tol: float = 1e-10, max_outer: int = 20, inner_tol: float = 1e-5,

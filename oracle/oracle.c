@@ -495,6 +495,256 @@ done:
 }
 
 /* ======================================================================
+ * Flexible CG (Notay, SIAM J. Sci. Comput. 22, 2000, truncated to one
+ * previous direction), optionally preconditioned.  CG with the
+ * Polak-Ribiere coefficient
+ *   beta = z_{k+1}.(r_{k+1} - r_k) / (z_k.r_k),
+ * which keeps consecutive directions A-conjugate when the preconditioner is
+ * not a fixed symmetric operator; with a fixed SPD preconditioner it equals
+ * CG's beta in exact arithmetic (z_{k+1}.r_k = 0).  Stopping, true-residual
+ * restarts and outputs as orc_cg.
+ * ====================================================================== */
+int orc_fcg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            const double *b, double *x, double tol, int32_t maxit,
+            const double *bj_inv, int32_t bs, double *out) {
+    double *r = (double *)malloc(sizeof(double) * n);
+    double *r_old = (double *)malloc(sizeof(double) * n);
+    double *z = (double *)malloc(sizeof(double) * n);
+    double *p = (double *)malloc(sizeof(double) * n);
+    double *q = (double *)malloc(sizeof(double) * n);
+    int rc = ORC_NOT_CONVERGED;
+    int32_t it = 0, restarts = 0;
+    double bnorm = orc_norm2(n, b), rnorm = 0.0, tnorm = 0.0;
+    if (!(bnorm > 0.0)) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        rc = (bnorm == 0.0) ? ORC_OK : ORC_BREAKDOWN;
+        goto done;
+    }
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, r);
+        rnorm = orc_norm2(n, r);
+        int conv = rnorm <= tol * bnorm;
+        if (!conv) {
+            if (bj_inv) orc_bj_apply(n, bs, bj_inv, r, z);
+            else for (int64_t i = 0; i < n; ++i) z[i] = r[i];
+            for (int64_t i = 0; i < n; ++i) p[i] = z[i];
+            double rho = orc_dot(n, r, z);
+            while (it < maxit) {
+                orc_csr_spmv(n, rp, ci, v, p, 1.0, 0.0, q);
+                double pq = orc_dot(n, p, q);
+                if (!(pq > 0.0)) { rc = isnan(pq) ? ORC_BREAKDOWN : ORC_NOT_SPD; ++it; goto done; }
+                double alpha = rho / pq;
+                for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * p[i];
+                for (int64_t i = 0; i < n; ++i) r_old[i] = r[i];
+                for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * q[i];
+                ++it;
+                rnorm = orc_norm2(n, r);
+                if (isnan(rnorm) || isinf(rnorm)) { rc = ORC_BREAKDOWN; goto done; }
+                if (rnorm <= tol * bnorm) { conv = 1; break; }
+                if (bj_inv) orc_bj_apply(n, bs, bj_inv, r, z);
+                else for (int64_t i = 0; i < n; ++i) z[i] = r[i];
+                double rho_new = orc_dot(n, r, z);
+                double zt = 0.0;   /* z_{k+1}.(r_{k+1} - r_k) */
+                for (int64_t i = 0; i < n; ++i) zt += z[i] * (r[i] - r_old[i]);
+                double beta = zt / rho;
+                rho = rho_new;
+                for (int64_t i = 0; i < n; ++i) p[i] = z[i] + beta * p[i];
+            }
+        }
+        if (!conv) { rc = ORC_NOT_CONVERGED; break; }
+        for (int64_t i = 0; i < n; ++i) q[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, q);
+        tnorm = orc_norm2(n, q);
+        if (tnorm <= tol * bnorm) { rc = ORC_OK; break; }
+        if (restarts == 2 || it >= maxit) { rc = ORC_NOT_CONVERGED; break; }
+        ++restarts;
+    }
+done:
+    if (out) {
+        for (int64_t i = 0; i < n; ++i) q[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, q);
+        tnorm = orc_norm2(n, q);
+        out[0] = it;
+        out[1] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        out[2] = bnorm > 0.0 ? tnorm / bnorm : 0.0;
+        out[3] = restarts;
+    }
+    free(r); free(r_old); free(z); free(p); free(q);
+    return rc;
+}
+
+/* ======================================================================
+ * CGS, conjugate gradients squared (Sonneveld, SIAM J. Sci. Stat. Comput.
+ * 10, 1989; Saad Alg. 7.5), unpreconditioned, shadow residual rhat = r0:
+ *   p = u = r0;  rho = r.rhat
+ *   repeat: v = A p;  alpha = rho / (v.rhat);  q = u - alpha v;
+ *           x += alpha (u + q);  r -= alpha A (u + q);
+ *           stop when ||r||_2 <= tol ||b||_2;
+ *           rho' = r.rhat;  beta = rho'/rho;  u = r + beta q;
+ *           p = u + beta (q + beta p).
+ * Breakdown when |rho| or |v.rhat| falls below 1e-300.
+ * out[0] = iterations, out[1] = recursive relres, out[2] = true relres.
+ * ====================================================================== */
+int orc_cgs(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+            const double *b, double *x, double tol, int32_t maxit, double *out) {
+    double *r = (double *)calloc(n, sizeof(double));
+    double *rh = (double *)calloc(n, sizeof(double));
+    double *p = (double *)calloc(n, sizeof(double));
+    double *u = (double *)calloc(n, sizeof(double));
+    double *q = (double *)calloc(n, sizeof(double));
+    double *w = (double *)calloc(n, sizeof(double));
+    double *t = (double *)calloc(n, sizeof(double));
+    int rc = ORC_NOT_CONVERGED;
+    int32_t it = 0;
+    double bnorm = orc_norm2(n, b), rnorm = 0.0;
+    if (!(bnorm > 0.0)) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        rc = (bnorm == 0.0) ? ORC_OK : ORC_BREAKDOWN;
+        goto done;
+    }
+    for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+    orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, r);
+    rnorm = orc_norm2(n, r);
+    if (rnorm <= tol * bnorm) { rc = ORC_OK; goto done; }
+    for (int64_t i = 0; i < n; ++i) { rh[i] = r[i]; p[i] = r[i]; u[i] = r[i]; }
+    double rho = orc_dot(n, r, rh);
+    while (it < maxit) {
+        if (!(fabs(rho) >= 1e-300)) { rc = ORC_BREAKDOWN; goto done; }
+        orc_csr_spmv(n, rp, ci, v, p, 1.0, 0.0, t);          /* t = A p */
+        double vr = orc_dot(n, t, rh);
+        if (!(fabs(vr) >= 1e-300)) { rc = ORC_BREAKDOWN; goto done; }
+        double alpha = rho / vr;
+        for (int64_t i = 0; i < n; ++i) q[i] = u[i] - alpha * t[i];
+        for (int64_t i = 0; i < n; ++i) w[i] = u[i] + q[i];
+        for (int64_t i = 0; i < n; ++i) x[i] = x[i] + alpha * w[i];
+        orc_csr_spmv(n, rp, ci, v, w, 1.0, 0.0, t);          /* t = A (u + q) */
+        for (int64_t i = 0; i < n; ++i) r[i] = r[i] - alpha * t[i];
+        ++it;
+        rnorm = orc_norm2(n, r);
+        if (isnan(rnorm) || isinf(rnorm)) { rc = ORC_BREAKDOWN; goto done; }
+        if (rnorm <= tol * bnorm) { rc = ORC_OK; goto done; }
+        double rho_new = orc_dot(n, r, rh);
+        double beta = rho_new / rho;
+        rho = rho_new;
+        for (int64_t i = 0; i < n; ++i) u[i] = r[i] + beta * q[i];
+        for (int64_t i = 0; i < n; ++i) p[i] = u[i] + beta * (q[i] + beta * p[i]);
+    }
+done:
+    if (out) {
+        for (int64_t i = 0; i < n; ++i) t[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, t);
+        out[0] = it;
+        out[1] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        out[2] = bnorm > 0.0 ? orc_norm2(n, t) / bnorm : 0.0;
+    }
+    free(r); free(rh); free(p); free(u); free(q); free(w); free(t);
+    return rc;
+}
+
+/* ======================================================================
+ * Restarted GMRES(m) (Saad and Schultz, SIAM J. Sci. Stat. Comput. 7, 1986;
+ * Saad Alg. 6.9 with the Givens-rotation least-squares update of Sec. 6.5.3),
+ * unpreconditioned.  A cycle: r = b - A x, beta = ||r||, v_0 = r / beta,
+ * g = beta e_0; for j = 0, 1, ...: w = A v_j; modified Gram-Schmidt
+ * h_ij = w.v_i, w -= h_ij v_i (i = 0..j); h_{j+1,j} = ||w||; the earlier
+ * rotations applied to column j, then the rotation (c, s) with
+ * c = h_jj / d, s = h_{j+1,j} / d, d = sqrt(h_jj^2 + h_{j+1,j}^2) that zeroes
+ * h_{j+1,j}, applied to g (g_{j+1} = -s g_j, g_j = c g_j).  |g_{j+1}| is the
+ * residual norm of the cycle's least-squares solution.  The cycle ends after
+ * m steps, when |g_{j+1}| <= tol ||b||, when h_{j+1,j} = 0 (the Krylov space
+ * is invariant) or at maxit; then R y = g (back substitution) and
+ * x += sum_i y_i v_i.  The true residual starts the next cycle and decides
+ * convergence.  out[0] = iterations (Arnoldi steps), out[1] = |g| / ||b|| of
+ * the last step, out[2] = true relres, out[3] = cycles.
+ * ====================================================================== */
+int orc_gmres(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+              const double *b, double *x, double tol, int32_t maxit, int32_t m, double *out) {
+    if (m < 1) return ORC_BAD;
+    double *V = (double *)calloc((size_t)(m + 1) * (size_t)(n > 0 ? n : 1), sizeof(double));
+    double *H = (double *)calloc((size_t)(m + 1) * (size_t)m, sizeof(double));  /* H[i*m + j] */
+    double *cs = (double *)calloc(m, sizeof(double));
+    double *sn = (double *)calloc(m, sizeof(double));
+    double *g = (double *)calloc(m + 1, sizeof(double));
+    double *y = (double *)calloc(m, sizeof(double));
+    double *w = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    int rc = ORC_NOT_CONVERGED;
+    int32_t it = 0, cycles = 0;
+    double bnorm = orc_norm2(n, b), est = 0.0, tnorm = 0.0;
+    if (!(bnorm > 0.0)) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        rc = (bnorm == 0.0) ? ORC_OK : ORC_BREAKDOWN;
+        goto done;
+    }
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i) w[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, w);
+        double beta = orc_norm2(n, w);
+        tnorm = beta;
+        if (isnan(beta) || isinf(beta)) { rc = ORC_BREAKDOWN; goto done; }
+        if (beta <= tol * bnorm) { rc = ORC_OK; goto done; }
+        if (it >= maxit) { rc = ORC_NOT_CONVERGED; goto done; }
+        ++cycles;
+        for (int64_t i = 0; i < n; ++i) V[i] = w[i] / beta;
+        for (int j = 0; j <= m; ++j) g[j] = 0.0;
+        g[0] = beta;
+        int k = 0;   /* columns of this cycle */
+        for (int j = 0; j < m; ++j) {
+            double *vj = V + (size_t)j * n, *vn = V + (size_t)(j + 1) * n;
+            orc_csr_spmv(n, rp, ci, v, vj, 1.0, 0.0, w);
+            for (int i = 0; i <= j; ++i) {
+                const double *vi = V + (size_t)i * n;
+                double h = orc_dot(n, w, vi);
+                H[i * m + j] = h;
+                for (int64_t l = 0; l < n; ++l) w[l] = w[l] - h * vi[l];
+            }
+            double hn = orc_norm2(n, w);
+            H[(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {
+                double a = H[i * m + j], c = H[(i + 1) * m + j];
+                H[i * m + j] = cs[i] * a + sn[i] * c;
+                H[(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            double a = H[j * m + j];
+            double d = sqrt(a * a + hn * hn);
+            if (!(d > 0.0)) { rc = ORC_BREAKDOWN; goto done; }
+            cs[j] = a / d;
+            sn[j] = hn / d;
+            H[j * m + j] = d;
+            H[(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            k = j + 1;
+            est = fabs(g[j + 1]);
+            if (isnan(est)) { rc = ORC_BREAKDOWN; goto done; }
+            if (est <= tol * bnorm || hn == 0.0 || it >= maxit) break;
+            for (int64_t l = 0; l < n; ++l) vn[l] = w[l] / hn;
+        }
+        for (int i = k - 1; i >= 0; --i) {
+            double s = g[i];
+            for (int l = i + 1; l < k; ++l) s = s - H[i * m + l] * y[l];
+            y[i] = s / H[i * m + i];
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (size_t)i * n;
+            for (int64_t l = 0; l < n; ++l) x[l] = x[l] + y[i] * vi[l];
+        }
+    }
+done:
+    if (out) {
+        for (int64_t i = 0; i < n; ++i) w[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, w);
+        out[0] = it;
+        out[1] = bnorm > 0.0 ? est / bnorm : 0.0;
+        out[2] = bnorm > 0.0 ? orc_norm2(n, w) / bnorm : 0.0;
+        out[3] = cycles;
+    }
+    free(V); free(H); free(cs); free(sn); free(g); free(y); free(w);
+    return rc;
+}
+
+/* ======================================================================
  * Mixed-precision iterative refinement around an FP32 inner PCG.
  * Outer loop in FP64:  r = b - A x;  stop when ||r|| <= tol ||b||;
  *   rt = fp32(r / ||r||);  solve A32 d = rt approximately;  x += ||r|| fp64(d).

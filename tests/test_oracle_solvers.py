@@ -2,9 +2,14 @@
 
 The paper (Sec. 6.2) benchmarks memory-bound Krylov solvers built on SpMV but
 does not write them out; the oracle follows the textbook algorithms (CG:
-Hestenes-Stiefel / Saad Alg. 9.1; BiCGSTAB: van der Vorst 1992).  Pinned by
-finite termination, closed-form spectra (condition numbers, iteration bounds),
-manufactured solutions and exact preconditioners.
+Hestenes-Stiefel / Saad Alg. 9.1; BiCGSTAB: van der Vorst 1992; flexible CG:
+Notay 2000; CGS: Sonneveld 1989 / Saad Alg. 7.5; restarted GMRES: Saad and
+Schultz 1986 / Saad Alg. 6.9).  Pinned by finite termination, closed-form
+spectra (condition numbers, iteration bounds), manufactured solutions, exact
+preconditioners, and each method's defining optimality or projection
+property computed independently with dense linear algebra (GMRES: minimal
+residual over the Krylov space; CGS: the squared BiCG residual polynomial;
+FCG: the Galerkin solution over the preconditioned residuals).
 """
 import math
 
@@ -267,3 +272,172 @@ def test_batch_ir_cg_fp32_storage(orc, gen_mod):
     rc64, x64, it64, rr64 = orc.batch_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, b, tol=1e-10)
     # the refined solution agrees with the FP64 solve of the same (FP32-valued) systems
     assert np.linalg.norm(x - x64) / np.linalg.norm(x64) <= 81 * 2e-10
+
+
+# --------------------------------------------------------------------------- FCG
+def test_fcg_equals_cg_with_fixed_spd_preconditioner(orc, gen_mod):
+    """With a fixed SPD preconditioner z_{k+1}.r_k = 0, so FCG's beta is CG's
+    (exact arithmetic): the same iterations and solution up to rounding."""
+    A = gen_mod.laplace3d(12)
+    n = 12 ** 3
+    xs = gen_mod.uniform(5, n)
+    b = orc.spmv(A, xs)
+    rc, inv = orc.bj_invert(A, 8)
+    for kw in ({}, {"bj_inv": inv, "bs": 8}):
+        r1, x1, i1 = orc.cg(A, b, tol=1e-10, **kw)
+        r2, x2, i2 = orc.fcg(A, b, tol=1e-10, **kw)
+        assert r1 == r2 == orc.OK and abs(i1["iters"] - i2["iters"]) <= 1
+        assert i2["true_relres"] <= 1e-10
+        assert np.linalg.norm(x1 - x2) <= 1e-8 * np.linalg.norm(xs)
+
+
+def test_fcg_finite_termination_and_exact_preconditioner(orc, gen_mod):
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    b = gen_mod.uniform(31, 50)
+    rc, x, info = orc.fcg(diag_csr(d), b, tol=1e-12, maxit=100)
+    assert rc == orc.OK and info["iters"] <= 3
+    rng = np.random.default_rng(9)
+    n, bs = 40, 8
+    D = np.zeros((n, n))
+    for b0 in range(0, n, bs):
+        G = rng.standard_normal((bs, bs))
+        D[b0:b0 + bs, b0:b0 + bs] = G @ G.T + bs * np.eye(bs)
+    A = dense_to_csr(D)
+    rc, inv = orc.bj_invert(A, bs)
+    rc, x, info = orc.fcg(A, rng.uniform(-1, 1, n), tol=1e-12, bj_inv=inv, bs=bs)
+    assert rc == orc.OK and info["iters"] == 1
+
+
+def test_fcg_two_steps_are_the_galerkin_solution_for_a_nonsymmetric_preconditioner(orc):
+    """FCG keeps consecutive directions A-conjugate for any preconditioner, so
+    x_2 minimises the A-norm error over x_0 + span{z_0, z_1}.  CG's beta does
+    not with a nonsymmetric preconditioner (checked too, so the pin tells the
+    two coefficients apart)."""
+    rng = np.random.default_rng(21)
+    n, bs = 24, 8
+    G = rng.standard_normal((n, n))
+    D = G @ G.T / n + np.eye(n)                       # SPD, well conditioned
+    A = dense_to_csr(D)
+    blocks = []
+    for b0 in range(0, n, bs):
+        L = np.tril(D[b0:b0 + bs, b0:b0 + bs])        # lower triangle: nonsymmetric inverse
+        blocks.append(np.linalg.inv(L))
+    inv = np.concatenate([B.ravel() for B in blocks])
+
+    def Minv(r):
+        return np.concatenate([blocks[k] @ r[k * bs:(k + 1) * bs] for k in range(n // bs)])
+
+    b = rng.uniform(-1, 1, n)
+    z0 = Minv(b)
+    x1 = z0 * (z0 @ b) / (z0 @ D @ z0)
+    z1 = Minv(b - D @ x1)
+    Z = np.stack([z0, z1], 1)
+    x2 = Z @ np.linalg.solve(Z.T @ D @ Z, Z.T @ b)
+    rc, xf, info = orc.fcg(A, b, tol=1e-15, maxit=2, bj_inv=inv, bs=bs)
+    assert rc == orc.NOT_CONVERGED and info["iters"] == 2
+    assert np.linalg.norm(xf - x2) <= 1e-12 * np.linalg.norm(x2)
+    rc, xc, info = orc.cg(A, b, tol=1e-15, maxit=2, bj_inv=inv, bs=bs)
+    assert np.linalg.norm(xc - x2) > 1e-6 * np.linalg.norm(x2)
+
+
+# --------------------------------------------------------------------------- CGS
+def bicg_poly_residual(D, r0, rh, k):
+    """phi_k(A) r0 for BiCG's residual polynomial: phi_k(0) = 1 and
+    phi_k(A) r0 orthogonal to span{rh, A^T rh, ..., (A^T)^{k-1} rh}."""
+    K = [r0]
+    for _ in range(k):
+        K.append(D @ K[-1])                            # A^j r0, j = 0..k
+    L = [rh]
+    for _ in range(k - 1):
+        L.append(D.T @ L[-1])
+    # phi_k(A) r0 = r0 + sum_j c_j A^j r0;  L_i . (...) = 0
+    M = np.array([[L[i] @ K[j] for j in range(1, k + 1)] for i in range(k)])
+    c = np.linalg.solve(M, -np.array([L[i] @ r0 for i in range(k)]))
+    coef = np.concatenate([[1.0], c])                  # phi_k(t) = sum coef_j t^j
+
+    def apply(v):
+        out, Ajv = np.zeros_like(v), v.copy()
+        for j, cj in enumerate(coef):
+            out += cj * Ajv
+            Ajv = D @ Ajv
+        return out
+    return apply(apply(r0))                            # CGS: phi_k(A)^2 r0
+
+
+def test_cgs_residual_is_the_squared_bicg_polynomial(orc):
+    rng = np.random.default_rng(17)
+    n = 20
+    D = np.eye(n) * 3 + rng.uniform(-1, 1, (n, n)) * 0.3   # nonsymmetric, well conditioned
+    A = dense_to_csr(D)
+    b = rng.uniform(-1, 1, n)
+    for k in (1, 2, 3):
+        rc, x, info = orc.cgs(A, b, tol=1e-15, maxit=k)
+        assert rc == orc.NOT_CONVERGED and info["iters"] == k
+        r = b - D @ x
+        ref = bicg_poly_residual(D, b, b, k)
+        assert np.linalg.norm(r - ref) <= 1e-10 * np.linalg.norm(b), k
+
+
+def test_cgs_finite_termination_identity_and_manufactured(orc, gen_mod):
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    b = gen_mod.uniform(31, 50)
+    rc, x, info = orc.cgs(diag_csr(d), b, tol=1e-12, maxit=100)
+    assert rc == orc.OK and info["iters"] <= 3
+    b = gen_mod.uniform(3, 10)
+    rc, x, info = orc.cgs(diag_csr([2.5] * 10), b)
+    assert rc == orc.OK and info["iters"] == 1 and np.allclose(x, b / 2.5, rtol=1e-15, atol=0)
+    A = gen_mod.convdiff2d(40, 0.5)
+    xs = gen_mod.uniform(8, 1600)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.cgs(A, b, tol=1e-10, maxit=2000)
+    assert rc == orc.OK and info["true_relres"] <= 1e-9   # recursive residual drifts in CGS
+    # breakdown: A = [[0,1],[1,0]], b = e1 gives (A p).rhat = 0 at the first step
+    A = (np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.array([1.0, 1.0]))
+    rc, x, info = orc.cgs(A, np.array([1.0, 0.0]))
+    assert rc == orc.BREAKDOWN
+
+
+# --------------------------------------------------------------------------- GMRES
+def test_gmres_minimises_the_residual_over_the_krylov_space(orc):
+    """k GMRES steps (no restart) give min ||b - A x|| over x in K_k(A, b),
+    computed here by least squares on an orthonormal Krylov basis."""
+    rng = np.random.default_rng(23)
+    n = 30
+    D = np.eye(n) * 2 + rng.uniform(-1, 1, (n, n)) * 0.25
+    A = dense_to_csr(D)
+    b = rng.uniform(-1, 1, n)
+    for k in range(1, 7):
+        rc, x, info = orc.gmres(A, b, tol=1e-15, maxit=k, m=30)
+        assert rc == orc.NOT_CONVERGED and info["iters"] == k and info["cycles"] == 1
+        K = np.stack([np.linalg.matrix_power(D, j) @ b for j in range(k)], 1)
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(D @ Q, b, rcond=None)
+        xref = Q @ y
+        rmin = np.linalg.norm(b - D @ xref)
+        assert abs(np.linalg.norm(b - D @ x) - rmin) <= 1e-10 * np.linalg.norm(b), k
+        assert np.linalg.norm(x - xref) <= 1e-8 * np.linalg.norm(xref), k
+        # the Givens estimate is the residual of the least-squares solution
+        assert abs(info["relres"] - rmin / np.linalg.norm(b)) <= 1e-10
+
+
+def test_gmres_finite_termination_restarts_and_bad_m(orc, gen_mod):
+    rng = np.random.default_rng(29)
+    n = 10
+    D = rng.uniform(-1, 1, (n, n)) + 3 * np.eye(n)
+    rc, x, info = orc.gmres(dense_to_csr(D), rng.uniform(-1, 1, n), tol=1e-10, m=10)
+    assert rc == orc.OK and info["iters"] <= n
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    b = gen_mod.uniform(31, 50)
+    rc, x, info = orc.gmres(diag_csr(d), b, tol=1e-12, m=30)
+    assert rc == orc.OK and info["iters"] <= 3
+    A = gen_mod.convdiff2d(40, 0.5)
+    xs = gen_mod.uniform(8, 1600)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.gmres(A, b, tol=1e-10, maxit=20000, m=20)
+    assert rc == orc.OK and info["true_relres"] <= 1e-10 and info["cycles"] > 1
+    rc, x, info = orc.gmres(A, b, tol=1e-10, maxit=50, m=20)
+    assert rc == orc.NOT_CONVERGED and info["iters"] == 50
+    rc, x, info = orc.gmres(A, b, m=0)
+    assert rc == orc.BAD
+    rc, x, info = orc.gmres(A, np.zeros(1600), m=5)
+    assert rc == orc.OK and info["iters"] == 0 and not x.any()
