@@ -239,10 +239,30 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out);
  * GKO_OK, GKO_ERR_NOT_CONVERGED, GKO_ERR_NOT_SPD or GKO_ERR_BREAKDOWN. */
 gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
+/* Flexible CG (Notay 2000, one previous direction kept conjugate): CG with
+ * the Polak-Ribiere coefficient beta = z'.(r' - r) / (z.r), which keeps
+ * consecutive directions A-conjugate also when the preconditioner is not a
+ * fixed symmetric operator; with the library's fixed SPD preconditioners it
+ * agrees with CG up to rounding.  The same options (precision, precond,
+ * block_size, check_every), stopping test, restarts, statuses and solve info
+ * as gko_cg_solve; no single-workgroup path. */
+gko_status gko_fcg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
 /* Solve A x = b by unpreconditioned BiCGSTAB (van der Vorst), shadow
  * residual r0, same conventions as gko_cg_solve.  Breakdown (|rho|, |rhat.v|
  * or t.t below 1e-300, or omega = 0) returns GKO_ERR_BREAKDOWN. */
 gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
+/* Solve A x = b by unpreconditioned CGS (Sonneveld 1989; Saad Alg. 7.5),
+ * shadow residual rhat = r0: t = A p, alpha = rho / t.rhat, q = u - alpha t,
+ * x += alpha (u + q), r -= alpha A (u + q), rho' = r.rhat,
+ * u = r + (rho'/rho) q, p = u + beta (q + beta p).  A square, FP64.  Stops
+ * when the recursive ||r||_2 <= tol ||b||_2; the true relative residual is
+ * reported in the solve info (CGS's recursive residual can drift from it),
+ * no restart.  Breakdown when |rho| or |t.rhat| falls below 1e-300.  Same
+ * argument conventions as gko_cg_solve; returns GKO_OK,
+ * GKO_ERR_NOT_CONVERGED or GKO_ERR_BREAKDOWN. */
+gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
 /* ---------------------------------------------------------------- batched CG */
 

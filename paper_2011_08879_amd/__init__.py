@@ -110,6 +110,8 @@ _SIGS = {
     "gko_batch_autotune": [_vp, _vp, _vp, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                            ctypes.POINTER(ctypes.c_float)],
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_fcg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_cgs_solve": [_vp, _vp, _vp, _f64, _i32],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -432,6 +434,16 @@ def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure
 def bicgstab(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
              raise_on_failure: bool = False):
     return _solve(_lib.gko_bicgstab_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+def fcg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
+    """Flexible (P)CG (Polak-Ribiere beta), the same options as cg()."""
+    return _solve(_lib.gko_fcg_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+def cgs(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
+    """Unpreconditioned CGS (FP64)."""
+    return _solve(_lib.gko_cgs_solve, A, b, x, tol, maxit, raise_on_failure)
 
 
 # ----------------------------------------------------------------------------- batched CG

@@ -706,7 +706,7 @@ gko_status flag_status(int32_t f) {
 // (P)CG on A with the value arrays `v` (FP64 or FP32), b and x of that type.
 // inv: block-Jacobi inverse of type v.t (bs > 0) or null.
 solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, double tol, int32_t maxit,
-                     const void *inv, int bs, int check_every, bool true_check) {
+                     const void *inv, int bs, int check_every, bool true_check, bool flexible) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     const int64_t n = A->n;
@@ -742,7 +742,7 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
                     HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
                 }
                 HIPC(cg_update(s, v.t, n, x, r.p, zz, p.p, q.p, inv, bs, S, partials.as<double>(),
-                               ticket.as<unsigned>()));
+                               ticket.as<unsigned>(), flexible));
                 HIPC(cg_direction(s, v.t, n, zz, p.p, S));
             }
             h = read_back(c, S);
@@ -775,7 +775,7 @@ struct mixed_result {
 };
 
 mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gko_solver_opts &o,
-                      int bs, double bnorm) {
+                      int bs, double bnorm, bool flexible) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     const int64_t n = A->n;
@@ -803,7 +803,8 @@ mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gk
         // of margin), never for less than inner_tol
         const double tau = std::max(o.inner_tol, 0.5 * (tol * bnorm / rn));
         solve_result in = cg_core(A, v32, rt.p, d.p, tau, o.max_inner,
-                                  bs > 0 ? (const void *)A->bj32 : nullptr, bs, o.check_every, false);
+                                  bs > 0 ? (const void *)A->bj32 : nullptr, bs, o.check_every, false,
+                                  flexible);
         res.inner += in.iters;
         if (in.flag == kNotSpd || in.flag == kBreakdown) {
             res.status = flag_status(in.flag);
@@ -1808,7 +1809,10 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out) {
     });
 }
 
-gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+// CG (flexible = false) or flexible CG: the same kernels and options; only
+// CG has the single-workgroup path for small systems.
+static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit,
+                           bool flexible) {
     gko_status st = GKO_OK;
     gko_status call = guarded([&] {
         check_square_f64(A);
@@ -1819,7 +1823,7 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
         const gko_solver_opts o = c->opts;
         const int64_t n = A->n;
         if (c->small_cg_rows < 0) c->small_cg_rows = small_cg_max_rows();
-        const bool single = o.single_workgroup && o.precision == GKO_PREC_FP64 &&
+        const bool single = !flexible && o.single_workgroup && o.precision == GKO_PREC_FP64 &&
                             o.precond == GKO_PRECOND_NONE && n > 0 && n <= c->small_cg_rows &&
                             (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE);
         if (single) {
@@ -1841,7 +1845,7 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
             return;
         }
         // ||b|| decides the trivial cases before any iteration
-            dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
+        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
         HIPC(hipMemsetAsync(ticket.p, 0, 8, c->stream));
         const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
                                          ticket.as<unsigned>());
@@ -1860,7 +1864,7 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
                 c->info.setup_seconds = now_seconds() - ts;
             }
             if (o.precision == GKO_PREC_MIXED_IR) {
-                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm);
+                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm, flexible);
                 st = r.status;
                 c->info.iterations = r.inner;
                 c->info.outer_iterations = r.outer;
@@ -1869,7 +1873,7 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
             } else {
                 solve_result r = cg_core(A, own_values(A), b, x, tol, maxit,
                                          bs > 0 ? (const void *)A->bj64 : nullptr, bs,
-                                         o.check_every, true);
+                                         o.check_every, true, flexible);
                 st = flag_status(r.flag);
                 c->info.iterations = r.iters;
                 c->info.restarts = r.restarts;
@@ -1885,8 +1889,16 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
         if (A) A->ctx->info.status = call;
         return call;
     }
-    if (st != GKO_OK) g_last_error = std::string("cg: ") + gko_status_string(st);
+    if (st != GKO_OK) g_last_error = std::string(flexible ? "fcg: " : "cg: ") + gko_status_string(st);
     return st;
+}
+
+gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    return cg_family_solve(A, b, x, tol, maxit, false);
+}
+
+gko_status gko_fcg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    return cg_family_solve(A, b, x, tol, maxit, true);
 }
 
 gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
@@ -1899,7 +1911,7 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         const double t0 = now_seconds();
         c->info = gko_solve_info{};
         const int64_t n = A->n;
-            const int check_every = c->opts.check_every;
+        const int check_every = c->opts.check_every;
         const values v = own_values(A);
         dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8), sc(c, sizeof(krylov_scalars));
         HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
@@ -1948,6 +1960,68 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         return call;
     }
     if (st != GKO_OK) g_last_error = std::string("bicgstab: ") + gko_status_string(st);
+    return st;
+}
+
+gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_square_f64(A);
+        check_solve_args(b, x, tol, maxit);
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const double t0 = now_seconds();
+        c->info = gko_solve_info{};
+        const int64_t n = A->n;
+        const int check_every = c->opts.check_every;
+        const values v = own_values(A);
+        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8), sc(c, sizeof(krylov_scalars));
+        HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
+                                         ticket.as<unsigned>());
+        if (!std::isfinite(bnorm)) {
+            st = GKO_ERR_BREAKDOWN;
+        } else if (bnorm == 0.0) {
+            HIPC(fill_zero(s, vt::f64, n, x));
+            st = GKO_OK;
+        } else {
+            dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), u(c, n * 8), q(c, n * 8), w(c, n * 8),
+                t(c, n * 8);
+            auto *S = sc.as<krylov_scalars>();
+            double *P = partials.as<double>();
+            unsigned *T = ticket.as<unsigned>();
+            HIPC(scalars_reset(s, S, maxit));
+            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            HIPC(cgs_init(s, n, b, r.p, rh.p, p.p, u.p, tol, S, P, T));
+            krylov_scalars h = read_back(c, S);
+            while (h.done == kRunning) {
+                for (int j = 0; j < check_every; ++j) {
+                    spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
+                    HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
+                    HIPC(cgs_qwx(s, n, u.p, t.p, q.p, w.p, x, S));
+                    spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
+                    HIPC(cgs_update(s, n, r.p, t.p, rh.p, S, P, T));
+                    HIPC(cgs_direction(s, n, r.p, q.p, u.p, p.p, S));
+                }
+                h = read_back(c, S);
+            }
+            st = flag_status(h.done);
+            c->info.iterations = h.iter;
+            c->info.rel_residual = std::sqrt(h.rr / h.bb);
+            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(), P, T) / bnorm;
+        }
+        c->sync();
+        c->info.status = st;
+        c->info.seconds = now_seconds() - t0;
+    });
+    if (call != GKO_OK) {
+        if (A) A->ctx->info.status = call;
+        return call;
+    }
+    if (st != GKO_OK) g_last_error = std::string("cgs: ") + gko_status_string(st);
     return st;
 }
 

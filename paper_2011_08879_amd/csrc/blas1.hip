@@ -72,9 +72,12 @@ struct cg_alpha_op {
     }
 };
 
-// After the update: totals r.z, r.r; convergence test, then beta.
+// After the update: totals r.z, r.r (and, for flexible CG, z.(r - r_old));
+// convergence test, then beta: r.z / rho (Fletcher-Reeves, CG) or
+// z.(r - r_old) / rho (Polak-Ribiere, flexible CG).
 struct cg_update_op {
     krylov_scalars *sc;
+    bool flex;
     __device__ bool skip() const { return sc->done != 0; }
     __device__ void operator()(const double *o) const {
         sc->iter += 1;
@@ -84,7 +87,7 @@ struct cg_update_op {
         } else if (o[1] <= sc->stop2) {
             sc->done = kConverged;
         } else {
-            sc->beta = o[0] / sc->rho;
+            sc->beta = (flex ? o[2] : o[0]) / sc->rho;
             sc->rho = o[0];
             if (sc->iter >= sc->maxit) sc->done = kMaxIter;
         }
@@ -425,7 +428,7 @@ __global__ __launch_bounds__(kB) void cg_pq_kernel(int64_t n, const V *__restric
 }
 
 // x += alpha p; r -= alpha q; z = M^-1 r; rho' = r.z; rr = r.r; then beta.
-template <typename V, int BS>
+template <typename V, int BS, bool FLEX>
 __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict__ x,
                                                        V *__restrict__ r, V *__restrict__ z,
                                                        const V *__restrict__ p,
@@ -436,13 +439,14 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict_
     __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
     if (sc->done) return;
     const double alpha = sc->alpha;
-    double a_rz = 0.0, a_rr = 0.0;
+    double a_rz = 0.0, a_rr = 0.0, a_zt = 0.0;
     for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
         const int64_t i = base + threadIdx.x;
-        V ri = V(0);
+        V ri = V(0), ro = V(0);
         if (i < n) {
             x[i] = (V)((double)x[i] + alpha * (double)p[i]);
-            ri = (V)((double)r[i] - alpha * (double)q[i]);
+            ro = r[i];
+            ri = (V)((double)ro - alpha * (double)q[i]);
             r[i] = ri;
         }
         V zi = ri;
@@ -451,10 +455,16 @@ __global__ __launch_bounds__(kB) void cg_update_kernel(int64_t n, V *__restrict_
             if constexpr (BS > 0) z[i] = zi;
             a_rz += (double)ri * (double)zi;
             a_rr += (double)ri * (double)ri;
+            if constexpr (FLEX) a_zt += (double)zi * ((double)ri - (double)ro);
         }
     }
-    double v[2] = {a_rz, a_rr};
-    grid_sum_apply<kB, 2>(v, ra, cg_update_op{sc});
+    if constexpr (FLEX) {
+        double v[3] = {a_rz, a_rr, a_zt};
+        grid_sum_apply<kB, 3>(v, ra, cg_update_op{sc, true});
+    } else {
+        double v[2] = {a_rz, a_rr};
+        grid_sum_apply<kB, 2>(v, ra, cg_update_op{sc, false});
+    }
 }
 
 // p = z + beta p  (z = r without a preconditioner).
@@ -555,7 +565,7 @@ hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, k
     return red_finish<1>(s, g, ra, cg_alpha_op{sc});
 }
 
-template <typename V>
+template <typename V, bool FLEX>
 static hipError_t launch_cg_update(hipStream_t s, int64_t n, void *x, void *r, void *z,
                                    const void *p, const void *q, const void *inv, int bs,
                                    krylov_scalars *sc, double *partials, unsigned *ticket) {
@@ -565,23 +575,28 @@ static hipError_t launch_cg_update(hipStream_t s, int64_t n, void *x, void *r, v
     const V *P = static_cast<const V *>(p), *Q = static_cast<const V *>(q);
     const V *I = static_cast<const V *>(inv);
     switch (bs) {
-        case 0: cg_update_kernel<V, 0><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
-        case 1: cg_update_kernel<V, 1><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
-        case 2: cg_update_kernel<V, 2><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
-        case 4: cg_update_kernel<V, 4><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
-        case 8: cg_update_kernel<V, 8><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
-        case 16: cg_update_kernel<V, 16><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 0: cg_update_kernel<V, 0, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 1: cg_update_kernel<V, 1, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 2: cg_update_kernel<V, 2, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 4: cg_update_kernel<V, 4, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 8: cg_update_kernel<V, 8, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
+        case 16: cg_update_kernel<V, 16, FLEX><<<g, kB, 0, s>>>(n, X, R, Z, P, Q, I, sc, ra); break;
         default: return hipErrorInvalidValue;
     }
-    return red_finish<2>(s, g, ra, cg_update_op{sc});
+    if constexpr (FLEX) return red_finish<3>(s, g, ra, cg_update_op{sc, true});
+    return red_finish<2>(s, g, ra, cg_update_op{sc, false});
 }
 
 hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,
                      const void *q, const void *inv, int bs, krylov_scalars *sc, double *partials,
-                     unsigned *ticket) {
+                     unsigned *ticket, bool flexible) {
+    if (flexible)
+        return t == vt::f64
+                   ? launch_cg_update<double, true>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket)
+                   : launch_cg_update<float, true>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket);
     return t == vt::f64
-               ? launch_cg_update<double>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket)
-               : launch_cg_update<float>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket);
+               ? launch_cg_update<double, false>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket)
+               : launch_cg_update<float, false>(s, n, x, r, z, p, q, inv, bs, sc, partials, ticket);
 }
 
 hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,

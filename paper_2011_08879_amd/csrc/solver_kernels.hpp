@@ -46,9 +46,10 @@ hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, co
                          double *partials, unsigned *ticket);
 hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
                  double *partials, unsigned *ticket);
+// flexible: beta = z.(r - r_old) / rho (flexible CG) instead of r.z / rho.
 hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, const void *p,
                      const void *q, const void *inv, int bs, krylov_scalars *sc, double *partials,
-                     unsigned *ticket);
+                     unsigned *ticket, bool flexible);
 hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
                         const krylov_scalars *sc);
 
@@ -66,6 +67,20 @@ hipError_t bicg_omega(hipStream_t st, int64_t n, const void *t, const void *s, k
 hipError_t bicg_update(hipStream_t st, int64_t n, void *x, void *r, const void *rh, const void *p,
                        const void *s, const void *t, krylov_scalars *sc, double *partials,
                        unsigned *ticket);
+
+// CGS (FP64, unpreconditioned; cgs.hip).  init from r = b - A x: rhat = p =
+// u = r, rho = r.r; then per iteration t = A p, cgs_alpha, cgs_qwx, t = A w,
+// cgs_update, cgs_direction.
+hipError_t cgs_init(hipStream_t s, int64_t n, const void *b, const void *r, void *rh, void *p,
+                    void *u, double tol, krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t cgs_alpha(hipStream_t s, int64_t n, const void *t, const void *rh, krylov_scalars *sc,
+                     double *partials, unsigned *ticket);
+hipError_t cgs_qwx(hipStream_t s, int64_t n, const void *u, const void *t, void *q, void *w,
+                   void *x, const krylov_scalars *sc);
+hipError_t cgs_update(hipStream_t s, int64_t n, void *r, const void *t, const void *rh,
+                      krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t cgs_direction(hipStream_t s, int64_t n, const void *r, const void *q, void *u, void *p,
+                         const krylov_scalars *sc);
 
 // Mixed precision helpers.
 hipError_t scaled_cast(hipStream_t s, int64_t n, const double *r, const double *norm, float *rt);

@@ -1,0 +1,122 @@
+"""GPU parity of the Krylov solvers beyond CG and BiCGSTAB: flexible CG, CGS
+and restarted GMRES, each against its pinned FP64 oracle on the same seeded
+inputs (iteration counts within the rounding slack of the stopping tests,
+true residuals, manufactured-solution error bounds), in several storage
+formats, plus their status paths."""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_util import dev, host
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def g():
+    import paper_2011_08879_amd as g
+    return g
+
+
+@pytest.fixture()
+def ctx(g):
+    c = g.default_context()
+    c.set_solver_opts()
+    yield c
+    c.set_solver_opts()
+
+
+def relres(orc, A, b, x):
+    return np.linalg.norm(b - orc.spmv(A, x)) / np.linalg.norm(b)
+
+
+# --------------------------------------------------------------------------- FCG
+@pytest.mark.parametrize("fmt", ["csr", "ell", "sellp", "coo"])
+def test_fcg_laplace2d_matches_oracle(g, orc, gen_mod, ctx, fmt):
+    N = 64
+    A = gen_mod.laplace2d(N)
+    xs = gen_mod.uniform(2, N * N)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.fcg(A, b, tol=1e-10)
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = dev(np.zeros(N * N))
+    info = g.fcg(M, dev(b), x, tol=1e-10, maxit=5000)
+    assert info["status"] == g.OK, info
+    assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    xg = host(x)
+    assert relres(orc, A, b, xg) <= 1e-10
+    kappa = (4 + 4 * math.cos(math.pi / (N + 1))) / (4 - 4 * math.cos(math.pi / (N + 1)))
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+
+
+def test_fcg_block_jacobi_and_mixed(g, orc, gen_mod, ctx):
+    N = 24
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    b = orc.spmv(A, gen_mod.uniform(5, n))
+    rc, inv = orc.bj_invert(A, 8)
+    rc, xo, info_o = orc.fcg(A, b, tol=1e-10, bj_inv=inv)
+    M = g.Matrix.from_csr(*A)
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    x = dev(np.zeros(n))
+    info = g.fcg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK and abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    assert relres(orc, A, b, host(x)) <= 1e-10
+    # with a fixed SPD preconditioner FCG and CG agree up to rounding
+    xc = dev(np.zeros(n))
+    infoc = g.cg(M, dev(b), xc, tol=1e-10)
+    assert abs(infoc["iterations"] - info["iterations"]) <= 1
+    ctx.set_solver_opts(precision=g.PREC_MIXED_IR, precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    x = dev(np.zeros(n))
+    info = g.fcg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK and info["outer_iterations"] >= 2
+    assert relres(orc, A, b, host(x)) <= 1e-10
+
+
+def test_fcg_statuses(g, gen_mod, ctx):
+    L = g.Matrix.from_csr(*gen_mod.laplace2d(32))
+    info = g.fcg(L, dev(np.zeros(1024)), dev(np.ones(1024)))
+    assert info["status"] == g.OK and info["iterations"] == 0
+    info = g.fcg(L, dev(np.ones(1024)), dev(np.zeros(1024)), tol=1e-10, maxit=5)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 5
+    D = g.Matrix.from_csr(np.arange(5, dtype=np.int32), np.arange(4, dtype=np.int32),
+                          np.array([1.0, 2.0, -1.0, 3.0]))
+    assert g.fcg(D, dev(np.ones(4)), dev(np.zeros(4)))["status"] == g.ERR_NOT_SPD
+
+
+# --------------------------------------------------------------------------- CGS
+@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "hybrid", "sellp"])
+def test_cgs_convdiff_matches_oracle(g, orc, gen_mod, ctx, fmt):
+    A = gen_mod.convdiff2d(40, 0.5)
+    n = 1600
+    xs = gen_mod.uniform(8, n)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.cgs(A, b, tol=1e-10, maxit=2000)
+    assert rc == orc.OK
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = dev(np.zeros(n))
+    info = g.cgs(M, dev(b), x, tol=1e-10, maxit=2000)
+    assert info["status"] == g.OK, info
+    # no closed form for CGS iteration counts: they must stay close
+    assert abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 10), (info, info_o)
+    xg = host(x)
+    true = relres(orc, A, b, xg)
+    assert true <= 1e-9 and abs(info["true_rel_residual"] - true) <= 1e-12
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-6
+
+
+def test_cgs_identity_and_breakdown(g, gen_mod, ctx):
+    b = gen_mod.uniform(3, 10)
+    I = g.Matrix.from_csr(np.arange(11, dtype=np.int32), np.arange(10, dtype=np.int32),
+                          np.full(10, 2.5))
+    x = dev(np.zeros(10))
+    info = g.cgs(I, dev(b), x)
+    assert info["status"] == g.OK and info["iterations"] == 1
+    assert np.allclose(host(x), b / 2.5, rtol=1e-15, atol=0)
+    B = g.Matrix.from_csr(np.array([0, 1, 2], np.int32), np.array([1, 0], np.int32), np.ones(2))
+    assert g.cgs(B, dev(np.array([1.0, 0.0])), dev(np.zeros(2)))["status"] == g.ERR_BREAKDOWN
+    L = g.Matrix.from_csr(*gen_mod.convdiff2d(20, 0.5))
+    info = g.cgs(L, dev(np.ones(400)), dev(np.zeros(400)), maxit=3)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 3
+    assert g.cgs(L, dev(np.zeros(400)), dev(np.ones(400)))["status"] == g.OK
