@@ -212,6 +212,7 @@ typedef struct gko_solver_opts {
                                  direction vector fits in one workgroup's LDS (n up to 8192 on
                                  gfx950) runs as one launch on one workgroup; 0: always the
                                  multi-kernel path.  Same steps and stopping test either way. */
+    int32_t krylov_dim;  /* GMRES restart length m, 1..128 (default 30) */
 } gko_solver_opts;
 
 typedef struct gko_solve_info {
@@ -263,6 +264,20 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
  * argument conventions as gko_cg_solve; returns GKO_OK,
  * GKO_ERR_NOT_CONVERGED or GKO_ERR_BREAKDOWN. */
 gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
+/* Solve A x = b by restarted GMRES(m) (Saad and Schultz 1986), m =
+ * krylov_dim of the solver options, unpreconditioned, FP64.  A cycle starts
+ * from r = b - A x, builds an orthonormal Krylov basis by classical
+ * Gram-Schmidt (a second round when the first leaves less than 1/sqrt(2) of
+ * the vector's length), reduces the Hessenberg matrix by Givens rotations,
+ * and ends after m steps, when the least-squares residual estimate reaches
+ * tol ||b||_2, on an invariant subspace, or at maxit; then x += V y.  The
+ * next cycle's true residual decides convergence.  Device memory: (m + 1)
+ * basis vectors of n_rows doubles.  iterations counts Arnoldi steps and
+ * outer_iterations the cycles; rel_residual is the last estimate.  Same
+ * argument conventions as gko_cg_solve; returns GKO_OK,
+ * GKO_ERR_NOT_CONVERGED or GKO_ERR_BREAKDOWN. */
+gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
 /* ---------------------------------------------------------------- batched CG */
 

@@ -56,7 +56,7 @@ class _MatrixDesc(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("precond", _i32), ("block_size", _i32),
                 ("check_every", _i32), ("inner_tol", _f64), ("max_inner", _i32),
-                ("max_outer", _i32), ("single_workgroup", _i32)]
+                ("max_outer", _i32), ("single_workgroup", _i32), ("krylov_dim", _i32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -112,6 +112,7 @@ _SIGS = {
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
     "gko_fcg_solve": [_vp, _vp, _vp, _f64, _i32],
     "gko_cgs_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_gmres_solve": [_vp, _vp, _vp, _f64, _i32],
 }
 for _name, _args in _SIGS.items():
     _fn = getattr(_lib, _name)
@@ -205,9 +206,10 @@ class Context:
 
     def set_solver_opts(self, precision: int = PREC_FP64, precond: int = PRECOND_NONE,
                         block_size: int = 8, check_every: int = 16, inner_tol: float = 1e-5,
-                        max_inner: int = 1000, max_outer: int = 20, single_workgroup: int = 1):
+                        max_inner: int = 1000, max_outer: int = 20, single_workgroup: int = 1,
+                        krylov_dim: int = 30):
         o = SolverOpts(precision, precond, block_size, check_every, inner_tol, max_inner, max_outer,
-                       single_workgroup)
+                       single_workgroup, krylov_dim)
         _check(_lib.gko_context_set_solver_opts(self.handle, ctypes.byref(o)))
 
     def solver_opts(self) -> dict:
@@ -444,6 +446,13 @@ def fcg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failur
 def cgs(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
     """Unpreconditioned CGS (FP64)."""
     return _solve(_lib.gko_cgs_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+def gmres(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
+          raise_on_failure: bool = False):
+    """Restarted GMRES(m), m = the context's krylov_dim option (FP64, unpreconditioned).
+    Solve info: iterations = Arnoldi steps, outer_iterations = cycles."""
+    return _solve(_lib.gko_gmres_solve, A, b, x, tol, maxit, raise_on_failure)
 
 
 # ----------------------------------------------------------------------------- batched CG

@@ -75,6 +75,7 @@ gko_solver_opts default_opts() {
     o.max_inner = 1000;
     o.max_outer = 20;
     o.single_workgroup = 1;
+    o.krylov_dim = 30;
     return o;
 }
 
@@ -1789,6 +1790,8 @@ gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *o
         require(o->check_every >= 1, GKO_ERR_INVALID_ARG, "check_every must be >= 1");
         require(o->inner_tol > 0.0 && o->inner_tol < 1.0, GKO_ERR_INVALID_ARG, "inner_tol in (0,1)");
         require(o->max_inner >= 1 && o->max_outer >= 1, GKO_ERR_INVALID_ARG, "iteration caps >= 1");
+        require(o->krylov_dim >= 1 && o->krylov_dim <= kGmresMaxKrylov, GKO_ERR_INVALID_ARG,
+                "krylov_dim must be in 1.." + std::to_string(kGmresMaxKrylov));
         require(o->single_workgroup == 0 || o->single_workgroup == 1, GKO_ERR_INVALID_ARG,
                 "single_workgroup must be 0 or 1");
         ctx->opts = *o;
@@ -2022,6 +2025,100 @@ gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32
         return call;
     }
     if (st != GKO_OK) g_last_error = std::string("cgs: ") + gko_status_string(st);
+    return st;
+}
+
+gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_square_f64(A);
+        check_solve_args(b, x, tol, maxit);
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const double t0 = now_seconds();
+        c->info = gko_solve_info{};
+        const int64_t n = A->n;
+        const int m = c->opts.krylov_dim;
+        const int check_every = c->opts.check_every;
+        const values v = own_values(A);
+        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
+        HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
+                                         ticket.as<unsigned>());
+        if (!std::isfinite(bnorm)) {
+            st = GKO_ERR_BREAKDOWN;
+        } else if (bnorm == 0.0) {
+            HIPC(fill_zero(s, vt::f64, n, x));
+            st = GKO_OK;
+        } else {
+            const int64_t ldv = gmres_ld(n);
+            dbuf V(c, (size_t)(m + 1) * ldv * 8);
+            // work arrays carved from one buffer
+            const int64_t np = gmres_partial_elems(n, m);
+            const int64_t sizes[] = {np, m + 2, m + 2, 1, 1, m + 1, (int64_t)(m + 1) * m, m, m,
+                                     m + 1, m};
+            int64_t total = 0;
+            for (int64_t z : sizes) total += z;
+            dbuf work(c, total * 8), state(c, sizeof(gmres_state));
+            double *q = work.as<double>();
+            gmres_work wk;
+            double **slots[] = {&wk.partials, &wk.dot1, &wk.dot2, &wk.upd1, &wk.upd2, &wk.hcol,
+                                &wk.H,        &wk.cs,   &wk.sn,   &wk.g,    &wk.y};
+            for (int i = 0; i < 11; ++i) {
+                *slots[i] = q;
+                q += sizes[i];
+            }
+            HIPC(fill_zero(s, vt::f64, total, work.p));
+            gmres_state h{};
+            h.stop = tol * bnorm;
+            h.maxit = maxit;
+            h.done = kRunning;
+            h.cycle_done = 1;
+            auto *S = state.as<gmres_state>();
+            HIPC(hipMemcpyAsync(S, &h, sizeof(h), hipMemcpyHostToDevice, s));
+            c->sync();   // h is reused as the read-back buffer below
+            double *V0 = V.as<double>();
+            for (;;) {
+                HIPC(hipMemcpyAsync(V0, b, n * 8, hipMemcpyDeviceToDevice, s));
+                spmv_dispatch(A, v, -1.0, x, 1.0, V0);
+                HIPC(gmres_cycle_start(s, n, V0, S, wk));
+                HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+                c->sync();
+                if (h.done != kRunning) break;
+                for (int j = 0; j < m; ++j) {
+                    spmv_dispatch(A, v, 1.0, V0 + (int64_t)j * ldv, 0.0, V0 + (int64_t)(j + 1) * ldv);
+                    HIPC(gmres_arnoldi_step(s, n, m, j, V0, ldv, S, wk));
+                    if ((j + 1) % check_every == 0 && j + 1 < m) {
+                        HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+                        c->sync();
+                        if (h.cycle_done) break;
+                    }
+                }
+                HIPC(gmres_cycle_end(s, n, m, V0, ldv, static_cast<double *>(x), S, wk));
+                HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+                c->sync();
+                if (h.done != kRunning) break;   // breakdown inside the cycle
+            }
+            st = flag_status(h.done);
+            c->info.iterations = h.iter;
+            c->info.outer_iterations = h.cycles;
+            c->info.rel_residual = h.est / bnorm;
+            dbuf r(c, n * 8);
+            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(),
+                                                    partials.as<double>(), ticket.as<unsigned>()) /
+                                        bnorm;
+        }
+        c->sync();
+        c->info.status = st;
+        c->info.seconds = now_seconds() - t0;
+    });
+    if (call != GKO_OK) {
+        if (A) A->ctx->info.status = call;
+        return call;
+    }
+    if (st != GKO_OK) g_last_error = std::string("gmres: ") + gko_status_string(st);
     return st;
 }
 

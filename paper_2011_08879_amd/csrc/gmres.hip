@@ -1,0 +1,316 @@
+// Restarted GMRES(m), FP64, unpreconditioned (Saad and Schultz 1986; Saad,
+// Iterative Methods, Alg. 6.9 with the Givens least-squares update of
+// Sec. 6.5.3).
+//
+// Arnoldi step j with w = A v_j written straight into basis slot j+1:
+//   dot     h = V_j^T w and w.w in one pass over the j+1 basis vectors
+//   update  w -= V_j h, and the new w.w, in one pass
+//   a second round of both (classical Gram-Schmidt twice) only when the
+//   first shrank w below 1/sqrt(2) of its length (Daniel, Gragg, Kaufman and
+//   Stewart's criterion); otherwise those launches return at once
+//   step    (one thread) the column of H, the earlier rotations, the new
+//   Givens rotation, |g_{j+1}| as the residual estimate, the cycle's end
+//   normalise v_{j+1} = w / h_{j+1,j}
+// The basis is column-major with a leading dimension rounded up to 64
+// doubles.  The multi-vector passes keep each thread's rows of w in
+// registers and read the basis vectors coalesced, one after another; the
+// per-vector sums are wave DPP reductions accumulated per wave in LDS, then
+// per-block partials summed in block order by a one-block-per-value kernel,
+// so every result repeats bitwise.  A cycle ends with the back substitution
+// (one thread) and x += V_k y in one pass.
+#include <cmath>
+
+#include "device.hpp"
+#include "kernels.hpp"
+#include "solver_kernels.hpp"
+#include "solver_state.hpp"
+
+namespace gko {
+
+namespace {
+
+constexpr int kG = 256;          // threads per workgroup
+constexpr int kGRows = 4;        // rows per thread per chunk
+constexpr int kGWaves = kG / kWave;
+
+inline int gmres_blocks(int64_t n) {
+    int64_t g = (n + (int64_t)kG * kGRows - 1) / ((int64_t)kG * kGRows);
+    if (g > kGmresMaxBlocks) g = kGmresMaxBlocks;
+    return g < 1 ? 1 : (int)g;
+}
+
+// Phase gates.  mode 0: the passes of an Arnoldi step run only while the
+// cycle is open; mode 1: the second Gram-Schmidt round also needs the step
+// to have asked for it; mode 2 (cycle start): while the solve runs.
+__device__ inline bool gate(const gmres_state *st, int mode) {
+    if (mode == 2) return st->done == kRunning;
+    return st->cycle_done == 0 && (mode == 0 || st->reorth != 0);
+}
+
+// partials[v * gridDim.x + block] <- block sums of V_i . w (v = i < k) and of
+// w . w (v = k)
+__global__ __launch_bounds__(kG) void gmres_dot_kernel(int64_t n, int k, const double *__restrict__ V,
+                                                       int64_t ldv, const double *__restrict__ w,
+                                                       const gmres_state *st, int mode,
+                                                       double *__restrict__ partials) {
+    __shared__ double part[kGmresMaxKrylov + 1][kGWaves];
+    if (!gate(st, mode)) return;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int e = threadIdx.x; e < (k + 1) * kGWaves; e += kG) part[e / kGWaves][e % kGWaves] = 0.0;
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kG * kGRows; base < n;
+         base += (int64_t)gridDim.x * kG * kGRows) {
+        double wr[kGRows];
+        double ww = 0.0;
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r) {
+            const int64_t l = base + r * kG + threadIdx.x;
+            wr[r] = l < n ? w[l] : 0.0;
+            ww += wr[r] * wr[r];
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (int64_t)i * ldv;
+            double s = 0.0;
+#pragma unroll
+            for (int r = 0; r < kGRows; ++r) {
+                const int64_t l = base + r * kG + threadIdx.x;
+                s += (l < n ? vi[l] : 0.0) * wr[r];
+            }
+            s = wave_total(s);
+            if (lane == 0) part[i][wv] += s;
+        }
+        ww = wave_total(ww);
+        if (lane == 0) part[k][wv] += ww;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v <= k; v += kG) {
+        double s = 0.0;
+        for (int q = 0; q < kGWaves; ++q) s += part[v][q];
+        partials[(int64_t)v * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// w -= sum_i h_i V_i (i ascending), block sums of the new w . w
+__global__ __launch_bounds__(kG) void gmres_update_kernel(int64_t n, int k,
+                                                          const double *__restrict__ V,
+                                                          int64_t ldv, const double *__restrict__ h,
+                                                          double *__restrict__ w,
+                                                          const gmres_state *st, int mode,
+                                                          double *__restrict__ partials) {
+    __shared__ double hs[kGmresMaxKrylov];
+    __shared__ double red[kGWaves];
+    if (!gate(st, mode)) return;
+    for (int i = threadIdx.x; i < k; i += kG) hs[i] = h[i];
+    __syncthreads();
+    double ww = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kG * kGRows; base < n;
+         base += (int64_t)gridDim.x * kG * kGRows) {
+        double acc[kGRows];
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r) {
+            const int64_t l = base + r * kG + threadIdx.x;
+            acc[r] = l < n ? w[l] : 0.0;
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (int64_t)i * ldv;
+            const double hi = hs[i];
+#pragma unroll
+            for (int r = 0; r < kGRows; ++r) {
+                const int64_t l = base + r * kG + threadIdx.x;
+                if (l < n) acc[r] = acc[r] - hi * vi[l];
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r) {
+            const int64_t l = base + r * kG + threadIdx.x;
+            if (l < n) {
+                w[l] = acc[r];
+                ww += acc[r] * acc[r];
+            }
+        }
+    }
+    ww = block_sum<kG>(ww, red);
+    if (threadIdx.x == 0) partials[blockIdx.x] = ww;
+}
+
+// out[v] <- sum over blocks of partials[v * g + b], block order, one
+// workgroup per value
+__global__ __launch_bounds__(kG) void gmres_sum_kernel(int g, const double *__restrict__ partials,
+                                                       double *__restrict__ out,
+                                                       const gmres_state *st, int mode) {
+    __shared__ double red[kGWaves];
+    if (!gate(st, mode)) return;
+    const double *p = partials + (int64_t)blockIdx.x * g;
+    double s = 0.0;
+    for (int b = threadIdx.x; b < g; b += kG) s += p[b];
+    s = block_sum<kG>(s, red);
+    if (threadIdx.x == 0) out[blockIdx.x] = s;
+}
+
+// After the first round: keep h, decide on a second round.
+__global__ void gmres_check_kernel(int j, const double *__restrict__ dot1,
+                                   const double *__restrict__ upd1, gmres_state *st,
+                                   double *__restrict__ hcol) {
+    if (st->cycle_done) return;
+    for (int i = 0; i <= j; ++i) hcol[i] = dot1[i];
+    // |w_after| < |w_before| / sqrt(2)
+    st->reorth = (2.0 * upd1[0] < dot1[j + 1]) ? 1 : 0;
+    st->ww = upd1[0];
+}
+
+// Close step j: h_{j+1,j}, rotations, residual estimate, end of cycle.
+__global__ void gmres_step_kernel(int j, int m, const double *__restrict__ dot2,
+                                  const double *__restrict__ upd2, gmres_state *st,
+                                  double *__restrict__ hcol, double *__restrict__ H,
+                                  double *__restrict__ cs, double *__restrict__ sn,
+                                  double *__restrict__ gv) {
+    if (st->cycle_done) return;
+    double ww = st->ww;
+    if (st->reorth) {
+        for (int i = 0; i <= j; ++i) hcol[i] = hcol[i] + dot2[i];
+        ww = upd2[0];
+    }
+    const double hn = sqrt(ww);
+    for (int i = 0; i < j; ++i) {
+        const double a = hcol[i], c = hcol[i + 1];
+        hcol[i] = cs[i] * a + sn[i] * c;
+        hcol[i + 1] = -sn[i] * a + cs[i] * c;
+    }
+    const double a = hcol[j];
+    const double d = sqrt(a * a + hn * hn);
+    st->iter += 1;
+    st->k = j + 1;
+    if (!(d > 0.0)) {
+        st->done = kBreakdown;
+        st->cycle_done = 1;
+        return;
+    }
+    cs[j] = a / d;
+    sn[j] = hn / d;
+    hcol[j] = d;
+    for (int i = 0; i <= j; ++i) H[(int64_t)i * m + j] = hcol[i];
+    H[(int64_t)(j + 1) * m + j] = 0.0;
+    gv[j + 1] = -sn[j] * gv[j];
+    gv[j] = cs[j] * gv[j];
+    const double est = fabs(gv[j + 1]);
+    st->est = est;
+    st->hn = hn;
+    if (std::isnan(est)) {
+        st->done = kBreakdown;
+        st->cycle_done = 1;
+    } else if (est <= st->stop || hn == 0.0 || st->iter >= st->maxit || j + 1 == m) {
+        st->cycle_done = 1;
+    }
+}
+
+__global__ __launch_bounds__(kG) void gmres_scale_kernel(int64_t n, double *__restrict__ v,
+                                                         const gmres_state *st) {
+    if (st->cycle_done) return;
+    const double hn = st->hn;
+    for (int64_t l = (int64_t)blockIdx.x * kG + threadIdx.x; l < n; l += (int64_t)gridDim.x * kG)
+        v[l] = v[l] / hn;
+}
+
+// Back substitution R y = g over the cycle's k columns.
+__global__ void gmres_solve_kernel(int m, const double *__restrict__ H,
+                                   const double *__restrict__ gv, double *__restrict__ y,
+                                   const gmres_state *st) {
+    if (st->done == kBreakdown) return;
+    const int k = st->k;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = gv[i];
+        for (int l = i + 1; l < k; ++l) s = s - H[(int64_t)i * m + l] * y[l];
+        y[i] = s / H[(int64_t)i * m + i];
+    }
+}
+
+// x += sum_i y_i V_i (i ascending)
+__global__ __launch_bounds__(kG) void gmres_xupdate_kernel(int64_t n, const double *__restrict__ V,
+                                                           int64_t ldv,
+                                                           const double *__restrict__ y,
+                                                           double *__restrict__ x,
+                                                           const gmres_state *st) {
+    __shared__ double ys[kGmresMaxKrylov];
+    if (st->done == kBreakdown) return;
+    const int k = st->k;
+    for (int i = threadIdx.x; i < k; i += kG) ys[i] = y[i];
+    __syncthreads();
+    for (int64_t l = (int64_t)blockIdx.x * kG + threadIdx.x; l < n; l += (int64_t)gridDim.x * kG) {
+        double xl = x[l];
+        for (int i = 0; i < k; ++i) xl = xl + ys[i] * V[(int64_t)i * ldv + l];
+        x[l] = xl;
+    }
+}
+
+// Cycle start from v0 = b - A x (unnormalised) and its squared norm.
+__global__ void gmres_cycle_kernel(const double *__restrict__ rr, gmres_state *st,
+                                   double *__restrict__ gv) {
+    if (st->done != kRunning) return;
+    const double beta = sqrt(rr[0]);
+    st->beta = beta;
+    st->cycle_done = 0;
+    st->reorth = 0;
+    st->k = 0;
+    st->hn = beta;   // v0 = r / beta by the scale kernel
+    gv[0] = beta;
+    if (std::isnan(beta) || std::isinf(beta)) {
+        st->done = kBreakdown;
+        st->cycle_done = 1;
+    } else if (beta <= st->stop) {
+        st->done = kConverged;
+        st->cycle_done = 1;
+    } else if (st->iter >= st->maxit) {
+        st->done = kMaxIter;
+        st->cycle_done = 1;
+    } else {
+        st->cycles += 1;
+    }
+}
+
+}  // namespace
+
+int64_t gmres_ld(int64_t n) { return (n + 63) / 64 * 64; }
+
+int64_t gmres_partial_elems(int64_t n, int m) { return (int64_t)(m + 2) * gmres_blocks(n); }
+
+hipError_t gmres_arnoldi_step(hipStream_t s, int64_t n, int m, int j, double *V, int64_t ldv,
+                              gmres_state *st, const gmres_work &wk) {
+    const int g = gmres_blocks(n);
+    double *w = V + (int64_t)(j + 1) * ldv;
+    const int k = j + 1;
+    // first Gram-Schmidt round
+    gmres_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, w, st, 0, wk.partials);
+    gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot1, st, 0);
+    gmres_update_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, 0, wk.partials);
+    gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd1, st, 0);
+    gmres_check_kernel<<<1, 1, 0, s>>>(j, wk.dot1, wk.upd1, st, wk.hcol);
+    // second round, only when the first lost too much of w
+    gmres_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, w, st, 1, wk.partials);
+    gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot2, st, 1);
+    gmres_update_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot2, w, st, 1, wk.partials);
+    gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd2, st, 1);
+    gmres_step_kernel<<<1, 1, 0, s>>>(j, m, wk.dot2, wk.upd2, st, wk.hcol, wk.H, wk.cs, wk.sn,
+                                      wk.g);
+    gmres_scale_kernel<<<reduction_blocks(n), kG, 0, s>>>(n, w, st);
+    return hipGetLastError();
+}
+
+hipError_t gmres_cycle_start(hipStream_t s, int64_t n, double *V, gmres_state *st,
+                             const gmres_work &wk) {
+    // v0 . v0 through the dot pass with no basis vectors
+    const int g = gmres_blocks(n);
+    gmres_dot_kernel<<<g, kG, 0, s>>>(n, 0, V, 0, V, st, 2, wk.partials);
+    gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd1, st, 2);
+    gmres_cycle_kernel<<<1, 1, 0, s>>>(wk.upd1, st, wk.g);
+    gmres_scale_kernel<<<reduction_blocks(n), kG, 0, s>>>(n, V, st);
+    return hipGetLastError();
+}
+
+hipError_t gmres_cycle_end(hipStream_t s, int64_t n, int m, const double *V, int64_t ldv, double *x,
+                           gmres_state *st, const gmres_work &wk) {
+    gmres_solve_kernel<<<1, 1, 0, s>>>(m, wk.H, wk.g, wk.y, st);
+    gmres_xupdate_kernel<<<reduction_blocks(n), kG, 0, s>>>(n, V, ldv, wk.y, x, st);
+    return hipGetLastError();
+}
+
+}  // namespace gko

@@ -82,6 +82,47 @@ hipError_t cgs_update(hipStream_t s, int64_t n, void *r, const void *t, const vo
 hipError_t cgs_direction(hipStream_t s, int64_t n, const void *r, const void *q, void *u, void *p,
                          const krylov_scalars *sc);
 
+// Restarted GMRES (FP64, unpreconditioned; gmres.hip).  The host computes
+// v0 = b - A x into basis slot 0, calls gmres_cycle_start, then for each step
+// j writes w = A v_j into slot j+1 and calls gmres_arnoldi_step, and closes
+// the cycle with gmres_cycle_end (x += V_k y).  Flags and scalars live in
+// gmres_state; every kernel of a closed cycle returns at once.
+constexpr int kGmresMaxKrylov = 128;   // largest restart length
+constexpr int kGmresMaxBlocks = 1024;  // grid of the multi-vector passes
+struct gmres_state {
+    double stop;        // tol * ||b||
+    double beta;        // ||b - A x|| at the cycle start
+    double est;         // |g_{j+1}|: residual norm of the cycle's least-squares solution
+    double hn;          // h_{j+1,j} (the next basis vector's scale)
+    double ww;          // w.w after the first Gram-Schmidt round
+    int32_t iter;       // Arnoldi steps over all cycles
+    int32_t maxit;
+    int32_t k;          // columns of the current cycle
+    int32_t cycles;
+    int32_t done;       // solver_flag of the solve
+    int32_t cycle_done; // the current cycle has ended
+    int32_t reorth;     // step asked for a second Gram-Schmidt round
+    int32_t pad;
+};
+struct gmres_work {
+    double *partials;      // gmres_partial_elems(n, m)
+    double *dot1, *dot2;   // m + 2 each
+    double *upd1, *upd2;   // 1 each
+    double *hcol;          // m + 1
+    double *H;             // (m + 1) * m, row-major
+    double *cs, *sn;       // m each
+    double *g;             // m + 1
+    double *y;             // m
+};
+int64_t gmres_ld(int64_t n);   // leading dimension of the basis
+int64_t gmres_partial_elems(int64_t n, int m);
+hipError_t gmres_cycle_start(hipStream_t s, int64_t n, double *V, gmres_state *st,
+                             const gmres_work &wk);
+hipError_t gmres_arnoldi_step(hipStream_t s, int64_t n, int m, int j, double *V, int64_t ldv,
+                              gmres_state *st, const gmres_work &wk);
+hipError_t gmres_cycle_end(hipStream_t s, int64_t n, int m, const double *V, int64_t ldv, double *x,
+                           gmres_state *st, const gmres_work &wk);
+
 // Mixed precision helpers.
 hipError_t scaled_cast(hipStream_t s, int64_t n, const double *r, const double *norm, float *rt);
 hipError_t refine_update(hipStream_t s, int64_t n, double *x, const double *norm, const float *d);

@@ -120,3 +120,95 @@ def test_cgs_identity_and_breakdown(g, gen_mod, ctx):
     info = g.cgs(L, dev(np.ones(400)), dev(np.zeros(400)), maxit=3)
     assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 3
     assert g.cgs(L, dev(np.zeros(400)), dev(np.ones(400)))["status"] == g.OK
+
+
+# --------------------------------------------------------------------------- GMRES
+@pytest.mark.parametrize("fmt", ["csr", "coo", "hybrid", "sellp"])
+def test_gmres_convdiff_matches_oracle(g, orc, gen_mod, ctx, fmt):
+    A = gen_mod.convdiff2d(40, 0.5)
+    n = 1600
+    xs = gen_mod.uniform(8, n)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.gmres(A, b, tol=1e-10, maxit=20000, m=20)
+    assert rc == orc.OK
+    ctx.set_solver_opts(krylov_dim=20)
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = dev(np.zeros(n))
+    info = g.gmres(M, dev(b), x, tol=1e-10, maxit=20000)
+    assert info["status"] == g.OK, info
+    # classical Gram-Schmidt (twice when needed) against the oracle's modified
+    # Gram-Schmidt: the same Krylov spaces, different rounding
+    assert abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 20), (info, info_o)
+    assert abs(info["outer_iterations"] - info_o["cycles"]) <= 1
+    xg = host(x)
+    assert relres(orc, A, b, xg) <= 1e-10
+    assert abs(info["true_rel_residual"] - relres(orc, A, b, xg)) <= 1e-13
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 1e-7
+
+
+def test_gmres_minimal_residual_steps(g, orc, ctx):
+    """k steps without restart: the residual is the least-squares minimum over
+    the Krylov space (numpy on an orthonormal Krylov basis), and x matches
+    the oracle's k-step iterate."""
+    rng = np.random.default_rng(23)
+    n = 30
+    D = np.eye(n) * 2 + rng.uniform(-1, 1, (n, n)) * 0.25
+    rp = np.arange(0, n * n + 1, n, dtype=np.int32)
+    A = (rp, np.tile(np.arange(n, dtype=np.int32), n), D.ravel())
+    b = rng.uniform(-1, 1, n)
+    ctx.set_solver_opts(krylov_dim=30)
+    M = g.Matrix.from_csr(*A)
+    for k in range(1, 7):
+        x = dev(np.zeros(n))
+        info = g.gmres(M, dev(b), x, tol=1e-15, maxit=k)
+        assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == k
+        xg = host(x)
+        K = np.stack([np.linalg.matrix_power(D, j) @ b for j in range(k)], 1)
+        Q, _ = np.linalg.qr(K)
+        y, *_ = np.linalg.lstsq(D @ Q, b, rcond=None)
+        rmin = np.linalg.norm(b - D @ (Q @ y))
+        assert abs(np.linalg.norm(b - D @ xg) - rmin) <= 1e-10 * np.linalg.norm(b), k
+        rc, xo, _ = orc.gmres(A, b, tol=1e-15, maxit=k, m=30)
+        assert np.linalg.norm(xg - xo) <= 1e-10 * np.linalg.norm(xo), k
+        assert abs(info["rel_residual"] - rmin / np.linalg.norm(b)) <= 1e-10
+
+
+@pytest.mark.parametrize("m", [1, 5, 30, 128])
+def test_gmres_restart_lengths_laplace(g, orc, gen_mod, ctx, m):
+    """n = 65,536 (64 workgroups of the multi-vector passes), restart lengths
+    from GMRES(1) to the largest supported."""
+    N = 256 if m >= 30 else 32
+    A = gen_mod.laplace2d(N)
+    n = N * N
+    b = orc.spmv(A, gen_mod.uniform(2, n))
+    tol = 1e-8
+    rc, xo, info_o = orc.gmres(A, b, tol=tol, maxit=4000, m=m)
+    ctx.set_solver_opts(krylov_dim=m)
+    M = g.Matrix.from_csr(*A)
+    x = dev(np.zeros(n))
+    info = g.gmres(M, dev(b), x, tol=tol, maxit=4000)
+    assert info["status"] == (g.OK if rc == orc.OK else g.ERR_NOT_CONVERGED), (info, info_o)
+    assert abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 20), (info, info_o)
+    if rc == orc.OK:
+        assert relres(orc, A, b, host(x)) <= tol
+
+
+def test_gmres_statuses(g, gen_mod, ctx):
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    Dm = g.Matrix.from_csr(np.arange(51, dtype=np.int32), np.arange(50, dtype=np.int32), d)
+    bb = gen_mod.uniform(31, 50)
+    x = dev(np.zeros(50))
+    info = g.gmres(Dm, dev(bb), x, tol=1e-12)
+    assert info["status"] == g.OK and info["iterations"] <= 3
+    assert np.allclose(host(x), bb / d, rtol=1e-11, atol=0)
+    L = g.Matrix.from_csr(*gen_mod.convdiff2d(20, 0.5))
+    info = g.gmres(L, dev(np.zeros(400)), dev(np.ones(400)))
+    assert info["status"] == g.OK and info["iterations"] == 0
+    info = g.gmres(L, dev(np.ones(400)), dev(np.zeros(400)), maxit=7)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 7
+    bn = np.ones(400)
+    bn[5] = np.nan
+    assert g.gmres(L, dev(bn), dev(np.zeros(400)))["status"] == g.ERR_BREAKDOWN
+    for bad in (0, 129):
+        with pytest.raises(g.GkoError):
+            ctx.set_solver_opts(krylov_dim=bad)
