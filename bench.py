@@ -243,6 +243,7 @@ def run_solvers(g, gen, torch):
         res[label + "_x"] = xh
         log("config-3 %s: %.3f s, %d it (%d outer)" % (label, min(runs), info["iterations"],
                                                       info["outer_iterations"]))
+    res["krylov_fixed_iterations"] = run_krylov(g, torch, ctx, M, b, n)
     x64, xmx = res.pop("fp64_x"), res.pop("mixed_x")
     res["mixed"]["rel_diff_vs_fp64_solution"] = float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64))
     res["speedup_mixed_over_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 3)
@@ -251,6 +252,64 @@ def run_solvers(g, gen, torch):
     del M, b, S
     torch.cuda.empty_cache()
     out["batch_cg_10k"] = run_batch(g, gen, torch)
+    return out
+
+
+def krylov_bytes(name, S, n, iters, m=30):
+    """Algorithmic bytes of `iters` FP64 iterations (S: one SpMV's bytes, n rows).
+    Per iteration: CG and FCG S + 9 vector passes (fused product with p.q;
+    x, r update with the sums; p update); BiCGSTAB 2S + 18; CGS 2S + 17;
+    GMRES Arnoldi step j: S + (2j + 7) passes with one Gram-Schmidt round
+    (dot over j+1 basis vectors and w, update reading them and writing w,
+    normalisation), plus per cycle the residual (S + 5 passes) and
+    x += V y (m + 2 passes).  A vector pass is 8n bytes."""
+    vp = 8.0 * n
+    if name in ("cg", "fcg"):
+        return iters * (S + 9 * vp)
+    if name == "bicgstab":
+        return iters * (2 * S + 18 * vp)
+    if name == "cgs":
+        return iters * (2 * S + 17 * vp)
+    if name == "gmres":
+        cycles, rest = divmod(iters, m)
+        steps = [j for _ in range(cycles) for j in range(m)] + list(range(rest))
+        per_cycle = S + 5 * vp + (m + 2) * vp
+        return sum(S + (2 * j + 7) * vp for j in steps) + (cycles + (rest > 0)) * per_cycle
+    raise ValueError(name)
+
+
+def run_krylov(g, torch, ctx, M, b, n):
+    """Every Krylov solver for a fixed number of FP64 iterations on the same
+    matrix (unpreconditioned, tolerance out of reach): time per iteration and
+    algorithmic bytes per second, as the paper's solver benchmark measures
+    bandwidth-bound solvers over a fixed iteration count."""
+    d = M.describe()
+    S = spmv_bytes(d)
+    out = {"format": d.format, "n": n, "spmv_alg_bytes": int(S)}
+    runs = (("cg", g.cg, 300), ("fcg", g.fcg, 300), ("bicgstab", g.bicgstab, 150),
+            ("cgs", g.cgs, 150), ("gmres", g.gmres, 300))
+    for name, fn, iters in runs:
+        ctx.set_solver_opts(single_workgroup=0, krylov_dim=30)
+        best = None
+        for _ in range(2):
+            x = torch.zeros(n, dtype=torch.float64, device="cuda")
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            info = fn(M, b, x, tol=1e-30, maxit=iters)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        it = info["iterations"]
+        nb = krylov_bytes(name, S, n, it)
+        out[name] = {"iterations": it, "seconds": round(best, 4),
+                     "ms_per_iteration": round(best / max(it, 1) * 1e3, 4),
+                     "alg_GB/s": round(nb / best / 1e9, 1),
+                     "frac_hbm_peak": round(nb / best / 1e9 / HBM_PEAK_GBS, 4),
+                     "status": info["status_name"]}
+        if name == "gmres":
+            out[name]["reorthogonalized_steps"] = info["reorthogonalized"]
+        log("krylov %-8s %4d it  %.3f ms/it  %.0f GB/s" % (name, it, out[name]["ms_per_iteration"],
+                                                         out[name]["alg_GB/s"]))
+    ctx.set_solver_opts()
     return out
 
 

@@ -218,12 +218,14 @@ typedef struct gko_solver_opts {
 typedef struct gko_solve_info {
     int32_t status;            /* gko_status of the solve */
     int32_t iterations;        /* Krylov iterations (FP64) or total inner iterations (MIXED_IR) */
-    int32_t outer_iterations;  /* MIXED_IR refinement steps, else 0 */
+    int32_t outer_iterations;  /* MIXED_IR refinement steps, GMRES cycles, else 0 */
     int32_t restarts;          /* true-residual restarts */
     double rel_residual;       /* recursive ||r|| / ||b|| at exit */
     double true_rel_residual;  /* ||b - A x|| / ||b|| recomputed at exit */
     double seconds;            /* wall time of the solve call */
     double setup_seconds;      /* part of it spent building the preconditioner */
+    int32_t reorthogonalized;  /* GMRES: Arnoldi steps that took a second Gram-Schmidt round */
+    int32_t pad;
 } gko_solve_info;
 
 gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *opts);

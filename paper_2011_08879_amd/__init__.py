@@ -62,7 +62,8 @@ class SolverOpts(ctypes.Structure):
 class _SolveInfo(ctypes.Structure):
     _fields_ = [("status", _i32), ("iterations", _i32), ("outer_iterations", _i32),
                 ("restarts", _i32), ("rel_residual", _f64), ("true_rel_residual", _f64),
-                ("seconds", _f64), ("setup_seconds", _f64)]
+                ("seconds", _f64), ("setup_seconds", _f64), ("reorthogonalized", _i32),
+                ("pad", _i32)]
 
 
 ALLOC_FN = ctypes.CFUNCTYPE(_vp, ctypes.c_size_t, _vp, _vp)

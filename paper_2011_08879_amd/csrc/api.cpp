@@ -2102,6 +2102,7 @@ gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int
             st = flag_status(h.done);
             c->info.iterations = h.iter;
             c->info.outer_iterations = h.cycles;
+            c->info.reorthogonalized = h.reorths;
             c->info.rel_residual = h.est / bnorm;
             dbuf r(c, n * 8);
             HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));

@@ -155,6 +155,7 @@ __global__ void gmres_check_kernel(int j, const double *__restrict__ dot1,
     for (int i = 0; i <= j; ++i) hcol[i] = dot1[i];
     // |w_after| < |w_before| / sqrt(2)
     st->reorth = (2.0 * upd1[0] < dot1[j + 1]) ? 1 : 0;
+    st->reorths += st->reorth;
     st->ww = upd1[0];
 }
 

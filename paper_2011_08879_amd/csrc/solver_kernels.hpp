@@ -102,7 +102,7 @@ struct gmres_state {
     int32_t done;       // solver_flag of the solve
     int32_t cycle_done; // the current cycle has ended
     int32_t reorth;     // step asked for a second Gram-Schmidt round
-    int32_t pad;
+    int32_t reorths;    // steps that took a second round
 };
 struct gmres_work {
     double *partials;      // gmres_partial_elems(n, m)
