@@ -235,9 +235,10 @@ void require(bool ok, gko_status s, const std::string &m) {
 
 int64_t round_up64(int64_t v) { return (v + 63) / 64 * 64; }
 
-// Scratch of the grid reductions: up to 3 values per block for the largest
-// grid any reduction kernel launches.
-constexpr size_t kPartialBytes = (size_t)3 * kMaxReductionBlocks * sizeof(double);
+// Scratch of the grid reductions: up to 3 values per block of the vector
+// kernels' grids, or one per block of a fused product's larger grid.
+constexpr size_t kPartialBytes =
+    (size_t)std::max(3 * kMaxReductionBlocks, kFusedMaxBlocks) * sizeof(double);
 
 void ensure_carries(gko_matrix A, int64_t elems) {
     if (A->carry_elems >= elems && A->carry_a) return;

@@ -21,6 +21,13 @@ namespace gko {
 
 constexpr int kB = kRedBlock;  // 256 threads, one row per thread per tile
 
+// Grid of a fused product over n rows (or row pairs), one per thread.
+static int fused_blocks(int64_t n) {
+    int64_t g = (n + kB - 1) / kB;
+    if (g > kFusedMaxBlocks) g = kFusedMaxBlocks;
+    return g < 1 ? 1 : (int)g;
+}
+
 int reduction_blocks(int64_t n) {
     int64_t g = (n + kB - 1) / kB;
     if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
@@ -365,7 +372,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, i
 hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
                        const void *eval, const void *p, void *q, krylov_scalars *sc,
                        double *partials, unsigned *ticket) {
-    const int g = reduction_blocks((n + 1) / 2);
+    const int g = fused_blocks((n + 1) / 2);
     const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_spmv_ell_kernel<double><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const double *>(eval),
@@ -401,7 +408,7 @@ __global__ __launch_bounds__(kB) void cg_spmv_sellp_kernel(int64_t n, const int6
 hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
                          const void *sval, const void *p, void *q, krylov_scalars *sc,
                          double *partials, unsigned *ticket) {
-    const int g = reduction_blocks(n);
+    const int g = fused_blocks(n);
     const red_args ra = red_for(g, partials, ticket);
     if (t == vt::f64)
         cg_spmv_sellp_kernel<double><<<g, kB, 0, s>>>(n, sets, scol, static_cast<const double *>(sval),
@@ -512,7 +519,7 @@ static hipError_t launch_cg_csr_w(hipStream_t s, int64_t n, const int32_t *rp, c
                                   double *partials, unsigned *ticket) {
     constexpr int RPB = kB / W * csr_shape<W>::U;
     int64_t g = (n + RPB - 1) / RPB;
-    if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
+    if (g > kFusedMaxBlocks) g = kFusedMaxBlocks;
     if (g < 1) g = 1;
     const red_args ra = red_for((int)g, partials, ticket);
     cg_spmv_csr_kernel<V, W><<<(unsigned)g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
@@ -526,7 +533,7 @@ static hipError_t launch_cg_csr(hipStream_t s, int64_t n, const int32_t *rp, con
                                 const void *val, const void *p, void *q, int w, krylov_scalars *sc,
                                 double *partials, unsigned *ticket) {
     if (w == kCsrRowThread) {
-        const int g = reduction_blocks(n);
+        const int g = fused_blocks(n);
         const red_args ra = red_for(g, partials, ticket);
         cg_spmv_csr_rowthread_kernel<V><<<g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
                                                          static_cast<const V *>(p),
