@@ -82,6 +82,7 @@ def _load():
     lib.orc_bj_apply.argtypes = [i64, i32, _f64p, _f64p, _f64p]
     lib.orc_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, vp, i32, _f64p]
     lib.orc_fcg.argtypes = lib.orc_cg.argtypes
+    lib.orc_pipecg.argtypes = lib.orc_cg.argtypes
     lib.orc_bicgstab.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, _f64p]
     lib.orc_ir_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, f64, i32, vp,
                               i32, _f64p]
@@ -302,6 +303,19 @@ def fcg(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, bj_inv=None, bs: 
     inv = None if bj_inv is None else _f64(np.asarray(bj_inv).reshape(-1))
     rc = _load().orc_fcg(n, rp, col, val, _f64(b), x, tol, maxit,
                          None if inv is None else inv.ctypes.data, bs, out)
+    return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2],
+                   "restarts": int(out[3])}
+
+
+def pipecg(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, bj_inv=None, bs: int = 8):
+    """Pipelined (P)CG (Ghysels-Vanroose).  Returns (status, x, info) as cg()."""
+    rp, col, val = _csr(A)
+    n = rp.shape[0] - 1
+    x = np.zeros(n) if x0 is None else _f64(x0).copy()
+    out = np.zeros(4)
+    inv = None if bj_inv is None else _f64(np.asarray(bj_inv).reshape(-1))
+    rc = _load().orc_pipecg(n, rp, col, val, _f64(b), x, tol, maxit,
+                            None if inv is None else inv.ctypes.data, bs, out)
     return rc, x, {"iters": int(out[0]), "relres": out[1], "true_relres": out[2],
                    "restarts": int(out[3])}
 

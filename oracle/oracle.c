@@ -495,6 +495,113 @@ done:
 }
 
 /* ======================================================================
+ * Pipelined preconditioned CG (Ghysels and Vanroose, Parallel Computing 40,
+ * 2014): CG rearranged so that one global reduction per iteration (the dots
+ * gamma = r.u, delta = w.u and r.r) can overlap the preconditioner and the
+ * product.  With u = M^{-1} r and w = A u kept by recurrences:
+ *   start: r = b - A x;  u = M^{-1} r;  w = A u
+ *   repeat: gamma = r.u;  delta = w.u;  m = M^{-1} w;  n = A m;
+ *           first step: beta = 0, alpha = gamma / delta;  later:
+ *           beta = gamma / gamma_old, alpha = gamma / (delta - beta gamma / alpha_old)
+ *           z = n + beta z;  q = m + beta q;  s = w + beta s;  p = u + beta p;
+ *           x += alpha p;  r -= alpha s;  u -= alpha q;  w -= alpha z;
+ *           stop when ||r||_2 <= tol ||b||_2.
+ * The denominator of alpha is p.Ap in exact arithmetic: <= 0 means A is not
+ * SPD.  In exact arithmetic the iterates are CG's.  True-residual check and
+ * restarts (at most two) and the outputs as orc_cg.
+ * ====================================================================== */
+int orc_pipecg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
+               const double *b, double *x, double tol, int32_t maxit,
+               const double *bj_inv, int32_t bs, double *out) {
+    double *r = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *u = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *w = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *m = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *nn = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *z = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *q = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *sv = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    double *p = (double *)calloc(n > 0 ? n : 1, sizeof(double));
+    int rc = ORC_NOT_CONVERGED;
+    int32_t it = 0, restarts = 0;
+    double bnorm = orc_norm2(n, b), rnorm = 0.0, tnorm = 0.0;
+    if (!(bnorm > 0.0)) {
+        for (int64_t i = 0; i < n; ++i) x[i] = 0.0;
+        rc = (bnorm == 0.0) ? ORC_OK : ORC_BREAKDOWN;
+        goto done;
+    }
+    for (;;) {
+        for (int64_t i = 0; i < n; ++i) r[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, r);
+        rnorm = orc_norm2(n, r);
+        int conv = rnorm <= tol * bnorm;
+        if (!conv) {
+            if (bj_inv) orc_bj_apply(n, bs, bj_inv, r, u);
+            else for (int64_t i = 0; i < n; ++i) u[i] = r[i];
+            orc_csr_spmv(n, rp, ci, v, u, 1.0, 0.0, w);
+            double gamma_old = 0.0, alpha_old = 0.0;
+            int first = 1;
+            while (it < maxit) {
+                double gamma = orc_dot(n, r, u), delta = orc_dot(n, w, u);
+                if (bj_inv) orc_bj_apply(n, bs, bj_inv, w, m);
+                else for (int64_t i = 0; i < n; ++i) m[i] = w[i];
+                orc_csr_spmv(n, rp, ci, v, m, 1.0, 0.0, nn);
+                double alpha, beta, den;
+                if (first) {
+                    beta = 0.0;
+                    den = delta;
+                } else {
+                    beta = gamma / gamma_old;
+                    den = delta - beta * gamma / alpha_old;
+                }
+                if (!(den > 0.0)) { rc = isnan(den) ? ORC_BREAKDOWN : ORC_NOT_SPD; ++it; goto done; }
+                alpha = gamma / den;
+                for (int64_t i = 0; i < n; ++i) {
+                    z[i] = nn[i] + beta * z[i];
+                    q[i] = m[i] + beta * q[i];
+                    sv[i] = w[i] + beta * sv[i];
+                    p[i] = u[i] + beta * p[i];
+                }
+                for (int64_t i = 0; i < n; ++i) {
+                    x[i] = x[i] + alpha * p[i];
+                    r[i] = r[i] - alpha * sv[i];
+                    u[i] = u[i] - alpha * q[i];
+                    w[i] = w[i] - alpha * z[i];
+                }
+                ++it;
+                first = 0;
+                gamma_old = gamma;
+                alpha_old = alpha;
+                rnorm = orc_norm2(n, r);
+                if (isnan(rnorm) || isinf(rnorm)) { rc = ORC_BREAKDOWN; goto done; }
+                if (rnorm <= tol * bnorm) { conv = 1; break; }
+            }
+        }
+        if (!conv) { rc = ORC_NOT_CONVERGED; break; }
+        for (int64_t i = 0; i < n; ++i) q[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, q);
+        tnorm = orc_norm2(n, q);
+        if (tnorm <= tol * bnorm) { rc = ORC_OK; break; }
+        if (restarts == 2 || it >= maxit) { rc = ORC_NOT_CONVERGED; break; }
+        ++restarts;
+        /* the recurrences restart from scratch: z, q, s, p are multiplied by beta = 0 */
+        for (int64_t i = 0; i < n; ++i) { z[i] = 0.0; q[i] = 0.0; sv[i] = 0.0; p[i] = 0.0; }
+    }
+done:
+    if (out) {
+        for (int64_t i = 0; i < n; ++i) q[i] = b[i];
+        orc_csr_spmv(n, rp, ci, v, x, -1.0, 1.0, q);
+        tnorm = orc_norm2(n, q);
+        out[0] = it;
+        out[1] = bnorm > 0.0 ? rnorm / bnorm : 0.0;
+        out[2] = bnorm > 0.0 ? tnorm / bnorm : 0.0;
+        out[3] = restarts;
+    }
+    free(r); free(u); free(w); free(m); free(nn); free(z); free(q); free(sv); free(p);
+    return rc;
+}
+
+/* ======================================================================
  * Flexible CG (Notay, SIAM J. Sci. Comput. 22, 2000, truncated to one
  * previous direction), optionally preconditioned.  CG with the
  * Polak-Ribiere coefficient

@@ -4,12 +4,13 @@ The paper (Sec. 6.2) benchmarks memory-bound Krylov solvers built on SpMV but
 does not write them out; the oracle follows the textbook algorithms (CG:
 Hestenes-Stiefel / Saad Alg. 9.1; BiCGSTAB: van der Vorst 1992; flexible CG:
 Notay 2000; CGS: Sonneveld 1989 / Saad Alg. 7.5; restarted GMRES: Saad and
-Schultz 1986 / Saad Alg. 6.9).  Pinned by finite termination, closed-form
+Schultz 1986 / Saad Alg. 6.9; pipelined CG: Ghysels and Vanroose 2014).  Pinned by finite termination, closed-form
 spectra (condition numbers, iteration bounds), manufactured solutions, exact
 preconditioners, and each method's defining optimality or projection
 property computed independently with dense linear algebra (GMRES: minimal
 residual over the Krylov space; CGS: the squared BiCG residual polynomial;
-FCG: the Galerkin solution over the preconditioned residuals).
+FCG: the Galerkin solution over the preconditioned residuals; pipelined CG:
+CG's iterates, step by step).
 """
 import math
 
@@ -441,3 +442,41 @@ def test_gmres_finite_termination_restarts_and_bad_m(orc, gen_mod):
     assert rc == orc.BAD
     rc, x, info = orc.gmres(A, np.zeros(1600), m=5)
     assert rc == orc.OK and info["iters"] == 0 and not x.any()
+
+
+# --------------------------------------------------------------------------- pipelined CG
+def test_pipecg_iterates_are_cg_iterates(orc, gen_mod):
+    """In exact arithmetic pipelined CG produces CG's iterates: after k steps
+    (no stop) the two agree to rounding, with and without block-Jacobi."""
+    rng = np.random.default_rng(41)
+    n = 40
+    G = rng.standard_normal((n, n))
+    D = G @ G.T / n + np.eye(n)                        # SPD, kappa ~ 5
+    A = dense_to_csr(D)
+    b = rng.uniform(-1, 1, n)
+    rc, inv = orc.bj_invert(A, 8)
+    for kw in ({}, {"bj_inv": inv, "bs": 8}):
+        for k in range(1, 11):
+            r1, xc, i1 = orc.cg(A, b, tol=1e-300, maxit=k, **kw)
+            r2, xp, i2 = orc.pipecg(A, b, tol=1e-300, maxit=k, **kw)
+            assert i1["iters"] == i2["iters"] == k
+            assert np.linalg.norm(xp - xc) <= 1e-12 * np.linalg.norm(xc), (k, kw.keys())
+
+
+def test_pipecg_terminates_and_meets_manufactured_bounds(orc, gen_mod):
+    d = np.array([1.0, 2.0, 3.0] * 17)[:50]
+    b = gen_mod.uniform(31, 50)
+    rc, x, info = orc.pipecg(diag_csr(d), b, tol=1e-12, maxit=100)
+    assert rc == orc.OK and info["iters"] <= 3
+    N = 64
+    A = gen_mod.laplace2d(N)
+    xs = gen_mod.uniform(2, N * N)
+    b = orc.spmv(A, xs)
+    rc, x, info = orc.pipecg(A, b, tol=1e-10)
+    kappa = (4 + 4 * math.cos(math.pi / (N + 1))) / (4 - 4 * math.cos(math.pi / (N + 1)))
+    assert rc == orc.OK and info["iters"] <= math.ceil(0.5 * math.sqrt(kappa) * math.log(2 / 1e-10))
+    assert info["true_relres"] <= 1e-10
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+    D = (np.arange(5, dtype=np.int32), np.arange(4, dtype=np.int32), np.array([1.0, 2.0, -1.0, 3.0]))
+    rc, x, info = orc.pipecg(D, np.ones(4))
+    assert rc == orc.NOT_SPD
