@@ -251,6 +251,17 @@ gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_
  * as gko_cg_solve; no single-workgroup path. */
 gko_status gko_fcg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
+/* Pipelined (P)CG (Ghysels and Vanroose, Parallel Computing 40, 2014): CG
+ * rearranged so that u = M^-1 r and w = A u are carried by recurrences and
+ * each iteration needs one product and one fused vector kernel with a single
+ * reduction (r.u, w.u, r.r), at the price of more vector traffic (13 vector
+ * passes per iteration without a preconditioner, CG's fused path 9).  Equal
+ * to CG's iterates in exact arithmetic; its recursive residual drifts
+ * further from the true one, which the true-residual check and restarts
+ * catch.  The same options, stopping test, statuses and solve info as
+ * gko_cg_solve; no single-workgroup path. */
+gko_status gko_pipecg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
 /* Solve A x = b by unpreconditioned BiCGSTAB (van der Vorst), shadow
  * residual r0, same conventions as gko_cg_solve.  Breakdown (|rho|, |rhat.v|
  * or t.t below 1e-300, or omega = 0) returns GKO_ERR_BREAKDOWN. */

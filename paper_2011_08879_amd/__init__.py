@@ -112,6 +112,7 @@ _SIGS = {
                            ctypes.POINTER(ctypes.c_float)],
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
     "gko_fcg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_pipecg_solve": [_vp, _vp, _vp, _f64, _i32],
     "gko_cgs_solve": [_vp, _vp, _vp, _f64, _i32],
     "gko_gmres_solve": [_vp, _vp, _vp, _f64, _i32],
 }
@@ -442,6 +443,12 @@ def bicgstab(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
 def fcg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
     """Flexible (P)CG (Polak-Ribiere beta), the same options as cg()."""
     return _solve(_lib.gko_fcg_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+def pipecg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
+           raise_on_failure: bool = False):
+    """Pipelined (P)CG (Ghysels-Vanroose): one reduction per iteration; options as cg()."""
+    return _solve(_lib.gko_pipecg_solve, A, b, x, tol, maxit, raise_on_failure)
 
 
 def cgs(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):

@@ -770,6 +770,84 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
     return res;
 }
 
+// Pipelined (P)CG (Ghysels and Vanroose) with the same stopping test,
+// true-residual check and restarts as cg_core; one product and one fused
+// vector kernel (one reduction) per iteration.
+solve_result pipecg_core(gko_matrix A, const values &v, const void *b, void *x, double tol,
+                         int32_t maxit, const void *inv, int bs, int check_every, bool true_check) {
+    gko_context c = A->ctx;
+    hipStream_t s = c->stream;
+    const int64_t n = A->n;
+    const size_t vb = vsize(v.t);
+    const size_t pre = bs > 0 ? n * vb : 8;
+    dbuf r(c, n * vb), w(c, n * vb), nn(c, n * vb), z(c, n * vb), sv(c, n * vb), p(c, n * vb);
+    dbuf u(c, pre), m(c, pre), q(c, pre);
+    dbuf partials(c, kPartialBytes), ticket(c, 8), sc(c, sizeof(krylov_scalars)), nrm(c, 8);
+    HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
+    auto *S = sc.as<krylov_scalars>();
+    HIPC(scalars_reset(s, S, maxit));
+    pipe_vectors pv;
+    pv.n = nn.p;
+    pv.z = z.p;
+    pv.s = sv.p;
+    pv.p = p.p;
+    pv.x = x;
+    pv.r = r.p;
+    pv.w = w.p;
+    pv.u = bs > 0 ? u.p : r.p;
+    pv.m = bs > 0 ? m.p : w.p;
+    pv.q = bs > 0 ? q.p : sv.p;
+    solve_result res;
+    krylov_scalars h{};
+    for (;;) {
+        HIPC(hipMemcpyAsync(r.p, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+        // the first step multiplies z, q, s, p by beta = 0: they start at zero
+        for (void *vec : {pv.z, pv.q, pv.s, pv.p}) HIPC(fill_zero(s, v.t, n, vec));
+        if (bs > 0) HIPC(pipe_precond(s, v.t, n, r.p, pv.u, inv, bs));
+        spmv_dispatch(A, v, 1.0, pv.u, 0.0, w.p);
+        HIPC(pipe_init(s, v.t, n, b, r.p, pv.u, w.p, pv.m, inv, bs, tol, S, partials.as<double>(),
+                       ticket.as<unsigned>()));
+        h = read_back(c, S);
+        while (h.done == kRunning) {
+            for (int j = 0; j < check_every; ++j) {
+                spmv_dispatch(A, v, 1.0, pv.m, 0.0, nn.p);
+                HIPC(pipe_update(s, v.t, n, pv, inv, bs, S, partials.as<double>(),
+                                 ticket.as<unsigned>()));
+            }
+            h = read_back(c, S);
+        }
+        res.flag = h.done;
+        res.iters = h.iter;
+        res.relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+        if (!true_check) break;
+        HIPC(hipMemcpyAsync(nn.p, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, nn.p);
+        const double tn = device_norm(c, v.t, n, nn.p, nrm.as<double>(), partials.as<double>(),
+                                      ticket.as<unsigned>());
+        res.true_relres = h.bb > 0 ? tn / std::sqrt(h.bb) : 0.0;
+        if (h.done != kConverged) break;
+        if (tn <= tol * std::sqrt(h.bb)) break;
+        if (res.restarts == 2 || h.iter >= maxit) {
+            res.flag = kMaxIter;
+            break;
+        }
+        res.restarts += 1;   // pipe_init restarts the recurrences; the count goes on
+    }
+    return res;
+}
+
+enum class cg_variant { plain, flexible, pipelined };
+
+solve_result cg_variant_core(cg_variant var, gko_matrix A, const values &v, const void *b, void *x,
+                             double tol, int32_t maxit, const void *inv, int bs, int check_every,
+                             bool true_check) {
+    if (var == cg_variant::pipelined)
+        return pipecg_core(A, v, b, x, tol, maxit, inv, bs, check_every, true_check);
+    return cg_core(A, v, b, x, tol, maxit, inv, bs, check_every, true_check,
+                   var == cg_variant::flexible);
+}
+
 struct mixed_result {
     gko_status status = GKO_OK;
     int32_t inner = 0, outer = 0;
@@ -777,7 +855,7 @@ struct mixed_result {
 };
 
 mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gko_solver_opts &o,
-                      int bs, double bnorm, bool flexible) {
+                      int bs, double bnorm, cg_variant var) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     const int64_t n = A->n;
@@ -804,9 +882,9 @@ mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gk
         // ask the inner solve only for the reduction still missing (factor 2
         // of margin), never for less than inner_tol
         const double tau = std::max(o.inner_tol, 0.5 * (tol * bnorm / rn));
-        solve_result in = cg_core(A, v32, rt.p, d.p, tau, o.max_inner,
-                                  bs > 0 ? (const void *)A->bj32 : nullptr, bs, o.check_every, false,
-                                  flexible);
+        solve_result in = cg_variant_core(var, A, v32, rt.p, d.p, tau, o.max_inner,
+                                          bs > 0 ? (const void *)A->bj32 : nullptr, bs,
+                                          o.check_every, false);
         res.inner += in.iters;
         if (in.flag == kNotSpd || in.flag == kBreakdown) {
             res.status = flag_status(in.flag);
@@ -1813,10 +1891,10 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out) {
     });
 }
 
-// CG (flexible = false) or flexible CG: the same kernels and options; only
-// CG has the single-workgroup path for small systems.
+// CG, flexible CG or pipelined CG: the same options; only CG has the
+// single-workgroup path for small systems.
 static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit,
-                           bool flexible) {
+                                  cg_variant var) {
     gko_status st = GKO_OK;
     gko_status call = guarded([&] {
         check_square_f64(A);
@@ -1827,7 +1905,8 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
         const gko_solver_opts o = c->opts;
         const int64_t n = A->n;
         if (c->small_cg_rows < 0) c->small_cg_rows = small_cg_max_rows();
-        const bool single = !flexible && o.single_workgroup && o.precision == GKO_PREC_FP64 &&
+        const bool single = var == cg_variant::plain && o.single_workgroup &&
+                            o.precision == GKO_PREC_FP64 &&
                             o.precond == GKO_PRECOND_NONE && n > 0 && n <= c->small_cg_rows &&
                             (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE);
         if (single) {
@@ -1868,16 +1947,16 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
                 c->info.setup_seconds = now_seconds() - ts;
             }
             if (o.precision == GKO_PREC_MIXED_IR) {
-                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm, flexible);
+                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm, var);
                 st = r.status;
                 c->info.iterations = r.inner;
                 c->info.outer_iterations = r.outer;
                 c->info.rel_residual = r.true_relres;
                 c->info.true_rel_residual = r.true_relres;
             } else {
-                solve_result r = cg_core(A, own_values(A), b, x, tol, maxit,
-                                         bs > 0 ? (const void *)A->bj64 : nullptr, bs,
-                                         o.check_every, true, flexible);
+                solve_result r = cg_variant_core(var, A, own_values(A), b, x, tol, maxit,
+                                                 bs > 0 ? (const void *)A->bj64 : nullptr, bs,
+                                                 o.check_every, true);
                 st = flag_status(r.flag);
                 c->info.iterations = r.iters;
                 c->info.restarts = r.restarts;
@@ -1893,16 +1972,24 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
         if (A) A->ctx->info.status = call;
         return call;
     }
-    if (st != GKO_OK) g_last_error = std::string(flexible ? "fcg: " : "cg: ") + gko_status_string(st);
+    if (st != GKO_OK)
+        g_last_error = std::string(var == cg_variant::plain      ? "cg: "
+                                   : var == cg_variant::flexible ? "fcg: "
+                                                                 : "pipecg: ") +
+                       gko_status_string(st);
     return st;
 }
 
 gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
-    return cg_family_solve(A, b, x, tol, maxit, false);
+    return cg_family_solve(A, b, x, tol, maxit, cg_variant::plain);
 }
 
 gko_status gko_fcg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
-    return cg_family_solve(A, b, x, tol, maxit, true);
+    return cg_family_solve(A, b, x, tol, maxit, cg_variant::flexible);
+}
+
+gko_status gko_pipecg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    return cg_family_solve(A, b, x, tol, maxit, cg_variant::pipelined);
 }
 
 gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {

@@ -618,6 +618,245 @@ hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ pipelined CG
+// Ghysels and Vanroose's pipelined (P)CG: u = M^-1 r and w = A u are carried
+// by recurrences, so an iteration is one product n = A m (m = M^-1 w) and one
+// fused vector kernel whose single reduction (gamma = r.u, delta = w.u, r.r)
+// yields the next alpha and beta.  Without a preconditioner u = r, m = w and
+// q = s, and the kernel carries the four vectors z, s, p, w besides x, r.
+
+// alpha and beta of the step that follows the sums gamma, delta:
+// first step beta = 0, alpha = gamma / delta; then beta = gamma / gamma_old,
+// alpha = gamma / (delta - beta gamma / alpha_old).  The denominator is
+// p.Ap in exact arithmetic, <= 0 means A is not SPD.
+__device__ inline void pipe_next(krylov_scalars *sc, double gamma, double delta, bool first) {
+    const double beta = first ? 0.0 : gamma / sc->rho;
+    const double den = first ? delta : delta - beta * gamma / sc->alpha;
+    sc->aux = den;
+    if (!(den > 0.0)) {
+        sc->done = std::isnan(den) ? kBreakdown : kNotSpd;
+        sc->iter += 1;
+        return;
+    }
+    sc->beta = beta;
+    sc->alpha = gamma / den;
+    sc->rho = gamma;
+}
+
+// Start: totals gamma, delta, r.r, b.b.
+struct pipe_init_op {
+    krylov_scalars *sc;
+    double tol;
+    __device__ bool skip() const { return false; }
+    __device__ void operator()(const double *o) const {
+        sc->rr = o[2];
+        sc->bb = o[3];
+        sc->stop2 = tol * tol * o[3];
+        if (!std::isfinite(o[2]) || !std::isfinite(o[0]) || !std::isfinite(o[1])) sc->done = kBreakdown;
+        else if (o[2] <= sc->stop2) sc->done = kConverged;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else {
+            sc->done = kRunning;
+            pipe_next(sc, o[0], o[1], true);
+        }
+    }
+};
+
+// After an update: totals gamma, delta, r.r.
+struct pipe_update_op {
+    krylov_scalars *sc;
+    __device__ bool skip() const { return sc->done != 0; }
+    __device__ void operator()(const double *o) const {
+        sc->iter += 1;
+        sc->rr = o[2];
+        if (!std::isfinite(o[2]) || !std::isfinite(o[0]) || !std::isfinite(o[1])) sc->done = kBreakdown;
+        else if (o[2] <= sc->stop2) sc->done = kConverged;
+        else if (sc->iter >= sc->maxit) sc->done = kMaxIter;
+        else pipe_next(sc, o[0], o[1], false);
+    }
+};
+
+// u = M^-1 r (preconditioned start only).
+template <typename V, int BS>
+__global__ __launch_bounds__(kB) void pipe_precond_kernel(int64_t n, const V *__restrict__ r,
+                                                          V *__restrict__ u,
+                                                          const V *__restrict__ inv) {
+    __shared__ V r_lds[kB];
+    __shared__ V inv_lds[kB / BS * bj_packed<BS>()];
+    for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
+        const int64_t i = base + threadIdx.x;
+        const V ri = i < n ? r[i] : V(0);
+        const V ui = bj_tile_apply<V, BS>(n, base, ri, inv, r_lds, inv_lds);
+        if (i < n) u[i] = ui;
+    }
+}
+
+// Start, after w = A u: m = M^-1 w, and the sums gamma, delta, r.r, b.b.
+template <typename V, int BS>
+__global__ __launch_bounds__(kB) void pipe_init_kernel(int64_t n, const V *__restrict__ b,
+                                                       const V *__restrict__ r,
+                                                       const V *__restrict__ u,
+                                                       const V *__restrict__ w, V *__restrict__ m,
+                                                       const V *__restrict__ inv, double tol,
+                                                       krylov_scalars *sc, red_args ra) {
+    __shared__ V r_lds[BS > 0 ? kB : 1];
+    __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
+    double a_g = 0.0, a_d = 0.0, a_rr = 0.0, a_bb = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
+        const int64_t i = base + threadIdx.x;
+        const V wi = i < n ? w[i] : V(0);
+        V mi = wi;
+        if constexpr (BS > 0) mi = bj_tile_apply<V, BS>(n, base, wi, inv, r_lds, inv_lds);
+        if (i < n) {
+            if constexpr (BS > 0) m[i] = mi;
+            const double ri = (double)r[i], ui = (double)u[i], bi = (double)b[i];
+            a_g += ri * ui;
+            a_d += (double)wi * ui;
+            a_rr += ri * ri;
+            a_bb += bi * bi;
+        }
+    }
+    double v[4] = {a_g, a_d, a_rr, a_bb};
+    grid_sum_apply<kB, 4>(v, ra, pipe_init_op{sc, tol});
+}
+
+// One iteration after n = A m:
+//   z = n + beta z; q = m + beta q; s = w + beta s; p = u + beta p;
+//   x += alpha p; r -= alpha s; u -= alpha q; w -= alpha z; m = M^-1 w;
+// then gamma = r.u, delta = w.u, r.r.  BS = 0: u = r, m = w, q = s.
+template <typename V, int BS>
+__global__ __launch_bounds__(kB) void pipe_update_kernel(
+    int64_t n, const V *__restrict__ nv, V *__restrict__ z, V *__restrict__ q, V *__restrict__ s,
+    V *__restrict__ p, V *__restrict__ x, V *__restrict__ r, V *__restrict__ u, V *__restrict__ w,
+    V *__restrict__ m, const V *__restrict__ inv, krylov_scalars *sc, red_args ra) {
+    __shared__ V r_lds[BS > 0 ? kB : 1];
+    __shared__ V inv_lds[BS > 0 ? kB / (BS > 0 ? BS : 1) * bj_packed<BS>() : 1];
+    if (sc->done) return;
+    const double alpha = sc->alpha, beta = sc->beta;
+    double a_g = 0.0, a_d = 0.0, a_rr = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * kB; base < n; base += (int64_t)gridDim.x * kB) {
+        const int64_t i = base + threadIdx.x;
+        V wi = V(0), ri = V(0), ui = V(0);
+        if (i < n) {
+            const double zi = (double)nv[i] + beta * (double)z[i];
+            const double si = (double)w[i] + beta * (double)s[i];
+            z[i] = (V)zi;
+            s[i] = (V)si;
+            if constexpr (BS > 0) {
+                const double qi = (double)m[i] + beta * (double)q[i];
+                const double pi = (double)u[i] + beta * (double)p[i];
+                q[i] = (V)qi;
+                p[i] = (V)pi;
+                x[i] = (V)((double)x[i] + alpha * (double)(V)pi);
+                ri = (V)((double)r[i] - alpha * (double)(V)si);
+                ui = (V)((double)u[i] - alpha * (double)(V)qi);
+                u[i] = ui;
+            } else {
+                const double pi = (double)r[i] + beta * (double)p[i];
+                p[i] = (V)pi;
+                x[i] = (V)((double)x[i] + alpha * (double)(V)pi);
+                ri = (V)((double)r[i] - alpha * (double)(V)si);
+                ui = ri;
+            }
+            r[i] = ri;
+            wi = (V)((double)w[i] - alpha * (double)(V)zi);
+            w[i] = wi;
+        }
+        if constexpr (BS > 0) {
+            const V mi = bj_tile_apply<V, BS>(n, base, wi, inv, r_lds, inv_lds);
+            if (i < n) m[i] = mi;
+        }
+        if (i < n) {
+            a_g += (double)ri * (double)ui;
+            a_d += (double)wi * (double)ui;
+            a_rr += (double)ri * (double)ri;
+        }
+    }
+    double v[3] = {a_g, a_d, a_rr};
+    grid_sum_apply<kB, 3>(v, ra, pipe_update_op{sc});
+}
+
+template <typename V>
+static hipError_t launch_pipe_init(hipStream_t s, int64_t n, const void *b, const void *r, void *u,
+                                   const void *w, void *m, const void *inv, int bs, double tol,
+                                   krylov_scalars *sc, double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    const V *B = static_cast<const V *>(b), *R = static_cast<const V *>(r);
+    const V *U = static_cast<const V *>(u), *W = static_cast<const V *>(w);
+    V *M = static_cast<V *>(m);
+    const V *I = static_cast<const V *>(inv);
+    switch (bs) {
+        case 0: pipe_init_kernel<V, 0><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        case 1: pipe_init_kernel<V, 1><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        case 2: pipe_init_kernel<V, 2><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        case 4: pipe_init_kernel<V, 4><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        case 8: pipe_init_kernel<V, 8><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        case 16: pipe_init_kernel<V, 16><<<g, kB, 0, s>>>(n, B, R, U, W, M, I, tol, sc, ra); break;
+        default: return hipErrorInvalidValue;
+    }
+    return red_finish<4>(s, g, ra, pipe_init_op{sc, tol});
+}
+
+template <typename V>
+static hipError_t launch_pipe_precond(hipStream_t s, int64_t n, const void *r, void *u,
+                                      const void *inv, int bs) {
+    const int g = reduction_blocks(n);
+    const V *R = static_cast<const V *>(r), *I = static_cast<const V *>(inv);
+    V *U = static_cast<V *>(u);
+    switch (bs) {
+        case 1: pipe_precond_kernel<V, 1><<<g, kB, 0, s>>>(n, R, U, I); break;
+        case 2: pipe_precond_kernel<V, 2><<<g, kB, 0, s>>>(n, R, U, I); break;
+        case 4: pipe_precond_kernel<V, 4><<<g, kB, 0, s>>>(n, R, U, I); break;
+        case 8: pipe_precond_kernel<V, 8><<<g, kB, 0, s>>>(n, R, U, I); break;
+        case 16: pipe_precond_kernel<V, 16><<<g, kB, 0, s>>>(n, R, U, I); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename V>
+static hipError_t launch_pipe_update(hipStream_t st, int64_t n, const pipe_vectors &v,
+                                     const void *inv, int bs, krylov_scalars *sc,
+                                     double *partials, unsigned *ticket) {
+    const int g = reduction_blocks(n);
+    const red_args ra = red_for(g, partials, ticket);
+    const V *N = static_cast<const V *>(v.n), *I = static_cast<const V *>(inv);
+    V *Z = static_cast<V *>(v.z), *Q = static_cast<V *>(v.q), *S = static_cast<V *>(v.s);
+    V *P = static_cast<V *>(v.p), *X = static_cast<V *>(v.x), *R = static_cast<V *>(v.r);
+    V *U = static_cast<V *>(v.u), *W = static_cast<V *>(v.w), *M = static_cast<V *>(v.m);
+    switch (bs) {
+        case 0: pipe_update_kernel<V, 0><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        case 1: pipe_update_kernel<V, 1><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        case 2: pipe_update_kernel<V, 2><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        case 4: pipe_update_kernel<V, 4><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        case 8: pipe_update_kernel<V, 8><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        case 16: pipe_update_kernel<V, 16><<<g, kB, 0, st>>>(n, N, Z, Q, S, P, X, R, U, W, M, I, sc, ra); break;
+        default: return hipErrorInvalidValue;
+    }
+    return red_finish<3>(st, g, ra, pipe_update_op{sc});
+}
+
+hipError_t pipe_precond(hipStream_t s, vt t, int64_t n, const void *r, void *u, const void *inv,
+                        int bs) {
+    return t == vt::f64 ? launch_pipe_precond<double>(s, n, r, u, inv, bs)
+                        : launch_pipe_precond<float>(s, n, r, u, inv, bs);
+}
+
+hipError_t pipe_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *u,
+                     const void *w, void *m, const void *inv, int bs, double tol,
+                     krylov_scalars *sc, double *partials, unsigned *ticket) {
+    return t == vt::f64
+               ? launch_pipe_init<double>(s, n, b, r, u, w, m, inv, bs, tol, sc, partials, ticket)
+               : launch_pipe_init<float>(s, n, b, r, u, w, m, inv, bs, tol, sc, partials, ticket);
+}
+
+hipError_t pipe_update(hipStream_t s, vt t, int64_t n, const pipe_vectors &v, const void *inv,
+                       int bs, krylov_scalars *sc, double *partials, unsigned *ticket) {
+    return t == vt::f64 ? launch_pipe_update<double>(s, n, v, inv, bs, sc, partials, ticket)
+                        : launch_pipe_update<float>(s, n, v, inv, bs, sc, partials, ticket);
+}
+
 // ------------------------------------------------------------------ BiCGSTAB (FP64)
 // Start from r = b - A x: rhat = r, p = v = 0, rho = rhat.r, bb = b.b,
 // rho_old = alpha = omega = 1, so the first direction is p = r.

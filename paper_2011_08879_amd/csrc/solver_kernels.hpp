@@ -53,6 +53,23 @@ hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, 
 hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
                         const krylov_scalars *sc);
 
+// Pipelined (P)CG (Ghysels and Vanroose).  Start from r = b - A x:
+// pipe_precond (u = M^-1 r, preconditioned only), w = A u by the format's
+// SpMV, pipe_init (m = M^-1 w and the first alpha); then per iteration
+// n = A m by the format's SpMV and pipe_update.  bs = 0: u aliases r, m
+// aliases w and q aliases s (pass the same pointers).
+struct pipe_vectors {
+    const void *n;
+    void *z, *q, *s, *p, *x, *r, *u, *w, *m;
+};
+hipError_t pipe_precond(hipStream_t s, vt t, int64_t n, const void *r, void *u, const void *inv,
+                        int bs);
+hipError_t pipe_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *u,
+                     const void *w, void *m, const void *inv, int bs, double tol,
+                     krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t pipe_update(hipStream_t s, vt t, int64_t n, const pipe_vectors &v, const void *inv,
+                       int bs, krylov_scalars *sc, double *partials, unsigned *ticket);
+
 // BiCGSTAB (FP64).
 hipError_t bicg_init(hipStream_t st, int64_t n, const void *b, const void *r, void *rh, void *p,
                      void *v, double tol, krylov_scalars *sc, double *partials, unsigned *ticket);

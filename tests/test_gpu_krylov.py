@@ -212,3 +212,78 @@ def test_gmres_statuses(g, gen_mod, ctx):
     for bad in (0, 129):
         with pytest.raises(g.GkoError):
             ctx.set_solver_opts(krylov_dim=bad)
+
+
+# --------------------------------------------------------------------------- pipelined CG
+@pytest.mark.parametrize("fmt", ["csr", "ell", "sellp", "coo"])
+def test_pipecg_laplace2d_matches_oracle(g, orc, gen_mod, ctx, fmt):
+    N = 64
+    A = gen_mod.laplace2d(N)
+    xs = gen_mod.uniform(2, N * N)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.pipecg(A, b, tol=1e-10)
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    x = dev(np.zeros(N * N))
+    info = g.pipecg(M, dev(b), x, tol=1e-10, maxit=5000)
+    assert info["status"] == g.OK, info
+    assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    xg = host(x)
+    assert relres(orc, A, b, xg) <= 1e-10
+    kappa = (4 + 4 * math.cos(math.pi / (N + 1))) / (4 - 4 * math.cos(math.pi / (N + 1)))
+    assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * 1e-10
+
+
+def test_pipecg_iterates_are_cg_iterates(g, orc, ctx):
+    """k steps of the GPU's pipelined CG against the oracle's CG (not its
+    pipelined CG): equal in exact arithmetic, with and without block-Jacobi."""
+    rng = np.random.default_rng(41)
+    n = 40
+    G = rng.standard_normal((n, n))
+    D = G @ G.T / n + np.eye(n)
+    D = (D + D.T) / 2
+    A = (np.arange(0, n * n + 1, n, dtype=np.int32), np.tile(np.arange(n, dtype=np.int32), n),
+         D.ravel())
+    b = rng.uniform(-1, 1, n)
+    rc, inv = orc.bj_invert(A, 8)
+    M = g.Matrix.from_csr(*A)
+    for bs in (0, 8):
+        if bs:
+            ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+        for k in (1, 2, 3, 5, 10):
+            x = dev(np.zeros(n))
+            info = g.pipecg(M, dev(b), x, tol=1e-300, maxit=k)
+            assert info["iterations"] == k
+            r1, xc, _ = orc.cg(A, b, tol=1e-300, maxit=k, **({"bj_inv": inv, "bs": 8} if bs else {}))
+            assert np.linalg.norm(host(x) - xc) <= 1e-11 * np.linalg.norm(xc), (bs, k)
+
+
+def test_pipecg_block_jacobi_mixed_and_statuses(g, orc, gen_mod, ctx):
+    N = 24
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    b = orc.spmv(A, gen_mod.uniform(5, n))
+    rc, inv = orc.bj_invert(A, 8)
+    rc, xo, info_o = orc.pipecg(A, b, tol=1e-10, bj_inv=inv)
+    M = g.Matrix.from_csr(*A)
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    x = dev(np.zeros(n))
+    info = g.pipecg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK and abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    assert relres(orc, A, b, host(x)) <= 1e-10
+    ctx.set_solver_opts(precision=g.PREC_MIXED_IR, precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    x = dev(np.zeros(n))
+    info = g.pipecg(M, dev(b), x, tol=1e-10)
+    assert info["status"] == g.OK and info["outer_iterations"] >= 2
+    assert relres(orc, A, b, host(x)) <= 1e-10
+    ctx.set_solver_opts()
+    L = g.Matrix.from_csr(*gen_mod.laplace2d(32))
+    info = g.pipecg(L, dev(np.zeros(1024)), dev(np.ones(1024)))
+    assert info["status"] == g.OK and info["iterations"] == 0
+    info = g.pipecg(L, dev(np.ones(1024)), dev(np.zeros(1024)), tol=1e-10, maxit=5)
+    assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 5
+    D = g.Matrix.from_csr(np.arange(5, dtype=np.int32), np.arange(4, dtype=np.int32),
+                          np.array([1.0, 2.0, -1.0, 3.0]))
+    rc, xd, info_d = orc.pipecg((np.arange(5, dtype=np.int32), np.arange(4, dtype=np.int32),
+                                 np.array([1.0, 2.0, -1.0, 3.0])), np.ones(4))
+    info = g.pipecg(D, dev(np.ones(4)), dev(np.zeros(4)))
+    assert info["status"] == g.ERR_NOT_SPD and info["iterations"] == info_d["iters"]
