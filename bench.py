@@ -258,7 +258,9 @@ def run_solvers(g, gen, torch):
 def krylov_bytes(name, S, n, iters, m=30):
     """Algorithmic bytes of `iters` FP64 iterations (S: one SpMV's bytes, n rows).
     Per iteration: CG and FCG S + 9 vector passes (fused product with p.q;
-    x, r update with the sums; p update); BiCGSTAB 2S + 18; CGS 2S + 17;
+    x, r update with the sums; p update); pipelined CG S + 13 (one update
+    kernel reading n, z, s, p, x, r, w and writing all but n); BiCGSTAB
+    2S + 18; CGS 2S + 17;
     GMRES Arnoldi step j: S + (2j + 7) passes with one Gram-Schmidt round
     (dot over j+1 basis vectors and w, update reading them and writing w,
     normalisation), plus per cycle the residual (S + 5 passes) and
@@ -266,6 +268,8 @@ def krylov_bytes(name, S, n, iters, m=30):
     vp = 8.0 * n
     if name in ("cg", "fcg"):
         return iters * (S + 9 * vp)
+    if name == "pipecg":
+        return iters * (S + 13 * vp)
     if name == "bicgstab":
         return iters * (2 * S + 18 * vp)
     if name == "cgs":
@@ -286,8 +290,8 @@ def run_krylov(g, torch, ctx, M, b, n):
     d = M.describe()
     S = spmv_bytes(d)
     out = {"format": d.format, "n": n, "spmv_alg_bytes": int(S)}
-    runs = (("cg", g.cg, 300), ("fcg", g.fcg, 300), ("bicgstab", g.bicgstab, 150),
-            ("cgs", g.cgs, 150), ("gmres", g.gmres, 300))
+    runs = (("cg", g.cg, 300), ("fcg", g.fcg, 300), ("pipecg", g.pipecg, 300),
+            ("bicgstab", g.bicgstab, 150), ("cgs", g.cgs, 150), ("gmres", g.gmres, 300))
     for name, fn, iters in runs:
         ctx.set_solver_opts(single_workgroup=0, krylov_dim=30)
         best = None
@@ -310,7 +314,40 @@ def run_krylov(g, torch, ctx, M, b, n):
         log("krylov %-8s %4d it  %.3f ms/it  %.0f GB/s" % (name, it, out[name]["ms_per_iteration"],
                                                          out[name]["alg_GB/s"]))
     ctx.set_solver_opts()
+    out["cg_vs_pipecg_by_size"] = cg_vs_pipecg(g, torch, ctx)
     return out
+
+
+def cg_vs_pipecg(g, torch, ctx):
+    """CG (three kernels and two reductions per iteration) against pipelined
+    CG (two kernels, one reduction, more vector traffic) on 3D Poisson
+    matrices from latency-bound to bandwidth-bound sizes: us per iteration."""
+    import gen
+    res = {}
+    for N in (16, 32, 64, 128):
+        A = gen.laplace3d(N)
+        n = N ** 3
+        M = g.Matrix.from_csr(*A)
+        M.convert("sellp")
+        b = torch.from_numpy(gen.uniform(5, n)).cuda()
+        row = {}
+        for name, fn in (("cg", g.cg), ("pipecg", g.pipecg)):
+            ctx.set_solver_opts(single_workgroup=0)
+            best = None
+            for _ in range(3):
+                x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = fn(M, b, x, tol=1e-30, maxit=200)
+                el = time.perf_counter() - t0
+                best = el if best is None else min(best, el)
+            row[name + "_us_per_iteration"] = round(best / info["iterations"] * 1e6, 2)
+        res["poisson3d_%d" % N] = row
+        log("cg vs pipecg n=%d: %.1f / %.1f us per iteration" %
+            (n, row["cg_us_per_iteration"], row["pipecg_us_per_iteration"]))
+        M.close()
+    ctx.set_solver_opts()
+    return res
 
 
 def run_batch(g, gen, torch, nsys=10000, reps=3):
