@@ -3,14 +3,18 @@
 // Sec. 6.5.3).
 //
 // Arnoldi step j with w = A v_j written straight into basis slot j+1:
-//   dot     h = V_j^T w and w.w in one pass over the j+1 basis vectors
-//   update  w -= V_j h, and the new w.w, in one pass
-//   a second round of both (classical Gram-Schmidt twice) only when the
-//   first shrank w below 1/sqrt(2) of its length (Daniel, Gragg, Kaufman and
-//   Stewart's criterion); otherwise those launches return at once
-//   step    (one thread) the column of H, the earlier rotations, the new
-//   Givens rotation, |g_{j+1}| as the residual estimate, the cycle's end
-//   normalise v_{j+1} = w / h_{j+1,j}
+//   dot         h = V_j^T w and w.w in one pass over the j+1 basis vectors
+//   update+dot  w -= V_j h, then h' = V_j^T w and the new w.w, in one pass
+//               (each thread re-reads its rows of V_j right after the
+//               update, mostly from the caches)
+//   update      w -= V_j h' (classical Gram-Schmidt twice) only when the
+//               first round shrank w below 1/sqrt(2) of its length (Daniel,
+//               Gragg, Kaufman and Stewart's criterion); otherwise the
+//               launch returns at once
+//   step        (one thread) the column of H, the earlier rotations, the new
+//               Givens rotation, |g_{j+1}| as the residual estimate, the end
+//               of the cycle
+//   normalise   v_{j+1} = w / h_{j+1,j}
 // The basis is column-major with a leading dimension rounded up to 64
 // doubles.  The multi-vector passes keep each thread's rows of w in
 // registers and read the basis vectors coalesced, one after another; the
@@ -133,6 +137,70 @@ __global__ __launch_bounds__(kG) void gmres_update_kernel(int64_t n, int k,
     if (threadIdx.x == 0) partials[blockIdx.x] = ww;
 }
 
+// The first round's update fused with the second round's dots:
+// w -= sum_i h_i V_i, then partials of V_i . w (i < k) and w . w (at k) for
+// the new w.  The second read of each V_i[l] follows the first within the
+// same thread's chunk, so it mostly hits the caches instead of HBM.
+__global__ __launch_bounds__(kG) void gmres_update_dot_kernel(int64_t n, int k,
+                                                              const double *__restrict__ V,
+                                                              int64_t ldv,
+                                                              const double *__restrict__ h,
+                                                              double *__restrict__ w,
+                                                              const gmres_state *st,
+                                                              double *__restrict__ partials) {
+    __shared__ double part[kGmresMaxKrylov + 1][kGWaves];
+    __shared__ double hs[kGmresMaxKrylov];
+    if (!gate(st, 0)) return;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int e = threadIdx.x; e < (k + 1) * kGWaves; e += kG) part[e / kGWaves][e % kGWaves] = 0.0;
+    for (int i = threadIdx.x; i < k; i += kG) hs[i] = h[i];
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kG * kGRows; base < n;
+         base += (int64_t)gridDim.x * kG * kGRows) {
+        double acc[kGRows];
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r) {
+            const int64_t l = base + r * kG + threadIdx.x;
+            acc[r] = l < n ? w[l] : 0.0;
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (int64_t)i * ldv;
+            const double hi = hs[i];
+#pragma unroll
+            for (int r = 0; r < kGRows; ++r) {
+                const int64_t l = base + r * kG + threadIdx.x;
+                if (l < n) acc[r] = acc[r] - hi * vi[l];
+            }
+        }
+        double ww = 0.0;
+#pragma unroll
+        for (int r = 0; r < kGRows; ++r) {
+            const int64_t l = base + r * kG + threadIdx.x;
+            if (l < n) w[l] = acc[r];
+            ww += acc[r] * acc[r];
+        }
+        for (int i = 0; i < k; ++i) {
+            const double *vi = V + (int64_t)i * ldv;
+            double sd = 0.0;
+#pragma unroll
+            for (int r = 0; r < kGRows; ++r) {
+                const int64_t l = base + r * kG + threadIdx.x;
+                sd += (l < n ? vi[l] : 0.0) * acc[r];
+            }
+            sd = wave_total(sd);
+            if (lane == 0) part[i][wv] += sd;
+        }
+        ww = wave_total(ww);
+        if (lane == 0) part[k][wv] += ww;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v <= k; v += kG) {
+        double sum = 0.0;
+        for (int q = 0; q < kGWaves; ++q) sum += part[v][q];
+        partials[(int64_t)v * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
 // out[v] <- sum over blocks of partials[v * g + b], block order, one
 // workgroup per value
 __global__ __launch_bounds__(kG) void gmres_sum_kernel(int g, const double *__restrict__ partials,
@@ -147,16 +215,17 @@ __global__ __launch_bounds__(kG) void gmres_sum_kernel(int g, const double *__re
     if (threadIdx.x == 0) out[blockIdx.x] = s;
 }
 
-// After the first round: keep h, decide on a second round.
+// After the first round: keep h, decide on a second round.  dot1: V^T w
+// and w.w before the round; dot2: V^T w and w.w after it.
 __global__ void gmres_check_kernel(int j, const double *__restrict__ dot1,
-                                   const double *__restrict__ upd1, gmres_state *st,
+                                   const double *__restrict__ dot2, gmres_state *st,
                                    double *__restrict__ hcol) {
     if (st->cycle_done) return;
     for (int i = 0; i <= j; ++i) hcol[i] = dot1[i];
     // |w_after| < |w_before| / sqrt(2)
-    st->reorth = (2.0 * upd1[0] < dot1[j + 1]) ? 1 : 0;
+    st->reorth = (2.0 * dot2[j + 1] < dot1[j + 1]) ? 1 : 0;
     st->reorths += st->reorth;
-    st->ww = upd1[0];
+    st->ww = dot2[j + 1];
 }
 
 // Close step j: h_{j+1,j}, rotations, residual estimate, end of cycle.
@@ -279,15 +348,13 @@ hipError_t gmres_arnoldi_step(hipStream_t s, int64_t n, int m, int j, double *V,
     const int g = gmres_blocks(n);
     double *w = V + (int64_t)(j + 1) * ldv;
     const int k = j + 1;
-    // first Gram-Schmidt round
+    // first Gram-Schmidt round; its update also forms the second round's dots
     gmres_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, w, st, 0, wk.partials);
     gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot1, st, 0);
-    gmres_update_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, 0, wk.partials);
-    gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd1, st, 0);
-    gmres_check_kernel<<<1, 1, 0, s>>>(j, wk.dot1, wk.upd1, st, wk.hcol);
-    // second round, only when the first lost too much of w
-    gmres_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, w, st, 1, wk.partials);
-    gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot2, st, 1);
+    gmres_update_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, wk.partials);
+    gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot2, st, 0);
+    gmres_check_kernel<<<1, 1, 0, s>>>(j, wk.dot1, wk.dot2, st, wk.hcol);
+    // the second round's update, only when the first lost too much of w
     gmres_update_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot2, w, st, 1, wk.partials);
     gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd2, st, 1);
     gmres_step_kernel<<<1, 1, 0, s>>>(j, m, wk.dot2, wk.upd2, st, wk.hcol, wk.H, wk.cs, wk.sn,
