@@ -287,3 +287,53 @@ def test_pipecg_block_jacobi_mixed_and_statuses(g, orc, gen_mod, ctx):
                                  np.array([1.0, 2.0, -1.0, 3.0])), np.ones(4))
     info = g.pipecg(D, dev(np.ones(4)), dev(np.zeros(4)))
     assert info["status"] == g.ERR_NOT_SPD and info["iterations"] == info_d["iters"]
+
+
+# --------------------------------------------------------------------------- shared edge cases
+def test_nonzero_initial_guess_and_long_restart(g, orc, gen_mod, ctx):
+    A = gen_mod.convdiff2d(30, 0.5)
+    n = 900
+    b = orc.spmv(A, gen_mod.uniform(8, n))
+    x0 = gen_mod.uniform(12, n)
+    M = g.Matrix.from_csr(*A)
+    ctx.set_solver_opts(krylov_dim=25)
+    rc, xo, info_o = orc.gmres(A, b, x0=x0, tol=1e-10, maxit=5000, m=25)
+    x = dev(x0.copy())
+    info = g.gmres(M, dev(b), x, tol=1e-10, maxit=5000)
+    assert info["status"] == g.OK and abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 20)
+    assert relres(orc, A, b, host(x)) <= 1e-10
+    rc, xo, info_o = orc.cgs(A, b, x0=x0, tol=1e-10, maxit=2000)
+    x = dev(x0.copy())
+    info = g.cgs(M, dev(b), x, tol=1e-10, maxit=2000)
+    assert info["status"] == g.OK and abs(info["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 10)
+    # restart length above n: the Krylov space becomes invariant (h_{j+1,j} = 0)
+    rng = np.random.default_rng(5)
+    D = rng.uniform(-1, 1, (40, 40)) + 4 * np.eye(40)
+    Ad = (np.arange(0, 1601, 40, dtype=np.int32), np.tile(np.arange(40, dtype=np.int32), 40), D.ravel())
+    ctx.set_solver_opts(krylov_dim=128)
+    bd = rng.uniform(-1, 1, 40)
+    x = dev(np.zeros(40))
+    info = g.gmres(g.Matrix.from_csr(*Ad), dev(bd), x, tol=1e-12)
+    assert info["status"] == g.OK and info["iterations"] <= 40 and info["outer_iterations"] <= 2
+    assert np.linalg.norm(D @ host(x) - bd) <= 1e-11 * np.linalg.norm(bd)
+
+
+@pytest.mark.parametrize("solver", ["fcg", "pipecg", "cgs", "gmres"])
+def test_solver_argument_checks(g, gen_mod, ctx, solver):
+    import torch
+    fn = getattr(g, solver)
+    A = gen_mod.laplace2d(8)
+    F = g.Matrix.from_csr(*A, dtype=torch.float32)
+    with pytest.raises(g.GkoError) as e:
+        fn(F, dev(np.ones(64)), dev(np.zeros(64)), raise_on_failure=True)
+    assert e.value.status == g.ERR_UNSUPPORTED          # solvers take FP64 matrices
+    R = g.Matrix.from_csr(np.array([0, 1, 2], np.int32), np.array([0, 2], np.int32), np.ones(2),
+                          n_cols=3)
+    with pytest.raises(g.GkoError) as e:
+        fn(R, dev(np.ones(2)), dev(np.zeros(3)), raise_on_failure=True)
+    assert e.value.status == g.ERR_DIM_MISMATCH
+    M = g.Matrix.from_csr(*A)
+    for tol in (0.0, float("inf")):
+        with pytest.raises(g.GkoError) as e:
+            fn(M, dev(np.ones(64)), dev(np.zeros(64)), tol=tol, raise_on_failure=True)
+        assert e.value.status == g.ERR_INVALID_ARG
