@@ -435,11 +435,16 @@ def run_sweep(args, g, gen, torch, result):
     dom = max(range(len(mats)), key=lambda k: per_kernel[k]["ms"])
     d = per_kernel[dom]
     achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9
+    traffic = measured_traffic("%s/%s" % (d["matrix"], d["format"]))
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic("%s/%s" % (d["matrix"], d["format"])),
+                "traffic": traffic,
                 "kernel": "spmv %s on %s" % (d["format"], d["matrix"]),
                 "alg_bytes_per_launch": d["alg_bytes"]}
+    if traffic:
+        # bytes the L2 exchanged with the fabric (Infinity Cache hits included)
+        # per second: above the algorithmic rate when x gathers miss the L2
+        roofline["traffic_GB/s"] = round(traffic / (d["ms"] * 1e-3) / 1e9, 1)
 
     result.update({
         "metric": METRIC,

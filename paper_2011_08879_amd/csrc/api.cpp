@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <iterator>
 #include <chrono>
 #include <numeric>
 #include <cmath>
@@ -2152,7 +2153,8 @@ gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int
             gmres_work wk;
             double **slots[] = {&wk.partials, &wk.dot1, &wk.dot2, &wk.upd1, &wk.upd2, &wk.hcol,
                                 &wk.H,        &wk.cs,   &wk.sn,   &wk.g,    &wk.y};
-            for (int i = 0; i < 11; ++i) {
+            static_assert(std::size(sizes) == std::size(slots), "one size per work array");
+            for (size_t i = 0; i < std::size(slots); ++i) {
                 *slots[i] = q;
                 q += sizes[i];
             }
