@@ -91,6 +91,51 @@ def test_poisson256_pcg_full_size(g, orc, poisson, mixed):
         ctx.set_solver_opts()
 
 
+@pytest.mark.parametrize("solver", ["fcg", "pipecg"])
+def test_poisson256_cg_variants_full_size(g, orc, poisson, solver):
+    """Flexible and pipelined block-Jacobi CG at the bench's size, in the
+    format AUTO picks: true residual from the oracle's SpMV, error bound."""
+    A, xs, b = poisson
+    N = 256
+    ctx = g.default_context()
+    ctx.set_solver_opts(precond=g.PRECOND_BLOCK_JACOBI, block_size=8)
+    try:
+        M = g.Matrix.from_csr(*A)
+        M.convert("auto")
+        x = dev(np.zeros(N ** 3))
+        info = getattr(g, solver)(M, dev(b), x, tol=1e-10, maxit=20000)
+        assert info["status"] == g.OK, info
+        assert 600 <= info["iterations"] <= 700, info      # block-Jacobi CG: 649
+        xg = host(x)
+        true = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+        assert true <= 1e-10
+        kappa = (6 + 6 * math.cos(math.pi / (N + 1))) / (6 - 6 * math.cos(math.pi / (N + 1)))
+        assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * true
+    finally:
+        ctx.set_solver_opts()
+
+
+def test_poisson256_gmres_estimate_full_size(g, orc, poisson):
+    """Two GMRES(30) cycles at the bench's size: the Givens residual estimate
+    of the returned iterate equals its true residual (the oracle's SpMV), and
+    the cycles reduce it."""
+    A, xs, b = poisson
+    ctx = g.default_context()
+    ctx.set_solver_opts(krylov_dim=30)
+    try:
+        M = g.Matrix.from_csr(*A)
+        M.convert("auto")
+        x = dev(np.zeros(256 ** 3))
+        info = g.gmres(M, dev(b), x, tol=1e-30, maxit=60)
+        assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 60
+        true = np.linalg.norm(b - orc.spmv(A, host(x))) / np.linalg.norm(b)
+        assert abs(info["rel_residual"] - true) <= 1e-8 * true
+        assert abs(info["true_rel_residual"] - true) <= 1e-12
+        assert true < 0.2
+    finally:
+        ctx.set_solver_opts()
+
+
 @pytest.mark.parametrize("f32", [False, True], ids=["fp64", "fp32"])
 def test_batch_10k_full_size(g, orc, gen_mod, f32):
     import torch
