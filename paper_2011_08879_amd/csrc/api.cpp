@@ -1993,7 +1993,15 @@ gko_status gko_pipecg_solve(gko_matrix A, const void *b, void *x, double tol, in
     return cg_family_solve(A, b, x, tol, maxit, cg_variant::pipelined);
 }
 
-gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+// The frame shared by the unpreconditioned FP64 solvers without a
+// single-workgroup path (BiCGSTAB, CGS, GMRES): argument checks, ||b||
+// (NaN/Inf: breakdown; 0: x = 0 at zero iterations), the true relative
+// residual at exit, timing and the error message.  body(bnorm, partials,
+// ticket) runs the iteration, fills the solve info and returns a solver_flag.
+extern "C++" {
+template <typename Body>
+static gko_status nonsym_solve(const char *name, gko_matrix A, const void *b, void *x, double tol,
+                               int32_t maxit, Body body) {
     gko_status st = GKO_OK;
     gko_status call = guarded([&] {
         check_square_f64(A);
@@ -2003,44 +2011,21 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         const double t0 = now_seconds();
         c->info = gko_solve_info{};
         const int64_t n = A->n;
-        const int check_every = c->opts.check_every;
-        const values v = own_values(A);
-        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8), sc(c, sizeof(krylov_scalars));
+        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
         HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
-        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
-                                         ticket.as<unsigned>());
+        double *P = partials.as<double>();
+        unsigned *T = ticket.as<unsigned>();
+        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), P, T);
         if (!std::isfinite(bnorm)) {
             st = GKO_ERR_BREAKDOWN;
         } else if (bnorm == 0.0) {
             HIPC(fill_zero(s, vt::f64, n, x));
             st = GKO_OK;
         } else {
-            dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), vv(c, n * 8), sv(c, n * 8), t(c, n * 8);
-            auto *S = sc.as<krylov_scalars>();
-            double *P = partials.as<double>();
-            unsigned *T = ticket.as<unsigned>();
-            HIPC(scalars_reset(s, S, maxit));
+            st = flag_status(body(bnorm, P, T));
+            dbuf r(c, n * 8);
             HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
-            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
-            HIPC(bicg_init(s, n, b, r.p, rh.p, p.p, vv.p, tol, S, P, T));
-            krylov_scalars h = read_back(c, S);
-            while (h.done == kRunning) {
-                for (int j = 0; j < check_every; ++j) {
-                    HIPC(bicg_p(s, n, r.p, vv.p, p.p, S));
-                    spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
-                    HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
-                    HIPC(bicg_s(s, n, r.p, vv.p, sv.p, S, P, T));
-                    spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
-                    HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
-                    HIPC(bicg_update(s, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
-                }
-                h = read_back(c, S);
-            }
-            st = flag_status(h.done);
-            c->info.iterations = h.iter;
-            c->info.rel_residual = std::sqrt(h.rr / h.bb);
-            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
-            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+            spmv_dispatch(A, own_values(A), -1.0, x, 1.0, r.p);
             c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(), P, T) / bnorm;
         }
         c->sync();
@@ -2051,166 +2036,138 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         if (A) A->ctx->info.status = call;
         return call;
     }
-    if (st != GKO_OK) g_last_error = std::string("bicgstab: ") + gko_status_string(st);
+    if (st != GKO_OK) g_last_error = std::string(name) + ": " + gko_status_string(st);
     return st;
+}
+}  // extern "C++"
+
+gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    return nonsym_solve("bicgstab", A, b, x, tol, maxit, [&](double, double *P, unsigned *T) {
+        gko_context c = A->ctx;
+        hipStream_t s = c->stream;
+        const int64_t n = A->n;
+        const values v = own_values(A);
+        dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), vv(c, n * 8), sv(c, n * 8), t(c, n * 8);
+        dbuf sc(c, sizeof(krylov_scalars));
+        auto *S = sc.as<krylov_scalars>();
+        HIPC(scalars_reset(s, S, maxit));
+        HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+        HIPC(bicg_init(s, n, b, r.p, rh.p, p.p, vv.p, tol, S, P, T));
+        krylov_scalars h = read_back(c, S);
+        while (h.done == kRunning) {
+            for (int j = 0; j < c->opts.check_every; ++j) {
+                HIPC(bicg_p(s, n, r.p, vv.p, p.p, S));
+                spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
+                HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
+                HIPC(bicg_s(s, n, r.p, vv.p, sv.p, S, P, T));
+                spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
+                HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
+                HIPC(bicg_update(s, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
+            }
+            h = read_back(c, S);
+        }
+        c->info.iterations = h.iter;
+        c->info.rel_residual = std::sqrt(h.rr / h.bb);
+        return h.done;
+    });
 }
 
 gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
-    gko_status st = GKO_OK;
-    gko_status call = guarded([&] {
-        check_square_f64(A);
-        check_solve_args(b, x, tol, maxit);
+    return nonsym_solve("cgs", A, b, x, tol, maxit, [&](double, double *P, unsigned *T) {
         gko_context c = A->ctx;
         hipStream_t s = c->stream;
-        const double t0 = now_seconds();
-        c->info = gko_solve_info{};
         const int64_t n = A->n;
-        const int check_every = c->opts.check_every;
         const values v = own_values(A);
-        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8), sc(c, sizeof(krylov_scalars));
-        HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
-        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
-                                         ticket.as<unsigned>());
-        if (!std::isfinite(bnorm)) {
-            st = GKO_ERR_BREAKDOWN;
-        } else if (bnorm == 0.0) {
-            HIPC(fill_zero(s, vt::f64, n, x));
-            st = GKO_OK;
-        } else {
-            dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), u(c, n * 8), q(c, n * 8), w(c, n * 8),
-                t(c, n * 8);
-            auto *S = sc.as<krylov_scalars>();
-            double *P = partials.as<double>();
-            unsigned *T = ticket.as<unsigned>();
-            HIPC(scalars_reset(s, S, maxit));
-            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
-            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
-            HIPC(cgs_init(s, n, b, r.p, rh.p, p.p, u.p, tol, S, P, T));
-            krylov_scalars h = read_back(c, S);
-            while (h.done == kRunning) {
-                for (int j = 0; j < check_every; ++j) {
-                    spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
-                    HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
-                    HIPC(cgs_qwx(s, n, u.p, t.p, q.p, w.p, x, S));
-                    spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
-                    HIPC(cgs_update(s, n, r.p, t.p, rh.p, S, P, T));
-                    HIPC(cgs_direction(s, n, r.p, q.p, u.p, p.p, S));
-                }
-                h = read_back(c, S);
+        dbuf r(c, n * 8), rh(c, n * 8), p(c, n * 8), u(c, n * 8), q(c, n * 8), w(c, n * 8),
+            t(c, n * 8);
+        dbuf sc(c, sizeof(krylov_scalars));
+        auto *S = sc.as<krylov_scalars>();
+        HIPC(scalars_reset(s, S, maxit));
+        HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
+        HIPC(cgs_init(s, n, b, r.p, rh.p, p.p, u.p, tol, S, P, T));
+        krylov_scalars h = read_back(c, S);
+        while (h.done == kRunning) {
+            for (int j = 0; j < c->opts.check_every; ++j) {
+                spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
+                HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
+                HIPC(cgs_qwx(s, n, u.p, t.p, q.p, w.p, x, S));
+                spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
+                HIPC(cgs_update(s, n, r.p, t.p, rh.p, S, P, T));
+                HIPC(cgs_direction(s, n, r.p, q.p, u.p, p.p, S));
             }
-            st = flag_status(h.done);
-            c->info.iterations = h.iter;
-            c->info.rel_residual = std::sqrt(h.rr / h.bb);
-            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
-            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
-            c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(), P, T) / bnorm;
+            h = read_back(c, S);
         }
-        c->sync();
-        c->info.status = st;
-        c->info.seconds = now_seconds() - t0;
+        c->info.iterations = h.iter;
+        c->info.rel_residual = std::sqrt(h.rr / h.bb);
+        return h.done;
     });
-    if (call != GKO_OK) {
-        if (A) A->ctx->info.status = call;
-        return call;
-    }
-    if (st != GKO_OK) g_last_error = std::string("cgs: ") + gko_status_string(st);
-    return st;
 }
 
 gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
-    gko_status st = GKO_OK;
-    gko_status call = guarded([&] {
-        check_square_f64(A);
-        check_solve_args(b, x, tol, maxit);
+    return nonsym_solve("gmres", A, b, x, tol, maxit, [&](double bnorm, double *, unsigned *) {
         gko_context c = A->ctx;
         hipStream_t s = c->stream;
-        const double t0 = now_seconds();
-        c->info = gko_solve_info{};
         const int64_t n = A->n;
         const int m = c->opts.krylov_dim;
         const int check_every = c->opts.check_every;
         const values v = own_values(A);
-        dbuf partials(c, kPartialBytes), ticket(c, 8), nrm(c, 8);
-        HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
-        const double bnorm = device_norm(c, vt::f64, n, b, nrm.as<double>(), partials.as<double>(),
-                                         ticket.as<unsigned>());
-        if (!std::isfinite(bnorm)) {
-            st = GKO_ERR_BREAKDOWN;
-        } else if (bnorm == 0.0) {
-            HIPC(fill_zero(s, vt::f64, n, x));
-            st = GKO_OK;
-        } else {
-            const int64_t ldv = gmres_ld(n);
-            dbuf V(c, (size_t)(m + 1) * ldv * 8);
-            // work arrays carved from one buffer
-            const int64_t np = gmres_partial_elems(n, m);
-            const int64_t sizes[] = {np, m + 2, m + 2, 1, 1, m + 1, (int64_t)(m + 1) * m, m, m,
-                                     m + 1, m};
-            int64_t total = 0;
-            for (int64_t z : sizes) total += z;
-            dbuf work(c, total * 8), state(c, sizeof(gmres_state));
-            double *q = work.as<double>();
-            gmres_work wk;
-            double **slots[] = {&wk.partials, &wk.dot1, &wk.dot2, &wk.upd1, &wk.upd2, &wk.hcol,
-                                &wk.H,        &wk.cs,   &wk.sn,   &wk.g,    &wk.y};
-            static_assert(std::size(sizes) == std::size(slots), "one size per work array");
-            for (size_t i = 0; i < std::size(slots); ++i) {
-                *slots[i] = q;
-                q += sizes[i];
-            }
-            HIPC(fill_zero(s, vt::f64, total, work.p));
-            gmres_state h{};
-            h.stop = tol * bnorm;
-            h.maxit = maxit;
-            h.done = kRunning;
-            h.cycle_done = 1;
-            auto *S = state.as<gmres_state>();
-            HIPC(hipMemcpyAsync(S, &h, sizeof(h), hipMemcpyHostToDevice, s));
-            c->sync();   // h is reused as the read-back buffer below
-            double *V0 = V.as<double>();
-            for (;;) {
-                HIPC(hipMemcpyAsync(V0, b, n * 8, hipMemcpyDeviceToDevice, s));
-                spmv_dispatch(A, v, -1.0, x, 1.0, V0);
-                HIPC(gmres_cycle_start(s, n, V0, S, wk));
-                HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
-                c->sync();
-                if (h.done != kRunning) break;
-                for (int j = 0; j < m; ++j) {
-                    spmv_dispatch(A, v, 1.0, V0 + (int64_t)j * ldv, 0.0, V0 + (int64_t)(j + 1) * ldv);
-                    HIPC(gmres_arnoldi_step(s, n, m, j, V0, ldv, S, wk));
-                    if ((j + 1) % check_every == 0 && j + 1 < m) {
-                        HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
-                        c->sync();
-                        if (h.cycle_done) break;
-                    }
-                }
-                HIPC(gmres_cycle_end(s, n, m, V0, ldv, static_cast<double *>(x), S, wk));
-                HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
-                c->sync();
-                if (h.done != kRunning) break;   // breakdown inside the cycle
-            }
-            st = flag_status(h.done);
-            c->info.iterations = h.iter;
-            c->info.outer_iterations = h.cycles;
-            c->info.reorthogonalized = h.reorths;
-            c->info.rel_residual = h.est / bnorm;
-            dbuf r(c, n * 8);
-            HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
-            spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
-            c->info.true_rel_residual = device_norm(c, vt::f64, n, r.p, nrm.as<double>(),
-                                                    partials.as<double>(), ticket.as<unsigned>()) /
-                                        bnorm;
+        const int64_t ldv = gmres_ld(n);
+        dbuf V(c, (size_t)(m + 1) * ldv * 8);
+        // work arrays carved from one buffer
+        const int64_t np = gmres_partial_elems(n, m);
+        const int64_t sizes[] = {np, m + 2, m + 2, 1, 1, m + 1, (int64_t)(m + 1) * m, m, m,
+                                 m + 1, m};
+        int64_t total = 0;
+        for (int64_t z : sizes) total += z;
+        dbuf work(c, total * 8), state(c, sizeof(gmres_state));
+        double *q = work.as<double>();
+        gmres_work wk;
+        double **slots[] = {&wk.partials, &wk.dot1, &wk.dot2, &wk.upd1, &wk.upd2, &wk.hcol,
+                            &wk.H,        &wk.cs,   &wk.sn,   &wk.g,    &wk.y};
+        static_assert(std::size(sizes) == std::size(slots), "one size per work array");
+        for (size_t i = 0; i < std::size(slots); ++i) {
+            *slots[i] = q;
+            q += sizes[i];
         }
-        c->sync();
-        c->info.status = st;
-        c->info.seconds = now_seconds() - t0;
+        HIPC(fill_zero(s, vt::f64, total, work.p));
+        gmres_state h{};
+        h.stop = tol * bnorm;
+        h.maxit = maxit;
+        h.done = kRunning;
+        h.cycle_done = 1;
+        auto *S = state.as<gmres_state>();
+        HIPC(hipMemcpyAsync(S, &h, sizeof(h), hipMemcpyHostToDevice, s));
+        c->sync();   // h is reused as the read-back buffer below
+        double *V0 = V.as<double>();
+        for (;;) {
+            HIPC(hipMemcpyAsync(V0, b, n * 8, hipMemcpyDeviceToDevice, s));
+            spmv_dispatch(A, v, -1.0, x, 1.0, V0);
+            HIPC(gmres_cycle_start(s, n, V0, S, wk));
+            HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+            c->sync();
+            if (h.done != kRunning) break;
+            for (int j = 0; j < m; ++j) {
+                spmv_dispatch(A, v, 1.0, V0 + (int64_t)j * ldv, 0.0, V0 + (int64_t)(j + 1) * ldv);
+                HIPC(gmres_arnoldi_step(s, n, m, j, V0, ldv, S, wk));
+                if ((j + 1) % check_every == 0 && j + 1 < m) {
+                    HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+                    c->sync();
+                    if (h.cycle_done) break;
+                }
+            }
+            HIPC(gmres_cycle_end(s, n, m, V0, ldv, static_cast<double *>(x), S, wk));
+            HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+            c->sync();
+            if (h.done != kRunning) break;   // breakdown inside the cycle
+        }
+        c->info.iterations = h.iter;
+        c->info.outer_iterations = h.cycles;
+        c->info.reorthogonalized = h.reorths;
+        c->info.rel_residual = h.est / bnorm;
+        return h.done;
     });
-    if (call != GKO_OK) {
-        if (A) A->ctx->info.status = call;
-        return call;
-    }
-    if (st != GKO_OK) g_last_error = std::string("gmres: ") + gko_status_string(st);
-    return st;
 }
 
 }  // extern "C"
