@@ -135,6 +135,8 @@ typedef struct gko_matrix_desc {
     int64_t sellp_slices;  /* SELLP: ceil(n_rows / sellp_slice), else 0 */
     int64_t sellp_slots;   /* SELLP: sets[sellp_slices], slots incl. padding, else 0 */
     int32_t sellp_slice;   /* SELLP: rows per slice (64), else 0 */
+    int32_t pad;
+    int64_t sellp_wide_slices; /* SELLP: slices wider than 512 slots, summed by column chunks */
 } gko_matrix_desc;
 gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out);
 

@@ -50,7 +50,7 @@ class _MatrixDesc(ctypes.Structure):
                 ("nnz", _i64), ("ell_width", _i64), ("ell_ld", _i64), ("coo_nnz", _i64),
                 ("stored_bytes", _i64), ("csr_kernel", _i32), ("max_row_len", _i32),
                 ("csr_long_rows", _i64), ("sellp_slices", _i64), ("sellp_slots", _i64),
-                ("sellp_slice", _i32)]
+                ("sellp_slice", _i32), ("pad", _i32), ("sellp_wide_slices", _i64)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -264,6 +264,7 @@ class Desc:
     sellp_slices: int    # SELLP: number of slices, else 0
     sellp_slots: int     # SELLP: slots including padding, else 0
     sellp_slice: int     # SELLP: rows per slice, else 0
+    sellp_wide_slices: int  # SELLP: slices summed by column chunks, else 0
 
 
 class Matrix:
@@ -306,7 +307,7 @@ class Matrix:
         return Desc(FORMAT_NAMES[d.format], "f64" if d.dtype == F64 else "f32", d.n_rows,
                     d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes,
                     d.csr_kernel, d.max_row_len, d.csr_long_rows, d.sellp_slices, d.sellp_slots,
-                    d.sellp_slice)
+                    d.sellp_slice, d.sellp_wide_slices)
 
     @property
     def shape(self):

@@ -168,6 +168,10 @@ struct gko_matrix_s {
     int64_t slots = 0;        // SELLP: slots of all slices (sets[slices])
     int64_t *sset = nullptr;  // SELLP: slices + 1 slot offsets
     int32_t *swidth = nullptr;  // SELLP: width of each slice
+    // SELLP slices wider than kSellpWide, split into column chunks
+    int64_t n_wide = 0, n_wide_items = 0;
+    int32_t *wide_slices = nullptr, *wide_first = nullptr, *wide_items = nullptr;
+    void *wide_partial = nullptr;  // n_wide_items * kSellpSlice doubles
     int64_t tnnz = 0;         // HYBRID tail
     int32_t *trow = nullptr, *tcol = nullptr;
     void *tval = nullptr;
@@ -189,6 +193,16 @@ struct gko_matrix_s {
     int64_t slices() const { return (n + kSellpSlice - 1) / kSellpSlice; }
     // elements of ecol / eval
     int64_t ell_elems() const { return fmt == GKO_FMT_SELLP ? slots : K * ld; }
+    sellp_wide wide() const {
+        sellp_wide w;
+        w.n_wide = n_wide;
+        w.n_items = n_wide_items;
+        w.slices = wide_slices;
+        w.first = wide_first;
+        w.items = wide_items;
+        w.partial = wide_partial;
+        return w;
+    }
 
     void drop(void *&p) {
         ctx->free_bytes(p);
@@ -210,8 +224,9 @@ struct gko_matrix_s {
     void drop_storage() {
         drop(rp); drop(row); drop(col); drop(val); drop(part); drop(ecol); drop(eval);
         drop(trow); drop(tcol); drop(tval); drop(carry_a); drop(carry_b); drop(long_rows);
-        drop(sset); drop(swidth);
-        tiles = K = ld = tnnz = carry_elems = n_long = slots = 0;
+        drop(sset); drop(swidth); drop(wide_slices); drop(wide_first); drop(wide_items);
+        drop(wide_partial);
+        tiles = K = ld = tnnz = carry_elems = n_long = slots = n_wide = n_wide_items = 0;
         drop_caches();
     }
     int64_t stored_bytes() const {
@@ -222,7 +237,9 @@ struct gko_matrix_s {
             case GKO_FMT_COO: return nnz * (8 + s);
             case GKO_FMT_ELL: return K * ld * (4 + s);
             case GKO_FMT_HYBRID: return K * ld * (4 + s) + tnnz * (8 + s);
-            case GKO_FMT_SELLP: return slots * (4 + s) + (slices() + 1) * 8 + slices() * 4;
+            case GKO_FMT_SELLP:
+                return slots * (4 + s) + (slices() + 1) * 8 + slices() * 4 + n_wide * 4 +
+                       (n_wide > 0 ? (n_wide + 1) * 4 : 0) + n_wide_items * (8 + kSellpSlice * 8);
             default: return 0;
         }
     }
@@ -283,7 +300,7 @@ void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, d
                               true, A->carry_a, A->carry_b));
             break;
         case GKO_FMT_SELLP:
-            HIPC(spmv_sellp(s, v.t, A->n, A->sset, A->ecol, v.eval, x, alpha, beta, y));
+            HIPC(spmv_sellp(s, v.t, A->n, A->sset, A->ecol, v.eval, x, alpha, beta, y, A->wide()));
             break;
         default:
             fail(GKO_ERR_INVALID_ARG, "matrix has no storage format");
@@ -543,11 +560,40 @@ void csr_to_format(gko_matrix A, gko_format fmt) {
             HIPC(hipMemcpyAsync(widths.p, L.widths.data(), ns * 4, hipMemcpyHostToDevice, s));
             HIPC(csr_to_sellp(s, A->type(), A->n, A->rp, A->col, A->val, sets.as<int64_t>(),
                               scol.as<int32_t>(), sval.p));
+            // wide slices: (slice, first column) work items of kSellpWideChunk columns
+            std::vector<int32_t> wsl, wfirst, witems;
+            for (int64_t k = 0; k < ns; ++k) {
+                if (L.widths[k] <= kSellpWide) continue;
+                wsl.push_back((int32_t)k);
+                wfirst.push_back((int32_t)(witems.size() / 2));
+                for (int64_t j = 0; j < L.widths[k]; j += kSellpWideChunk) {
+                    witems.push_back((int32_t)k);
+                    witems.push_back((int32_t)j);
+                }
+            }
+            wfirst.push_back((int32_t)(witems.size() / 2));
+            const int64_t nw = (int64_t)wsl.size(), nitems = (int64_t)witems.size() / 2;
+            dbuf dws, dwf, dwi, dwp;
+            if (nw > 0) {
+                dws = dbuf(c, nw * 4);
+                dwf = dbuf(c, (nw + 1) * 4);
+                dwi = dbuf(c, nitems * 8);
+                dwp = dbuf(c, nitems * kSellpSlice * 8);
+                HIPC(hipMemcpyAsync(dws.p, wsl.data(), nw * 4, hipMemcpyHostToDevice, s));
+                HIPC(hipMemcpyAsync(dwf.p, wfirst.data(), (nw + 1) * 4, hipMemcpyHostToDevice, s));
+                HIPC(hipMemcpyAsync(dwi.p, witems.data(), nitems * 8, hipMemcpyHostToDevice, s));
+            }
             c->sync();
             A->drop_storage();
             A->slots = L.sets[ns];
             A->sset = static_cast<int64_t *>(sets.release());
             A->swidth = static_cast<int32_t *>(widths.release());
+            A->n_wide = nw;
+            A->n_wide_items = nitems;
+            A->wide_slices = static_cast<int32_t *>(dws.release());
+            A->wide_first = static_cast<int32_t *>(dwf.release());
+            A->wide_items = static_cast<int32_t *>(dwi.release());
+            A->wide_partial = dwp.release();
             A->ecol = static_cast<int32_t *>(scol.release());
             A->eval = sval.release();
             A->fmt = GKO_FMT_SELLP;
@@ -737,7 +783,7 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
                 } else if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
                     HIPC(cg_spmv_ell(s, v.t, n, A->K, A->ld, A->ecol, v.eval, p.p, q.p, S,
                                      partials.as<double>(), ticket.as<unsigned>()));
-                } else if (A->fmt == GKO_FMT_SELLP) {
+                } else if (A->fmt == GKO_FMT_SELLP && A->n_wide == 0) {
                     HIPC(cg_spmv_sellp(s, v.t, n, A->sset, A->ecol, v.eval, p.p, q.p, S,
                                        partials.as<double>(), ticket.as<unsigned>()));
                 } else {
@@ -1558,6 +1604,12 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
             B->eval = copy(A->eval, A->ell_elems() * vb);
             B->sset = (int64_t *)copy(A->sset, (A->slices() + 1) * 8);
             B->swidth = (int32_t *)copy(A->swidth, A->slices() * 4);
+            B->n_wide = A->n_wide;
+            B->n_wide_items = A->n_wide_items;
+            B->wide_slices = (int32_t *)copy(A->wide_slices, A->n_wide * 4);
+            B->wide_first = (int32_t *)copy(A->wide_first, (A->n_wide + 1) * 4);
+            B->wide_items = (int32_t *)copy(A->wide_items, A->n_wide_items * 8);
+            if (A->wide_partial) B->wide_partial = c->alloc_bytes(A->n_wide_items * kSellpSlice * 8);
             B->trow = (int32_t *)copy(A->trow, A->tnnz * 4);
             B->tcol = (int32_t *)copy(A->tcol, A->tnnz * 4);
             B->tval = copy(A->tval, A->tnnz * vb);
@@ -1593,6 +1645,7 @@ gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out) {
         out->sellp_slice = sellp ? kSellpSlice : 0;
         out->sellp_slices = sellp ? A->slices() : 0;
         out->sellp_slots = sellp ? A->slots : 0;
+        out->sellp_wide_slices = sellp ? A->n_wide : 0;
     });
 }
 

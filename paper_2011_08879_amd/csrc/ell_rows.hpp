@@ -54,25 +54,36 @@ __device__ inline void ell_pair_rows(int64_t K, int64_t ld, int64_t i,
 // (128^3): 141 us with two rows per thread (two slices per wave), 135 us
 // with one and four slot loads in flight, 133 us with eight; ELL on the same
 // matrix 140 us.
-// Returns row i of A x; the caller must give a wavefront 64 consecutive rows
-// starting at a multiple of 64 (rows >= n of the last slice are padding).
-template <typename V>
-__device__ inline V sellp_row(int64_t i, const int64_t *__restrict__ sets,
-                              const int32_t *__restrict__ scol, const V *__restrict__ sval,
-                              const V *__restrict__ x) {
+struct sellp_slice_of {
+    int64_t base;  // first slot of the slice
+    int64_t w;     // slice width
+    int64_t r;     // the row's position in the slice
+};
+
+// The caller must give a wavefront 64 consecutive rows starting at a
+// multiple of 64 (rows >= n of the last slice are padding).
+__device__ inline sellp_slice_of sellp_slice(int64_t i, const int64_t *__restrict__ sets) {
     static_assert(kWave == kSellpSlice, "one slice per wavefront");
     const int32_t k = __builtin_amdgcn_readfirstlane((int32_t)(i / kSellpSlice));
-    const int64_t base = sets[k], w = (sets[k + 1] - base) / kSellpSlice;
-    const int64_t r = i - (int64_t)k * kSellpSlice;
+    const int64_t base = sets[k];
+    return {base, (sets[k + 1] - base) / kSellpSlice, i - (int64_t)k * kSellpSlice};
+}
+
+// Sum over the slots j0 <= j < j1 of row r of the slice starting at base,
+// eight loads in flight; a row stops at its first padding slot.
+template <typename V>
+__device__ inline V sellp_slots_sum(int64_t base, int64_t r, int64_t j0, int64_t j1,
+                                    const int32_t *__restrict__ scol,
+                                    const V *__restrict__ sval, const V *__restrict__ x) {
     const int32_t *c = scol + base + r;
     const V *v = sval + base + r;
     V s = V(0);
-    for (int64_t j = 0; j < w; j += 8) {
+    for (int64_t j = j0; j < j1; j += 8) {
         int32_t cc[8];
         V vv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const bool ok = j + u < w;
+            const bool ok = j + u < j1;
             cc[u] = ok ? load_stream(c + (j + u) * kSellpSlice) : -1;
             vv[u] = ok ? load_stream(v + (j + u) * kSellpSlice) : V(0);
         }
@@ -82,6 +93,15 @@ __device__ inline V sellp_row(int64_t i, const int64_t *__restrict__ sets,
         if (cc[7] < 0) break;  // the row's padding has begun
     }
     return s;
+}
+
+// Row i of A x over its whole slice.
+template <typename V>
+__device__ inline V sellp_row(int64_t i, const int64_t *__restrict__ sets,
+                              const int32_t *__restrict__ scol, const V *__restrict__ sval,
+                              const V *__restrict__ x) {
+    const sellp_slice_of sl = sellp_slice(i, sets);
+    return sellp_slots_sum(sl.base, sl.r, 0, sl.w, scol, sval, x);
 }
 
 }  // namespace gko

@@ -62,8 +62,23 @@ hipError_t spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const
 // sets[s] + j*kSellpSlice + r, sets[s+1] = sets[s] + w_s*kSellpSlice.
 // Padding (and rows >= n of the last slice): col = -1, val = +0.0.
 constexpr int kSellpSlice = 64;
+// Slices wider than kSellpWide (a few very long rows) are not walked by one
+// wavefront: their slots are cut into work items of kSellpWideChunk columns
+// (one wavefront each, partial sums per row), which a second kernel adds in
+// item order.  wide: the n_wide slices (wide.slices), the [first, last) item
+// range of each (wide.first, n_wide + 1 entries), the items as (slice,
+// first column) pairs (wide.items, n_items of them) and partial-sum scratch
+// of n_items * kSellpSlice values (wide.partial).
+constexpr int64_t kSellpWide = 512;
+constexpr int64_t kSellpWideChunk = 256;
+struct sellp_wide {
+    int64_t n_wide = 0, n_items = 0;
+    const int32_t *slices = nullptr, *first = nullptr, *items = nullptr;
+    void *partial = nullptr;
+};
 hipError_t spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
-                      const void *sval, const void *x, double alpha, double beta, void *y);
+                      const void *sval, const void *x, double alpha, double beta, void *y,
+                      const sellp_wide &wide);
 
 // y <- beta * y (beta == 0: y <- 0 without reading y).
 hipError_t scale(hipStream_t s, vt t, int64_t n, double beta, void *y);

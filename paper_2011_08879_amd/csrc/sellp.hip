@@ -6,7 +6,10 @@
 // fewer padding slots, while the column-major slots inside a slice keep the
 // coalesced, reduction-free access of ELL.  A slice of 64 rows is one
 // wavefront (a row per thread) and a workgroup of 256 threads covers 4
-// slices.  No row sorting, stride factor 1.
+// slices.  No row sorting, stride factor 1.  A slice made wide by a few very
+// long rows is split into column chunks instead, so no single wavefront
+// walks thousands of slots (one 10,000-entry row among lognormal rows of
+// mean 16: 2.8 ms with one wavefront for its slice).
 #include "device.hpp"
 #include "ell_rows.hpp"
 #include "kernels.hpp"
@@ -28,16 +31,61 @@ __global__ __launch_bounds__(kSellpBlock) void spmv_sellp_kernel(int64_t n,
                                                                  V beta, V *__restrict__ y) {
     const int64_t i = (int64_t)blockIdx.x * kSellpBlock + threadIdx.x;
     if (i >= n) return;
-    const V s0 = sellp_row(i, sets, scol, sval, x);
+    const sellp_slice_of sl = sellp_slice(i, sets);
+    if (sl.w > kSellpWide) return;  // the whole wavefront: the wide-slice kernels
+    const V s0 = sellp_slots_sum(sl.base, sl.r, 0, sl.w, scol, sval, x);
     y[i] = (beta == V(0)) ? alpha * s0 : alpha * s0 + beta * y[i];
+}
+
+// Work item q of the wide slices: columns [j0, j0 + kSellpWideChunk) of
+// slice s, a wavefront; partial[q * 64 + r] <- the partial sum of row r.
+template <typename V>
+__global__ __launch_bounds__(kSellpBlock) void sellp_wide_kernel(int64_t n_items,
+                                                                 const int32_t *__restrict__ items,
+                                                                 const int64_t *__restrict__ sets,
+                                                                 const int32_t *__restrict__ scol,
+                                                                 const V *__restrict__ sval,
+                                                                 const V *__restrict__ x,
+                                                                 V *__restrict__ partial) {
+    const int64_t q = (int64_t)blockIdx.x * (kSellpBlock / kWave) + threadIdx.x / kWave;
+    if (q >= n_items) return;  // a whole wavefront
+    const int r = threadIdx.x % kWave;
+    const int64_t sl = items[2 * q], j0 = items[2 * q + 1];
+    const int64_t base = sets[sl], w = (sets[sl + 1] - base) / kSellpSlice;
+    const int64_t j1 = j0 + kSellpWideChunk < w ? j0 + kSellpWideChunk : w;
+    partial[q * kSellpSlice + r] = sellp_slots_sum(base, r, j0, j1, scol, sval, x);
+}
+
+// Wide slice q (a wavefront): row r's partials in item order, then y.
+template <typename V>
+__global__ __launch_bounds__(kSellpBlock) void sellp_wide_sum_kernel(
+    int64_t n, int64_t n_wide, const int32_t *__restrict__ slices,
+    const int32_t *__restrict__ first, const V *__restrict__ partial, V alpha, V beta,
+    V *__restrict__ y) {
+    const int64_t q = (int64_t)blockIdx.x * (kSellpBlock / kWave) + threadIdx.x / kWave;
+    if (q >= n_wide) return;
+    const int r = threadIdx.x % kWave;
+    V s = V(0);
+    for (int32_t t = first[q]; t < first[q + 1]; ++t) s += partial[(int64_t)t * kSellpSlice + r];
+    const int64_t i = (int64_t)slices[q] * kSellpSlice + r;
+    if (i < n) y[i] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[i];
 }
 
 template <typename V>
 hipError_t launch_sellp(hipStream_t s, int64_t n, const int64_t *sets, const int32_t *scol,
-                        const void *sval, const void *x, double alpha, double beta, void *y) {
+                        const void *sval, const void *x, double alpha, double beta, void *y,
+                        const sellp_wide &wide) {
+    const V *SV = static_cast<const V *>(sval), *X = static_cast<const V *>(x);
+    V *Y = static_cast<V *>(y);
     spmv_sellp_kernel<V><<<blocks_for(n, kSellpBlock), kSellpBlock, 0, s>>>(
-        n, sets, scol, static_cast<const V *>(sval), static_cast<const V *>(x), (V)alpha,
-        (V)beta, static_cast<V *>(y));
+        n, sets, scol, SV, X, (V)alpha, (V)beta, Y);
+    if (wide.n_wide == 0) return hipGetLastError();
+    constexpr int WPB = kSellpBlock / kWave;
+    V *P = static_cast<V *>(wide.partial);
+    sellp_wide_kernel<V><<<blocks_for(wide.n_items, WPB), kSellpBlock, 0, s>>>(
+        wide.n_items, wide.items, sets, scol, SV, X, P);
+    sellp_wide_sum_kernel<V><<<blocks_for(wide.n_wide, WPB), kSellpBlock, 0, s>>>(
+        n, wide.n_wide, wide.slices, wide.first, P, (V)alpha, (V)beta, Y);
     return hipGetLastError();
 }
 
@@ -105,10 +153,11 @@ __global__ void sellp_to_csr_kernel(int64_t n, const int64_t *__restrict__ sets,
 }  // namespace
 
 hipError_t spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
-                      const void *sval, const void *x, double alpha, double beta, void *y) {
+                      const void *sval, const void *x, double alpha, double beta, void *y,
+                      const sellp_wide &wide) {
     if (n == 0) return hipSuccess;
-    return t == vt::f64 ? launch_sellp<double>(s, n, sets, scol, sval, x, alpha, beta, y)
-                        : launch_sellp<float>(s, n, sets, scol, sval, x, alpha, beta, y);
+    return t == vt::f64 ? launch_sellp<double>(s, n, sets, scol, sval, x, alpha, beta, y, wide)
+                        : launch_sellp<float>(s, n, sets, scol, sval, x, alpha, beta, y, wide);
 }
 
 hipError_t sellp_widths(hipStream_t s, int64_t n, const int32_t *rp, int32_t *widths) {

@@ -187,7 +187,11 @@ def test_conversions_bit_exact(g, orc, cases, f32):
             assert np.array_equal(host(s["col"]), sc), name
             assert np.array_equal(bits(host(s["val"])), bits(sv.astype(vals.dtype))), name
             vb = 4 if f32 else 8
-            assert d.stored_bytes == sets[-1] * (vb + 4) + (len(w) + 1) * 8 + len(w) * 4, name
+            wide = [int(x) for x in w if x > 512]       # slices summed by column chunks
+            items = sum((x + 255) // 256 for x in wide)
+            assert d.sellp_wide_slices == len(wide), name
+            extra = (len(wide) * 4 + (len(wide) + 1) * 4 + items * (8 + 64 * 8)) if wide else 0
+            assert d.stored_bytes == sets[-1] * (vb + 4) + (len(w) + 1) * 8 + len(w) * 4 + extra, name
             B = A.clone()
             assert B.describe() == d
             sb = B.export_sellp()
@@ -280,3 +284,67 @@ def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
         absy = orc.spmv_absbound(A, x, 1.0, 0.0, np.zeros(n))
         assert_spmv_close(host(y), ref, absy, lens, False, name)
         M.close()
+
+
+def arrow_matrix(n, arms, seed):
+    """SPD: diagonal 4 + |row degree|, a tridiagonal band, and rows/columns
+    0..len(arms)-1 coupled to `arms[k]` random far columns (a few long rows)."""
+    rng = np.random.default_rng(seed)
+    ent = {}
+    for i in range(n):
+        for j in (i - 1, i + 1):
+            if 0 <= j < n:
+                ent[(i, j)] = -1.0
+    for k, a in enumerate(arms):
+        for j in rng.choice(np.arange(len(arms), n), size=a, replace=False):
+            v = rng.uniform(-0.5, 0.5)
+            ent[(k, int(j))] = v
+            ent[(int(j), k)] = v
+    rows = [[] for _ in range(n)]
+    for (i, j), v in ent.items():
+        rows[i].append((j, v))
+    rp, col, val = [0], [], []
+    for i in range(n):
+        r = sorted(rows[i])
+        diag = 4.0 + sum(abs(v) for _, v in r)
+        r = sorted(r + [(i, diag)])
+        col += [j for j, _ in r]
+        val += [v for _, v in r]
+        rp.append(len(col))
+    return np.array(rp, np.int32), np.array(col, np.int32), np.array(val)
+
+
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_sellp_wide_slices(g, orc, gen_mod, f32):
+    """Slices made wide by a few long rows are summed by column chunks: parity
+    of the product, an unchanged layout, and CG through the unfused path."""
+    import torch
+    n = 20000
+    rp, col, val = arrow_matrix(n, [3000, 700, 1500], 5)
+    case = (n, n, rp, col, val)
+    assert not sellp_infeasible(case, 4 if f32 else 8)
+    A = make(g, case, f32).convert("sellp")
+    d = A.describe()
+    assert d.sellp_wide_slices == 1                  # rows 0-2 share the first slice
+    vals = val.astype(np.float32).astype(np.float64) if f32 else val
+    w, sets, sc, sv = orc.csr_to_sellp((rp, col, vals))
+    s = A.export_sellp()
+    assert np.array_equal(host(s["col"]), sc) and np.array_equal(host(s["sets"]), sets)
+    x = gen_mod.uniform(7, n)
+    y0 = gen_mod.uniform(8, n)
+    if f32:
+        x, y0 = x.astype(np.float32).astype(np.float64), y0.astype(np.float32).astype(np.float64)
+    tdt = torch.float32 if f32 else torch.float64
+    for alpha, beta in [(1.0, 0.0), (1.5, -0.5)]:
+        yd = dev(y0, tdt)
+        g.spmv(A, alpha, dev(x, tdt), beta, yd)
+        ref = orc.spmv_dot2((rp, col, vals), x, alpha, beta, y0)
+        absy = orc.spmv_absbound((rp, col, vals), x, alpha, beta, y0)
+        assert_spmv_close(host(yd), ref, absy, np.diff(rp), f32, "arrow/sellp")
+    if not f32:
+        b = orc.spmv((rp, col, val), gen_mod.uniform(2, n))
+        rc, xo, info_o = orc.cg((rp, col, val), b, tol=1e-10)
+        xg = dev(np.zeros(n))
+        info = g.cg(A, dev(b), xg, tol=1e-10)
+        assert info["status"] == g.OK and abs(info["iterations"] - info_o["iters"]) <= 2
+        assert np.linalg.norm(b - orc.spmv((rp, col, val), host(xg))) <= 1e-10 * np.linalg.norm(b)
