@@ -546,7 +546,51 @@ def run_sellp(args, g, torch, base, mats, per_kernel):
         log("sellp %-14s %8.4f ms %8.1f GB/s (slots/nnz %.4f)" %
             (name, ms, out[name]["GB/s"], out[name]["padding_ratio"]))
         M.close()
+    out["lognormal_sigma05_1M"] = sellp_mild_irregular(args, g, torch)
     return out
+
+
+def time_spmv(g, torch, M, x, y, warmup, reps):
+    for _ in range(warmup):
+        g.spmv(M, 1.0, x, 0.0, y)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(reps):
+        g.spmv(M, 1.0, x, 0.0, y)
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / reps
+
+
+def sellp_mild_irregular(args, g, torch):
+    """Lognormal rows with sigma 0.5 (mean 16, n = 10^6): irregular enough that
+    ELL pads to the longest row, mild enough for 64-row slices.  Every format's
+    SpMV time (ms) and its storage relative to CSR."""
+    import gen
+    A = gen.random_lognormal(9, 1_000_000, mean=16.0, sigma=0.5, max_len=10000)
+    n = len(A[0]) - 1
+    x = torch.from_numpy(gen.uniform(10, n)).cuda()
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    base = g.Matrix.from_csr(*A)
+    csr_stored = base.describe().stored_bytes
+    res = {"n": n, "nnz": int(len(A[1])), "max_row_len": int(np.diff(A[0]).max())}
+    for fmt in ("csr", "csr_merge", "coo", "ell", "hybrid", "sellp"):
+        try:
+            M = base.clone().convert(fmt)
+        except g.GkoError as e:
+            assert e.status == g.ERR_UNSUPPORTED
+            res[fmt] = {"skipped": "unsupported: padding above 4x the CSR storage"}
+            continue
+        d = M.describe()
+        ms = time_spmv(g, torch, M, x, y, args.warmup, max(args.steps, 10))
+        res[fmt] = {"ms": round(ms, 5), "storage_vs_csr": round(d.stored_bytes / csr_stored, 3)}
+        M.close()
+    base.close()
+    log("sellp vs formats, lognormal sigma 0.5: " +
+        ", ".join("%s %s" % (f, res[f].get("ms", "-")) for f in
+                  ("csr", "csr_merge", "coo", "ell", "hybrid", "sellp")))
+    return res
 
 
 def main():

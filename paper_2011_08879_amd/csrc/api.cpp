@@ -254,9 +254,10 @@ void require(bool ok, gko_status s, const std::string &m) {
 int64_t round_up64(int64_t v) { return (v + 63) / 64 * 64; }
 
 // Scratch of the grid reductions: up to 3 values per block of the vector
-// kernels' grids, or one per block of a fused product's larger grid.
+// kernels' grids, or up to kFusedMaxSums per block of a fused product's
+// larger grid.
 constexpr size_t kPartialBytes =
-    (size_t)std::max(3 * kMaxReductionBlocks, kFusedMaxBlocks) * sizeof(double);
+    (size_t)std::max(3 * kMaxReductionBlocks, kFusedMaxSums * kFusedMaxBlocks) * sizeof(double);
 
 void ensure_carries(gko_matrix A, int64_t elems) {
     if (A->carry_elems >= elems && A->carry_a) return;
@@ -752,6 +753,40 @@ gko_status flag_status(int32_t f) {
     }
 }
 
+// The fused-product view of A with the value arrays v; false when its
+// storage has no fused kernel (COO, CSR merge, CSR with long rows, HYB with
+// a tail, SELL-P with wide slices): the solvers then run the format's SpMV
+// and a separate reduction.
+bool fused_view(gko_matrix A, const values &v, fused_matrix &f) {
+    f = fused_matrix{};
+    f.t = v.t;
+    f.n = A->n;
+    if (A->fmt == GKO_FMT_CSR && A->n_long == 0) {
+        f.format = fused_matrix::csr;
+        f.rp = A->rp;
+        f.col = A->col;
+        f.val = v.val;
+        f.w = A->subwarp;
+        return true;
+    }
+    if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
+        f.format = fused_matrix::ell;
+        f.K = A->K;
+        f.ld = A->ld;
+        f.ecol = A->ecol;
+        f.eval = v.eval;
+        return true;
+    }
+    if (A->fmt == GKO_FMT_SELLP && A->n_wide == 0) {
+        f.format = fused_matrix::sellp;
+        f.sets = A->sset;
+        f.scol = A->ecol;
+        f.sval = v.eval;
+        return true;
+    }
+    return false;
+}
+
 // (P)CG on A with the value arrays `v` (FP64 or FP32), b and x of that type.
 // inv: block-Jacobi inverse of type v.t (bs > 0) or null.
 solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, double tol, int32_t maxit,
@@ -766,7 +801,8 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
     auto *S = sc.as<krylov_scalars>();
     HIPC(scalars_reset(s, S, maxit));
     void *zz = bs > 0 ? z.p : r.p;
-    const bool fused = A->fmt == GKO_FMT_CSR && A->n_long == 0;
+    fused_matrix fm;
+    const bool fused = fused_view(A, v, fm);
     solve_result res;
     krylov_scalars h{};
     for (;;) {
@@ -778,14 +814,7 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
         while (h.done == kRunning) {
             for (int j = 0; j < check_every; ++j) {
                 if (fused) {
-                    HIPC(cg_spmv_csr(s, v.t, n, A->rp, A->col, v.val, p.p, q.p, A->subwarp, S,
-                                     partials.as<double>(), ticket.as<unsigned>()));
-                } else if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
-                    HIPC(cg_spmv_ell(s, v.t, n, A->K, A->ld, A->ecol, v.eval, p.p, q.p, S,
-                                     partials.as<double>(), ticket.as<unsigned>()));
-                } else if (A->fmt == GKO_FMT_SELLP && A->n_wide == 0) {
-                    HIPC(cg_spmv_sellp(s, v.t, n, A->sset, A->ecol, v.eval, p.p, q.p, S,
-                                       partials.as<double>(), ticket.as<unsigned>()));
+                    HIPC(cg_spmv(s, fm, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
                 } else {
                     spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
                     HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
@@ -2107,15 +2136,25 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
         spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
         HIPC(bicg_init(s, n, b, r.p, rh.p, p.p, vv.p, tol, S, P, T));
+        fused_matrix fm;
+        const bool fused = fused_view(A, v, fm);
         krylov_scalars h = read_back(c, S);
         while (h.done == kRunning) {
             for (int j = 0; j < c->opts.check_every; ++j) {
                 HIPC(bicg_p(s, n, r.p, vv.p, p.p, S));
-                spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
-                HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
+                if (fused) {
+                    HIPC(bicg_spmv_alpha(s, fm, p.p, vv.p, rh.p, S, P, T));
+                } else {
+                    spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
+                    HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
+                }
                 HIPC(bicg_s(s, n, r.p, vv.p, sv.p, S, P, T));
-                spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
-                HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
+                if (fused) {
+                    HIPC(bicg_spmv_omega(s, fm, sv.p, t.p, S, P, T));
+                } else {
+                    spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
+                    HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
+                }
                 HIPC(bicg_update(s, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
             }
             h = read_back(c, S);
@@ -2140,11 +2179,17 @@ gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32
         HIPC(hipMemcpyAsync(r.p, b, n * 8, hipMemcpyDeviceToDevice, s));
         spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
         HIPC(cgs_init(s, n, b, r.p, rh.p, p.p, u.p, tol, S, P, T));
+        fused_matrix fm;
+        const bool fused = fused_view(A, v, fm);
         krylov_scalars h = read_back(c, S);
         while (h.done == kRunning) {
             for (int j = 0; j < c->opts.check_every; ++j) {
-                spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
-                HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
+                if (fused) {
+                    HIPC(cgs_spmv_alpha(s, fm, p.p, t.p, rh.p, S, P, T));
+                } else {
+                    spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
+                    HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
+                }
                 HIPC(cgs_qwx(s, n, u.p, t.p, q.p, w.p, x, S));
                 spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
                 HIPC(cgs_update(s, n, r.p, t.p, rh.p, S, P, T));

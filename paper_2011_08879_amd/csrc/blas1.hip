@@ -16,6 +16,7 @@
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
 #include "solver_state.hpp"
+#include "krylov_ops.hpp"
 
 namespace gko {
 
@@ -289,136 +290,144 @@ __global__ __launch_bounds__(kB) void cg_init_kernel(int64_t n, const V *__restr
     grid_sum_apply<kB, 3>(v, ra, cg_init_op{sc, tol});
 }
 
-// q = A p for CSR (a subwarp of W lanes per U rows, as in the plain SpMV),
-// fused with p.q.
-template <typename V, int W>
-__global__ __launch_bounds__(kB) void cg_spmv_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
-                                                         const int32_t *__restrict__ col,
-                                                         const V *__restrict__ val,
-                                                         const V *__restrict__ p, V *__restrict__ q,
-                                                         krylov_scalars *sc, red_args ra) {
-    if (sc->done) return;
+// ------------------------------------------------------------------ fused products
+// out = A in by a format's SpMV row sums, with the sums a Krylov step needs
+// next formed in the same pass and finished by the step's reduction op.
+// What is summed is a policy:
+//   pq_dot     in.out                  (CG: p.q)
+//   aux_dot    aux.out                 (BiCGSTAB: rhat.v; CGS: t.rhat)
+//   omega_dot  out.in and out.out      (BiCGSTAB: t.s and t.t)
+template <typename V, typename Op>
+struct pq_dot {
+    static constexpr int NV = 1;
+    Op op;
+    __device__ bool skip() const { return op.skip(); }
+    __device__ void add(double (&a)[NV], int64_t, V in, V out) const {
+        a[0] += (double)in * (double)out;
+    }
+};
+template <typename V, typename Op>
+struct aux_dot {
+    static constexpr int NV = 1;
+    const V *aux;
+    Op op;
+    __device__ bool skip() const { return op.skip(); }
+    __device__ void add(double (&a)[NV], int64_t i, V, V out) const {
+        a[0] += (double)aux[i] * (double)out;
+    }
+};
+template <typename V, typename Op>
+struct omega_dot {
+    static constexpr int NV = 2;
+    Op op;
+    __device__ bool skip() const { return op.skip(); }
+    __device__ void add(double (&a)[NV], int64_t, V in, V out) const {
+        a[0] += (double)out * (double)in;
+        a[1] += (double)out * (double)out;
+    }
+};
+
+// CSR, a subwarp of W lanes per U rows (as in the plain SpMV).
+template <typename V, int W, typename P>
+__global__ __launch_bounds__(kB) void fused_csr_kernel(int64_t n, const int32_t *__restrict__ rp,
+                                                       const int32_t *__restrict__ col,
+                                                       const V *__restrict__ val,
+                                                       const V *__restrict__ in, V *__restrict__ out,
+                                                       P pol, red_args ra) {
+    if (pol.skip()) return;
     constexpr int U = csr_shape<W>::U;
     constexpr int RPB = kB / W * U;
     const int lane = threadIdx.x % W;
-    double acc = 0.0;
+    double acc[P::NV] = {};
     for (int64_t g0 = (int64_t)blockIdx.x * RPB; g0 < n; g0 += (int64_t)gridDim.x * RPB) {
         const int64_t row0 = g0 + (int64_t)(threadIdx.x / W) * U;
         if (row0 < n) {  // uniform across the subwarp
             V s[U];
-            csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, p, s, INT_MAX);
+            csr_rows_sum<V, W, U>(n, row0, lane, rp, col, val, in, s, INT_MAX);
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t r = row0 + u;
                 if ((W >= U ? lane == u : lane == 0) && r < n) {
-                    q[r] = s[u];
-                    acc += (double)p[r] * (double)s[u];
+                    out[r] = s[u];
+                    pol.add(acc, r, in[r], s[u]);
                 }
             }
         }
     }
-    double v[1] = {acc};
-    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
+    grid_sum_apply<kB, P::NV>(acc, ra, pol.op);
 }
 
-// q = A p for CSR with a thread per row (short regular rows, as in the
-// plain SpMV), fused with p.q; the workgroup strides over tiles of rows.
-template <typename V>
-__global__ __launch_bounds__(kRowThreadBlock) void cg_spmv_csr_rowthread_kernel(
+// CSR with a thread per row (short regular rows, as in the plain SpMV); the
+// workgroup strides over tiles of rows.
+template <typename V, typename P>
+__global__ __launch_bounds__(kRowThreadBlock) void fused_csr_rowthread_kernel(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
-    const V *__restrict__ val, const V *__restrict__ p, V *__restrict__ q, krylov_scalars *sc,
-    red_args ra) {
+    const V *__restrict__ val, const V *__restrict__ in, V *__restrict__ out, P pol, red_args ra) {
     static_assert(kRowThreadBlock == kB, "one reduction block shape");
     __shared__ rowthread_lds<V> L;
-    if (sc->done) return;
-    double acc = 0.0;
+    if (pol.skip()) return;
+    double acc[P::NV] = {};
     for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n; r0 += (int64_t)gridDim.x * kB) {
-        const V s = csr_rowthread_sum(n, r0, rp, col, val, p, L);
+        const V s = csr_rowthread_sum(n, r0, rp, col, val, in, L);
         const int64_t i = r0 + threadIdx.x;
         if (i < n) {
-            q[i] = s;
-            acc += (double)p[i] * (double)s;
+            out[i] = s;
+            pol.add(acc, i, in[i], s);
         }
     }
-    double v[1] = {acc};
-    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
+    grid_sum_apply<kB, P::NV>(acc, ra, pol.op);
 }
 
-// q = A p for ELL (two adjacent rows per thread, as in the plain SpMV),
-// fused with p.q.
-template <typename V>
-__global__ __launch_bounds__(kB) void cg_spmv_ell_kernel(int64_t n, int64_t K, int64_t ld,
-                                                         const int32_t *__restrict__ ecol,
-                                                         const V *__restrict__ eval,
-                                                         const V *__restrict__ p, V *__restrict__ q,
-                                                         krylov_scalars *sc, red_args ra) {
-    if (sc->done) return;
-    double acc = 0.0;
+// ELL, two adjacent rows per thread (as in the plain SpMV).
+template <typename V, typename P>
+__global__ __launch_bounds__(kB) void fused_ell_kernel(int64_t n, int64_t K, int64_t ld,
+                                                       const int32_t *__restrict__ ecol,
+                                                       const V *__restrict__ eval,
+                                                       const V *__restrict__ in, V *__restrict__ out,
+                                                       P pol, red_args ra) {
+    if (pol.skip()) return;
+    double acc[P::NV] = {};
     for (int64_t i = 2 * ((int64_t)blockIdx.x * kB + threadIdx.x); i < n;
          i += 2 * (int64_t)gridDim.x * kB) {
         V s0, s1;
-        ell_pair_rows(K, ld, i, ecol, eval, p, s0, s1);
-        q[i] = s0;
-        acc += (double)p[i] * (double)s0;
+        ell_pair_rows(K, ld, i, ecol, eval, in, s0, s1);
+        out[i] = s0;
+        pol.add(acc, i, in[i], s0);
         if (i + 1 < n) {
-            q[i + 1] = s1;
-            acc += (double)p[i + 1] * (double)s1;
+            out[i + 1] = s1;
+            pol.add(acc, i + 1, in[i + 1], s1);
         }
     }
-    double v[1] = {acc};
-    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
+    grid_sum_apply<kB, P::NV>(acc, ra, pol.op);
 }
 
-hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
-                       const void *eval, const void *p, void *q, krylov_scalars *sc,
-                       double *partials, unsigned *ticket) {
-    const int g = fused_blocks((n + 1) / 2);
-    const red_args ra = red_for(g, partials, ticket);
-    if (t == vt::f64)
-        cg_spmv_ell_kernel<double><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const double *>(eval),
-                                                    static_cast<const double *>(p),
-                                                    static_cast<double *>(q), sc, ra);
-    else
-        cg_spmv_ell_kernel<float><<<g, kB, 0, s>>>(n, K, ld, ecol, static_cast<const float *>(eval),
-                                                   static_cast<const float *>(p),
-                                                   static_cast<float *>(q), sc, ra);
-    return red_finish<1>(s, g, ra, cg_alpha_op{sc});
-}
-
-// The same for SELL-P: a row per thread, a slice per wavefront (the
-// grid-stride step is a multiple of the slice size).
-template <typename V>
-__global__ __launch_bounds__(kB) void cg_spmv_sellp_kernel(int64_t n, const int64_t *__restrict__ sets,
-                                                           const int32_t *__restrict__ scol,
-                                                           const V *__restrict__ sval,
-                                                           const V *__restrict__ p, V *__restrict__ q,
-                                                           krylov_scalars *sc, red_args ra) {
+// SELL-P: a row per thread, a slice per wavefront (the grid-stride step is a
+// multiple of the slice size).  Matrices with wide slices do not come here.
+// STRIDE: the grid is smaller than the row count.  Without the grid-stride
+// loop the FP64 kernel needs 40 VGPRs instead of 92 (8 waves per SIMD
+// instead of 5).
+template <typename V, typename P, bool STRIDE>
+__global__ __launch_bounds__(kB) void fused_sellp_kernel(int64_t n, const int64_t *__restrict__ sets,
+                                                         const int32_t *__restrict__ scol,
+                                                         const V *__restrict__ sval,
+                                                         const V *__restrict__ in,
+                                                         V *__restrict__ out, P pol, red_args ra) {
     static_assert(kB % kSellpSlice == 0, "whole slices per workgroup");
-    if (sc->done) return;
-    double acc = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x; i < n; i += (int64_t)gridDim.x * kB) {
-        const V s0 = sellp_row(i, sets, scol, sval, p);
-        q[i] = s0;
-        acc += (double)p[i] * (double)s0;
+    if (pol.skip()) return;
+    double acc[P::NV] = {};
+    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    if constexpr (STRIDE) {
+        for (; i < n; i += (int64_t)gridDim.x * kB) {
+            const V s0 = sellp_row(i, sets, scol, sval, in);
+            out[i] = s0;
+            pol.add(acc, i, in[i], s0);
+        }
+    } else if (i < n) {
+        const V s0 = sellp_row(i, sets, scol, sval, in);
+        out[i] = s0;
+        pol.add(acc, i, in[i], s0);
     }
-    double v[1] = {acc};
-    grid_sum_apply<kB, 1>(v, ra, cg_alpha_op{sc});
-}
-
-hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
-                         const void *sval, const void *p, void *q, krylov_scalars *sc,
-                         double *partials, unsigned *ticket) {
-    const int g = fused_blocks(n);
-    const red_args ra = red_for(g, partials, ticket);
-    if (t == vt::f64)
-        cg_spmv_sellp_kernel<double><<<g, kB, 0, s>>>(n, sets, scol, static_cast<const double *>(sval),
-                                                      static_cast<const double *>(p),
-                                                      static_cast<double *>(q), sc, ra);
-    else
-        cg_spmv_sellp_kernel<float><<<g, kB, 0, s>>>(n, sets, scol, static_cast<const float *>(sval),
-                                                     static_cast<const float *>(p),
-                                                     static_cast<float *>(q), sc, ra);
-    return red_finish<1>(s, g, ra, cg_alpha_op{sc});
+    grid_sum_apply<kB, P::NV>(acc, ra, pol.op);
 }
 
 // p.q after a SpMV done by a format's own kernel.
@@ -513,50 +522,90 @@ hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r,
                         : launch_cg_init<float>(s, n, b, r, z, p, inv, bs, tol, sc, partials, ticket);
 }
 
-template <typename V, int W>
-static hipError_t launch_cg_csr_w(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
-                                  const void *val, const void *p, void *q, krylov_scalars *sc,
-                                  double *partials, unsigned *ticket) {
+template <typename V, int W, typename P>
+static hipError_t launch_fused_csr_w(hipStream_t s, const fused_matrix &A, const V *in, V *out,
+                                     const P &pol, double *partials, unsigned *ticket) {
     constexpr int RPB = kB / W * csr_shape<W>::U;
-    int64_t g = (n + RPB - 1) / RPB;
+    int64_t g = (A.n + RPB - 1) / RPB;
     if (g > kFusedMaxBlocks) g = kFusedMaxBlocks;
     if (g < 1) g = 1;
     const red_args ra = red_for((int)g, partials, ticket);
-    cg_spmv_csr_kernel<V, W><<<(unsigned)g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
-                                                        static_cast<const V *>(p),
-                                                        static_cast<V *>(q), sc, ra);
-    return red_finish<1>(s, (int)g, ra, cg_alpha_op{sc});
+    fused_csr_kernel<V, W, P><<<(unsigned)g, kB, 0, s>>>(
+        A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
+    return red_finish<P::NV>(s, (int)g, ra, pol.op);
 }
 
-template <typename V>
-static hipError_t launch_cg_csr(hipStream_t s, int64_t n, const int32_t *rp, const int32_t *col,
-                                const void *val, const void *p, void *q, int w, krylov_scalars *sc,
-                                double *partials, unsigned *ticket) {
-    if (w == kCsrRowThread) {
-        const int g = fused_blocks(n);
+template <typename V, typename P>
+static hipError_t launch_fused(hipStream_t s, const fused_matrix &A, const void *in_, void *out_,
+                               const P &pol, double *partials, unsigned *ticket) {
+    static_assert(P::NV <= kFusedMaxSums, "the partials scratch holds kFusedMaxSums per block");
+    const V *in = static_cast<const V *>(in_);
+    V *out = static_cast<V *>(out_);
+    if (A.format == fused_matrix::ell) {
+        const int g = fused_blocks((A.n + 1) / 2);
         const red_args ra = red_for(g, partials, ticket);
-        cg_spmv_csr_rowthread_kernel<V><<<g, kB, 0, s>>>(n, rp, col, static_cast<const V *>(val),
-                                                         static_cast<const V *>(p),
-                                                         static_cast<V *>(q), sc, ra);
-        return red_finish<1>(s, g, ra, cg_alpha_op{sc});
+        fused_ell_kernel<V, P><<<g, kB, 0, s>>>(A.n, A.K, A.ld, A.ecol,
+                                                static_cast<const V *>(A.eval), in, out, pol, ra);
+        return red_finish<P::NV>(s, g, ra, pol.op);
     }
-    switch (w) {
-        case 1: return launch_cg_csr_w<V, 1>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 2: return launch_cg_csr_w<V, 2>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 4: return launch_cg_csr_w<V, 4>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 8: return launch_cg_csr_w<V, 8>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 16: return launch_cg_csr_w<V, 16>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 32: return launch_cg_csr_w<V, 32>(s, n, rp, col, val, p, q, sc, partials, ticket);
-        case 64: return launch_cg_csr_w<V, 64>(s, n, rp, col, val, p, q, sc, partials, ticket);
+    if (A.format == fused_matrix::sellp) {
+        const int g = fused_blocks(A.n);
+        const red_args ra = red_for(g, partials, ticket);
+        if ((int64_t)g * kB >= A.n)
+            fused_sellp_kernel<V, P, false><<<g, kB, 0, s>>>(
+                A.n, A.sets, A.scol, static_cast<const V *>(A.sval), in, out, pol, ra);
+        else
+            fused_sellp_kernel<V, P, true><<<g, kB, 0, s>>>(
+                A.n, A.sets, A.scol, static_cast<const V *>(A.sval), in, out, pol, ra);
+        return red_finish<P::NV>(s, g, ra, pol.op);
+    }
+    if (A.w == kCsrRowThread) {
+        const int g = fused_blocks(A.n);
+        const red_args ra = red_for(g, partials, ticket);
+        fused_csr_rowthread_kernel<V, P><<<g, kB, 0, s>>>(
+            A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
+        return red_finish<P::NV>(s, g, ra, pol.op);
+    }
+    switch (A.w) {
+        case 1: return launch_fused_csr_w<V, 1>(s, A, in, out, pol, partials, ticket);
+        case 2: return launch_fused_csr_w<V, 2>(s, A, in, out, pol, partials, ticket);
+        case 4: return launch_fused_csr_w<V, 4>(s, A, in, out, pol, partials, ticket);
+        case 8: return launch_fused_csr_w<V, 8>(s, A, in, out, pol, partials, ticket);
+        case 16: return launch_fused_csr_w<V, 16>(s, A, in, out, pol, partials, ticket);
+        case 32: return launch_fused_csr_w<V, 32>(s, A, in, out, pol, partials, ticket);
+        case 64: return launch_fused_csr_w<V, 64>(s, A, in, out, pol, partials, ticket);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
-                       const void *val, const void *p, void *q, int w, krylov_scalars *sc,
-                       double *partials, unsigned *ticket) {
-    return t == vt::f64 ? launch_cg_csr<double>(s, n, rp, col, val, p, q, w, sc, partials, ticket)
-                        : launch_cg_csr<float>(s, n, rp, col, val, p, q, w, sc, partials, ticket);
+hipError_t cg_spmv(hipStream_t s, const fused_matrix &A, const void *p, void *q, krylov_scalars *sc,
+                   double *partials, unsigned *ticket) {
+    if (A.t == vt::f64)
+        return launch_fused<double>(s, A, p, q, pq_dot<double, cg_alpha_op>{cg_alpha_op{sc}},
+                                    partials, ticket);
+    return launch_fused<float>(s, A, p, q, pq_dot<float, cg_alpha_op>{cg_alpha_op{sc}}, partials,
+                               ticket);
+}
+
+hipError_t bicg_spmv_alpha(hipStream_t s, const fused_matrix &A, const void *p, void *v,
+                           const void *rh, krylov_scalars *sc, double *partials, unsigned *ticket) {
+    if (A.t != vt::f64) return hipErrorInvalidValue;
+    const aux_dot<double, bicg_alpha_op> pol{static_cast<const double *>(rh), bicg_alpha_op{sc}};
+    return launch_fused<double>(s, A, p, v, pol, partials, ticket);
+}
+
+hipError_t bicg_spmv_omega(hipStream_t s, const fused_matrix &A, const void *sv, void *t,
+                           krylov_scalars *sc, double *partials, unsigned *ticket) {
+    if (A.t != vt::f64) return hipErrorInvalidValue;
+    return launch_fused<double>(s, A, sv, t, omega_dot<double, bicg_omega_op>{bicg_omega_op{sc}},
+                                partials, ticket);
+}
+
+hipError_t cgs_spmv_alpha(hipStream_t s, const fused_matrix &A, const void *p, void *t,
+                          const void *rh, krylov_scalars *sc, double *partials, unsigned *ticket) {
+    if (A.t != vt::f64) return hipErrorInvalidValue;
+    const aux_dot<double, cgs_alpha_op> pol{static_cast<const double *>(rh), cgs_alpha_op{sc}};
+    return launch_fused<double>(s, A, p, t, pol, partials, ticket);
 }
 
 hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,

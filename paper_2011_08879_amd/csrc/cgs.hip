@@ -13,6 +13,7 @@
 #include "kernels.hpp"
 #include "solver_kernels.hpp"
 #include "solver_state.hpp"
+#include "krylov_ops.hpp"
 
 namespace gko {
 
@@ -37,16 +38,6 @@ struct cgs_init_op {
     }
 };
 
-// alpha = rho / (t.rhat)
-struct cgs_alpha_op {
-    krylov_scalars *sc;
-    __device__ bool skip() const { return sc->done != 0; }
-    __device__ void operator()(const double *o) const {
-        sc->aux = o[0];
-        if (!(fabs(o[0]) >= 1e-300)) sc->done = kBreakdown;
-        else sc->alpha = sc->rho / o[0];
-    }
-};
 
 // After r -= alpha A (u + q): totals r.r, r.rhat; convergence, then beta.
 struct cgs_update_op {

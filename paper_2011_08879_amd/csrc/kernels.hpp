@@ -129,13 +129,16 @@ constexpr int kRedBlock = 256;
 // Reduction kernels launch at most this many blocks (grid-stride loops
 // beyond), so partial-sum scratch of NV * kMaxReductionBlocks doubles fits
 // every launch of the vector kernels (the fused products below need
-// kFusedMaxBlocks doubles).
+// kFusedMaxSums * kFusedMaxBlocks doubles).
 constexpr int kMaxReductionBlocks = 2048;
 // The CG products with p.q fused in launch a thread (or row pair) per row up
 // to this many blocks, with one partial sum per block: a 2048-block
 // grid-stride product ran 6% slower per CG iteration on the 7-point Poisson
 // matrix 256^3 (SELL-P 609 -> 574 us, CSR 635 -> 597 us).
 constexpr int kFusedMaxBlocks = 65536;
+// A fused product forms at most this many sums per block, so its scratch is
+// kFusedMaxSums * kFusedMaxBlocks doubles.
+constexpr int kFusedMaxSums = 2;
 int reduction_blocks(int64_t n);
 // result: one device double. partials: kMaxReductionBlocks doubles; ticket: zeroed uint.
 hipError_t dot(hipStream_t s, vt t, int64_t n, const void *x, const void *y, double *result,

@@ -35,15 +35,36 @@ hipError_t small_cg(hipStream_t s, int64_t n, int64_t max_len, const int32_t *rp
 hipError_t cg_init(hipStream_t s, vt t, int64_t n, const void *b, const void *r, void *z, void *p,
                    const void *inv, int bs, double tol, krylov_scalars *sc, double *partials,
                    unsigned *ticket);
-hipError_t cg_spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
-                       const void *val, const void *p, void *q, int w, krylov_scalars *sc,
-                       double *partials, unsigned *ticket);
-hipError_t cg_spmv_ell(hipStream_t s, vt t, int64_t n, int64_t K, int64_t ld, const int32_t *ecol,
-                       const void *eval, const void *p, void *q, krylov_scalars *sc,
-                       double *partials, unsigned *ticket);
-hipError_t cg_spmv_sellp(hipStream_t s, vt t, int64_t n, const int64_t *sets, const int32_t *scol,
-                         const void *sval, const void *p, void *q, krylov_scalars *sc,
-                         double *partials, unsigned *ticket);
+// A matrix as the fused products read it (out = A in together with the
+// sums a Krylov step needs next): CSR without long rows, ELL (or HYB with an
+// empty tail) or SELL-P without wide slices, in value type t.
+struct fused_matrix {
+    enum kind { csr = 0, ell = 1, sellp = 2 };
+    kind format = csr;
+    vt t = vt::f64;
+    int64_t n = 0;
+    const int32_t *rp = nullptr, *col = nullptr;  // CSR
+    const void *val = nullptr;
+    int w = 0;                                    // CSR kernel (see csr_kernel_width)
+    int64_t K = 0, ld = 0;                        // ELL
+    const int32_t *ecol = nullptr;
+    const void *eval = nullptr;
+    const int64_t *sets = nullptr;                // SELL-P
+    const int32_t *scol = nullptr;
+    const void *sval = nullptr;
+};
+// The fused products take partials of kFusedMaxSums * kFusedMaxBlocks doubles.
+// CG: q = A p with p.q, then alpha (or NOT_SPD).
+hipError_t cg_spmv(hipStream_t s, const fused_matrix &A, const void *p, void *q, krylov_scalars *sc,
+                   double *partials, unsigned *ticket);
+// BiCGSTAB: v = A p with rhat.v, then alpha; t = A s with t.s and t.t, then
+// omega.  CGS: t = A p with t.rhat, then alpha.  FP64 only.
+hipError_t bicg_spmv_alpha(hipStream_t s, const fused_matrix &A, const void *p, void *v,
+                           const void *rh, krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t bicg_spmv_omega(hipStream_t s, const fused_matrix &A, const void *sv, void *t,
+                           krylov_scalars *sc, double *partials, unsigned *ticket);
+hipError_t cgs_spmv_alpha(hipStream_t s, const fused_matrix &A, const void *p, void *t,
+                          const void *rh, krylov_scalars *sc, double *partials, unsigned *ticket);
 hipError_t cg_pq(hipStream_t s, vt t, int64_t n, const void *p, const void *q, krylov_scalars *sc,
                  double *partials, unsigned *ticket);
 // flexible: beta = z.(r - r_old) / rho (flexible CG) instead of r.z / rho.

@@ -136,6 +136,54 @@ def test_poisson256_gmres_estimate_full_size(g, orc, poisson):
         ctx.set_solver_opts()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "ell", "sellp"])
+@pytest.mark.parametrize("solver", ["bicgstab", "cgs"])
+def test_poisson256_nonsymmetric_fused_full_size(g, orc, poisson, solver, fmt):
+    """BiCGSTAB and CGS for 20 iterations at the bench's size in each format
+    whose SpMV fuses the step's dot products (a 65536-block grid with two
+    sums per block for BiCGSTAB's t.s, t.t): the reported true residual is
+    the oracle's, and the recurrence's estimate has not drifted from it."""
+    A, xs, b = poisson
+    M = g.Matrix.from_csr(*A)
+    try:
+        M.convert(fmt)
+        x = dev(np.zeros(256 ** 3))
+        info = getattr(g, solver)(M, dev(b), x, tol=1e-30, maxit=20)
+        assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 20, info
+        true = np.linalg.norm(b - orc.spmv(A, host(x))) / np.linalg.norm(b)
+        assert abs(info["true_rel_residual"] - true) <= 1e-12
+        assert abs(info["rel_residual"] - true) <= 1e-6 * true
+        assert true < 1e-3    # the oracle's 20 iterations: 9.6e-5 (BiCGSTAB), 4.5e-5 (CGS)
+    finally:
+        M.close()
+
+
+@pytest.fixture(scope="module")
+def laplace1d_big(gen_mod):
+    n = (1 << 24) + 4096      # more rows than the fused products' largest grid
+    return gen_mod.laplace1d(n), gen_mod.uniform(12, n)
+
+
+@pytest.mark.parametrize("solver", ["cg", "bicgstab", "cgs"])
+def test_sellp_fused_grid_stride(g, orc, laplace1d_big, solver):
+    """SELL-P with more than 65536 x 256 rows: the fused products take their
+    grid-stride form.  Ten iterations against the oracle's ten."""
+    A, b = laplace1d_big
+    M = g.Matrix.from_csr(*A)
+    try:
+        M.convert("sellp")
+        x = dev(np.zeros(len(b)))
+        info = getattr(g, solver)(M, dev(b), x, tol=1e-30, maxit=10)
+        rc, xo, oi = getattr(orc, solver)(A, b, tol=1e-30, maxit=10)
+        assert rc == orc.NOT_CONVERGED and oi["iters"] == 10
+        assert info["status"] == g.ERR_NOT_CONVERGED and info["iterations"] == 10, info
+        xg = host(x)
+        assert np.abs(xg - xo).max() <= 1e-9 * np.abs(xo).max()
+        assert abs(info["rel_residual"] - oi["relres"]) <= 1e-9 * oi["relres"]
+    finally:
+        M.close()
+
+
 @pytest.mark.parametrize("f32", [False, True], ids=["fp64", "fp32"])
 def test_batch_10k_full_size(g, orc, gen_mod, f32):
     import torch
