@@ -271,7 +271,9 @@ def krylov_bytes(name, S, n, iters, m=30):
     Per iteration: CG and FCG S + 9 vector passes (fused product with p.q;
     x, r update with the sums; p update); pipelined CG S + 13 (one update
     kernel reading n, z, s, p, x, r, w and writing all but n); BiCGSTAB
-    2S + 18; CGS 2S + 17;
+    2S + 15 (rhat read by the fused v = A p; s = r - alpha v; t.s and t.t
+    formed in t = A s; x, r update reading x, p, s, t, rhat; p update);
+    CGS 2S + 16 (rhat read by the fused t = A p);
     GMRES Arnoldi step j: S + (2j + 7) passes with one Gram-Schmidt round
     (dot over j+1 basis vectors and w, update reading them and writing w,
     normalisation), plus per cycle the residual (S + 5 passes) and
@@ -282,9 +284,9 @@ def krylov_bytes(name, S, n, iters, m=30):
     if name == "pipecg":
         return iters * (S + 13 * vp)
     if name == "bicgstab":
-        return iters * (2 * S + 18 * vp)
+        return iters * (2 * S + 15 * vp)
     if name == "cgs":
-        return iters * (2 * S + 17 * vp)
+        return iters * (2 * S + 16 * vp)
     if name == "gmres":
         cycles, rest = divmod(iters, m)
         steps = [j for _ in range(cycles) for j in range(m)] + list(range(rest))
