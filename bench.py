@@ -502,6 +502,7 @@ def run_sweep(args, g, gen, torch, result):
     roofline["frac_of_stream_copy"] = round(achieved / result["stream"]["copy_GB/s"], 4)
     result["config"]["frac_of_stream_copy"] = round(value / result["stream"]["copy_GB/s"], 4)
     result["sellp"] = run_sellp(args, g, torch, base, mats, per_kernel)
+    result["cache_protocol"] = cache_protocol(g, torch, mats)
     for e in mats:
         e["M"].close()
     for M in base.values():
@@ -510,6 +511,39 @@ def run_sweep(args, g, gen, torch, result):
     torch.cuda.empty_cache()
 
     return result, inputs
+
+
+def cache_protocol(g, torch, mats, reps=20, warmup=5, scratch_mib=1024):
+    """Each sweep SpMV alone, outside the timed step: the median of `reps`
+    single-launch event timings, warm (launches back to back, so a matrix that
+    fits the 256 MB Infinity Cache is served from it) and cold (a 1 GiB fill
+    of a scratch buffer before every launch evicts the L2s and the Infinity
+    Cache).  The timed sweep sits between the two: its SpMVs alternate
+    matrices, so the random matrix never runs right after itself."""
+    scratch = torch.empty((scratch_mib << 20) // 8, dtype=torch.float64, device="cuda")
+    out = []
+    for e in mats:
+        row = {"matrix": e["matrix"], "format": e["format"]}
+        for mode in ("warm", "cold"):
+            for _ in range(warmup):
+                g.spmv(e["M"], 1.0, e["x"], 0.0, e["y"])
+            ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                  for _ in range(reps)]
+            for k, (a, b) in enumerate(ev):
+                if mode == "cold":
+                    scratch.fill_(float(k))
+                a.record()
+                g.spmv(e["M"], 1.0, e["x"], 0.0, e["y"])
+                b.record()
+            torch.cuda.synchronize()
+            ms = float(np.median([a.elapsed_time(b) for a, b in ev]))
+            row[mode + "_ms"] = round(ms, 5)
+            row[mode + "_GB/s"] = round(e["bytes"] / (ms * 1e-3) / 1e9, 1)
+        out.append(row)
+        log("  %-14s %-10s warm %8.4f ms  cold %8.4f ms" % (row["matrix"], row["format"],
+                                                          row["warm_ms"], row["cold_ms"]))
+    del scratch
+    return {"reps": reps, "scratch_bytes": scratch_mib << 20, "kernels": out}
 
 
 def run_sellp(args, g, torch, base, mats, per_kernel):
