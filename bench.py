@@ -393,7 +393,14 @@ def run_batch(g, gen, torch, nsys=10000, reps=3):
             best = el if best is None else min(best, el)
         it, rr, xh = it.cpu().numpy(), rr.cpu().numpy(), x.cpu().numpy()
         err = np.abs(xh - B.xstar).max() / np.abs(B.xstar).max()
+        # HBM floor: one read of every system (local row_ptr, col, val, the two
+        # int64 offset arrays), of b and of the initial x, one write of x
+        vs = 8 if label == "fp64" else 4
+        floor_bytes = ((out["rows"] + nsys) * 4 + out["nnz"] * (4 + vs) + 2 * (nsys + 1) * 8
+                       + 3 * out["rows"] * 8)
         out[label] = {"solves_per_s": round(nsys / best, 1), "seconds": round(best, 5),
+                      "hbm_floor_bytes": int(floor_bytes),
+                      "hbm_floor_seconds": round(floor_bytes / (HBM_PEAK_GBS * 1e9), 7),
                       "block": blk, "autotune_ms": {str(k): round(v, 3) for k, v in times.items()},
                       "status": g.status_string(st), "iters_mean": round(float(it.mean()), 1),
                       "iters_max": int(it.max()), "max_true_rel_residual": float(rr.max()),
