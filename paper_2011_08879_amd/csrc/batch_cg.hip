@@ -37,6 +37,25 @@ __device__ inline double wg_sum(double v, double *red) {
     }
 }
 
+// The same with one barrier: no thread may write `red` again before every
+// thread has passed a later barrier (the CG loop alternates two buffers).
+template <int T>
+__device__ inline double wg_sum_once(double v, double *red) {
+    v = wave_total(v);
+    if constexpr (T == kWave) {
+        return v;
+    } else {
+        constexpr int NW = T / kWave;
+        const int w = threadIdx.x / kWave;
+        if ((threadIdx.x % kWave) == 0) red[w] = v;
+        __syncthreads();
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < NW; ++j) s += red[j];
+        return s;
+    }
+}
+
 template <int T>
 __device__ inline void wg_sync() {
     __syncthreads();
@@ -94,42 +113,23 @@ struct sys_regs {
         }
         return wg_sum<T>(fits ? 0.0 : 1.0, red) == 0.0;
     }
-
-    // q = A p over this thread's rows, returns sum of p_i q_i (as spmv_rows).
-    template <typename VV>
-    __device__ double spmv(int32_t m, const VV *p, VV *q) const {
-        double pq = 0.0;
-#pragma unroll
-        for (int j = 0; j < R; ++j) {
-            const int i = threadIdx.x + j * T;
-            if (i < m) {
-                VV s = VV(0);
-#pragma unroll
-                for (int k = 0; k < L; ++k) s += (VV)v[j][k] * p[c[j][k]];
-                q[i] = s;
-                pq += (double)p[i] * (double)s;
-            }
-        }
-        return pq;
-    }
 };
 
 // Plain CG on A x = rhs from x = 0, vectors x, r, p, q in LDS (type VV),
-// dots in FP64.  q = A p comes from the register-held rows (CACHED) or from
-// memory.  Returns iterations; *flag = 1 not SPD, 2 breakdown.
-template <typename VA, typename VV, int T, bool CACHED>
-__device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val,
-                                const sys_regs<VA, T> &regs, VV *x, VV *r, VV *p, VV *q,
-                                double rhs_norm2, double stop2, int maxit, double *red,
-                                int *flag) {
+// dots in FP64, q = A p from the system's rows in memory.  Returns
+// iterations; *flag = 1 not SPD, 2 breakdown.
+// Three barriers per iteration: p.q into red2[0], r.r into red2[1], and the
+// one after the p update.  A buffer's next write comes two barriers after
+// its last read; the caller passes a barrier before any other use of red2.
+template <typename VA, typename VV, int T>
+__device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val, VV *x, VV *r,
+                                VV *p, VV *q, double rhs_norm2, double stop2, int maxit,
+                                double (*red2)[T / kWave], int *flag) {
     double rr = rhs_norm2;
     int it = 0;
     *flag = 0;
     while (it < maxit && rr > stop2) {
-        double pq_local;
-        if constexpr (CACHED) pq_local = regs.template spmv<VV>(S.m, p, q);
-        else pq_local = spmv_rows<VA, VV, T>(S, val, p, q);
-        const double pq = wg_sum<T>(pq_local, red);
+        const double pq = wg_sum_once<T>(spmv_rows<VA, VV, T>(S, val, p, q), red2[0]);
         ++it;
         if (!(pq > 0.0)) {
             *flag = std::isnan(pq) ? 2 : 1;
@@ -143,7 +143,7 @@ __device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val,
             r[i] = ri;
             loc += (double)ri * (double)ri;
         }
-        const double rr_new = wg_sum<T>(loc, red);
+        const double rr_new = wg_sum_once<T>(loc, red2[1]);
         if (!std::isfinite(rr_new)) {
             *flag = 2;
             break;
@@ -152,6 +152,79 @@ __device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val,
         rr = rr_new;
         for (int i = threadIdx.x; i < S.m; i += T) p[i] = (VV)((double)r[i] + beta * (double)p[i]);
         wg_sync<T>();
+    }
+    return it;
+}
+
+// The same CG when the system's rows are held in registers: a thread's own
+// entries of x, r, p and q (rows tid + j T) stay in registers too, and only p
+// goes through LDS, for the neighbours' gathers.  Per row and iteration the
+// LDS then serves the row's p gathers and one p store, against those plus
+// eight vector reads and writes with every vector in LDS.  x comes in and
+// goes out in LDS (own rows); r starts from rhs (own rows, LDS) and p = r.
+template <typename VA, typename VV, int T>
+__device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, const VV *rhs,
+                                VV *p, double rhs_norm2, double stop2, int maxit,
+                                double (*red2)[T / kWave], int *flag) {
+    constexpr int R = sys_regs<VA, T>::R, L = sys_regs<VA, T>::L;
+    VV xr[R], rr_[R], pr[R];
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = threadIdx.x + j * T;
+        xr[j] = i < m ? x[i] : VV(0);
+        rr_[j] = i < m ? rhs[i] : VV(0);
+        pr[j] = rr_[j];
+        if (i < m) p[i] = pr[j];
+    }
+    __syncthreads();
+    double rr = rhs_norm2;
+    int it = 0;
+    *flag = 0;
+    while (it < maxit && rr > stop2) {
+        VV qr[R];
+        double pq_local = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            VV s = VV(0);
+#pragma unroll
+            for (int k = 0; k < L; ++k) s += (VV)regs.v[j][k] * p[regs.c[j][k]];
+            qr[j] = s;
+            // rows >= m hold p = 0 in registers, so they add nothing
+            pq_local += (double)pr[j] * (double)s;
+        }
+        const double pq = wg_sum_once<T>(pq_local, red2[0]);
+        ++it;
+        if (!(pq > 0.0)) {
+            *flag = std::isnan(pq) ? 2 : 1;
+            break;
+        }
+        const double alpha = rr / pq;
+        double loc = 0.0;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            xr[j] = (VV)((double)xr[j] + alpha * (double)pr[j]);
+            rr_[j] = (VV)((double)rr_[j] - alpha * (double)qr[j]);
+            loc += (double)rr_[j] * (double)rr_[j];
+        }
+        const double rr_new = wg_sum_once<T>(loc, red2[1]);
+        if (!std::isfinite(rr_new)) {
+            *flag = 2;
+            break;
+        }
+        const double beta = rr_new / rr;
+        rr = rr_new;
+#pragma unroll
+        for (int j = 0; j < R; ++j) {
+            const int i = threadIdx.x + j * T;
+            pr[j] = (VV)((double)rr_[j] + beta * (double)pr[j]);
+            if (i < m) p[i] = pr[j];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        const int i = threadIdx.x + j * T;
+        if (i < m) x[i] = xr[j];
     }
     return it;
 }
@@ -165,6 +238,7 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
     int32_t *__restrict__ iters, double *__restrict__ relres, int *status) {
     extern __shared__ double lds[];
     __shared__ double red[T / kWave];
+    __shared__ double red2[2][T / kWave];
     __shared__ unsigned s_next;
     constexpr bool kRefine = sizeof(VA) == 4;  // FP32 storage: FP32 CG inside FP64 refinement
     for (;;) {
@@ -197,10 +271,10 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                 p[i] = bs[i];
             }
             wg_sync<T>();
-            its = cached ? cg_in_lds<VA, double, T, true>(S, A, regs, x64, r, p, q, bb,
-                                                          tol * tol * bb, maxit, red, &flag)
-                         : cg_in_lds<VA, double, T, false>(S, A, regs, x64, r, p, q, bb,
-                                                           tol * tol * bb, maxit, red, &flag);
+            its = cached ? cg_cached<VA, double, T>(S.m, regs, x64, r, p, bb, tol * tol * bb,
+                                                    maxit, red2, &flag)
+                         : cg_in_lds<VA, double, T>(S, A, x64, r, p, q, bb, tol * tol * bb, maxit,
+                                                    red2, &flag);
         } else {
             double *r64 = x64 + S.m;
             float *d = reinterpret_cast<float *>(r64 + S.m);
@@ -225,12 +299,10 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                     rt2 += (double)ri * (double)ri;
                 }
                 rt2 = wg_sum<T>(rt2, red);
-                its += cached ? cg_in_lds<VA, float, T, true>(S, A, regs, d, r, p, q, rt2,
-                                                              tau * tau * rt2, maxit - its, red,
-                                                              &flag)
-                              : cg_in_lds<VA, float, T, false>(S, A, regs, d, r, p, q, rt2,
-                                                               tau * tau * rt2, maxit - its, red,
-                                                               &flag);
+                its += cached ? cg_cached<VA, float, T>(S.m, regs, d, r, p, rt2, tau * tau * rt2,
+                                                        maxit - its, red2, &flag)
+                              : cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
+                                                        maxit - its, red2, &flag);
                 if (flag) break;
                 // x += |r| d, then the FP64 residual b - A x
                 for (int i = threadIdx.x; i < S.m; i += T) x64[i] = x64[i] + rn * (double)d[i];
