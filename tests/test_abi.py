@@ -59,6 +59,67 @@ def test_argument_errors_without_device(lib):
     assert lib.gko_dot(None, 0, 0, None, None, None) == 1
 
 
+def test_null_handles_rejected(lib):
+    """Every call that takes a handle rejects a null one with INVALID_ARG and a
+    message, before any device work; destroying a null handle is a no-op."""
+    d, f = ctypes.c_double, ctypes.c_float
+    calls = {
+        "gko_context_destroy": (None,),
+        "gko_context_set_stream": (None, None),
+        "gko_context_set_allocator": (None, None, None, None),
+        "gko_matrix_clone": (None, None),
+        "gko_matrix_describe": (None, None),
+        "gko_matrix_export_csr": (None, None, None, None),
+        "gko_matrix_export_storage": (None, None, None, None, None, None),
+        "gko_matrix_export_sellp": (None, None, None, None, None),
+        "gko_spmv": (None, d(1.0), None, d(0.0), None),
+        "gko_convert": (None, 0),
+        "gko_dot": (None, 0, 0, None, None, None),
+        "gko_norm2": (None, 0, 0, None, None),
+        "gko_stream": (None, 0, 0, None, None, d(1.0), None),
+        "gko_context_set_solver_opts": (None, None),
+        "gko_context_get_solver_opts": (None, None),
+        "gko_context_get_solve_info": (None, None),
+        "gko_cg_solve": (None, None, None, d(1e-10), 10),
+        "gko_fcg_solve": (None, None, None, d(1e-10), 10),
+        "gko_pipecg_solve": (None, None, None, d(1e-10), 10),
+        "gko_bicgstab_solve": (None, None, None, d(1e-10), 10),
+        "gko_cgs_solve": (None, None, None, d(1e-10), 10),
+        "gko_gmres_solve": (None, None, None, d(1e-10), 10),
+        "gko_batch_create_csr": (None, 0, None, None, None, None, None, 0, None),
+        "gko_batch_cg_solve": (None, None, None, d(1e-10), 10, None, None),
+        "gko_batch_set_block": (None, 256),
+        "gko_batch_get_block": (None, None),
+        "gko_batch_autotune": (None, None, None, d(1e-10), 10, None, None, None, None),
+        "gko_matrix_features": (None, None),
+        "gko_autotune_format": (None, None, None),
+        "gko_mlp_create": (None, None, None),
+        "gko_mlp_get_params": (None, None, None),
+        "gko_mlp_fit_normalization": (None, 0, None),
+        "gko_mlp_forward": (None, 0, None, None),
+        "gko_mlp_loss_grad": (None, 0, None, None, None, None, None),
+        "gko_mlp_train": (None, 0, None, None, None, 1, f(1e-3), None),
+        "gko_mlp_save": (None, b"/nonexistent"),
+        "gko_mlp_load": (None, b"/nonexistent", None),
+        "gko_select_format": (None, None, None, None),
+        "gko_context_set_selector": (None, None),
+    }
+    lib.gko_last_error.restype = ctypes.c_char_p
+    for name, args in calls.items():
+        st = getattr(lib, name)(*args)
+        if name == "gko_context_destroy":
+            assert st == 0, name
+            continue
+        assert st == 1, (name, st)
+        assert lib.gko_last_error(), name
+    for name in ("gko_batch_destroy", "gko_mlp_destroy", "gko_matrix_destroy"):
+        assert getattr(lib, name)(None) == 0, name
+    handled = set(calls) | {"gko_batch_destroy", "gko_mlp_destroy", "gko_matrix_destroy",
+                            "gko_context_create", "gko_matrix_create_csr", "gko_status_string",
+                            "gko_last_error"}
+    assert set(declared()) <= handled, sorted(set(declared()) - handled)
+
+
 def test_missing_library_fails_loudly(tmp_path):
     """Importing the binding from a copy without the built library raises."""
     import shutil
