@@ -86,7 +86,7 @@ def test_fcg_statuses(g, gen_mod, ctx):
 
 
 # --------------------------------------------------------------------------- CGS
-@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "hybrid", "sellp"])
+@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "ell", "hybrid", "sellp"])
 def test_cgs_convdiff_matches_oracle(g, orc, gen_mod, ctx, fmt):
     A = gen_mod.convdiff2d(40, 0.5)
     n = 1600

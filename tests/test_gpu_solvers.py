@@ -137,7 +137,9 @@ def test_bicgstab_convdiff(g, orc, gen_mod, ctx):
     xs = gen_mod.uniform(8, 1600)
     b = orc.spmv(A, xs)
     rc, xo, info_o = orc.bicgstab(A, b, tol=1e-10)
-    for fmt in ["csr", "coo", "hybrid"]:
+    # CSR, ELL, HYB without a tail and SELL-P fuse r̂·v and t·s, t·t into their
+    # SpMVs; COO and merge-path run separate dot kernels
+    for fmt in ["csr", "csr_merge", "coo", "ell", "hybrid", "sellp"]:
         M = g.Matrix.from_csr(*A).convert(fmt)
         x = dev(np.zeros(1600))
         info = g.bicgstab(M, dev(b), x, tol=1e-10)
