@@ -215,6 +215,12 @@ typedef struct gko_solver_opts {
                                  gfx950) runs as one launch on one workgroup; 0: always the
                                  multi-kernel path.  Same steps and stopping test either way. */
     int32_t krylov_dim;  /* GMRES restart length m, 1..128 (default 30) */
+    int32_t graphs;      /* 1 (default): on matrices of at most 2^20 rows, the multi-kernel
+                            CG, flexible CG, pipelined CG, BiCGSTAB and CGS loops capture one
+                            polling interval (check_every iterations of kernel launches) into
+                            a HIP graph once per solve and replay it on the context stream;
+                            0: always launch kernel by kernel.  The graph holds the same
+                            kernels with the same arguments, so results are identical. */
 } gko_solver_opts;
 
 typedef struct gko_solve_info {

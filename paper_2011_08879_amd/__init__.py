@@ -56,7 +56,8 @@ class _MatrixDesc(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", _i32), ("precond", _i32), ("block_size", _i32),
                 ("check_every", _i32), ("inner_tol", _f64), ("max_inner", _i32),
-                ("max_outer", _i32), ("single_workgroup", _i32), ("krylov_dim", _i32)]
+                ("max_outer", _i32), ("single_workgroup", _i32), ("krylov_dim", _i32),
+                ("graphs", _i32)]
 
 
 class _SolveInfo(ctypes.Structure):
@@ -209,9 +210,9 @@ class Context:
     def set_solver_opts(self, precision: int = PREC_FP64, precond: int = PRECOND_NONE,
                         block_size: int = 8, check_every: int = 16, inner_tol: float = 1e-5,
                         max_inner: int = 1000, max_outer: int = 20, single_workgroup: int = 1,
-                        krylov_dim: int = 30):
+                        krylov_dim: int = 30, graphs: int = 1):
         o = SolverOpts(precision, precond, block_size, check_every, inner_tol, max_inner, max_outer,
-                       single_workgroup, krylov_dim)
+                       single_workgroup, krylov_dim, graphs)
         _check(_lib.gko_context_set_solver_opts(self.handle, ctypes.byref(o)))
 
     def solver_opts(self) -> dict:

@@ -77,6 +77,7 @@ gko_solver_opts default_opts() {
     o.max_outer = 20;
     o.single_workgroup = 1;
     o.krylov_dim = 30;
+    o.graphs = 1;
     return o;
 }
 
@@ -787,6 +788,66 @@ bool fused_view(gko_matrix A, const values &v, fused_matrix &f) {
     return false;
 }
 
+// One polling interval of a solver loop (check_every iterations of kernel
+// launches) as a HIP graph: the first run() captures the body's launches on a
+// stream of its own, which the body sees as the context stream, and every
+// run() replays them on the context stream with one call instead of one
+// enqueue per kernel.  The body must only launch kernels: no allocation, copy,
+// memset or synchronization.  Disabled, run() calls the body directly.
+// Used for matrices of at most kGraphMaxRows rows: Poisson 3D, per iteration,
+// 32^3 rows CG 21.1 -> 17.9 us and BiCGSTAB 34.5 -> 27.4 us; 128^3 and 256^3
+// rows 0.5% slower from a graph, where the kernels hide the enqueue cost.
+constexpr int64_t kGraphMaxRows = int64_t(1) << 20;
+
+class interval_graph {
+  public:
+    interval_graph(gko_context c, int64_t n)
+        : c_(c), enabled_(c->opts.graphs != 0 && n <= kGraphMaxRows) {}
+    interval_graph(const interval_graph &) = delete;
+    interval_graph &operator=(const interval_graph &) = delete;
+    ~interval_graph() {
+        if (exec_) (void)hipGraphExecDestroy(exec_);
+        if (cap_) (void)hipStreamDestroy(cap_);
+    }
+
+    template <typename F>
+    void run(F &&body) {
+        if (!enabled_) {
+            body();
+            return;
+        }
+        if (!exec_) capture(body);
+        HIPC(hipGraphLaunch(exec_, c_->stream));
+    }
+
+  private:
+    template <typename F>
+    void capture(F &body) {
+        HIPC(hipStreamCreateWithFlags(&cap_, hipStreamNonBlocking));
+        HIPC(hipStreamBeginCapture(cap_, hipStreamCaptureModeThreadLocal));
+        const hipStream_t saved = c_->stream;
+        hipGraph_t g = nullptr;
+        c_->stream = cap_;
+        try {
+            body();
+        } catch (...) {
+            c_->stream = saved;
+            if (hipStreamEndCapture(cap_, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        c_->stream = saved;
+        HIPC(hipStreamEndCapture(cap_, &g));
+        const hipError_t e = hipGraphInstantiate(&exec_, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPC(e);
+    }
+
+    gko_context c_;
+    bool enabled_;
+    hipStream_t cap_ = nullptr;
+    hipGraphExec_t exec_ = nullptr;
+};
+
 // (P)CG on A with the value arrays `v` (FP64 or FP32), b and x of that type.
 // inv: block-Jacobi inverse of type v.t (bs > 0) or null.
 solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, double tol, int32_t maxit,
@@ -803,6 +864,7 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
     void *zz = bs > 0 ? z.p : r.p;
     fused_matrix fm;
     const bool fused = fused_view(A, v, fm);
+    interval_graph graph(c, n);
     solve_result res;
     krylov_scalars h{};
     for (;;) {
@@ -812,17 +874,22 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
                      ticket.as<unsigned>()));
         h = read_back(c, S);
         while (h.done == kRunning) {
-            for (int j = 0; j < check_every; ++j) {
-                if (fused) {
-                    HIPC(cg_spmv(s, fm, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
-                } else {
-                    spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
-                    HIPC(cg_pq(s, v.t, n, p.p, q.p, S, partials.as<double>(), ticket.as<unsigned>()));
+            graph.run([&] {
+                const hipStream_t st = c->stream;
+                for (int j = 0; j < check_every; ++j) {
+                    if (fused) {
+                        HIPC(cg_spmv(st, fm, p.p, q.p, S, partials.as<double>(),
+                                     ticket.as<unsigned>()));
+                    } else {
+                        spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
+                        HIPC(cg_pq(st, v.t, n, p.p, q.p, S, partials.as<double>(),
+                                   ticket.as<unsigned>()));
+                    }
+                    HIPC(cg_update(st, v.t, n, x, r.p, zz, p.p, q.p, inv, bs, S,
+                                   partials.as<double>(), ticket.as<unsigned>(), flexible));
+                    HIPC(cg_direction(st, v.t, n, zz, p.p, S));
                 }
-                HIPC(cg_update(s, v.t, n, x, r.p, zz, p.p, q.p, inv, bs, S, partials.as<double>(),
-                               ticket.as<unsigned>(), flexible));
-                HIPC(cg_direction(s, v.t, n, zz, p.p, S));
-            }
+            });
             h = read_back(c, S);
         }
         res.flag = h.done;
@@ -873,6 +940,7 @@ solve_result pipecg_core(gko_matrix A, const values &v, const void *b, void *x, 
     pv.u = bs > 0 ? u.p : r.p;
     pv.m = bs > 0 ? m.p : w.p;
     pv.q = bs > 0 ? q.p : sv.p;
+    interval_graph graph(c, n);
     solve_result res;
     krylov_scalars h{};
     for (;;) {
@@ -886,11 +954,13 @@ solve_result pipecg_core(gko_matrix A, const values &v, const void *b, void *x, 
                        ticket.as<unsigned>()));
         h = read_back(c, S);
         while (h.done == kRunning) {
-            for (int j = 0; j < check_every; ++j) {
-                spmv_dispatch(A, v, 1.0, pv.m, 0.0, nn.p);
-                HIPC(pipe_update(s, v.t, n, pv, inv, bs, S, partials.as<double>(),
-                                 ticket.as<unsigned>()));
-            }
+            graph.run([&] {
+                for (int j = 0; j < check_every; ++j) {
+                    spmv_dispatch(A, v, 1.0, pv.m, 0.0, nn.p);
+                    HIPC(pipe_update(c->stream, v.t, n, pv, inv, bs, S, partials.as<double>(),
+                                     ticket.as<unsigned>()));
+                }
+            });
             h = read_back(c, S);
         }
         res.flag = h.done;
@@ -1956,6 +2026,7 @@ gko_status gko_context_set_solver_opts(gko_context ctx, const gko_solver_opts *o
                 "krylov_dim must be in 1.." + std::to_string(kGmresMaxKrylov));
         require(o->single_workgroup == 0 || o->single_workgroup == 1, GKO_ERR_INVALID_ARG,
                 "single_workgroup must be 0 or 1");
+        require(o->graphs == 0 || o->graphs == 1, GKO_ERR_INVALID_ARG, "graphs must be 0 or 1");
         ctx->opts = *o;
     });
 }
@@ -2139,24 +2210,28 @@ gko_status gko_bicgstab_solve(gko_matrix A, const void *b, void *x, double tol, 
         fused_matrix fm;
         const bool fused = fused_view(A, v, fm);
         krylov_scalars h = read_back(c, S);
+        interval_graph graph(c, n);
         while (h.done == kRunning) {
-            for (int j = 0; j < c->opts.check_every; ++j) {
-                HIPC(bicg_p(s, n, r.p, vv.p, p.p, S));
-                if (fused) {
-                    HIPC(bicg_spmv_alpha(s, fm, p.p, vv.p, rh.p, S, P, T));
-                } else {
-                    spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
-                    HIPC(bicg_alpha(s, n, rh.p, vv.p, S, P, T));
+            graph.run([&] {
+                const hipStream_t st = c->stream;
+                for (int j = 0; j < c->opts.check_every; ++j) {
+                    HIPC(bicg_p(st, n, r.p, vv.p, p.p, S));
+                    if (fused) {
+                        HIPC(bicg_spmv_alpha(st, fm, p.p, vv.p, rh.p, S, P, T));
+                    } else {
+                        spmv_dispatch(A, v, 1.0, p.p, 0.0, vv.p);
+                        HIPC(bicg_alpha(st, n, rh.p, vv.p, S, P, T));
+                    }
+                    HIPC(bicg_s(st, n, r.p, vv.p, sv.p, S, P, T));
+                    if (fused) {
+                        HIPC(bicg_spmv_omega(st, fm, sv.p, t.p, S, P, T));
+                    } else {
+                        spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
+                        HIPC(bicg_omega(st, n, t.p, sv.p, S, P, T));
+                    }
+                    HIPC(bicg_update(st, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
                 }
-                HIPC(bicg_s(s, n, r.p, vv.p, sv.p, S, P, T));
-                if (fused) {
-                    HIPC(bicg_spmv_omega(s, fm, sv.p, t.p, S, P, T));
-                } else {
-                    spmv_dispatch(A, v, 1.0, sv.p, 0.0, t.p);
-                    HIPC(bicg_omega(s, n, t.p, sv.p, S, P, T));
-                }
-                HIPC(bicg_update(s, n, x, r.p, rh.p, p.p, sv.p, t.p, S, P, T));
-            }
+            });
             h = read_back(c, S);
         }
         c->info.iterations = h.iter;
@@ -2182,19 +2257,23 @@ gko_status gko_cgs_solve(gko_matrix A, const void *b, void *x, double tol, int32
         fused_matrix fm;
         const bool fused = fused_view(A, v, fm);
         krylov_scalars h = read_back(c, S);
+        interval_graph graph(c, n);
         while (h.done == kRunning) {
-            for (int j = 0; j < c->opts.check_every; ++j) {
-                if (fused) {
-                    HIPC(cgs_spmv_alpha(s, fm, p.p, t.p, rh.p, S, P, T));
-                } else {
-                    spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
-                    HIPC(cgs_alpha(s, n, t.p, rh.p, S, P, T));
+            graph.run([&] {
+                const hipStream_t st = c->stream;
+                for (int j = 0; j < c->opts.check_every; ++j) {
+                    if (fused) {
+                        HIPC(cgs_spmv_alpha(st, fm, p.p, t.p, rh.p, S, P, T));
+                    } else {
+                        spmv_dispatch(A, v, 1.0, p.p, 0.0, t.p);
+                        HIPC(cgs_alpha(st, n, t.p, rh.p, S, P, T));
+                    }
+                    HIPC(cgs_qwx(st, n, u.p, t.p, q.p, w.p, x, S));
+                    spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
+                    HIPC(cgs_update(st, n, r.p, t.p, rh.p, S, P, T));
+                    HIPC(cgs_direction(st, n, r.p, q.p, u.p, p.p, S));
                 }
-                HIPC(cgs_qwx(s, n, u.p, t.p, q.p, w.p, x, S));
-                spmv_dispatch(A, v, 1.0, w.p, 0.0, t.p);
-                HIPC(cgs_update(s, n, r.p, t.p, rh.p, S, P, T));
-                HIPC(cgs_direction(s, n, r.p, q.p, u.p, p.p, S));
-            }
+            });
             h = read_back(c, S);
         }
         c->info.iterations = h.iter;

@@ -337,3 +337,69 @@ def test_solver_argument_checks(g, gen_mod, ctx, solver):
         with pytest.raises(g.GkoError) as e:
             fn(M, dev(np.ones(64)), dev(np.zeros(64)), tol=tol, raise_on_failure=True)
         assert e.value.status == g.ERR_INVALID_ARG
+
+
+# ----------------------------------------------------------------- HIP graphs
+def _solve_pair(g, ctx, solver, M, b, n, **opts):
+    """The same solve with the polling interval replayed from a HIP graph and
+    launched kernel by kernel: x and the iteration count."""
+    out = []
+    for graphs in (1, 0):
+        ctx.set_solver_opts(graphs=graphs, single_workgroup=0, **opts)
+        x = dev(np.zeros(n))
+        info = getattr(g, solver)(M, dev(b), x, tol=1e-10, maxit=5000)
+        out.append((host(x), info))
+    return out
+
+
+@pytest.mark.parametrize("fmt", ["csr", "csr_merge", "coo", "ell", "hybrid", "sellp"])
+@pytest.mark.parametrize("solver", ["cg", "fcg", "pipecg"])
+def test_graph_replay_matches_eager_spd(g, orc, gen_mod, ctx, solver, fmt):
+    """CG, flexible and pipelined CG: the graph holds the eager path's kernels
+    with the same arguments, so every replay (one per polling interval, with
+    the host's convergence poll between them) gives the same bits."""
+    A = gen_mod.laplace2d(100)
+    n = 10000
+    b = orc.spmv(A, gen_mod.uniform(21, n))
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    (xg, ig), (xe, ie) = _solve_pair(g, ctx, solver, M, b, n, check_every=7)
+    assert ig["status"] == g.OK and ie["status"] == g.OK
+    assert ig["iterations"] == ie["iterations"] and ig["iterations"] > 7 * 10
+    assert np.array_equal(xg, xe)
+    assert relres(orc, A, b, xg) <= 1e-10
+
+
+@pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
+def test_graph_replay_matches_eager_pcg(g, orc, gen_mod, ctx, mixed):
+    A = gen_mod.laplace3d(24)
+    n = 24 ** 3
+    b = orc.spmv(A, gen_mod.uniform(22, n))
+    M = g.Matrix.from_csr(*A).convert("sellp")
+    (xg, ig), (xe, ie) = _solve_pair(
+        g, ctx, "cg", M, b, n, precond=g.PRECOND_BLOCK_JACOBI, block_size=8,
+        precision=g.PREC_MIXED_IR if mixed else g.PREC_FP64)
+    assert ig["status"] == g.OK and ie["status"] == g.OK
+    assert ig["iterations"] == ie["iterations"]
+    assert ig["outer_iterations"] == ie["outer_iterations"]
+    assert np.array_equal(xg, xe)
+
+
+@pytest.mark.parametrize("fmt", ["csr", "coo", "ell", "sellp"])
+@pytest.mark.parametrize("solver", ["bicgstab", "cgs"])
+def test_graph_replay_matches_eager_nonsymmetric(g, orc, gen_mod, ctx, solver, fmt):
+    A = gen_mod.convdiff2d(100, 0.5)
+    n = 10000
+    b = orc.spmv(A, gen_mod.uniform(23, n))
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    (xg, ig), (xe, ie) = _solve_pair(g, ctx, solver, M, b, n)
+    assert ig["status"] == g.OK and ie["status"] == g.OK
+    assert ig["iterations"] == ie["iterations"]
+    assert np.array_equal(xg, xe)
+    assert relres(orc, A, b, xg) <= 1e-9
+
+
+def test_graphs_option_validated(g, ctx):
+    with pytest.raises(g.GkoError) as e:
+        ctx.set_solver_opts(graphs=2)
+    assert e.value.status == g.ERR_INVALID_ARG
+    assert ctx.solver_opts()["graphs"] == 1
