@@ -179,7 +179,10 @@ __global__ __launch_bounds__(kG) void gmres_update_dot_kernel(int64_t n, int k,
             if (l < n) w[l] = acc[r];
             ww += acc[r] * acc[r];
         }
-        for (int i = 0; i < k; ++i) {
+        // newest vectors first: they were read last, so the most of them are
+        // still in the caches (each V_i . w is formed on its own, so the
+        // order changes no result)
+        for (int i = k - 1; i >= 0; --i) {
             const double *vi = V + (int64_t)i * ldv;
             double sd = 0.0;
 #pragma unroll
