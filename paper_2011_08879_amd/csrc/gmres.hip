@@ -204,6 +204,55 @@ __global__ __launch_bounds__(kG) void gmres_update_dot_kernel(int64_t n, int k,
     }
 }
 
+// The same for k <= kGRegVecs with one row per thread per chunk: the
+// thread's element of every V_i stays in registers between the update and
+// the dots, so V is read once (the loops are unrolled to kGRegVecs so the
+// register array is indexed statically).
+constexpr int kGRegVecs = 32;
+
+__global__ __launch_bounds__(kG) void gmres_update_dot_regs_kernel(int64_t n, int k,
+                                                                   const double *__restrict__ V,
+                                                                   int64_t ldv,
+                                                                   const double *__restrict__ h,
+                                                                   double *__restrict__ w,
+                                                                   const gmres_state *st,
+                                                                   double *__restrict__ partials) {
+    __shared__ double part[kGRegVecs + 1][kGWaves];
+    __shared__ double hs[kGRegVecs];
+    if (!gate(st, 0)) return;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    for (int e = threadIdx.x; e < (k + 1) * kGWaves; e += kG) part[e / kGWaves][e % kGWaves] = 0.0;
+    for (int i = threadIdx.x; i < k; i += kG) hs[i] = h[i];
+    __syncthreads();
+    for (int64_t base = (int64_t)blockIdx.x * kG; base < n; base += (int64_t)gridDim.x * kG) {
+        const int64_t l = base + threadIdx.x;
+        const bool ok = l < n;
+        double vr[kGRegVecs];
+        double acc = ok ? w[l] : 0.0;
+#pragma unroll
+        for (int i = 0; i < kGRegVecs; ++i) {
+            vr[i] = (i < k && ok) ? V[(int64_t)i * ldv + l] : 0.0;
+            acc = acc - (i < k ? hs[i] : 0.0) * vr[i];
+        }
+        if (ok) w[l] = acc;
+#pragma unroll
+        for (int i = 0; i < kGRegVecs; ++i) {
+            if (i < k) {  // uniform
+                const double sd = wave_total(vr[i] * acc);
+                if (lane == 0) part[i][wv] += sd;
+            }
+        }
+        const double ww = wave_total(acc * acc);
+        if (lane == 0) part[k][wv] += ww;
+    }
+    __syncthreads();
+    for (int v = threadIdx.x; v <= k; v += kG) {
+        double sum = 0.0;
+        for (int q = 0; q < kGWaves; ++q) sum += part[v][q];
+        partials[(int64_t)v * gridDim.x + blockIdx.x] = sum;
+    }
+}
+
 // out[v] <- sum over blocks of partials[v * g + b], block order, one
 // workgroup per value
 __global__ __launch_bounds__(kG) void gmres_sum_kernel(int g, const double *__restrict__ partials,
@@ -354,7 +403,10 @@ hipError_t gmres_arnoldi_step(hipStream_t s, int64_t n, int m, int j, double *V,
     // first Gram-Schmidt round; its update also forms the second round's dots
     gmres_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, w, st, 0, wk.partials);
     gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot1, st, 0);
-    gmres_update_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, wk.partials);
+    if (k <= kGRegVecs)
+        gmres_update_dot_regs_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, wk.partials);
+    else
+        gmres_update_dot_kernel<<<g, kG, 0, s>>>(n, k, V, ldv, wk.dot1, w, st, wk.partials);
     gmres_sum_kernel<<<k + 1, kG, 0, s>>>(g, wk.partials, wk.dot2, st, 0);
     gmres_check_kernel<<<1, 1, 0, s>>>(j, wk.dot1, wk.dot2, st, wk.hcol);
     // the second round's update, only when the first lost too much of w
