@@ -29,6 +29,8 @@ static int fused_blocks(int64_t n) {
     return g < 1 ? 1 : (int)g;
 }
 
+int stream_blocks(int64_t n) { return fused_blocks(n); }
+
 int reduction_blocks(int64_t n) {
     int64_t g = (n + kB - 1) / kB;
     if (g > kMaxReductionBlocks) g = kMaxReductionBlocks;
@@ -657,7 +659,7 @@ hipError_t cg_update(hipStream_t s, vt t, int64_t n, void *x, void *r, void *z, 
 
 hipError_t cg_direction(hipStream_t s, vt t, int64_t n, const void *z, void *p,
                         const krylov_scalars *sc) {
-    const int g = reduction_blocks(n);
+    const int g = stream_blocks(n);
     if (t == vt::f64)
         cg_direction_kernel<double><<<g, kB, 0, s>>>(n, static_cast<const double *>(z),
                                                      static_cast<double *>(p), sc);
@@ -1024,7 +1026,7 @@ hipError_t bicg_init(hipStream_t st, int64_t n, const void *b, const void *r, vo
 
 hipError_t bicg_p(hipStream_t st, int64_t n, const void *r, const void *v, void *p,
                   const krylov_scalars *sc) {
-    bicg_p_kernel<<<reduction_blocks(n), kB, 0, st>>>(n, cd(r), cd(v), md(p), sc);
+    bicg_p_kernel<<<stream_blocks(n), kB, 0, st>>>(n, cd(r), cd(v), md(p), sc);
     return hipGetLastError();
 }
 

@@ -161,7 +161,7 @@ hipError_t cgs_alpha(hipStream_t s, int64_t n, const void *t, const void *rh, kr
 
 hipError_t cgs_qwx(hipStream_t s, int64_t n, const void *u, const void *t, void *q, void *w,
                    void *x, const krylov_scalars *sc) {
-    cgs_qwx_kernel<<<reduction_blocks(n), kB, 0, s>>>(
+    cgs_qwx_kernel<<<stream_blocks(n), kB, 0, s>>>(
         n, static_cast<const double *>(u), static_cast<const double *>(t), static_cast<double *>(q),
         static_cast<double *>(w), static_cast<double *>(x), sc);
     return hipGetLastError();
@@ -178,7 +178,7 @@ hipError_t cgs_update(hipStream_t s, int64_t n, void *r, const void *t, const vo
 
 hipError_t cgs_direction(hipStream_t s, int64_t n, const void *r, const void *q, void *u, void *p,
                          const krylov_scalars *sc) {
-    cgs_direction_kernel<<<reduction_blocks(n), kB, 0, s>>>(
+    cgs_direction_kernel<<<stream_blocks(n), kB, 0, s>>>(
         n, static_cast<const double *>(r), static_cast<const double *>(q), static_cast<double *>(u),
         static_cast<double *>(p), sc);
     return hipGetLastError();
