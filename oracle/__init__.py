@@ -84,8 +84,12 @@ def _load():
     lib.orc_fcg.argtypes = lib.orc_cg.argtypes
     lib.orc_pipecg.argtypes = lib.orc_cg.argtypes
     lib.orc_bicgstab.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, _f64p]
-    lib.orc_ir_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, f64, i32, vp,
-                              i32, _f64p]
+    lib.orc_ir_cg.argtypes = [i64, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32, f64, i32, i32,
+                              vp, i32, _f64p, _i32p]
+    lib.orc_pcg_f32.argtypes = [i64, _i32p, _i32p, _f32p, _f32p, _f32p, f64, i32, vp, i32,
+                                ctypes.POINTER(i32)]
+    lib.orc_pcg_f32.restype = i32
+    lib.orc_bj_apply_f32.argtypes = [i64, i32, _f32p, _f32p, _f32p]
     lib.orc_batch_cg.argtypes = [i64, _i64p, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32,
                                  _i32p, _f64p]
     lib.orc_batch_ir_cg.argtypes = [i64, _i64p, _i64p, _i32p, _i32p, _f64p, _f64p, _f64p, f64, i32,
@@ -341,17 +345,51 @@ def gmres(A, b, x0=None, tol: float = 1e-10, maxit: int = 10000, m: int = 30):
 
 
 def ir_cg(A, b, x0=None, tol: float = 1e-10, max_outer: int = 20, inner_tol: float = 1e-5,
-          max_inner: int = 1000, bj_inv=None, bs: int = 8):
-    """FP64 iterative refinement around an FP32 inner PCG."""
+          max_inner: int = 1000, bj_inv=None, bs: int = 8, maxit: int = 2 ** 31 - 1):
+    """FP64 iterative refinement around an FP32 inner PCG.
+
+    info = {inner_iters (total), outer_iters, true_relres, inner_per_outer (list)}.
+    maxit caps the inner iterations summed over the outer steps."""
     rp, col, val = _csr(A)
     n = rp.shape[0] - 1
     x = np.zeros(n) if x0 is None else _f64(x0).copy()
     out = np.zeros(3)
+    counts = np.zeros(max(max_outer, 1), np.int32)
     inv = None if bj_inv is None else _f64(np.asarray(bj_inv).reshape(-1))
     rc = _load().orc_ir_cg(n, rp, col, val, _f64(b), x, tol, max_outer, inner_tol, max_inner,
-                           None if inv is None else inv.ctypes.data, bs, out)
-    return rc, x, {"inner_iters": int(out[0]), "outer_iters": int(out[1]),
-                   "true_relres": out[2]}
+                           maxit, None if inv is None else inv.ctypes.data, bs, out, counts)
+    outer = int(out[1])
+    # an outer step whose inner solve broke down is counted in inner but not in outer
+    steps = outer + (1 if rc in (NOT_SPD, BREAKDOWN) else 0)
+    return rc, x, {"inner_iters": int(out[0]), "outer_iters": outer,
+                   "true_relres": out[2], "inner_per_outer": [int(c) for c in counts[:steps]]}
+
+
+def pcg_f32(A32, rhs, tol: float, maxit: int = 1000, inv32=None, bs: int = 8):
+    """The inner FP32 PCG of ir_cg on its own, from d = 0.
+
+    A32 = (row_ptr, col, float32 values); rhs and inv32 (nblocks*bs*bs, row-major
+    blocks) float32.  Returns (status, d float32, iterations)."""
+    rp = np.ascontiguousarray(A32[0], np.int32)
+    col = np.ascontiguousarray(A32[1], np.int32)
+    v32 = np.ascontiguousarray(A32[2], np.float32)
+    rhs = np.ascontiguousarray(rhs, np.float32)
+    n = rp.shape[0] - 1
+    d = np.zeros(n, np.float32)
+    inv = None if inv32 is None else np.ascontiguousarray(np.asarray(inv32).reshape(-1), np.float32)
+    st = ctypes.c_int32(0)
+    it = _load().orc_pcg_f32(n, rp, col, v32, rhs, d, tol, maxit,
+                             None if inv is None else inv.ctypes.data, bs, ctypes.byref(st))
+    return int(st.value), d, int(it)
+
+
+def bj_apply_f32(inv32, r32, bs: int = 8):
+    """z = D^-1 r blockwise in FP32 arithmetic (the inner solve's preconditioner)."""
+    inv = np.ascontiguousarray(np.asarray(inv32).reshape(-1), np.float32)
+    r = np.ascontiguousarray(r32, np.float32)
+    z = np.empty_like(r)
+    _load().orc_bj_apply_f32(r.shape[0], bs, inv, r, z)
+    return z
 
 
 def batch_cg(row_off, nnz_off, rp_local, col, val, b, tol: float = 1e-10, maxit: int = 10000):

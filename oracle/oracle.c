@@ -864,9 +864,12 @@ done:
  * missing (with a factor 2 of margin), but never less than inner_tol:
  *   tau_k = max(inner_tol, 0.5 tol ||b|| / ||r_k||).
  * Outer stop: converged, max_outer, or a residual that did not halve
- * (stagnation, -> not converged).
+ * (stagnation, -> not converged).  maxit caps the inner iterations summed
+ * over all outer steps: step k may run at most min(max_inner, maxit - done)
+ * of them, and a solve whose budget is spent stops as not converged.
  * out[0] = total inner iterations, out[1] = outer iterations,
- * out[2] = final true relres.
+ * out[2] = final true relres.  inner_counts (may be NULL; room for
+ * max_outer entries) receives the inner iterations of each outer step.
  * ====================================================================== */
 static void spmv_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *v,
                      const float *x, float *y) {
@@ -883,7 +886,7 @@ static double dot_f32(int64_t n, const float *x, const float *y) {
     return s;
 }
 
-static void bj_apply_f32(int64_t n, int32_t bs, const float *inv, const float *r, float *z) {
+void orc_bj_apply_f32(int64_t n, int32_t bs, const float *inv, const float *r, float *z) {
     int64_t nb = (n + bs - 1) / bs;
     for (int64_t b = 0; b < nb; ++b) {
         int64_t r0 = b * bs;
@@ -907,7 +910,7 @@ static int32_t pcg_f32(int64_t n, const int32_t *rp, const int32_t *ci, const fl
     int32_t it = 0;
     *status = ORC_OK;
     if (rn0 == 0.0) return 0;
-    if (inv32) bj_apply_f32(n, bs, inv32, r, z); else memcpy(z, r, sizeof(float) * n);
+    if (inv32) orc_bj_apply_f32(n, bs, inv32, r, z); else memcpy(z, r, sizeof(float) * n);
     memcpy(p, z, sizeof(float) * n);
     double rho = dot_f32(n, r, z);
     while (it < maxit) {
@@ -921,7 +924,7 @@ static int32_t pcg_f32(int64_t n, const int32_t *rp, const int32_t *ci, const fl
         double rn = sqrt(dot_f32(n, r, r));
         if (isnan(rn)) { *status = ORC_BREAKDOWN; return it; }
         if (rn <= tol * rn0) return it;
-        if (inv32) bj_apply_f32(n, bs, inv32, r, z); else memcpy(z, r, sizeof(float) * n);
+        if (inv32) orc_bj_apply_f32(n, bs, inv32, r, z); else memcpy(z, r, sizeof(float) * n);
         double rho_new = dot_f32(n, r, z);
         double beta = rho_new / rho;
         rho = rho_new;
@@ -931,10 +934,25 @@ static int32_t pcg_f32(int64_t n, const int32_t *rp, const int32_t *ci, const fl
     return it;
 }
 
+/* The inner solve on its own: FP32 PCG on A32 d = rhs from d = 0 to
+ * ||r|| <= tol ||rhs|| or maxit iterations (inv32 may be NULL: no
+ * preconditioner).  Returns the iterations done; *status as pcg_f32. */
+int32_t orc_pcg_f32(int64_t n, const int32_t *rp, const int32_t *ci, const float *v32,
+                    const float *rhs, float *d, double tol, int32_t maxit,
+                    const float *inv32, int32_t bs, int32_t *status) {
+    float *w = (float *)malloc(sizeof(float) * (size_t)(4 * n + 4));
+    int st = ORC_OK;
+    int32_t it = pcg_f32(n, rp, ci, v32, rhs, d, tol, maxit, inv32, bs, w, w + n, w + 2 * n,
+                         w + 3 * n, &st);
+    free(w);
+    *status = st;
+    return it;
+}
+
 int orc_ir_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
               const double *b, double *x, double tol, int32_t max_outer,
-              double inner_tol, int32_t max_inner, const double *bj_inv, int32_t bs,
-              double *out) {
+              double inner_tol, int32_t max_inner, int32_t maxit, const double *bj_inv,
+              int32_t bs, double *out, int32_t *inner_counts) {
     float *v32 = (float *)malloc(sizeof(float) * (size_t)rp[n]);
     float *inv32 = NULL;
     float *rt = (float *)malloc(sizeof(float) * n), *d = (float *)malloc(sizeof(float) * n);
@@ -962,14 +980,20 @@ int orc_ir_cg(int64_t n, const int32_t *rp, const int32_t *ci, const double *v,
         rnorm = orc_norm2(n, r);
         if (isnan(rnorm)) { rc = ORC_BREAKDOWN; break; }
         if (rnorm <= tol * bnorm) { rc = ORC_OK; break; }
-        if (outer >= max_outer || !(rnorm <= 0.5 * prev)) { rc = ORC_NOT_CONVERGED; break; }
+        if (outer >= max_outer || !(rnorm <= 0.5 * prev) || inner_total >= maxit) {
+            rc = ORC_NOT_CONVERGED;
+            break;
+        }
         prev = rnorm;
         for (int64_t i = 0; i < n; ++i) rt[i] = (float)(r[i] / rnorm);
         double tau = 0.5 * (tol * bnorm / rnorm);
         if (tau < inner_tol) tau = inner_tol;
+        int32_t cap = max_inner;
+        if (maxit - inner_total < cap) cap = (int32_t)(maxit - inner_total);
         int st;
-        inner_total += pcg_f32(n, rp, ci, v32, rt, d, tau, max_inner, inv32, bs,
-                               w1, w2, w3, w4, &st);
+        int32_t done_k = pcg_f32(n, rp, ci, v32, rt, d, tau, cap, inv32, bs, w1, w2, w3, w4, &st);
+        inner_total += done_k;
+        if (inner_counts) inner_counts[outer] = done_k;
         if (st == ORC_NOT_SPD || st == ORC_BREAKDOWN) { rc = st; break; }
         for (int64_t i = 0; i < n; ++i) x[i] = x[i] + rnorm * (double)d[i];
         ++outer;
@@ -1029,7 +1053,7 @@ int orc_batch_ir_cg(int64_t nsys, const int64_t *row_off, const int64_t *nnz_off
         double out[3];
         for (int64_t i = 0; i < m; ++i) x[row_off[s] + i] = 0.0;
         int rc = orc_ir_cg(m, rp, ci + nnz_off[s], v + nnz_off[s], b + row_off[s], x + row_off[s],
-                           tol, 20, 1e-5, max_inner, NULL, 0, out);
+                           tol, 20, 1e-5, max_inner, 20 * max_inner, NULL, 0, out, NULL);
         iters[s] = (int32_t)out[0];
         relres[s] = out[2];
         if (rc != ORC_OK && worst == ORC_OK) worst = rc;

@@ -46,7 +46,10 @@ int orc_cgs(int64_t, const int32_t *, const int32_t *, const double *, const dou
 int orc_gmres(int64_t, const int32_t *, const int32_t *, const double *, const double *, double *,
               double, int32_t, int32_t, double *);
 int orc_ir_cg(int64_t, const int32_t *, const int32_t *, const double *, const double *, double *,
-              double, int32_t, double, int32_t, const double *, int32_t, double *);
+              double, int32_t, double, int32_t, int32_t, const double *, int32_t, double *,
+              int32_t *);
+int32_t orc_pcg_f32(int64_t, const int32_t *, const int32_t *, const float *, const float *,
+                    float *, double, int32_t, const float *, int32_t, int32_t *);
 int orc_batch_cg(int64_t, const int64_t *, const int64_t *, const int32_t *, const int32_t *,
                  const double *, const double *, double *, double, int32_t, int32_t *, double *);
 int orc_batch_ir_cg(int64_t, const int64_t *, const int64_t *, const int32_t *, const int32_t *,
@@ -193,7 +196,19 @@ static void solvers(void) {
     memset(x, 0, sizeof x);
     CHECK(orc_fcg(N, rp, ci, v, b, x, 1e-10, 500, inv, 8, out) == 0);
     memset(x, 0, sizeof x);
-    CHECK(orc_ir_cg(N, rp, ci, v, b, x, 1e-10, 20, 1e-5, 1000, inv, 8, out) == 0);
+    {
+        int32_t counts[20];
+        float d32[N], b32[N], v32[5 * N];
+        int32_t st;
+        /* a budget of 3 inner iterations in total runs out before 1e-10 */
+        CHECK(orc_ir_cg(N, rp, ci, v, b, x, 1e-10, 20, 1e-5, 1000, 3, inv, 8, out, counts) == 6);
+        CHECK(out[0] <= 3);
+        for (int i = 0; i < N; ++i) b32[i] = (float)b[i];
+        for (int k = 0; k < rp[N]; ++k) v32[k] = (float)v[k];
+        CHECK(orc_pcg_f32(N, rp, ci, v32, b32, d32, 1e-5, 500, NULL, 8, &st) > 0 && st == 0);
+        memset(x, 0, sizeof x);
+        CHECK(orc_ir_cg(N, rp, ci, v, b, x, 1e-10, 20, 1e-5, 1000, 20000, inv, 8, out, counts) == 0);
+    }
     for (int i = 0; i < N; ++i) CHECK(fabs(x[i] - xs[i]) < 1e-6);
 
     /* nonsymmetric */

@@ -234,6 +234,152 @@ def test_ir_cg_stagnation_reported(orc, gen_mod):
     assert rc == orc.NOT_CONVERGED
 
 
+def _scaled_blocks_spd(n, bs, seed):
+    """An SPD matrix whose bs x bs diagonal blocks differ in scale by up to 1e4,
+    each coupled weakly to the next block: block-Jacobi
+    removes the scale spread, so with the preconditioner PCG needs a handful of
+    steps and without it many more."""
+    rng = np.random.default_rng(seed)
+    D = np.zeros((n, n))
+    for b0 in range(0, n, bs):
+        m = min(bs, n - b0)
+        G = rng.standard_normal((m, m))
+        s = 10.0 ** rng.uniform(0, 4)
+        D[b0:b0 + m, b0:b0 + m] = s * (G @ G.T / m + np.eye(m))
+    for i in range(n - 1):
+        if (i + 1) % bs == 0:            # couple neighbouring blocks, keep SPD
+            c = 0.1 * math.sqrt(D[i, i] * D[i + 1, i + 1])
+            D[i, i + 1] = D[i + 1, i] = -c
+    return D
+
+
+def _f32_data(A):
+    """The FP32-rounded matrix: (row_ptr, col, float32 values) and the same
+    values widened back to FP64, so the FP64 oracle runs on the data the FP32
+    solve sees."""
+    rp, col, val = A
+    v32 = np.asarray(val, np.float64).astype(np.float32)
+    return (rp, col, v32), (rp, col, v32.astype(np.float64))
+
+
+def test_bj_apply_f32_is_the_rounded_blockwise_product(orc):
+    """The FP32 preconditioner apply against numpy's dense block products of
+    the same FP32 data in FP64: each entry within the FP32 rounding bound
+    (bs + 1) u |D^-1| |r|; nonsymmetric blocks and a short last block, so a
+    transposed block or a dropped entry fails."""
+    rng = np.random.default_rng(11)
+    bs, n = 8, 8 * 7 + 3
+    nb = (n + bs - 1) // bs
+    inv = np.zeros((nb, bs, bs), np.float32)
+    for k in range(nb):
+        m = min(bs, n - k * bs)
+        inv[k, :m, :m] = rng.uniform(-1, 1, (m, m))
+    r = rng.uniform(-1, 1, n).astype(np.float32)
+    z = orc.bj_apply_f32(inv, r, bs)
+    ref, bound = np.zeros(n), np.zeros(n)
+    for k in range(nb):
+        m = min(bs, n - k * bs)
+        blk = inv[k, :m, :m].astype(np.float64)
+        rb = r[k * bs:k * bs + m].astype(np.float64)
+        ref[k * bs:k * bs + m] = blk @ rb
+        bound[k * bs:k * bs + m] = np.abs(blk) @ np.abs(rb)
+    u = 2.0 ** -24
+    assert np.all(np.abs(z.astype(np.float64) - ref) <= (bs + 1) * u * bound)
+    assert not np.allclose(inv[0], inv[0].T)
+
+
+def test_pcg_f32_iterates_follow_fp64_pcg(orc):
+    """The inner FP32 PCG takes the pinned FP64 PCG's steps: after k = 1..6
+    iterations on the same FP32-rounded matrix, right-hand side and FP32
+    block inverses, its iterate equals the FP64 one to FP32 accuracy.  A wrong
+    beta fails from k = 2 on, a dropped or misapplied preconditioner from k = 1."""
+    n, bs = 96, 8
+    D = _scaled_blocks_spd(n, bs, 3)
+    A32, A64 = _f32_data(dense_to_csr(D))
+    rc, inv = orc.bj_invert(A64, bs)
+    assert rc == orc.OK
+    inv32 = inv.astype(np.float32)
+    rhs = np.random.default_rng(4).uniform(-1, 1, n).astype(np.float32)
+    for k in range(1, 7):
+        st, d, it = orc.pcg_f32(A32, rhs, tol=1e-30, maxit=k, inv32=inv32, bs=bs)
+        assert it == k and st == orc.NOT_CONVERGED
+        rc, xk, info = orc.cg(A64, rhs.astype(np.float64), tol=1e-30, maxit=k,
+                              bj_inv=inv32.astype(np.float64), bs=bs)
+        assert info["iters"] == k
+        err = np.linalg.norm(d - xk) / np.linalg.norm(xk)
+        assert err <= 1e-4, (k, err)
+    # without the preconditioner the first step already points elsewhere
+    st, d1, _ = orc.pcg_f32(A32, rhs, tol=1e-30, maxit=1, inv32=None, bs=bs)
+    rc, x1, _ = orc.cg(A64, rhs.astype(np.float64), tol=1e-30, maxit=1,
+                       bj_inv=inv32.astype(np.float64), bs=bs)
+    assert np.linalg.norm(d1 - x1) / np.linalg.norm(x1) > 1e-2
+
+
+def test_pcg_f32_iteration_count_and_solution(orc):
+    """To tau = 1e-5 the FP32 PCG stops within 2 iterations of the FP64 PCG on
+    the same data, its solution meets the manufactured one within kappa times
+    the requested reduction, and block-Jacobi is what makes it converge fast
+    (without it the count is several times larger)."""
+    n, bs = 200, 8
+    D = _scaled_blocks_spd(n, bs, 5)
+    A32, A64 = _f32_data(dense_to_csr(D))
+    rc, inv = orc.bj_invert(A64, bs)
+    inv32 = inv.astype(np.float32)
+    xs = np.random.default_rng(6).uniform(-1, 1, n)
+    rhs = orc.spmv(A64, xs).astype(np.float32)
+    tau = 1e-5
+    st, d, it = orc.pcg_f32(A32, rhs, tol=tau, maxit=1000, inv32=inv32, bs=bs)
+    assert st == orc.OK
+    rc, x64, info = orc.cg(A64, rhs.astype(np.float64), tol=tau, maxit=1000,
+                           bj_inv=inv32.astype(np.float64), bs=bs)
+    assert abs(it - info["iters"]) <= 2, (it, info)
+    # the FP64 system that the FP32 data define, solved densely
+    Ad = np.zeros((n, n))
+    for i in range(n):
+        Ad[i, A64[1][A64[0][i]:A64[0][i + 1]]] = A64[2][A64[0][i]:A64[0][i + 1]]
+    xe = np.linalg.solve(Ad, rhs.astype(np.float64))
+    kappa = np.linalg.cond(Ad)
+    assert np.linalg.norm(d - xe) / np.linalg.norm(xe) <= kappa * 2 * tau
+    st, d0, it0 = orc.pcg_f32(A32, rhs, tol=tau, maxit=5000, inv32=None, bs=bs)
+    assert it0 >= 3 * it, (it0, it)
+
+
+def test_ir_cg_first_inner_solve_is_fp64_pcg_to_inner_tol(orc, gen_mod):
+    """The first refinement step solves A32 d = fp32(b / ||b||) from d = 0 to
+    tau_0 = max(inner_tol, tol / 2): its inner count is the FP64 PCG's on that
+    data within 2, for the block-scaled matrix and the 3D Laplacian."""
+    cases = []
+    D = _scaled_blocks_spd(160, 8, 7)
+    cases.append(dense_to_csr(D))
+    cases.append(gen_mod.laplace3d(12))
+    for A in cases:
+        n = A[0].shape[0] - 1
+        xs = gen_mod.uniform(5, n)
+        b = orc.spmv(A, xs)
+        rc, inv = orc.bj_invert(A, 8)
+        rc, x, info = orc.ir_cg(A, b, tol=1e-10, inner_tol=1e-5, bj_inv=inv)
+        assert rc == orc.OK and len(info["inner_per_outer"]) == info["outer_iters"]
+        assert sum(info["inner_per_outer"]) == info["inner_iters"]
+        A32, A64 = _f32_data(A)
+        rt = (b / np.linalg.norm(b)).astype(np.float32)
+        rc, _, ref = orc.cg(A64, rt.astype(np.float64), tol=1e-5, maxit=1000,
+                            bj_inv=inv.astype(np.float32).astype(np.float64), bs=8)
+        assert abs(info["inner_per_outer"][0] - ref["iters"]) <= 2, (info, ref)
+
+
+def test_ir_cg_total_budget(orc, gen_mod):
+    """maxit caps the inner iterations summed over the outer steps."""
+    A = gen_mod.laplace3d(12)
+    b = orc.spmv(A, gen_mod.uniform(5, 12 ** 3))
+    rc, inv = orc.bj_invert(A, 8)
+    rc, x, full = orc.ir_cg(A, b, tol=1e-10, bj_inv=inv)
+    assert rc == orc.OK
+    cap = full["inner_iters"] - 3
+    rc, x, info = orc.ir_cg(A, b, tol=1e-10, bj_inv=inv, maxit=cap)
+    assert rc == orc.NOT_CONVERGED and info["inner_iters"] == cap
+    assert info["inner_per_outer"][:-1] == full["inner_per_outer"][:len(info["inner_per_outer"]) - 1]
+
+
 # --------------------------------------------------------------------------- batched
 def test_batch_cg_closed_form_bounds(orc, gen_mod):
     B = gen_mod.batch_systems(40, master_seed=6)
