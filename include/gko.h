@@ -61,15 +61,15 @@ typedef enum gko_itype { GKO_I32 = 0, GKO_I64 = 1 } gko_itype;
  *              ties to the smaller K.
  *  AUTO      : (gko_convert only) the context's selector model if one is set
  *              (gko_context_set_selector), else the fastest by timing of the
- *              five formats above.
+ *              six formats CSR, CSR_MERGE, COO, ELL, HYBRID and SELLP.
  *  SELLP     : sliced ELL with padding (Anzt, Tomov and Dongarra 2014), not
  *              sorted, stride factor 1: slices of 64 consecutive rows, slice s
  *              padded to its own longest row w_s and column-major inside the
  *              slice.  Entry j of row i = 64 s + r is slot sets[s] + 64 j + r,
  *              sets[0] = 0, sets[s+1] = sets[s] + 64 w_s; padding (and rows
- *              >= n_rows of the last slice) is col = -1, val = +0.0.  Not a
- *              choice of AUTO or the selector, whose model scores the five
- *              formats of Sec. 6.1. */
+ *              >= n_rows of the last slice) is col = -1, val = +0.0.  AUTO
+ *              and the selector score it beside the five formats of Sec. 6.1
+ *              (six classes). */
 typedef enum gko_format {
     GKO_FMT_CSR = 0,
     GKO_FMT_CSR_MERGE = 1,
@@ -205,7 +205,7 @@ typedef enum gko_precond { GKO_PRECOND_NONE = 0, GKO_PRECOND_BLOCK_JACOBI = 1 } 
 typedef struct gko_solver_opts {
     int32_t precision;   /* gko_precision; MIXED_IR = FP64 refinement around an FP32 inner PCG */
     int32_t precond;     /* gko_precond */
-    int32_t block_size;  /* block-Jacobi block size, 1..32 (default 8) */
+    int32_t block_size;  /* block-Jacobi block size: 1, 2, 4, 8 or 16 (default 8) */
     int32_t check_every; /* host convergence polls every this many iterations (default 16) */
     double inner_tol;    /* MIXED_IR: inner relative tolerance (default 1e-5) */
     int32_t max_inner;   /* MIXED_IR: inner iteration cap per outer step (default 1000) */
@@ -246,8 +246,10 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out);
  * n_rows; x is the initial guess on entry and the solution on return.  Stops
  * when ||r||_2 <= tol ||b||_2; the true residual is then recomputed and the
  * iteration restarted from x if it misses tol (at most twice).  ||b|| = 0
- * gives x = 0.  tol > 0 and finite, maxit >= 0.  Synchronous.  Returns
- * GKO_OK, GKO_ERR_NOT_CONVERGED, GKO_ERR_NOT_SPD or GKO_ERR_BREAKDOWN. */
+ * gives x = 0.  tol > 0 and finite, maxit >= 0; with MIXED_IR precision
+ * maxit caps the inner iterations summed over all refinement steps.  b and x
+ * must not overlap (GKO_ERR_INVALID_ARG).  Synchronous.  Returns GKO_OK,
+ * GKO_ERR_NOT_CONVERGED, GKO_ERR_NOT_SPD or GKO_ERR_BREAKDOWN. */
 gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
 /* Flexible CG (Notay 2000, one previous direction kept conjugate): CG with
@@ -326,7 +328,8 @@ gko_status gko_batch_destroy(gko_batch B);
  * time with its vectors in LDS, so no host round trip happens until all are
  * done.  FP64 batches run FP64 CG; FP32 batches run FP32 CG iterations inside
  * FP64 iterative refinement (residual, norms and update in FP64).
- *   b, x            : FP64 device arrays of row_off[nsys] entries (x is output).
+ *   b, x            : FP64 device arrays of row_off[nsys] entries (x is output);
+ *                     they must not overlap (GKO_ERR_INVALID_ARG).
  *   tol             : per-system stop ||b_i - A_i x_i||_2 <= tol ||b_i||_2.
  *   maxit           : iteration cap per system (inner iterations for FP32).
  *   iters_out       : device int32[nsys], iterations used.

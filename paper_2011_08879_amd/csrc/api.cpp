@@ -1000,8 +1000,10 @@ struct mixed_result {
     double true_relres = 0.0;
 };
 
-mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gko_solver_opts &o,
-                      int bs, double bnorm, cg_variant var) {
+// maxit caps the inner iterations summed over the outer steps, as in the
+// FP64 solvers (Sec. 6.2 solvers; mixed-precision reading of the cap)
+mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, int32_t maxit,
+                      const gko_solver_opts &o, int bs, double bnorm, cg_variant var) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     const int64_t n = A->n;
@@ -1018,7 +1020,7 @@ mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gk
         res.true_relres = rn / bnorm;
         if (std::isnan(rn)) { res.status = GKO_ERR_BREAKDOWN; break; }
         if (rn <= tol * bnorm) { res.status = GKO_OK; break; }
-        if (res.outer >= o.max_outer || !(rn <= 0.5 * prev)) {
+        if (res.outer >= o.max_outer || !(rn <= 0.5 * prev) || res.inner >= maxit) {
             res.status = GKO_ERR_NOT_CONVERGED;
             break;
         }
@@ -1028,7 +1030,8 @@ mixed_result mixed_ir(gko_matrix A, const void *b, void *x, double tol, const gk
         // ask the inner solve only for the reduction still missing (factor 2
         // of margin), never for less than inner_tol
         const double tau = std::max(o.inner_tol, 0.5 * (tol * bnorm / rn));
-        solve_result in = cg_variant_core(var, A, v32, rt.p, d.p, tau, o.max_inner,
+        const int32_t cap = std::min(o.max_inner, maxit - res.inner);
+        solve_result in = cg_variant_core(var, A, v32, rt.p, d.p, tau, cap,
                                           bs > 0 ? (const void *)A->bj32 : nullptr, bs,
                                           o.check_every, false);
         res.inner += in.iters;
@@ -1048,15 +1051,19 @@ void check_square_f64(gko_matrix A) {
     require(A->dt == GKO_F64, GKO_ERR_UNSUPPORTED, "solvers take FP64 matrices (mixed precision makes its own FP32 copy)");
 }
 
-void check_solve_args(const void *b, void *x, double tol, int32_t maxit) {
-    require(b && x, GKO_ERR_INVALID_ARG, "null b or x");
-    require(tol > 0.0 && std::isfinite(tol), GKO_ERR_INVALID_ARG, "tol must be positive and finite");
-    require(maxit >= 0, GKO_ERR_INVALID_ARG, "maxit must be >= 0");
-}
-
 bool overlap(const void *a, size_t na, const void *b, size_t nb) {
     const char *pa = static_cast<const char *>(a), *pb = static_cast<const char *>(b);
     return pa < pb + nb && pb < pa + na;
+}
+
+// b is re-read after x has changed (true residual, restarts, refinement
+// steps), so the two must not share memory.
+void check_solve_args(const void *b, void *x, int64_t n, double tol, int32_t maxit) {
+    require(b && x, GKO_ERR_INVALID_ARG, "null b or x");
+    require(!overlap(b, size_t(n) * 8, x, size_t(n) * 8), GKO_ERR_INVALID_ARG,
+            "b and x overlap");
+    require(tol > 0.0 && std::isfinite(tol), GKO_ERR_INVALID_ARG, "tol must be positive and finite");
+    require(maxit >= 0, GKO_ERR_INVALID_ARG, "maxit must be >= 0");
 }
 
 }  // namespace
@@ -1135,6 +1142,8 @@ void check_batch_solve_args(gko_batch B, const double *b, double *x, double tol,
                             int32_t *iters, double *relres) {
     require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
     require(B->nsys == 0 || (b && x && iters && relres), GKO_ERR_INVALID_ARG, "null array");
+    require(B->nsys == 0 || !overlap(b, size_t(B->rows) * 8, x, size_t(B->rows) * 8),
+            GKO_ERR_INVALID_ARG, "b and x overlap");
     require(tol > 0.0 && std::isfinite(tol), GKO_ERR_INVALID_ARG, "tol must be positive and finite");
     require(maxit >= 0, GKO_ERR_INVALID_ARG, "maxit must be >= 0");
 }
@@ -2052,7 +2061,7 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
     gko_status st = GKO_OK;
     gko_status call = guarded([&] {
         check_square_f64(A);
-        check_solve_args(b, x, tol, maxit);
+        check_solve_args(b, x, A->n, tol, maxit);
         gko_context c = A->ctx;
         const double t0 = now_seconds();
         c->info = gko_solve_info{};
@@ -2101,7 +2110,7 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
                 c->info.setup_seconds = now_seconds() - ts;
             }
             if (o.precision == GKO_PREC_MIXED_IR) {
-                mixed_result r = mixed_ir(A, b, x, tol, o, bs, bnorm, var);
+                mixed_result r = mixed_ir(A, b, x, tol, maxit, o, bs, bnorm, var);
                 st = r.status;
                 c->info.iterations = r.inner;
                 c->info.outer_iterations = r.outer;
@@ -2158,7 +2167,7 @@ static gko_status nonsym_solve(const char *name, gko_matrix A, const void *b, vo
     gko_status st = GKO_OK;
     gko_status call = guarded([&] {
         check_square_f64(A);
-        check_solve_args(b, x, tol, maxit);
+        check_solve_args(b, x, A->n, tol, maxit);
         gko_context c = A->ctx;
         hipStream_t s = c->stream;
         const double t0 = now_seconds();

@@ -127,9 +127,47 @@ def test_mixed_ir_reaches_fp64_residual(g, orc, gen_mod, ctx):
     kappa = (6 + 6 * math.cos(math.pi / (N + 1))) / (6 - 6 * math.cos(math.pi / (N + 1)))
     assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * 1e-10
     assert np.linalg.norm(xg - x64) / np.linalg.norm(x64) <= 2 * kappa * 1e-10
-    # the oracle's mixed solve takes a comparable number of steps
+    # the oracle's mixed solve takes a comparable number of steps, outer and
+    # inner: the same recurrences in FP32, so each inner solve's stop test may
+    # trip a step or two apart
     rc, xo, info_o = orc.ir_cg(A, b, tol=1e-10, inner_tol=1e-5, bj_inv=inv)
     assert abs(info["outer_iterations"] - info_o["outer_iters"]) <= 1
+    slack = 2 * max(info["outer_iterations"], info_o["outer_iters"]) + 2
+    assert abs(info["iterations"] - info_o["inner_iters"]) <= slack, (info, info_o)
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+
+
+def test_mixed_ir_maxit_caps_inner_total(g, orc, gen_mod, ctx):
+    """With mixed precision, maxit bounds the inner iterations summed over
+    the refinement steps, for every CG variant; the oracle stops on the same
+    budget."""
+    N = 24
+    A = gen_mod.laplace3d(N)
+    n = N ** 3
+    b = orc.spmv(A, gen_mod.uniform(5, n))
+    rc, inv = orc.bj_invert(A, 8)
+    ctx.set_solver_opts(precision=g.PREC_MIXED_IR, precond=g.PRECOND_BLOCK_JACOBI, block_size=8,
+                        inner_tol=1e-5)
+    M = g.Matrix.from_csr(*A)
+    rc, xo, info_o = orc.ir_cg(A, b, tol=1e-10, inner_tol=1e-5, bj_inv=inv, maxit=30)
+    assert rc == orc.NOT_CONVERGED and info_o["inner_iters"] == 30
+    for solve in (g.cg, g.fcg, g.pipecg):
+        for maxit in (0, 1, 30):
+            info = solve(M, dev(b), dev(np.zeros(n)), tol=1e-10, maxit=maxit)
+            assert info["status"] == g.ERR_NOT_CONVERGED, (solve.__name__, maxit, info)
+            assert info["iterations"] <= maxit, (solve.__name__, maxit, info)
+        assert info["iterations"] == 30
+
+
+def test_solvers_reject_overlapping_b_and_x(g, gen_mod, ctx):
+    """b is re-read after x changes, so every solver refuses aliased b and x."""
+    A = g.Matrix.from_csr(*gen_mod.laplace2d(16))
+    buf = dev(np.ones(512))
+    for solve in (g.cg, g.fcg, g.pipecg, g.bicgstab, g.cgs, g.gmres):
+        assert solve(A, buf, buf)["status"] == g.ERR_INVALID_ARG, solve.__name__
+        assert solve(A, buf[:256], buf[100:356])["status"] == g.ERR_INVALID_ARG
+        info = solve(A, buf[:256], buf[256:], tol=1e-8)
+        assert info["status"] == g.OK, (solve.__name__, info)
 
 
 def test_bicgstab_convdiff(g, orc, gen_mod, ctx):
