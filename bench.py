@@ -20,7 +20,15 @@ CSR entry and 16 per COO entry.
 
 After the timed sweep (outside it): CG on the 2D 5-point Laplacian 64x64
 (to 1e-10), and block-Jacobi PCG on the 3D 7-point Poisson 256^3 in FP64 and
-in mixed precision (FP32 inner solve, FP64 refinement), each to 1e-10.
+in mixed precision (FP32 inner solve, FP64 refinement), each to 1e-10, the
+10,000-system batched CG and the learned format selector.
+
+The CPU baseline is the oracle, one host core per run: the sweep's SpMVs, the
+solves of both CG workloads, the per-system batch loop and the selector's
+features.  The two Poisson 256^3 oracle solves (minutes of serial work) run
+in child processes started before the GPU is touched, on other host cores
+while the GPU legs run; their solutions also give each GPU solve's error
+against the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -28,7 +36,9 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
+import tempfile
 import time
 
 import numpy as np
@@ -75,8 +85,9 @@ def kernel_source_hash():
 
 def measured_traffic(key):
     """HBM bytes per launch of one sweep SpMV from the committed rocprofv3 counter
-    summary (FETCH_SIZE x fetch_scale + WRITE_SIZE x write_scale, both scaled by a
-    1 GiB copy of known size), or None when the kernels changed since."""
+    summary (32 x the L2's DRAM-bound 32-byte read and write request counts, which
+    reproduce a 1 GiB copy without a scale factor), or None when the kernels
+    changed since."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -122,6 +133,72 @@ def build_sweep(g, gen, torch):
     except g.GkoError as e:
         assert e.status == g.ERR_UNSUPPORTED
     return mats, skipped, inputs, base
+
+
+def host_info():
+    """The host CPU the oracle ran on: model name and core counts."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "cpus_available": len(os.sched_getaffinity(0))}
+
+
+def cpu_solver_baselines(keep, gpu_solvers, selector_lat, n_feature_matrices=12):
+    """The oracle, serial, on the solver, batch and selector workloads: config-1
+    CG seconds and iterations, the per-system batch loop in FP64 and FP32
+    (refined) storage, and the selector's 32 features per corpus matrix."""
+    import gen
+    import oracle
+    out = {}
+    if "cg_laplace2d_64" in keep:
+        A, b = keep["cg_laplace2d_64"]
+        best = None
+        for _ in range(5):
+            t0 = time.perf_counter()
+            rc, x, info = oracle.cg(A, b, tol=1e-10)
+            el = time.perf_counter() - t0
+            best = el if best is None else min(best, el)
+        out["cg_laplace2d_64"] = {"seconds": round(best, 6), "iterations": info["iters"],
+                                  "true_rel_residual": float(info["true_relres"])}
+        if gpu_solvers:
+            out["cg_laplace2d_64"]["gpu_seconds"] = gpu_solvers["cg_laplace2d_64"]["seconds"]
+    if "batch" in keep:
+        Bk = keep["batch"]
+        B = Bk["B"]
+        res = {}
+        for label, fn, vals in (("fp64", oracle.batch_cg, B.val),
+                                ("fp32", oracle.batch_ir_cg,
+                                 B.val.astype(np.float32).astype(np.float64))):
+            t0 = time.perf_counter()
+            rc, x, it, rr = fn(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, Bk[label], tol=1e-10)
+            el = time.perf_counter() - t0
+            res[label] = {"seconds": round(el, 4), "solves_per_s": round(B.nsys / el, 1),
+                          "iters_mean": round(float(it.mean()), 1),
+                          "max_true_rel_residual": float(rr.max())}
+            if gpu_solvers:
+                res[label]["gpu_solves_per_s"] = gpu_solvers["batch_cg_10k"][label]["solves_per_s"]
+        out["batch_cg_10k"] = res
+    if selector_lat is not None:
+        secs, rows = [], []
+        for i in range(n_feature_matrices):
+            A = gen.corpus_matrix(gen.corpus_spec(i))
+            t0 = time.perf_counter()
+            oracle.features(A)
+            secs.append(time.perf_counter() - t0)
+            rows.append(len(A[0]) - 1)
+        out["selector_features"] = {"matrices": n_feature_matrices,
+                                    "seconds_per_matrix": round(float(np.mean(secs)), 5),
+                                    "mean_rows": int(np.mean(rows)),
+                                    "gpu_seconds_per_matrix_corpus":
+                                        round(selector_lat["features_s_mean"], 5)}
+    return out
 
 
 def cpu_baseline(inputs, step_alg_bytes, budget_s=15.0):
@@ -183,7 +260,110 @@ def stream_probe(g, torch, n=1 << 27, reps=10):
     return out
 
 
-def run_solvers(g, gen, torch):
+def poisson256_inputs(gen):
+    """Config-3 inputs: the 3D 7-point Poisson matrix on 256^3, x* ~ U[-1,1]
+    (seed 5), b = A x* by scipy (neither the oracle nor the library)."""
+    import scipy.sparse as sp
+    A = gen.laplace3d(256)
+    n = 256 ** 3
+    S = sp.csr_matrix((A[2], A[1], A[0]), shape=(n, n))
+    xs = gen.uniform(5, n)
+    return A, S, xs, S @ xs
+
+
+def kappa_laplace3d(N):
+    """Condition number of the 3D 7-point Dirichlet Laplacian on N^3."""
+    c = math.cos(math.pi / (N + 1))
+    return (6 + 6 * c) / (6 - 6 * c)
+
+
+def oracle_poisson_worker(outdir, mode):
+    """Child process: the oracle's FP64 block-Jacobi PCG ("fp64") or its
+    mixed-precision refinement ("mixed") on the config-3 system, serial.
+    Writes <mode>.json (timings, counts) and <mode>_x.npy.  Never touches
+    the GPU."""
+    import hashlib
+
+    import gen
+    import oracle
+    if not os.path.exists(oracle._LIB):
+        raise SystemExit("oracle library missing")
+    A, S, xs, bh = poisson256_inputs(gen)
+    del S
+    t0 = time.perf_counter()
+    rc, inv = oracle.bj_invert(A, 8)
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    if mode == "fp64":
+        rc, x, info = oracle.cg(A, bh, tol=1e-10, maxit=20000, bj_inv=inv)
+        it = {"iterations": info["iters"], "restarts": info["restarts"]}
+        relres = info["true_relres"]
+    else:
+        rc, x, info = oracle.ir_cg(A, bh, tol=1e-10, inner_tol=1e-5, bj_inv=inv)
+        it = {"iterations": info["inner_iters"], "outer_iterations": info["outer_iters"]}
+        relres = info["true_relres"]
+    el = time.perf_counter() - t0
+    np.save(os.path.join(outdir, mode + "_x.npy"), x)
+    res = dict(it, status=int(rc), seconds=round(el, 3), setup_seconds=round(setup, 3),
+               seconds_per_iteration=round(el / max(it["iterations"], 1), 5),
+               true_rel_residual=float(relres),
+               b_sha256=hashlib.sha256(np.ascontiguousarray(bh).tobytes()).hexdigest())
+    with open(os.path.join(outdir, mode + ".json"), "w") as fh:
+        json.dump(res, fh)
+
+
+def start_oracle_workers():
+    """Start both config-3 oracle solves as child processes (before this
+    process initialises the GPU)."""
+    outdir = tempfile.mkdtemp(prefix="gko_oracle_")
+    procs = {}
+    for mode in ("fp64", "mixed"):
+        procs[mode] = subprocess.Popen(
+            [sys.executable, os.path.abspath(__file__), "--oracle-poisson-worker", mode,
+             "--worker-dir", outdir], stdout=subprocess.DEVNULL,
+            stderr=open(os.path.join(outdir, mode + ".err"), "w"))
+    return {"dir": outdir, "procs": procs, "t0": time.time()}
+
+
+def finish_oracle_workers(w, gpu, deadline_s):
+    """Wait (up to deadline_s after the start) for the oracle solves; report
+    their timings and each GPU solution's error against the FP64 oracle's."""
+    out = {}
+    for mode, p in w["procs"].items():
+        try:
+            p.wait(timeout=max(1.0, deadline_s - (time.time() - w["t0"])))
+        except subprocess.TimeoutExpired:
+            p.kill()
+            p.wait()
+            out[mode] = {"unfinished": "killed after %.0f s" % (time.time() - w["t0"])}
+            continue
+        path = os.path.join(w["dir"], mode + ".json")
+        if p.returncode != 0 or not os.path.exists(path):
+            with open(os.path.join(w["dir"], mode + ".err")) as fh:
+                out[mode] = {"failed": "rc %d: %s" % (p.returncode, fh.read()[-300:])}
+            continue
+        with open(path) as fh:
+            out[mode] = json.load(fh)
+    errs = {}
+    if "seconds" in out.get("fp64", {}) and gpu is not None:
+        xo = np.load(os.path.join(w["dir"], "fp64_x.npy"))
+        same_b = out["fp64"].pop("b_sha256") == gpu["b_sha256"]
+        no = np.linalg.norm(xo)
+        for label in ("fp64", "mixed"):
+            errs["gpu_" + label] = float(np.linalg.norm(gpu[label] - xo) / no)
+        if "seconds" in out.get("mixed", {}):
+            xm = np.load(os.path.join(w["dir"], "mixed_x.npy"))
+            errs["oracle_mixed"] = float(np.linalg.norm(xm - xo) / no)
+            out["mixed"].pop("b_sha256", None)
+        errs["same_b"] = same_b
+        errs["bound_2kappa_tol"] = 2 * kappa_laplace3d(256) * 1e-10
+    for f in os.listdir(w["dir"]):
+        os.remove(os.path.join(w["dir"], f))
+    os.rmdir(w["dir"])
+    return out, errs
+
+
+def run_solvers(g, gen, torch, keep):
     import scipy.sparse as sp
     out = {}
     ctx = g.default_context()
@@ -216,13 +396,11 @@ def run_solvers(g, gen, torch):
     ctx.set_solver_opts()
     res1["seconds"] = min(res1["single_workgroup"]["seconds"], res1["multi_kernel"]["seconds"])
     out["cg_laplace2d_64"] = res1
+    keep["cg_laplace2d_64"] = (A, S @ xs)
     # config 3: 3D 7-point Poisson 256^3, block-Jacobi(8), FP64 PCG vs mixed IR
     t0 = time.time()
-    A = gen.laplace3d(256)
+    A, S, xs, bh = poisson256_inputs(gen)
     n = 256 ** 3
-    S = sp.csr_matrix((A[2], A[1], A[0]), shape=(n, n))
-    xs = gen.uniform(5, n)
-    bh = S @ xs
     log("poisson 256^3 ready (%.1fs)" % (time.time() - t0))
     b = torch.from_numpy(bh).cuda()
     M = g.Matrix.from_csr(*A)
@@ -257,12 +435,15 @@ def run_solvers(g, gen, torch):
     res["krylov_fixed_iterations"] = run_krylov(g, torch, ctx, M, b, n)
     x64, xmx = res.pop("fp64_x"), res.pop("mixed_x")
     res["mixed"]["rel_diff_vs_fp64_solution"] = float(np.linalg.norm(xmx - x64) / np.linalg.norm(x64))
+    import hashlib
+    keep["poisson256"] = {"fp64": x64, "mixed": xmx,
+                          "b_sha256": hashlib.sha256(np.ascontiguousarray(bh).tobytes()).hexdigest()}
     res["speedup_mixed_over_fp64"] = round(res["fp64"]["seconds"] / res["mixed"]["seconds"], 3)
     out["pcg_bj8_poisson3d_256"] = res
     ctx.set_solver_opts()
     del M, b, S
     torch.cuda.empty_cache()
-    out["batch_cg_10k"] = run_batch(g, gen, torch)
+    out["batch_cg_10k"] = run_batch(g, gen, torch, keep)
     return out
 
 
@@ -363,10 +544,13 @@ def cg_vs_pipecg(g, torch, ctx):
     return res
 
 
-def run_batch(g, gen, torch, nsys=10000, reps=3):
+def run_batch(g, gen, torch, keep, nsys=10000, reps=3):
     """10,000 SPD systems (3-/5-point, 32..1024 rows, shift U[0.1, 2]) to 1e-10 each,
     one persistent launch per solve; FP64 and FP32 storage (FP32 CG inside FP64
-    refinement).  The workgroup size is autotuned first."""
+    refinement).  The workgroup size is autotuned first.  A secondary line
+    runs the FP32 batch to 1e-5, which FP32 iterations reach on their own: the
+    kernel's first inner solve then meets the tolerance and its FP64 residual
+    check ends the solve without a refinement step."""
     import scipy.sparse as sp
     B = gen.batch_systems(nsys, master_seed=6)
     # b = A x* from a block-diagonal assembly of all systems (scipy, not the library)
@@ -375,19 +559,23 @@ def run_batch(g, gen, torch, nsys=10000, reps=3):
     sys_of_entry = np.repeat(np.arange(nsys), np.diff(B.nnz_off))
     cols = B.col.astype(np.int64) + B.row_off[:-1][sys_of_entry]
     out = {"nsys": nsys, "rows": int(B.row_off[-1]), "nnz": int(B.nnz_off[-1])}
-    for label, vals, tdt in (("fp64", B.val, torch.float64),
-                             ("fp32", B.val.astype(np.float32), torch.float32)):
+    keep["batch"] = {"B": B}
+    for label, vals, tdt, tol in (("fp64", B.val, torch.float64, 1e-10),
+                                  ("fp32", B.val.astype(np.float32), torch.float32, 1e-10),
+                                  ("fp32_only_tol1e-5", B.val.astype(np.float32), torch.float32,
+                                   1e-5)):
         S = sp.csr_matrix((vals.astype(np.float64), (rows, cols)), shape=(out["rows"], out["rows"]))
         bh = S @ B.xstar
+        keep["batch"][label] = bh
         b = torch.from_numpy(bh).cuda()
         G = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, dtype=tdt)
         x = torch.zeros(out["rows"], dtype=torch.float64, device="cuda")
-        blk, times = G.autotune(b, x, tol=1e-10, maxit=1000)
+        blk, times = G.autotune(b, x, tol=tol, maxit=1000)
         best = None
         for _ in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            st, it, rr = G.solve(b, x, tol=1e-10, maxit=1000)
+            st, it, rr = G.solve(b, x, tol=tol, maxit=1000)
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
             best = el if best is None else min(best, el)
@@ -398,7 +586,7 @@ def run_batch(g, gen, torch, nsys=10000, reps=3):
         vs = 8 if label == "fp64" else 4
         floor_bytes = ((out["rows"] + nsys) * 4 + out["nnz"] * (4 + vs) + 2 * (nsys + 1) * 8
                        + 3 * out["rows"] * 8)
-        out[label] = {"solves_per_s": round(nsys / best, 1), "seconds": round(best, 5),
+        out[label] = {"solves_per_s": round(nsys / best, 1), "seconds": round(best, 5), "tol": tol,
                       "hbm_floor_bytes": int(floor_bytes),
                       "hbm_floor_seconds": round(floor_bytes / (HBM_PEAK_GBS * 1e9), 7),
                       "block": blk, "autotune_ms": {str(k): round(v, 3) for k, v in times.items()},
@@ -518,6 +706,37 @@ def run_sweep(args, g, gen, torch, result):
     torch.cuda.empty_cache()
 
     return result, inputs
+
+
+def profile_sweep(args, g, gen, torch):
+    """Launch sequence for rocprofv3 runs: every sweep SpMV (and SELL-P on the
+    stencil) `reps` times in a group of its own, each group opened by a small
+    library COPY of 512 (k+1) doubles (grid 256 (k+1) threads) that marks
+    group k, and a 1 GiB COPY last (group "copy_1GiB") as the counters'
+    calibration transfer.  Returns the group names in order."""
+    mats, skipped, inputs, base = build_sweep(g, gen, torch)
+    st = base["stencil27_128"].clone().convert("sellp")
+    d = st.describe()
+    mats.append({"matrix": "stencil27_128", "format": "sellp", "M": st,
+                 "x": mats[0]["x"], "y": torch.empty(d.n_rows, dtype=torch.float64, device="cuda"),
+                 "desc": d, "bytes": spmv_bytes(d)})
+    sep_src = torch.zeros(512 * (len(mats) + 2), dtype=torch.float64, device="cuda")
+    sep_dst = torch.empty_like(sep_src)
+    groups = []
+    for k, e in enumerate(mats):
+        g.stream(g.STREAM_COPY, sep_src[:512 * (k + 1)], sep_dst)
+        for _ in range(args.steps):
+            g.spmv(e["M"], 1.0, e["x"], 0.0, e["y"])
+        groups.append({"name": "%s/%s" % (e["matrix"], e["format"]), "launches": args.steps,
+                       "alg_bytes": int(e["bytes"])})
+    g.stream(g.STREAM_COPY, sep_src[:512 * (len(mats) + 1)], sep_dst)
+    nel = (1 << 30) // 8
+    src = torch.ones(nel, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    g.stream(g.STREAM_COPY, src, dst)
+    groups.append({"name": "copy_1GiB", "launches": 1, "alg_bytes": 2 * nel * 8})
+    torch.cuda.synchronize()
+    return groups
 
 
 def cache_protocol(g, torch, mats, reps=20, warmup=5, scratch_mib=1024):
@@ -643,28 +862,52 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-solvers", action="store_true", help="skip the solver measurements")
-    ap.add_argument("--selector-matrices", type=int, default=400,
+    ap.add_argument("--selector-matrices", type=int, default=2000,
                     help="corpus size of the learned-selector leg (0 skips it)")
+    ap.add_argument("--profile-sweep", default="",
+                    help="only launch the sweep SpMVs in marked groups (--steps launches "
+                         "each) for rocprofv3, and write the group list to this JSON file")
+    ap.add_argument("--oracle-poisson-worker", choices=("fp64", "mixed"), default=None,
+                    help=argparse.SUPPRESS)
+    ap.add_argument("--worker-dir", default="", help=argparse.SUPPRESS)
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the SpMV sweep (profiling the solvers alone)")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="after the sweep, copy this many MiB device-to-device (a transfer of "
                          "known size for scaling hardware byte counters)")
     args = ap.parse_args()
+    if args.oracle_poisson_worker:
+        oracle_poisson_worker(args.worker_dir, args.oracle_poisson_worker)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
-    import torch
-
     import gen
-    import paper_2011_08879_amd as g
-
     if not os.path.exists(gen._LIB):
         gen.build()
+    # the config-3 oracle solves start first, before anything touches the GPU
+    workers = None
+    if not args.no_cpu and not args.no_solvers and not args.profile_sweep:
+        import oracle
+        if not os.path.exists(oracle._LIB):
+            oracle.build()
+        workers = start_oracle_workers()
+
+    import torch
+
+    import paper_2011_08879_amd as g
+
     torch.cuda.set_device(0)
     g.default_context()
+    if args.profile_sweep:
+        groups = profile_sweep(args, g, gen, torch)
+        with open(args.profile_sweep, "w") as fh:
+            json.dump({"groups": groups, "marker": "stream_copy_kernel",
+                       "source_sha256": kernel_source_hash()}, fh, indent=1)
+        log("profile groups written: %d" % len(groups))
+        return
     result = {"metric": METRIC, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
               "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
               "dtype": "f64", "data": "synthetic"}
@@ -672,22 +915,48 @@ def main():
     if not args.no_sweep:
         result, inputs = run_sweep(args, g, gen, torch, result)
 
+    keep = {}
     if not args.no_solvers:
-        result["solvers"] = run_solvers(g, gen, torch)
+        result["solvers"] = run_solvers(g, gen, torch, keep)
+    poisson = None
+    if workers is not None:
+        # the oracle solves finish before the selector leg loads the host cores
+        log("waiting for the oracle's Poisson 256^3 solves ...")
+        poisson, errs = finish_oracle_workers(workers, keep.get("poisson256"), deadline_s=420.0)
+        keep.pop("poisson256", None)
+        pc = result["solvers"]["pcg_bj8_poisson3d_256"]
+        for label in ("fp64", "mixed"):
+            if "gpu_" + label in errs:
+                pc[label]["rel_error_vs_oracle_fp64"] = errs["gpu_" + label]
+        pc["oracle_check"] = errs
+        log("poisson oracle: %s; errors vs oracle FP64 x: %s" %
+            ({k: v.get("seconds", v) for k, v in poisson.items()}, errs))
+    sel_lat = None
     if args.selector_matrices > 0:
         import paper_2011_08879_amd.selector as sel
         t0 = time.time()
         res, model = sel.run(n_matrices=args.selector_matrices, n_lo=1e4, n_hi=1e6, steps=3000,
-                             lr=3e-3, workers=8, log=log)
+                             lr=3e-3, workers=8, log=log, retimed=True, five_class=True)
         res["wall_s"] = round(time.time() - t0, 1)
         result["selector"] = res
+        sel_lat = res["latency"]
         log("selector (%d matrices): test regret %.3f (CSR alone %.3f), gain vs CSR %.3f" %
             (args.selector_matrices, res["test"]["regret_total"], res["test"]["csr_regret_total"],
              res["test"]["gain_vs_csr_total"]))
         model.close()
     if not args.no_cpu and inputs is not None:
         log("cpu baseline (oracle, 1 core) ...")
-        result["cpu_baseline"] = cpu_baseline(inputs, result["config"]["step_alg_bytes"])
+        cb = cpu_baseline(inputs, result["config"]["step_alg_bytes"])
+        cb["host"] = host_info()
+        cb.update(cpu_solver_baselines(keep, result.get("solvers"), sel_lat))
+        if poisson is not None:
+            cb["pcg_bj8_poisson3d_256"] = dict(
+                poisson, note="each solve serial on its own host core, run beside the GPU legs")
+            for label in ("fp64", "mixed"):
+                if "seconds" in poisson.get(label, {}):
+                    poisson[label]["gpu_seconds"] = \
+                        result["solvers"]["pcg_bj8_poisson3d_256"][label]["seconds"]
+        result["cpu_baseline"] = cb
         log("cpu baseline: %.2f GB/s" % result["cpu_baseline"]["value"])
     print(json.dumps(result))
 
