@@ -10,6 +10,18 @@ namespace gko {
 constexpr int kWave = 64;
 using lane_mask = uint64_t;
 
+// The dispatcher deals a grid's workgroups to the 8 XCDs round-robin
+// (workgroup b to XCD b mod 8), and each XCD has its own L2.  Kernels whose
+// neighbouring work items share x lines renumber their workgroups so that
+// each XCD takes one contiguous range: xcd_block maps the hardware index b of
+// a grid of G workgroups to that order (a bijection on [0, G)).
+constexpr int kXcds = 8;
+
+__device__ inline int64_t xcd_block(int64_t b, int64_t G) {
+    const int64_t x = b % kXcds, q = G / kXcds, r = G % kXcds;
+    return x * q + (x < r ? x : r) + b / kXcds;
+}
+
 // Load of a matrix stream (values, indices) that is read once per product:
 // the non-temporal hint lets the caches drop these lines first, so the
 // gathered vector x keeps its place in L2.

@@ -42,7 +42,9 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
     int64_t n, int64_t nnz, const int32_t *__restrict__ row, const int32_t *__restrict__ col,
     const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y,
     V *__restrict__ head, V *__restrict__ tail) {
-    const int64_t c = (int64_t)blockIdx.x * (kCooBlock / kWave) + threadIdx.x / kWave;
+    // each XCD streams one contiguous share of the chunks, so x lines shared
+    // by neighbouring chunks are fetched into one L2 only
+    const int64_t c = xcd_block(blockIdx.x, gridDim.x) * (kCooBlock / kWave) + threadIdx.x / kWave;
     const int lane = threadIdx.x % kWave;
     const int64_t cb = c * kCooChunk;
     if (cb >= nnz) return;

@@ -313,20 +313,27 @@ __global__ __launch_bounds__(kMergeBlock) void spmv_merge_kernel(
     __shared__ V w_tot[kMergeBlock / kWave];
 
     const int tid = threadIdx.x;
-    int64_t w = blockIdx.x;
-    if (w >= tiles) return;
+    // The tiles are split over the XCDs in proportion to their workgroups,
+    // in contiguous ranges (neighbouring tiles share x lines); the
+    // workgroups of an XCD stride through its range.
+    const int64_t G = gridDim.x, xcd = blockIdx.x % kXcds, q = G / kXcds, rq = G % kXcds;
+    const int64_t gx = q + (xcd < rq ? 1 : 0);
+    const int64_t p0 = xcd * q + (xcd < rq ? xcd : rq);
+    const int64_t t_end = tiles * (p0 + gx) / G;
+    int64_t w = tiles * p0 / G + blockIdx.x / kXcds;
+    if (w >= t_end) return;
     merge_tile_in<V> cur;
     merge_fetch(w, n, rp, col, val, part, cur);
-    for (; w < tiles; w += gridDim.x) {
+    for (; w < t_end; w += gx) {
         V pr[kMergeIpt];
 #pragma unroll
         for (int j = 0; j < kMergeIpt; ++j) {
             const int t = tid + j * kMergeBlock;
             pr[j] = t < cur.nk ? cur.v[j] * x[cur.c[j]] : V(0);
         }
-        const bool more = w + gridDim.x < tiles;
+        const bool more = w + gx < t_end;
         merge_tile_in<V> nxt;
-        if (more) merge_fetch(w + gridDim.x, n, rp, col, val, part, nxt);
+        if (more) merge_fetch(w + gx, n, rp, col, val, part, nxt);
         const int32_t i0 = cur.i0, nrows = cur.nrows, nk = cur.nk;
 #pragma unroll
         for (int j = 0; j < kMergeIpt; ++j) {
