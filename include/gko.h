@@ -252,6 +252,27 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out);
  * GKO_ERR_NOT_CONVERGED, GKO_ERR_NOT_SPD or GKO_ERR_BREAKDOWN. */
 gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
 
+/* gko_cg_solve for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same CG, from the same kernels, with every work buffer (r, p, q, the
+ * reduction partials and ticket, the iteration scalars) in one static device
+ * array of GKO_NOALLOC_SCRATCH_BYTES that the library holds on each device
+ * until the process ends.  It calls no hipMalloc, hipFree or other allocating
+ * routine, and launches kernel by kernel (no HIP graph is instantiated); it
+ * still copies the iteration scalars to the host and synchronizes the stream
+ * to test convergence.  The caller passes A, b and x as for gko_cg_solve.
+ *   Requires precision FP64 and no preconditioner (else GKO_ERR_UNSUPPORTED),
+ *   and n_rows <= GKO_CG_NOALLOC_MAX_ROWS (else GKO_ERR_INVALID_ARG, nothing
+ *   launched).  Small CSR systems take the single-workgroup launch as in
+ *   gko_cg_solve.  Results are bitwise those of gko_cg_solve (its graph
+ *   replay does not change them).
+ *   Every call on a device shares that device's array, which keeps the last
+ *   call's contents (each call clears what must start at zero): calls that
+ *   overlap on one device, from several streams or host threads, race. */
+#define GKO_NOALLOC_SCRATCH_BYTES (64u << 20)
+#define GKO_CG_NOALLOC_MAX_ROWS 2752448
+gko_status gko_cg_solve_noalloc(gko_matrix A, const void *b, void *x, double tol, int32_t maxit);
+
 /* Flexible CG (Notay 2000, one previous direction kept conjugate): CG with
  * the Polak-Ribiere coefficient beta = z'.(r' - r) / (z.r), which keeps
  * consecutive directions A-conjugate also when the preconditioner is not a

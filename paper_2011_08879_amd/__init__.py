@@ -91,6 +91,7 @@ _SIGS = {
     "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
     "gko_cg_solve": [_vp, _vp, _vp, _f64, _i32],
+    "gko_cg_solve_noalloc": [_vp, _vp, _vp, _f64, _i32],
     "gko_matrix_features": [_vp, ctypes.POINTER(ctypes.c_float)],
     "gko_autotune_format": [_vp, ctypes.POINTER(_st), ctypes.POINTER(ctypes.c_float)],
     "gko_select_format": [_vp, _vp, ctypes.POINTER(_st), ctypes.POINTER(ctypes.c_float)],
@@ -424,17 +425,29 @@ def stream(op: int, a, c, b=None, s: float = 0.0, ctx: Context | None = None):
 
 def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):
     st = fn(A.handle, _ptr(b), _ptr(x), tol, maxit)
+    err = last_error() if st != OK else ""   # read before the next call clears it
     info = A.ctx.solve_info()
     info["status"] = st
     info["status_name"] = status_string(st)
+    info["error"] = err
     if st != OK and raise_on_failure:
-        raise GkoError(st, last_error())
+        raise GkoError(st, err)
     return info
 
 
 def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):
     """(P)CG, options from the context.  x: initial guess in, solution out.  Returns solve info."""
     return _solve(_lib.gko_cg_solve, A, b, x, tol, maxit, raise_on_failure)
+
+
+CG_NOALLOC_MAX_ROWS = 2752448   # GKO_CG_NOALLOC_MAX_ROWS
+
+
+def cg_noalloc(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
+               raise_on_failure: bool = False):
+    """cg() without device allocation: FP64, no preconditioner, at most
+    CG_NOALLOC_MAX_ROWS rows; work buffers in the library's static scratch."""
+    return _solve(_lib.gko_cg_solve_noalloc, A, b, x, tol, maxit, raise_on_failure)
 
 
 def bicgstab(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,

@@ -13,6 +13,7 @@
 #include <cstring>
 #include <fstream>
 #include <limits>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -96,6 +97,7 @@ struct gko_context_s {
     unsigned *red_ticket = nullptr;
     struct gko_mlp_s *selector = nullptr;  // used by gko_convert(AUTO) when set
     int64_t small_cg_rows = -1;            // single-workgroup CG limit, queried once
+    unsigned char *scratch = nullptr;      // this device's copy of the no-allocation scratch
 
     void *alloc_bytes(size_t bytes) {
         if (bytes == 0) bytes = 8;
@@ -259,6 +261,37 @@ int64_t round_up64(int64_t v) { return (v + 63) / 64 * 64; }
 // larger grid.
 constexpr size_t kPartialBytes =
     (size_t)std::max(3 * kMaxReductionBlocks, kFusedMaxSums * kFusedMaxBlocks) * sizeof(double);
+
+// ---------------------------------------------------------------- no-allocation scratch
+// The device memory of gko_cg_solve_noalloc: one static array per device,
+// held until the process ends.  Host code never uses the array's name as an
+// address (on the host it is only a stand-in for the symbol): each device's
+// address comes from hipGetSymbolAddress, resolved once per device when the
+// first context on it is created, and kept in a per-device table.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::vector<unsigned char *> g_scratch_addr;  // indexed by device
+
+// Address of this device's scratch array; the device must be current.
+unsigned char *resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if ((int)g_scratch_addr.size() <= device) g_scratch_addr.resize(device + 1, nullptr);
+    if (!g_scratch_addr[device]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            fail(GKO_ERR_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_addr[device] = static_cast<unsigned char *>(p);
+    }
+    return g_scratch_addr[device];
+}
 
 void ensure_carries(gko_matrix A, int64_t elems) {
     if (A->carry_elems >= elems && A->carry_a) return;
@@ -850,44 +883,74 @@ class interval_graph {
 
 // (P)CG on A with the value arrays `v` (FP64 or FP32), b and x of that type.
 // inv: block-Jacobi inverse of type v.t (bs > 0) or null.
+// Device buffers of one (P)CG solve: vectors r, p, q (and z with a
+// preconditioner) of n values, the grid reductions' partials and ticket, the
+// iteration scalars and a norm slot.  The solvers allocate them per call
+// (cg_buffers); gko_cg_solve_noalloc carves them from the library's static
+// scratch array instead.  graphs = false keeps the iteration kernel by
+// kernel (no graph is instantiated).
+struct cg_workspace {
+    void *r = nullptr, *p = nullptr, *q = nullptr, *z = nullptr;
+    double *partials = nullptr, *nrm = nullptr;
+    unsigned *ticket = nullptr;
+    krylov_scalars *S = nullptr;
+    bool graphs = true;
+};
+
+struct cg_buffers {
+    dbuf r, p, q, z, partials, ticket, sc, nrm;
+    cg_buffers(gko_context c, int64_t n, size_t vb, int bs)
+        : r(c, n * vb), p(c, n * vb), q(c, n * vb), z(c, bs > 0 ? n * vb : 8),
+          partials(c, kPartialBytes), ticket(c, 8), sc(c, sizeof(krylov_scalars)), nrm(c, 8) {}
+    cg_workspace view() {
+        cg_workspace w;
+        w.r = r.p;
+        w.p = p.p;
+        w.q = q.p;
+        w.z = z.p;
+        w.partials = partials.as<double>();
+        w.nrm = nrm.as<double>();
+        w.ticket = ticket.as<unsigned>();
+        w.S = sc.as<krylov_scalars>();
+        return w;
+    }
+};
+
 solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, double tol, int32_t maxit,
-                     const void *inv, int bs, int check_every, bool true_check, bool flexible) {
+                     const void *inv, int bs, int check_every, bool true_check, bool flexible,
+                     const cg_workspace &w) {
     gko_context c = A->ctx;
     hipStream_t s = c->stream;
     const int64_t n = A->n;
     const size_t vb = vsize(v.t);
-    dbuf r(c, n * vb), p(c, n * vb), q(c, n * vb), z(c, bs > 0 ? n * vb : 8);
-    dbuf partials(c, kPartialBytes), ticket(c, 8), sc(c, sizeof(krylov_scalars)), nrm(c, 8);
-    HIPC(hipMemsetAsync(ticket.p, 0, 8, s));
-    auto *S = sc.as<krylov_scalars>();
+    // a fill kernel, not a memset, so that no memset node is ever captured
+    HIPC(fill_zero(s, vt::f64, 1, w.ticket));
+    krylov_scalars *S = w.S;
     HIPC(scalars_reset(s, S, maxit));
-    void *zz = bs > 0 ? z.p : r.p;
+    void *zz = bs > 0 ? w.z : w.r;
     fused_matrix fm;
     const bool fused = fused_view(A, v, fm);
-    interval_graph graph(c, n);
+    interval_graph graph(c, w.graphs ? n : kGraphMaxRows + 1);
     solve_result res;
     krylov_scalars h{};
     for (;;) {
-        HIPC(hipMemcpyAsync(r.p, b, n * vb, hipMemcpyDeviceToDevice, s));
-        spmv_dispatch(A, v, -1.0, x, 1.0, r.p);
-        HIPC(cg_init(s, v.t, n, b, r.p, zz, p.p, inv, bs, tol, S, partials.as<double>(),
-                     ticket.as<unsigned>()));
+        HIPC(hipMemcpyAsync(w.r, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, w.r);
+        HIPC(cg_init(s, v.t, n, b, w.r, zz, w.p, inv, bs, tol, S, w.partials, w.ticket));
         h = read_back(c, S);
         while (h.done == kRunning) {
             graph.run([&] {
                 const hipStream_t st = c->stream;
                 for (int j = 0; j < check_every; ++j) {
                     if (fused) {
-                        HIPC(cg_spmv(st, fm, p.p, q.p, S, partials.as<double>(),
-                                     ticket.as<unsigned>()));
+                        HIPC(cg_spmv(st, fm, w.p, w.q, S, w.partials, w.ticket));
                     } else {
-                        spmv_dispatch(A, v, 1.0, p.p, 0.0, q.p);
-                        HIPC(cg_pq(st, v.t, n, p.p, q.p, S, partials.as<double>(),
-                                   ticket.as<unsigned>()));
+                        spmv_dispatch(A, v, 1.0, w.p, 0.0, w.q);
+                        HIPC(cg_pq(st, v.t, n, w.p, w.q, S, w.partials, w.ticket));
                     }
-                    HIPC(cg_update(st, v.t, n, x, r.p, zz, p.p, q.p, inv, bs, S,
-                                   partials.as<double>(), ticket.as<unsigned>(), flexible));
-                    HIPC(cg_direction(st, v.t, n, zz, p.p, S));
+                    HIPC(cg_update(st, v.t, n, x, w.r, zz, w.p, w.q, inv, bs, S, w.partials,
+                                   w.ticket, flexible));
+                    HIPC(cg_direction(st, v.t, n, zz, w.p, S));
                 }
             });
             h = read_back(c, S);
@@ -897,10 +960,9 @@ solve_result cg_core(gko_matrix A, const values &v, const void *b, void *x, doub
         res.relres = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
         if (!true_check) break;
         // true residual b - A x (q is free now)
-        HIPC(hipMemcpyAsync(q.p, b, n * vb, hipMemcpyDeviceToDevice, s));
-        spmv_dispatch(A, v, -1.0, x, 1.0, q.p);
-        const double tn = device_norm(c, v.t, n, q.p, nrm.as<double>(), partials.as<double>(),
-                                      ticket.as<unsigned>());
+        HIPC(hipMemcpyAsync(w.q, b, n * vb, hipMemcpyDeviceToDevice, s));
+        spmv_dispatch(A, v, -1.0, x, 1.0, w.q);
+        const double tn = device_norm(c, v.t, n, w.q, w.nrm, w.partials, w.ticket);
         res.true_relres = h.bb > 0 ? tn / std::sqrt(h.bb) : 0.0;
         if (h.done != kConverged) break;
         if (tn <= tol * std::sqrt(h.bb)) break;
@@ -990,8 +1052,9 @@ solve_result cg_variant_core(cg_variant var, gko_matrix A, const values &v, cons
                              bool true_check) {
     if (var == cg_variant::pipelined)
         return pipecg_core(A, v, b, x, tol, maxit, inv, bs, check_every, true_check);
+    cg_buffers buf(A->ctx, A->n, vsize(v.t), bs);
     return cg_core(A, v, b, x, tol, maxit, inv, bs, check_every, true_check,
-                   var == cg_variant::flexible);
+                   var == cg_variant::flexible, buf.view());
 }
 
 struct mixed_result {
@@ -1577,6 +1640,7 @@ gko_status gko_context_create(void *hip_stream, gko_context *out) {
         auto c = new gko_context_s();
         try {
             HIPC(hipGetDevice(&c->device));
+            c->scratch = resolve_scratch(c->device);
             c->stream = static_cast<hipStream_t>(hip_stream);
             HIPC(hipMalloc(&c->red_partials, kPartialBytes));
             HIPC(hipMalloc(&c->red_ticket, 8));
@@ -2054,6 +2118,26 @@ gko_status gko_context_get_solve_info(gko_context ctx, gko_solve_info *out) {
     });
 }
 
+// FP64 CG on one workgroup in one launch (the matrix's longest row known);
+// the kernel leaves its counts and residuals in *res.  Fills the solve info.
+static gko_status run_small_cg(gko_matrix A, const void *b, void *x, double tol, int32_t maxit,
+                               small_cg_result *res, double t0) {
+    gko_context c = A->ctx;
+    HIPC(small_cg(c->stream, A->n, A->max_len, A->rp, A->col, static_cast<const double *>(A->val),
+                  static_cast<const double *>(b), static_cast<double *>(x), tol, maxit, res));
+    small_cg_result h{};
+    HIPC(hipMemcpyAsync(&h, res, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+    c->sync();
+    const gko_status st = h.bb == 0.0 ? GKO_OK : flag_status(h.flag);
+    c->info.iterations = h.iters;
+    c->info.restarts = h.restarts;
+    c->info.rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
+    c->info.true_rel_residual = h.bb > 0 ? std::sqrt(h.tr2 / h.bb) : 0.0;
+    c->info.status = st;
+    c->info.seconds = now_seconds() - t0;
+    return st;
+}
+
 // CG, flexible CG or pipelined CG: the same options; only CG has the
 // single-workgroup path for small systems.
 static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit,
@@ -2075,19 +2159,7 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
         if (single) {
             if (A->max_len < 0) A->max_len = max_len_of_csr(A);
             dbuf res(c, sizeof(small_cg_result));
-            HIPC(small_cg(c->stream, n, A->max_len, A->rp, A->col, static_cast<const double *>(A->val),
-                          static_cast<const double *>(b), static_cast<double *>(x), tol, maxit,
-                          res.as<small_cg_result>()));
-            small_cg_result h{};
-            HIPC(hipMemcpyAsync(&h, res.p, sizeof(h), hipMemcpyDeviceToHost, c->stream));
-            c->sync();
-            st = h.bb == 0.0 ? GKO_OK : flag_status(h.flag);
-            c->info.iterations = h.iters;
-            c->info.restarts = h.restarts;
-            c->info.rel_residual = h.bb > 0 ? std::sqrt(h.rr / h.bb) : 0.0;
-            c->info.true_rel_residual = h.bb > 0 ? std::sqrt(h.tr2 / h.bb) : 0.0;
-            c->info.status = st;
-            c->info.seconds = now_seconds() - t0;
+            st = run_small_cg(A, b, x, tol, maxit, res.as<small_cg_result>(), t0);
             return;
         }
         // ||b|| decides the trivial cases before any iteration
@@ -2145,6 +2217,92 @@ static gko_status cg_family_solve(gko_matrix A, const void *b, void *x, double t
 
 gko_status gko_cg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
     return cg_family_solve(A, b, x, tol, maxit, cg_variant::plain);
+}
+
+// ---------------------------------------------------------------- CG without allocation
+// Byte offsets of gko_cg_solve_noalloc's buffers in the scratch array: the
+// single-workgroup result and the longest-row slot, the reduction ticket, the
+// iteration scalars, a norm slot, the reduction partials, then r, p and q.
+namespace {
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+constexpr size_t kNaSmall = 0, kNaMaxLen = 128, kNaTicket = 256, kNaScalars = 512;
+constexpr size_t kNaNorm = kNaScalars + round256(sizeof(krylov_scalars));
+constexpr size_t kNaPartials = kNaNorm + 256;
+constexpr size_t kNaVectors = kNaPartials + round256(kPartialBytes);
+static_assert(sizeof(small_cg_result) <= kNaMaxLen, "small-CG result overlaps the max-length slot");
+// each of r, p, q takes round256(8 n) bytes
+constexpr int64_t kNaMaxRows = int64_t((kScratchBytes - kNaVectors) / 3 / 256 * 256 / 8);
+static_assert(kNaMaxRows == GKO_CG_NOALLOC_MAX_ROWS, "header limit out of date");
+static_assert(kScratchBytes == GKO_NOALLOC_SCRATCH_BYTES, "header scratch size out of date");
+}  // namespace
+
+gko_status gko_cg_solve_noalloc(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {
+    gko_status st = GKO_OK;
+    gko_status call = guarded([&] {
+        check_square_f64(A);
+        check_solve_args(b, x, A->n, tol, maxit);
+        gko_context c = A->ctx;
+        const gko_solver_opts o = c->opts;
+        require(o.precision == GKO_PREC_FP64 && o.precond == GKO_PRECOND_NONE,
+                GKO_ERR_UNSUPPORTED, "only FP64 CG without a preconditioner runs without allocation");
+        const int64_t n = A->n;
+        require(n <= kNaMaxRows, GKO_ERR_INVALID_ARG,
+                "n_rows " + std::to_string(n) + " above the no-allocation limit of " +
+                    std::to_string(kNaMaxRows) + " rows");
+        require(c->scratch != nullptr, GKO_ERR_HIP, "scratch address not resolved");
+        unsigned char *base = c->scratch;
+        hipStream_t s = c->stream;
+        const double t0 = now_seconds();
+        c->info = gko_solve_info{};
+        if (c->small_cg_rows < 0) c->small_cg_rows = small_cg_max_rows();
+        if (o.single_workgroup && n > 0 && n <= c->small_cg_rows &&
+            (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE)) {
+            if (A->max_len < 0) {
+                int *ml = reinterpret_cast<int *>(base + kNaMaxLen);
+                HIPC(fill_zero(s, vt::f32, 1, ml));
+                HIPC(max_row_len(s, n, A->rp, ml));
+                A->max_len = read_int(c, ml);
+            }
+            st = run_small_cg(A, b, x, tol, maxit,
+                              reinterpret_cast<small_cg_result *>(base + kNaSmall), t0);
+            return;
+        }
+        cg_workspace w;
+        w.ticket = reinterpret_cast<unsigned *>(base + kNaTicket);
+        w.S = reinterpret_cast<krylov_scalars *>(base + kNaScalars);
+        w.nrm = reinterpret_cast<double *>(base + kNaNorm);
+        w.partials = reinterpret_cast<double *>(base + kNaPartials);
+        const size_t vb = round256(size_t(n) * 8);
+        w.r = base + kNaVectors;
+        w.p = base + kNaVectors + vb;
+        w.q = base + kNaVectors + 2 * vb;
+        w.graphs = false;
+        HIPC(fill_zero(s, vt::f64, 1, w.ticket));
+        const double bnorm = device_norm(c, vt::f64, n, b, w.nrm, w.partials, w.ticket);
+        if (!std::isfinite(bnorm)) {
+            st = GKO_ERR_BREAKDOWN;
+        } else if (bnorm == 0.0) {
+            HIPC(fill_zero(s, vt::f64, n, x));
+            st = GKO_OK;
+        } else {
+            solve_result r = cg_core(A, own_values(A), b, x, tol, maxit, nullptr, 0, o.check_every,
+                                     true, false, w);
+            st = flag_status(r.flag);
+            c->info.iterations = r.iters;
+            c->info.restarts = r.restarts;
+            c->info.rel_residual = r.relres;
+            c->info.true_rel_residual = r.true_relres;
+        }
+        c->sync();
+        c->info.status = st;
+        c->info.seconds = now_seconds() - t0;
+    });
+    if (call != GKO_OK) {
+        if (A) A->ctx->info.status = call;
+        return call;
+    }
+    if (st != GKO_OK) g_last_error = std::string("cg_noalloc: ") + gko_status_string(st);
+    return st;
 }
 
 gko_status gko_fcg_solve(gko_matrix A, const void *b, void *x, double tol, int32_t maxit) {

@@ -81,6 +81,7 @@ def test_null_handles_rejected(lib):
         "gko_context_get_solver_opts": (None, None),
         "gko_context_get_solve_info": (None, None),
         "gko_cg_solve": (None, None, None, d(1e-10), 10),
+        "gko_cg_solve_noalloc": (None, None, None, d(1e-10), 10),
         "gko_fcg_solve": (None, None, None, d(1e-10), 10),
         "gko_pipecg_solve": (None, None, None, d(1e-10), 10),
         "gko_bicgstab_solve": (None, None, None, d(1e-10), 10),
