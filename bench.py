@@ -593,10 +593,73 @@ def run_batch(g, gen, torch, keep, nsys=10000, reps=3):
                       "status": g.status_string(st), "iters_mean": round(float(it.mean()), 1),
                       "iters_max": int(it.max()), "max_true_rel_residual": float(rr.max()),
                       "max_abs_err_rel_to_max_xstar": float(err)}
+        if label == "fp64":
+            out[label]["bound"] = batch_bound(g, torch, B, vals, bh, G, it, best, floor_bytes)
         log("batch %s: %.0f solves/s (%.2f ms, block %d, mean %.1f it, max relres %.1e)" %
             (label, nsys / best, best * 1e3, blk, it.mean(), rr.max()))
         G.close()
     return out
+
+
+LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz
+
+
+def batch_bound(g, torch, B, vals, bh, G, its, measured_s, floor_bytes):
+    """Lower bounds on the batched solve's time and the fraction achieved.
+
+    * HBM: one read of every system, b and x0, one write of x.
+    * LDS: per system and iteration the p gathers of its entries and one p
+      store per row (8 bytes each), against 256 CUs x 128 B/clk.
+    * latency: an iteration cannot take less than on a workgroup alone on the
+      GPU.  t_iter(m) is measured on one-system batches (the smallest and the
+      largest system, in a batch of their own, kernel time at the batch's
+      workgroup size, full solve minus a one-iteration solve) and interpolated
+      in m; with R workgroups resident, the batch needs at least
+      max(sum_s its_s t_iter(m_s) / R, max_s its_s t_iter(m_s)).
+    fraction = the largest bound / the measured time."""
+    m = np.diff(B.row_off)
+    nz = np.diff(B.nnz_off)
+    resident, lds_bytes = G.launch_info()
+    t_iter = {}
+    for sid in (int(np.argmin(m)), int(np.argmax(m))):
+        rp, c, _ = B.system(sid)
+        k0, k1 = int(B.nnz_off[sid]), int(B.nnz_off[sid + 1])
+        r0, r1 = int(B.row_off[sid]), int(B.row_off[sid + 1])
+        one = g.Batch(np.array([0, r1 - r0], np.int64), np.array([0, k1 - k0], np.int64),
+                      np.ascontiguousarray(rp), np.ascontiguousarray(c), vals[k0:k1],
+                      dtype=torch.float64)
+        b1 = torch.from_numpy(np.ascontiguousarray(bh[r0:r1])).cuda()
+        x1 = torch.zeros(r1 - r0, dtype=torch.float64, device="cuda")
+        one.block = G.block
+        ts = {}
+        for mi in (1, 1000):
+            best = None
+            for _ in range(5):
+                one.block = G.block
+                st, it1, _ = one.solve(b1, x1, tol=1e-10, maxit=mi)
+                a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                one.solve(b1, x1, tol=1e-10, maxit=mi)
+                e.record()
+                torch.cuda.synchronize()
+                ms = a.elapsed_time(e)
+                best = ms if best is None else min(best, ms)
+            ts[mi] = (best * 1e-3, int(it1.cpu()[0]))
+        one.close()
+        t_iter[int(m[sid])] = (ts[1000][0] - ts[1][0]) / max(ts[1000][1] - 1, 1)
+    (m0, t0), (m1, t1) = sorted(t_iter.items())
+    tm = t0 + (t1 - t0) * (m - m0) / max(m1 - m0, 1)
+    work = its.astype(np.float64) * tm
+    latency_s = max(work.sum() / resident, work.max())
+    lds_s = float((its.astype(np.float64) * (nz + m) * 8).sum()) / (LDS_PEAK_GBS * 1e9)
+    hbm_s = floor_bytes / (HBM_PEAK_GBS * 1e9)
+    bound = max(latency_s, lds_s, hbm_s)
+    return {"resident_workgroups": resident, "lds_bytes_per_workgroup": lds_bytes,
+            "t_iter_lone_us": {str(k): round(v * 1e6, 3) for k, v in t_iter.items()},
+            "latency_floor_s": round(latency_s, 7), "lds_floor_s": round(lds_s, 7),
+            "hbm_floor_s": round(hbm_s, 7), "bound": "latency" if bound == latency_s else
+            ("lds" if bound == lds_s else "hbm"),
+            "frac": round(bound / measured_s, 4)}
 
 
 def run_sweep(args, g, gen, torch, result):

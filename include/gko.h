@@ -361,14 +361,29 @@ gko_status gko_batch_destroy(gko_batch B);
 gko_status gko_batch_cg_solve(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
                               int32_t *iters_out, double *relres_out);
 
-/* Workgroup size used by gko_batch_cg_solve: 64, 128, 256 or 512 threads. */
+/* Workgroup size used by gko_batch_cg_solve: 64, 128, 256 or 512 threads.
+ * A new batch starts from the autotune cache's choice for its device
+ * architecture and shape (dtype, nsys, total rows, nnz, largest system) when
+ * the cache holds one, else from 64 (largest system <= 256 rows) or 128. */
 gko_status gko_batch_set_block(gko_batch B, int32_t block);
 gko_status gko_batch_get_block(gko_batch B, int32_t *block);
+
+/* The launch gko_batch_cg_solve makes at the current workgroup size: how
+ * many workgroups are resident on the device at once (the persistent grid,
+ * capped by nsys at launch) and the dynamic LDS each takes (the iteration
+ * vectors of the largest system).  Host outputs. */
+gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
+                                 int64_t *lds_bytes_per_workgroup);
 
 /* Time one full batched solve for each workgroup size (64, 128, 256, 512) on
  * the given right-hand sides and keep the fastest for this batch.
  * times_ms[4] (host) receives the timings; *block_out (host) the choice.
- * x, iters and relres are scratch outputs as in gko_batch_cg_solve. */
+ * x, iters and relres are scratch outputs as in gko_batch_cg_solve.
+ * The choice is also stored in the on-disk autotune cache, a text file of
+ * "key value" lines: the file named by the environment variable
+ * GKO_AUTOTUNE_CACHE (set but empty: no cache), else
+ * $XDG_CACHE_HOME/gko_mi355x/autotune, else ~/.cache/gko_mi355x/autotune;
+ * a file that cannot be written is skipped without an error. */
 gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
                               int32_t *iters_out, double *relres_out, int32_t *block_out,
                               float *times_ms);

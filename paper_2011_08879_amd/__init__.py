@@ -110,6 +110,7 @@ _SIGS = {
     "gko_batch_cg_solve": [_vp, _vp, _vp, _f64, _i32, _vp, _vp],
     "gko_batch_set_block": [_vp, _i32],
     "gko_batch_get_block": [_vp, ctypes.POINTER(_i32)],
+    "gko_batch_launch_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
     "gko_batch_autotune": [_vp, _vp, _vp, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                            ctypes.POINTER(ctypes.c_float)],
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
@@ -511,6 +512,13 @@ class Batch:
     @block.setter
     def block(self, v: int):
         _check(_lib.gko_batch_set_block(self.handle, v))
+
+    def launch_info(self):
+        """(workgroups resident at once, dynamic LDS bytes per workgroup) of the
+        persistent launch at the current workgroup size."""
+        r, l = _i32(), _i64()
+        _check(_lib.gko_batch_launch_info(self.handle, ctypes.byref(r), ctypes.byref(l)))
+        return r.value, l.value
 
     def _outs(self):
         torch = _torch()

@@ -3,6 +3,8 @@
 // runs in the HIP kernels; this file only orders launches and moves a few
 // scalars to the host for convergence checks.
 #include <hip/hip_runtime.h>
+#include <sys/stat.h>
+#include <unistd.h>
 
 #include <algorithm>
 #include <iterator>
@@ -10,6 +12,7 @@
 #include <numeric>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <fstream>
 #include <limits>
@@ -1476,6 +1479,95 @@ extern "C" {
 
 const char *gko_last_error(void) { return g_last_error.c_str(); }
 
+// ---------------------------------------------------------------- autotune cache
+// Choices of gko_batch_autotune persist in a text file, one "key value" line
+// per entry, keyed by the device architecture and the batch's shape; a batch
+// created later with the same key starts from the stored choice.  The file
+// is GKO_AUTOTUNE_CACHE when that is set (empty: no cache), else
+// $XDG_CACHE_HOME/gko_mi355x/autotune, else ~/.cache/gko_mi355x/autotune.
+namespace {
+
+std::mutex g_cache_mu;
+
+std::string autotune_cache_path() {
+    if (const char *p = std::getenv("GKO_AUTOTUNE_CACHE")) return p;
+    std::string dir;
+    if (const char *x = std::getenv("XDG_CACHE_HOME"); x && *x) dir = x;
+    else if (const char *h = std::getenv("HOME"); h && *h) dir = std::string(h) + "/.cache";
+    else return "";
+    return dir + "/gko_mi355x/autotune";
+}
+
+std::string device_arch(int device) {
+    hipDeviceProp_t prop{};
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    for (char &ch : a)
+        if (ch == ' ') ch = '_';
+    return a.empty() ? "unknown" : a;
+}
+
+std::string batch_cache_key(const gko_batch_s *B) {
+    return "batch_cg " + device_arch(B->ctx->device) + " " + (B->dt == GKO_F64 ? "f64" : "f32") +
+           " nsys=" + std::to_string(B->nsys) + " rows=" + std::to_string(B->rows) +
+           " nnz=" + std::to_string(B->nnz) + " max_m=" + std::to_string(B->max_m);
+}
+
+// The stored value of key, or -1.
+int cache_lookup(const std::string &key) {
+    const std::string path = autotune_cache_path();
+    if (path.empty()) return -1;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    std::ifstream in(path);
+    std::string line;
+    int found = -1;
+    while (std::getline(in, line)) {
+        const size_t sp = line.rfind(' ');
+        if (sp != std::string::npos && line.compare(0, sp, key) == 0 && sp == key.size())
+            found = std::atoi(line.c_str() + sp + 1);
+    }
+    return found;
+}
+
+// Replaces (or adds) key's line; the file is rewritten through a temporary
+// file and a rename, so readers never see a partial file.  Failures to
+// write leave the cache as it was (the choice still applies to this batch).
+void cache_store(const std::string &key, int value) {
+    const std::string path = autotune_cache_path();
+    if (path.empty()) return;
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    std::vector<std::string> lines;
+    {
+        std::ifstream in(path);
+        std::string line;
+        while (std::getline(in, line)) {
+            const size_t sp = line.rfind(' ');
+            if (!(sp != std::string::npos && sp == key.size() && line.compare(0, sp, key) == 0))
+                lines.push_back(line);
+        }
+    }
+    lines.push_back(key + " " + std::to_string(value));
+    const size_t slash = path.rfind('/');
+    if (slash != std::string::npos && slash > 0) {
+        std::string dir = path.substr(0, slash);
+        for (size_t i = 1; i <= dir.size(); ++i)
+            if (i == dir.size() || dir[i] == '/') (void)mkdir(dir.substr(0, i).c_str(), 0755);
+    }
+    const std::string tmp = path + ".tmp" + std::to_string(getpid());
+    {
+        std::ofstream out(tmp);
+        if (!out) return;
+        for (const auto &l : lines) out << l << "\n";
+        if (!out) {
+            std::remove(tmp.c_str());
+            return;
+        }
+    }
+    if (std::rename(tmp.c_str(), path.c_str()) != 0) std::remove(tmp.c_str());
+}
+
+}  // namespace
+
 gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *row_off,
                                 const int64_t *nnz_off, const int32_t *row_ptr_local,
                                 const int32_t *col_idx, const void *values, gko_dtype dt,
@@ -1548,6 +1640,8 @@ gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *ro
             if (read_int(ctx, B->status))
                 fail(GKO_ERR_INVALID_ARG, "malformed system (offsets or column indices)");
             B->block = max_m <= 256 ? 64 : 128;
+            const int cached = cache_lookup(batch_cache_key(B));
+            if (cached == 64 || cached == 128 || cached == 256 || cached == 512) B->block = cached;
         } catch (...) {
             B->free_all();
             delete B;
@@ -1571,6 +1665,19 @@ gko_status gko_batch_set_block(gko_batch B, int32_t block) {
         require(block == 64 || block == 128 || block == 256 || block == 512, GKO_ERR_INVALID_ARG,
                 "block must be 64, 128, 256 or 512");
         B->block = block;
+    });
+}
+
+gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
+                                 int64_t *lds_bytes_per_workgroup) {
+    return guarded([&] {
+        require(B && resident_workgroups && lds_bytes_per_workgroup, GKO_ERR_INVALID_ARG,
+                "null batch or output");
+        const vt t = B->dt == GKO_F64 ? vt::f64 : vt::f32;
+        int r = 0;
+        HIPC(batch_resident(t, B->block, B->max_m, &r));
+        *resident_workgroups = r;
+        *lds_bytes_per_workgroup = (int64_t)batch_lds_bytes(t, B->max_m);
     });
 }
 
@@ -1615,6 +1722,7 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
         }
         B->block = best;
         if (block_out) *block_out = best;
+        cache_store(batch_cache_key(B), best);
     });
 }
 

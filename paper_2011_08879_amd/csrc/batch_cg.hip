@@ -382,9 +382,10 @@ size_t batch_lds_bytes(vt t, int64_t max_m) {
     return (size_t)max_m * (t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4);
 }
 
+// Workgroups of batch_cg_kernel<VA, T> resident on the device at once.
 template <typename VA, int T>
-static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
-    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m);
+static hipError_t resident_t(int64_t max_m, int *out) {
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, max_m);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
@@ -392,7 +393,33 @@ static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T>, T, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
-    int64_t grid = (int64_t)cus * per_cu;
+    *out = cus * per_cu;
+    return hipSuccess;
+}
+
+template <typename VA>
+static hipError_t resident_v(int block, int64_t max_m, int *out) {
+    switch (block) {
+        case 64: return resident_t<VA, 64>(max_m, out);
+        case 128: return resident_t<VA, 128>(max_m, out);
+        case 256: return resident_t<VA, 256>(max_m, out);
+        case 512: return resident_t<VA, 512>(max_m, out);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t batch_resident(vt t, int block, int64_t max_m, int *workgroups) {
+    return t == vt::f64 ? resident_v<double>(block, max_m, workgroups)
+                        : resident_v<float>(block, max_m, workgroups);
+}
+
+template <typename VA, int T>
+static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m);
+    int resident = 0;
+    hipError_t e = resident_t<VA, T>(a.max_m, &resident);
+    if (e != hipSuccess) return e;
+    int64_t grid = resident;
     if (grid > a.nsys) grid = a.nsys;
     if (grid < 1) grid = 1;
     batch_reset_kernel<<<1, 1, 0, s>>>(a.counter, a.status);

@@ -42,5 +42,8 @@ hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
                           const int64_t *nnz_off, const int32_t *rp_local, const int32_t *col,
                           int *err);
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a);
+// Workgroups of the persistent kernel resident at once (its grid for batches
+// of at least that many systems).
+hipError_t batch_resident(vt t, int block, int64_t max_m, int *workgroups);
 
 }  // namespace gko

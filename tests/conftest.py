@@ -9,6 +9,10 @@ if ROOT not in sys.path:
 
 
 def pytest_configure(config):
+    # batched-CG autotune choices go to a cache file of this session only
+    import tempfile
+    os.environ.setdefault("GKO_AUTOTUNE_CACHE",
+                          os.path.join(tempfile.mkdtemp(prefix="gko_tests_"), "autotune"))
     config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
     config.addinivalue_line("markers", "slow: long-running CPU test")
 

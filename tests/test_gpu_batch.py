@@ -103,6 +103,38 @@ def test_batch_deterministic_and_autotune(g, orc, gen_mod):
     assert all(t > 0 for t in times.values()) and times[blk] == min(times.values())
 
 
+def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
+    """gko_batch_autotune stores its choice in the on-disk cache under the
+    device architecture and the batch's shape; a later batch of the same
+    shape starts from it, one of another shape does not; an empty
+    GKO_AUTOTUNE_CACHE turns the cache off."""
+    path = tmp_path / "autotune"
+    monkeypatch.setenv("GKO_AUTOTUNE_CACHE", str(path))
+    B = gen_mod.batch_systems(200, master_seed=13)
+    b = dev(rhs(orc, B))
+    G = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val)
+    blk, _ = G.autotune(b, dev(np.zeros(B.xstar.shape)))
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("batch_cg gfx950")
+    key = lines[0].rsplit(" ", 1)[0]
+    assert lines[0] == "%s %d" % (key, blk)
+    assert " f64 nsys=200 rows=%d nnz=%d " % (B.row_off[-1], B.nnz_off[-1]) in key
+    # a stored choice other than the default is what a new batch of this shape takes
+    other = 512 if blk != 512 else 256
+    path.write_text("%s %d\n" % (key, other))
+    assert g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val).block == other
+    # retuning replaces the line; a batch of another shape keeps its default
+    G.autotune(b, dev(np.zeros(B.xstar.shape)))
+    assert path.read_text().splitlines() == ["%s %d" % (key, G.block)]
+    C = gen_mod.batch_systems(150, master_seed=13)
+    default = 64 if int(C.m.max()) <= 256 else 128
+    assert g.Batch(C.row_off, C.nnz_off, C.row_ptr, C.col, C.val).block == default
+    monkeypatch.setenv("GKO_AUTOTUNE_CACHE", "")
+    path.unlink()
+    G.autotune(b, dev(np.zeros(B.xstar.shape)))
+    assert not path.exists()
+
+
 def test_batch_edge_cases_and_statuses(g, orc):
     import torch
     # one 1x1 system, one 2x2 SPD system, one indefinite diagonal system

@@ -69,8 +69,23 @@ def poisson(gen_mod, orc):
     return A, xs, b
 
 
+@pytest.fixture(scope="module")
+def poisson_oracle_x(orc, poisson):
+    """The oracle's FP64 block-Jacobi(8) PCG solution of the config-3 system
+    (serial; about 100 s on the GPU machine's host)."""
+    A, xs, b = poisson
+    rc, inv = orc.bj_invert(A, 8)
+    rc, x, info = orc.cg(A, b, tol=1e-10, maxit=20000, bj_inv=inv)
+    assert rc == orc.OK and info["iters"] == 649, info
+    return x
+
+
+@pytest.mark.timeout(900)
 @pytest.mark.parametrize("mixed", [False, True], ids=["fp64", "mixed"])
-def test_poisson256_pcg_full_size(g, orc, poisson, mixed):
+def test_poisson256_pcg_full_size(g, orc, poisson, poisson_oracle_x, mixed):
+    """FP64 and mixed-precision PCG at the bench's size: the oracle's true
+    residual, the manufactured-solution bound, and the per-solve error
+    against the FP64 oracle's own solution within 2 kappa tol."""
     A, xs, b = poisson
     N = 256
     ctx = g.default_context()
@@ -87,6 +102,10 @@ def test_poisson256_pcg_full_size(g, orc, poisson, mixed):
         assert true <= 1e-10
         kappa = (6 + 6 * math.cos(math.pi / (N + 1))) / (6 - 6 * math.cos(math.pi / (N + 1)))
         assert np.linalg.norm(xg - xs) / np.linalg.norm(xs) <= kappa * true
+        xo = poisson_oracle_x
+        assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+        if not mixed:   # the oracle's recurrence in the same precision: 649 iterations
+            assert abs(info["iterations"] - 649) <= 2, info
     finally:
         ctx.set_solver_opts()
 
