@@ -8,7 +8,6 @@
 namespace gko {
 
 constexpr int kWave = 64;
-using lane_mask = uint64_t;
 
 // The dispatcher deals a grid's workgroups to the 8 XCDs round-robin
 // (workgroup b to XCD b mod 8), and each XCD has its own L2.  Kernels whose
@@ -32,21 +31,12 @@ __device__ __forceinline__ T load_stream(const T *p) {
 
 // ------------------------------------------------------------------ subwarps
 // Contiguous subwarps of Size lanes (a power of two <= 64) inside a wavefront,
-// as in Sec. 4 (cooperative groups): Rank = tid % Size, LaneOffset =
-// floor((tid % 64) / Size) * Size, Mask = (~0 >> (64 - Size)) << LaneOffset.
+// as in Sec. 4 (cooperative groups): lane tid belongs to the subwarp of lanes
+// floor((tid % 64) / Size) * Size .. + Size - 1.  The kernels need only the
+// subwarp sum; __shfl_xor with width Size stays inside that lane group.
 template <int Size>
 struct subwarp {
     static_assert(Size >= 1 && Size <= kWave && (Size & (Size - 1)) == 0, "power of two");
-    __device__ static int rank() { return threadIdx.x % Size; }
-    __device__ static int lane_offset() { return ((threadIdx.x % kWave) / Size) * Size; }
-    __device__ static lane_mask mask() {
-        return (~lane_mask(0) >> (kWave - Size)) << lane_offset();
-    }
-    __device__ static lane_mask ballot(bool p) {
-        return (__ballot(p) & mask()) >> lane_offset();
-    }
-    __device__ static bool any(bool p) { return (__ballot(p) & mask()) != 0; }
-    __device__ static bool all(bool p) { return (__ballot(p) & mask()) == mask(); }
 
     // Xor butterfly (Sec. 5 subgroup reduction): every lane of the subwarp
     // ends with the subwarp sum; the combination order is fixed.
