@@ -16,7 +16,10 @@ Algorithmic bytes per SpMV (value size s, beta = 0; x read once, y written once)
   ELL:            n K (s+4) + n_cols s + n s
   HYBRID:         n K (s+4) + tail (s+8) + n_cols s + n s (+ n s when a tail exists)
 The paper's own model (Sec. 6.1) counts only the matrix entries: 12 bytes per
-CSR entry and 16 per COO entry.
+CSR entry and 16 per COO entry.  The padded formats count their stored slots,
+padding included, although their kernels stop at a row's first padding slot;
+per_kernel reports those unread bytes beside the figure (on the stencil
+10.6 MB, 1.5% of ELL's bytes: the shorter rows at the grid's faces).
 
 After the timed sweep (outside it): CG on the 2D 5-point Laplacian 64x64
 (to 1e-10), and block-Jacobi PCG on the 3D 7-point Poisson 256^3 in FP64 and
@@ -65,6 +68,20 @@ def spmv_bytes(desc, s=8):
     if f == "sellp":
         return desc.sellp_slots * (s + 4) + (desc.sellp_slices + 1) * 8 + m * s + n * s
     raise ValueError(f)
+
+
+def padding_bytes(desc, s=8):
+    """Bytes of the padding slots that the algorithmic bytes of ELL, HYB and
+    SELL-P count (the stored slots) but their kernels never read: a row stops
+    at its first padding slot."""
+    f = desc.format
+    if f == "ell":
+        return (desc.n_rows * desc.ell_width - desc.nnz) * (s + 4)
+    if f == "hybrid":
+        return (desc.n_rows * desc.ell_width - (desc.nnz - desc.coo_nnz)) * (s + 4)
+    if f == "sellp":
+        return (desc.sellp_slots - desc.nnz) * (s + 4)
+    return 0
 
 
 def csr_bytes(n, m, nnz, s=8):
@@ -589,7 +606,9 @@ def run_batch(g, gen, torch, keep, nsys=10000, reps=3):
         out[label] = {"solves_per_s": round(nsys / best, 1), "seconds": round(best, 5), "tol": tol,
                       "hbm_floor_bytes": int(floor_bytes),
                       "hbm_floor_seconds": round(floor_bytes / (HBM_PEAK_GBS * 1e9), 7),
-                      "block": blk, "autotune_ms": {str(k): round(v, 3) for k, v in times.items()},
+                      "block": blk, "lds_mode": G.lds_mode,
+                      "autotune_ms": {"%d/%s" % k: (round(v, 3) if np.isfinite(v) else None)
+                                      for k, v in times.items()},
                       "status": g.status_string(st), "iters_mean": round(float(it.mean()), 1),
                       "iters_max": int(it.max()), "max_true_rel_residual": float(rr.max()),
                       "max_abs_err_rel_to_max_xstar": float(err)}
@@ -702,7 +721,8 @@ def run_sweep(args, g, gen, torch, result):
                            "useful_GB/s": round(e["useful_bytes"] / (ms * 1e-3) / 1e9, 1),
                            "GFLOP/s": round(e["flops"] / (ms * 1e-3) / 1e9, 1),
                            "frac_hbm_peak": round(e["bytes"] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                           "alg_bytes": int(e["bytes"])})
+                           "alg_bytes": int(e["bytes"]),
+                           "unread_padding_bytes": int(padding_bytes(e["desc"]))})
     dom = max(range(len(mats)), key=lambda k: per_kernel[k]["ms"])
     d = per_kernel[dom]
     achieved = d["alg_bytes"] / (d["ms"] * 1e-3) / 1e9
@@ -864,7 +884,8 @@ def run_sellp(args, g, torch, base, mats, per_kernel):
         nb = spmv_bytes(d)
         out[name] = {"ms": round(ms, 5), "GB/s": round(nb / (ms * 1e-3) / 1e9, 1),
                      "frac_hbm_peak": round(nb / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                     "alg_bytes": int(nb), "slots": d.sellp_slots,
+                     "alg_bytes": int(nb), "unread_padding_bytes": int(padding_bytes(d)),
+                     "slots": d.sellp_slots,
                      "padding_ratio": round(d.sellp_slots / max(d.nnz, 1), 4)}
         if name in ell_ms:
             out[name]["ell_ms_in_sweep"] = ell_ms[name]

@@ -362,11 +362,26 @@ gko_status gko_batch_cg_solve(gko_batch B, const double *b, double *x, double to
                               int32_t *iters_out, double *relres_out);
 
 /* Workgroup size used by gko_batch_cg_solve: 64, 128, 256 or 512 threads.
- * A new batch starts from the autotune cache's choice for its device
- * architecture and shape (dtype, nsys, total rows, nnz, largest system) when
- * the cache holds one, else from 64 (largest system <= 256 rows) or 128. */
+ * A new batch starts from the autotune cache's choice (size and LDS mode)
+ * for its device architecture and shape (dtype, nsys, total rows, nnz,
+ * largest system) when the cache holds one, else from 64 (largest system
+ * <= 256 rows) or 128 threads with the direction-only LDS mode where it fits. */
 gko_status gko_batch_set_block(gko_batch B, int32_t block);
 gko_status gko_batch_get_block(gko_batch B, int32_t *block);
+
+/* What the persistent kernel keeps in LDS.  ALL: x, r, p and q of the
+ * current system (rows that do not fit the register cache are read from
+ * memory each iteration).  DIRECTION: every system's rows (up to 5 entries,
+ * up to min(4, 1024 / block) rows per thread) and its x, r and q stay in
+ * registers and only the direction p goes through LDS (m doubles per
+ * workgroup instead of 4m): FP64 batches whose every system fits the
+ * register cache at the workgroup size.  set_lds_mode(DIRECTION) fails with
+ * GKO_ERR_UNSUPPORTED where it does not fit; a later set_block to a size
+ * where it does not fit falls back to ALL.  get_lds_mode returns the mode in
+ * effect. */
+typedef enum gko_batch_lds { GKO_BATCH_LDS_ALL = 0, GKO_BATCH_LDS_DIRECTION = 1 } gko_batch_lds;
+gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode);
+gko_status gko_batch_get_lds_mode(gko_batch B, int32_t *mode);
 
 /* The launch gko_batch_cg_solve makes at the current workgroup size: how
  * many workgroups are resident on the device at once (the persistent grid,
@@ -375,12 +390,14 @@ gko_status gko_batch_get_block(gko_batch B, int32_t *block);
 gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
                                  int64_t *lds_bytes_per_workgroup);
 
-/* Time one full batched solve for each workgroup size (64, 128, 256, 512) on
- * the given right-hand sides and keep the fastest for this batch.
- * times_ms[4] (host) receives the timings; *block_out (host) the choice.
+/* Time one full batched solve for each workgroup size (64, 128, 256, 512)
+ * and LDS mode on the given right-hand sides and keep the fastest pair for
+ * this batch.  times_ms[8] (host) receives the timings, entry 2 j + mode for
+ * size j of that list (infinity where the mode does not fit); *block_out
+ * (host) the chosen size (gko_batch_get_lds_mode gives the mode).
  * x, iters and relres are scratch outputs as in gko_batch_cg_solve.
  * The choice is also stored in the on-disk autotune cache, a text file of
- * "key value" lines: the file named by the environment variable
+ * "key = block mode" lines: the file named by the environment variable
  * GKO_AUTOTUNE_CACHE (set but empty: no cache), else
  * $XDG_CACHE_HOME/gko_mi355x/autotune, else ~/.cache/gko_mi355x/autotune;
  * a file that cannot be written is skipped without an error. */

@@ -111,6 +111,8 @@ _SIGS = {
     "gko_batch_set_block": [_vp, _i32],
     "gko_batch_get_block": [_vp, ctypes.POINTER(_i32)],
     "gko_batch_launch_info": [_vp, ctypes.POINTER(_i32), ctypes.POINTER(_i64)],
+    "gko_batch_set_lds_mode": [_vp, _i32],
+    "gko_batch_get_lds_mode": [_vp, ctypes.POINTER(_i32)],
     "gko_batch_autotune": [_vp, _vp, _vp, _f64, _i32, _vp, _vp, ctypes.POINTER(_i32),
                            ctypes.POINTER(ctypes.c_float)],
     "gko_bicgstab_solve": [_vp, _vp, _vp, _f64, _i32],
@@ -442,6 +444,7 @@ def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure
 
 
 CG_NOALLOC_MAX_ROWS = 2752448   # GKO_CG_NOALLOC_MAX_ROWS
+BATCH_LDS_MODES = ("all", "direction")   # gko_batch_lds
 
 
 def cg_noalloc(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
@@ -534,14 +537,27 @@ class Batch:
             raise GkoError(st, last_error())
         return st, it, rr
 
+    @property
+    def lds_mode(self) -> str:
+        """"all" (x, r, p, q in LDS) or "direction" (only p; rows and the rest in registers)."""
+        m = _i32()
+        _check(_lib.gko_batch_get_lds_mode(self.handle, ctypes.byref(m)))
+        return BATCH_LDS_MODES[m.value]
+
+    @lds_mode.setter
+    def lds_mode(self, mode: str):
+        _check(_lib.gko_batch_set_lds_mode(self.handle, BATCH_LDS_MODES.index(mode)))
+
     def autotune(self, b, x, tol: float = 1e-10, maxit: int = 1000):
-        """Times every workgroup size, keeps the fastest.  Returns (block, {block: ms})."""
+        """Times every workgroup size and LDS mode, keeps the fastest pair.
+        Returns (block, {(block, mode): ms}) (ms infinite where a mode does not fit)."""
         it, rr = self._outs()
         blk = _i32()
-        ms = (ctypes.c_float * 4)()
+        ms = (ctypes.c_float * 8)()
         _check(_lib.gko_batch_autotune(self.handle, _ptr(b), _ptr(x), tol, maxit, _ptr(it),
                                        _ptr(rr), ctypes.byref(blk), ms))
-        return blk.value, dict(zip((64, 128, 256, 512), list(ms)))
+        keys = [(bk, md) for bk in (64, 128, 256, 512) for md in BATCH_LDS_MODES]
+        return blk.value, dict(zip(keys, list(ms)))
 
     def close(self):
         if getattr(self, "handle", None):

@@ -1138,7 +1138,9 @@ void check_solve_args(const void *b, void *x, int64_t n, double tol, int32_t max
 struct gko_batch_s {
     gko_context ctx = nullptr;
     gko_dtype dt = GKO_F64;
-    int64_t nsys = 0, rows = 0, nnz = 0, max_m = 0;
+    int64_t nsys = 0, rows = 0, nnz = 0, max_m = 0, max_row_len = 0;
+    bool want_lean = true;  // direction-only LDS requested (used where it fits)
+    bool lean = false;      // in effect: only the direction in LDS (FP64, rows in registers)
     int64_t *row_off = nullptr, *nnz_off = nullptr;
     int32_t *rp_local = nullptr, *col = nullptr, *order = nullptr;
     void *val = nullptr;
@@ -1158,6 +1160,17 @@ struct gko_batch_s {
 };
 
 namespace {
+
+bool batch_lean_ok(const gko_batch_s *B, int block) {
+    return batch_lean_fits(B->dt == GKO_F64 ? vt::f64 : vt::f32, block, B->max_m, B->max_row_len);
+}
+
+// The workgroup size and the LDS mode (direction only where requested and
+// where every system fits the register cache at that size).
+void batch_use_block(gko_batch B, int block) {
+    B->block = block;
+    B->lean = B->want_lean && batch_lean_ok(B, block);
+}
 
 gko_status batch_run(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
                      int32_t *iters, double *relres, float *ms) {
@@ -1180,7 +1193,9 @@ gko_status batch_run(gko_batch B, const double *b, double *x, double tol, int32_
     a.relres = relres;
     a.status = B->status;
     a.max_m = B->max_m;
+    a.max_row_len = B->max_row_len;
     a.block = B->block;
+    a.lean = B->lean;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         HIPC(hipEventCreate(&e0));
@@ -1513,40 +1528,38 @@ std::string batch_cache_key(const gko_batch_s *B) {
            " nnz=" + std::to_string(B->nnz) + " max_m=" + std::to_string(B->max_m);
 }
 
-// The stored value of key, or -1.
-int cache_lookup(const std::string &key) {
+// Lines are "<key> = <value>"; the key never contains " = ".
+constexpr const char *kCacheSep = " = ";
+
+// The stored value of key (the last line for it), or "".
+std::string cache_lookup(const std::string &key) {
     const std::string path = autotune_cache_path();
-    if (path.empty()) return -1;
+    if (path.empty()) return "";
     std::lock_guard<std::mutex> lock(g_cache_mu);
     std::ifstream in(path);
-    std::string line;
-    int found = -1;
-    while (std::getline(in, line)) {
-        const size_t sp = line.rfind(' ');
-        if (sp != std::string::npos && line.compare(0, sp, key) == 0 && sp == key.size())
-            found = std::atoi(line.c_str() + sp + 1);
-    }
+    std::string line, found;
+    const std::string head = key + kCacheSep;
+    while (std::getline(in, line))
+        if (line.compare(0, head.size(), head) == 0) found = line.substr(head.size());
     return found;
 }
 
 // Replaces (or adds) key's line; the file is rewritten through a temporary
 // file and a rename, so readers never see a partial file.  Failures to
 // write leave the cache as it was (the choice still applies to this batch).
-void cache_store(const std::string &key, int value) {
+void cache_store(const std::string &key, const std::string &value) {
     const std::string path = autotune_cache_path();
     if (path.empty()) return;
     std::lock_guard<std::mutex> lock(g_cache_mu);
     std::vector<std::string> lines;
+    const std::string head = key + kCacheSep;
     {
         std::ifstream in(path);
         std::string line;
-        while (std::getline(in, line)) {
-            const size_t sp = line.rfind(' ');
-            if (!(sp != std::string::npos && sp == key.size() && line.compare(0, sp, key) == 0))
-                lines.push_back(line);
-        }
+        while (std::getline(in, line))
+            if (line.compare(0, head.size(), head) != 0) lines.push_back(line);
     }
-    lines.push_back(key + " " + std::to_string(value));
+    lines.push_back(head + value);
     const size_t slash = path.rfind('/');
     if (slash != std::string::npos && slash > 0) {
         std::string dir = path.substr(0, slash);
@@ -1635,13 +1648,21 @@ gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *ro
                 HIPC(hipMemcpyAsync(B->col, col_idx, nnz * 4, hipMemcpyDeviceToDevice, s));
                 HIPC(hipMemcpyAsync(B->val, values, nnz * vb, hipMemcpyDeviceToDevice, s));
             }
-            HIPC(hipMemsetAsync(B->status, 0, 4, s));
+            HIPC(hipMemsetAsync(B->status, 0, 8, s));
             HIPC(batch_validate(s, nsys, B->row_off, B->nnz_off, B->rp_local, B->col, B->status));
             if (read_int(ctx, B->status))
                 fail(GKO_ERR_INVALID_ARG, "malformed system (offsets or column indices)");
+            B->max_row_len = read_int(ctx, B->status + 1);
             B->block = max_m <= 256 ? 64 : 128;
-            const int cached = cache_lookup(batch_cache_key(B));
-            if (cached == 64 || cached == 128 || cached == 256 || cached == 512) B->block = cached;
+            // a stored "block lds_mode" choice for this architecture and shape
+            int cb = 0, cm = 0;
+            const std::string cv = cache_lookup(batch_cache_key(B));
+            if (std::sscanf(cv.c_str(), "%d %d", &cb, &cm) == 2 &&
+                (cb == 64 || cb == 128 || cb == 256 || cb == 512) && (cm == 0 || cm == 1)) {
+                B->want_lean = cm == 1;
+                B->block = cb;
+            }
+            batch_use_block(B, B->block);
         } catch (...) {
             B->free_all();
             delete B;
@@ -1664,7 +1685,7 @@ gko_status gko_batch_set_block(gko_batch B, int32_t block) {
         require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
         require(block == 64 || block == 128 || block == 256 || block == 512, GKO_ERR_INVALID_ARG,
                 "block must be 64, 128, 256 or 512");
-        B->block = block;
+        batch_use_block(B, block);
     });
 }
 
@@ -1675,9 +1696,29 @@ gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
                 "null batch or output");
         const vt t = B->dt == GKO_F64 ? vt::f64 : vt::f32;
         int r = 0;
-        HIPC(batch_resident(t, B->block, B->max_m, &r));
+        HIPC(batch_resident(t, B->block, B->max_m, B->lean, &r));
         *resident_workgroups = r;
-        *lds_bytes_per_workgroup = (int64_t)batch_lds_bytes(t, B->max_m);
+        *lds_bytes_per_workgroup = (int64_t)batch_lds_bytes(t, B->max_m, B->lean);
+    });
+}
+
+gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode) {
+    return guarded([&] {
+        require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
+        require(mode == GKO_BATCH_LDS_ALL || mode == GKO_BATCH_LDS_DIRECTION, GKO_ERR_INVALID_ARG,
+                "unknown LDS mode");
+        require(mode == GKO_BATCH_LDS_ALL || batch_lean_ok(B, B->block), GKO_ERR_UNSUPPORTED,
+                "direction-only LDS needs FP64 values and every system in the register cache at "
+                "this workgroup size");
+        B->want_lean = mode == GKO_BATCH_LDS_DIRECTION;
+        batch_use_block(B, B->block);
+    });
+}
+
+gko_status gko_batch_get_lds_mode(gko_batch B, int32_t *mode) {
+    return guarded([&] {
+        require(B && mode, GKO_ERR_INVALID_ARG, "null batch or output");
+        *mode = B->lean ? GKO_BATCH_LDS_DIRECTION : GKO_BATCH_LDS_ALL;
     });
 }
 
@@ -1707,22 +1748,28 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
     return guarded([&] {
         check_batch_solve_args(B, b, x, tol, maxit, iters_out, relres_out);
         const int cand[4] = {64, 128, 256, 512};
-        int best = B->block;
+        int best = B->block, best_mode = B->lean ? 1 : 0;
         float best_ms = std::numeric_limits<float>::infinity();
-        for (int j = 0; j < 4; ++j) {
-            B->block = cand[j];
-            float ms = 0.f;
-            (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);  // warm-up
-            (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, &ms);
-            if (times_ms) times_ms[j] = ms;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best = cand[j];
+        for (int j = 0; j < 4; ++j)
+            for (int mode = 0; mode < 2; ++mode) {
+                float ms = std::numeric_limits<float>::infinity();
+                if (mode == 0 || batch_lean_ok(B, cand[j])) {
+                    B->want_lean = mode == 1;
+                    batch_use_block(B, cand[j]);
+                    (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);  // warm-up
+                    (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, &ms);
+                }
+                if (times_ms) times_ms[2 * j + mode] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best = cand[j];
+                    best_mode = mode;
+                }
             }
-        }
-        B->block = best;
+        B->want_lean = best_mode == 1;
+        batch_use_block(B, best);
         if (block_out) *block_out = best;
-        cache_store(batch_cache_key(B), best);
+        cache_store(batch_cache_key(B), std::to_string(best) + " " + std::to_string(best_mode));
     });
 }
 

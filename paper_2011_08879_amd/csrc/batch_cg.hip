@@ -88,8 +88,6 @@ __device__ inline double spmv_rows(const sys_view &S, const VA *__restrict__ val
 // with more rows or longer rows are read from memory every iteration.
 template <int T>
 constexpr int batch_cache_rows() { return 1024 / T < 4 ? 1024 / T : 4; }
-constexpr int kBatchCacheLen = 5;
-
 template <typename VA, int T>
 struct sys_regs {
     static constexpr int R = batch_cache_rows<T>(), L = kBatchCacheLen;
@@ -162,7 +160,9 @@ __device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val, V
 // LDS then serves the row's p gathers and one p store, against those plus
 // eight vector reads and writes with every vector in LDS.  x comes in and
 // goes out in LDS (own rows); r starts from rhs (own rows, LDS) and p = r.
-template <typename VA, typename VV, int T>
+// LEAN: x starts at zero in registers and rhs is read from global memory, so
+// p is the only vector in LDS; on return x is left in p's place.
+template <typename VA, typename VV, int T, bool LEAN = false>
 __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, const VV *rhs,
                                 VV *p, double rhs_norm2, double stop2, int maxit,
                                 double (*red2)[T / kWave], int *flag) {
@@ -171,7 +171,7 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int i = threadIdx.x + j * T;
-        xr[j] = i < m ? x[i] : VV(0);
+        xr[j] = (LEAN || i >= m) ? VV(0) : x[i];
         rr_[j] = i < m ? rhs[i] : VV(0);
         pr[j] = rr_[j];
         if (i < m) p[i] = pr[j];
@@ -221,15 +221,18 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
         }
         __syncthreads();
     }
+    // every read of p ended before the last barrier the loop passed
 #pragma unroll
     for (int j = 0; j < R; ++j) {
         const int i = threadIdx.x + j * T;
-        if (i < m) x[i] = xr[j];
+        if (i < m) (LEAN ? p : x)[i] = xr[j];
     }
     return it;
 }
 
-template <typename VA, int T>
+// LEAN (FP64 batches whose every system fits the register cache): only the
+// direction p, later x, is in LDS, m doubles per workgroup instead of 4m.
+template <typename VA, int T, bool LEAN>
 __global__ __launch_bounds__(T) void batch_cg_kernel(
     int64_t nsys, const int64_t *__restrict__ row_off, const int64_t *__restrict__ nnz_off,
     const int32_t *__restrict__ rp_local, const int32_t *__restrict__ col,
@@ -263,7 +266,14 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
         const bool cached = regs.load(S, A, red);
         int its = 0, flag = 0;
         double *x64 = lds;            // m doubles
-        if constexpr (!kRefine) {
+        if constexpr (LEAN) {
+            // the host chooses LEAN only when every system is cached
+            if (cached)
+                its = cg_cached<VA, double, T, true>(S.m, regs, nullptr, bs, x64, bb,
+                                                     tol * tol * bb, maxit, red2, &flag);
+            else
+                flag = 2;
+        } else if constexpr (!kRefine) {
             double *r = x64 + S.m, *p = r + S.m, *q = p + S.m;
             for (int i = threadIdx.x; i < S.m; i += T) {
                 x64[i] = 0.0;
@@ -348,6 +358,7 @@ __global__ void batch_validate_kernel(int64_t nsys, const int64_t *__restrict__ 
                                       const int64_t *__restrict__ nnz_off,
                                       const int32_t *__restrict__ rp_local,
                                       const int32_t *__restrict__ col, int *err) {
+    int longest = 0;
     const int64_t sid = blockIdx.x;
     if (sid >= nsys) return;
     const int64_t m = row_off[sid + 1] - row_off[sid];
@@ -358,11 +369,14 @@ __global__ void batch_validate_kernel(int64_t nsys, const int64_t *__restrict__ 
     if (threadIdx.x == 0 && (rp[0] != 0 || (int64_t)rp[m] != nz)) bad = 1;
     for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
         if (rp[i + 1] < rp[i]) bad = 1;
-        else
+        else {
+            if (rp[i + 1] - rp[i] > longest) longest = rp[i + 1] - rp[i];
             for (int32_t k = rp[i]; k < rp[i + 1]; ++k)
                 if (c[k] < 0 || c[k] >= m) bad = 1;
+        }
     }
     if (bad) atomicOr(err, 1);
+    if (longest) atomicMax(err + 1, longest);  // err[1]: the longest row of any system
 }
 
 hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
@@ -378,71 +392,83 @@ __global__ void batch_reset_kernel(unsigned *counter, int *status) {
     *status = 0;
 }
 
-size_t batch_lds_bytes(vt t, int64_t max_m) {
+size_t batch_lds_bytes(vt t, int64_t max_m, bool lean) {
+    if (lean) return (size_t)max_m * 8;
     return (size_t)max_m * (t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4);
 }
 
-// Workgroups of batch_cg_kernel<VA, T> resident on the device at once.
-template <typename VA, int T>
+bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len) {
+    if (t != vt::f64 || block <= 0) return false;
+    const int64_t rows = (1024 / block < 4 ? 1024 / block : 4) * (int64_t)block;
+    return max_m <= rows && max_row_len <= kBatchCacheLen;
+}
+
+// Workgroups of batch_cg_kernel<VA, T, LEAN> resident on the device at once.
+template <typename VA, int T, bool LEAN>
 static hipError_t resident_t(int64_t max_m, int *out) {
-    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, max_m);
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, max_m, LEAN);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T>, T, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T, LEAN>, T,
+                                                         lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     *out = cus * per_cu;
     return hipSuccess;
 }
 
-template <typename VA>
+template <typename VA, bool LEAN>
 static hipError_t resident_v(int block, int64_t max_m, int *out) {
     switch (block) {
-        case 64: return resident_t<VA, 64>(max_m, out);
-        case 128: return resident_t<VA, 128>(max_m, out);
-        case 256: return resident_t<VA, 256>(max_m, out);
-        case 512: return resident_t<VA, 512>(max_m, out);
+        case 64: return resident_t<VA, 64, LEAN>(max_m, out);
+        case 128: return resident_t<VA, 128, LEAN>(max_m, out);
+        case 256: return resident_t<VA, 256, LEAN>(max_m, out);
+        case 512: return resident_t<VA, 512, LEAN>(max_m, out);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t batch_resident(vt t, int block, int64_t max_m, int *workgroups) {
-    return t == vt::f64 ? resident_v<double>(block, max_m, workgroups)
-                        : resident_v<float>(block, max_m, workgroups);
+hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, int *workgroups) {
+    if (lean && t != vt::f64) return hipErrorInvalidValue;
+    if (t == vt::f32) return resident_v<float, false>(block, max_m, workgroups);
+    return lean ? resident_v<double, true>(block, max_m, workgroups)
+                : resident_v<double, false>(block, max_m, workgroups);
 }
 
-template <typename VA, int T>
+template <typename VA, int T, bool LEAN>
 static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
-    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m);
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m, LEAN);
     int resident = 0;
-    hipError_t e = resident_t<VA, T>(a.max_m, &resident);
+    hipError_t e = resident_t<VA, T, LEAN>(a.max_m, &resident);
     if (e != hipSuccess) return e;
     int64_t grid = resident;
     if (grid > a.nsys) grid = a.nsys;
     if (grid < 1) grid = 1;
     batch_reset_kernel<<<1, 1, 0, s>>>(a.counter, a.status);
-    batch_cg_kernel<VA, T><<<(unsigned)grid, T, lds, s>>>(
+    batch_cg_kernel<VA, T, LEAN><<<(unsigned)grid, T, lds, s>>>(
         a.nsys, a.row_off, a.nnz_off, a.rp_local, a.col, static_cast<const VA *>(a.val), a.order,
         a.counter, a.b, a.x, a.tol, a.maxit, a.iters, a.relres, a.status);
     return hipGetLastError();
 }
 
-template <typename VA>
+template <typename VA, bool LEAN>
 static hipError_t launch_batch_v(hipStream_t s, const batch_args &a) {
     switch (a.block) {
-        case 64: return launch_batch_t<VA, 64>(s, a);
-        case 128: return launch_batch_t<VA, 128>(s, a);
-        case 256: return launch_batch_t<VA, 256>(s, a);
-        case 512: return launch_batch_t<VA, 512>(s, a);
+        case 64: return launch_batch_t<VA, 64, LEAN>(s, a);
+        case 128: return launch_batch_t<VA, 128, LEAN>(s, a);
+        case 256: return launch_batch_t<VA, 256, LEAN>(s, a);
+        case 512: return launch_batch_t<VA, 512, LEAN>(s, a);
         default: return hipErrorInvalidValue;
     }
 }
 
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a) {
     if (a.nsys == 0) return hipSuccess;
-    return t == vt::f64 ? launch_batch_v<double>(s, a) : launch_batch_v<float>(s, a);
+    if (a.lean && !batch_lean_fits(t, a.block, a.max_m, a.max_row_len)) return hipErrorInvalidValue;
+    if (t == vt::f32) return launch_batch_v<float, false>(s, a);
+    return a.lean ? launch_batch_v<double, true>(s, a) : launch_batch_v<double, false>(s, a);
 }
 
 }  // namespace gko

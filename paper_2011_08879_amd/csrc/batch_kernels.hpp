@@ -33,17 +33,26 @@ struct batch_args {
     double *relres;
     int *status;
     int64_t max_m;
+    int64_t max_row_len;      // longest row of any system
     int block;                // workgroup size: 64, 128, 256 or 512
+    bool lean;                // only p in LDS (batch_lean_fits must hold)
 };
 
-size_t batch_lds_bytes(vt t, int64_t max_m);
-// err: device int set to 1 on a malformed system.
+// Rows of up to this many entries are held in registers for a system's solve.
+constexpr int kBatchCacheLen = 5;
+
+size_t batch_lds_bytes(vt t, int64_t max_m, bool lean);
+// Whether every system of the batch fits the register cache at this
+// workgroup size (FP64 only), so that only p needs LDS.
+bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len);
+// err[0]: set to 1 on a malformed system; err[1]: atomicMax of the longest
+// row (both must start at zero).
 hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
                           const int64_t *nnz_off, const int32_t *rp_local, const int32_t *col,
                           int *err);
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a);
 // Workgroups of the persistent kernel resident at once (its grid for batches
 // of at least that many systems).
-hipError_t batch_resident(vt t, int block, int64_t max_m, int *workgroups);
+hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, int *workgroups);
 
 }  // namespace gko

@@ -93,6 +93,8 @@ def test_null_handles_rejected(lib):
         "gko_batch_get_block": (None, None),
         "gko_batch_autotune": (None, None, None, d(1e-10), 10, None, None, None, None),
         "gko_batch_launch_info": (None, None, None),
+        "gko_batch_set_lds_mode": (None, 0),
+        "gko_batch_get_lds_mode": (None, None),
         "gko_matrix_features": (None, None),
         "gko_autotune_format": (None, None, None),
         "gko_mlp_create": (None, None, None),

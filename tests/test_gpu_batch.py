@@ -100,7 +100,23 @@ def test_batch_deterministic_and_autotune(g, orc, gen_mod):
     x = dev(np.zeros(B.xstar.shape))
     blk, times = G.autotune(dev(b), x)
     assert blk in (64, 128, 256, 512) and G.block == blk
-    assert all(t > 0 for t in times.values()) and times[blk] == min(times.values())
+    assert all(t > 0 for t in times.values())
+    assert times[(blk, G.lds_mode)] == min(times.values())
+    # direction-only LDS fits FP64 systems of up to 4 * 256 rows at 256 threads, not at 64
+    assert np.isfinite(times[(256, "direction")]) and np.isinf(times[(64, "direction")])
+    # both LDS modes give the oracle's solutions
+    for mode in ("all", "direction"):
+        G.block = 256
+        G.lds_mode = mode
+        x = dev(np.zeros(B.xstar.shape))
+        st, it, rr = G.solve(dev(b), x)
+        assert st == g.OK and G.lds_mode == mode
+        assert float(host(rr).max()) <= 1e-10
+        assert np.abs(host(x) - B.xstar).max() <= 1e-6 * np.abs(B.xstar).max()
+    G.block = 64
+    assert G.lds_mode == "all"
+    with pytest.raises(g.GkoError):
+        G.lds_mode = "direction"
 
 
 def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
@@ -116,16 +132,19 @@ def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
     blk, _ = G.autotune(b, dev(np.zeros(B.xstar.shape)))
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("batch_cg gfx950")
-    key = lines[0].rsplit(" ", 1)[0]
-    assert lines[0] == "%s %d" % (key, blk)
+    key, val = lines[0].split(" = ")
+    mode = 1 if G.lds_mode == "direction" else 0
+    assert val == "%d %d" % (blk, mode)
     assert " f64 nsys=200 rows=%d nnz=%d " % (B.row_off[-1], B.nnz_off[-1]) in key
     # a stored choice other than the default is what a new batch of this shape takes
     other = 512 if blk != 512 else 256
-    path.write_text("%s %d\n" % (key, other))
-    assert g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val).block == other
+    path.write_text("%s = %d 0\n" % (key, other))
+    H = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val)
+    assert H.block == other and H.lds_mode == "all"
     # retuning replaces the line; a batch of another shape keeps its default
     G.autotune(b, dev(np.zeros(B.xstar.shape)))
-    assert path.read_text().splitlines() == ["%s %d" % (key, G.block)]
+    mode = 1 if G.lds_mode == "direction" else 0
+    assert path.read_text().splitlines() == ["%s = %d %d" % (key, G.block, mode)]
     C = gen_mod.batch_systems(150, master_seed=13)
     default = 64 if int(C.m.max()) <= 256 else 128
     assert g.Batch(C.row_off, C.nnz_off, C.row_ptr, C.col, C.val).block == default
