@@ -19,6 +19,8 @@ Usage:
   python -m paper_2011_08879_amd.prof_summary --trace G0.json:T.csv \\
       --pmc G1.json:C1.csv [--pmc G2.json:C2.csv ...] --md OUT.md --json OUT.json \\
       --command "..."
+  python -m paper_2011_08879_amd.prof_summary stats KERNEL_STATS.csv [TOP]
+  python -m paper_2011_08879_amd.prof_summary counters COUNTER_COLLECTION.csv NAME_PART
 """
 from __future__ import annotations
 
@@ -172,7 +174,49 @@ def to_markdown(res, command):
     return "\n".join(head + lines) + "\n"
 
 
+def kernel_stats_table(path, top=25):
+    """Markdown table of rocprofv3's kernel_stats.csv: the `top` kernels by
+    total time (calls, total ms, mean us, share)."""
+    rows = []
+    with open(path) as fh:
+        for r in csv.DictReader(fh):
+            rows.append((float(r["TotalDurationNs"]), int(r["Calls"]), float(r["AverageNs"]),
+                         float(r["Percentage"]), _short(r["Name"])))
+    rows.sort(reverse=True)
+    out = ["| kernel | calls | total ms | mean us | share % |", "|---|---:|---:|---:|---:|"]
+    for tot, calls, avg, pct, name in rows[:top]:
+        out.append("| %s | %d | %.2f | %.2f | %.2f |" % (name, calls, tot / 1e6, avg / 1e3, pct))
+    return "\n".join(out) + "\n"
+
+
+def kernel_counters_table(path, match):
+    """Per kernel instantiation whose name contains `match`: dispatches and
+    the mean of every counter over them (counter CSV of rocprofv3)."""
+    per = collections.OrderedDict()
+    for kern, grid, ctr in read_counters(path):
+        if match not in kern:
+            continue
+        e = per.setdefault("%s[grid %d]" % (_short(kern), grid), [0, {}])
+        e[0] += 1
+        for c, v in ctr.items():
+            e[1][c] = e[1].get(c, 0.0) + v
+    names = sorted({c for _, (n, d) in per.items() for c in d})
+    out = ["| kernel | dispatches | " + " | ".join(names) + " |",
+           "|---|---:|" + "---:|" * len(names)]
+    for k, (n, d) in per.items():
+        out.append("| %s | %d | " % (k, n) + " | ".join("%.4g" % (d.get(c, 0.0) / n) for c in names)
+                   + " |")
+    return "\n".join(out) + "\n"
+
+
 def main():
+    import sys
+    if len(sys.argv) > 1 and sys.argv[1] == "stats":
+        print(kernel_stats_table(sys.argv[2], int(sys.argv[3]) if len(sys.argv) > 3 else 25))
+        return
+    if len(sys.argv) > 1 and sys.argv[1] == "counters":
+        print(kernel_counters_table(sys.argv[2], sys.argv[3]))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--trace", default="", help="GROUPS.json:kernel_trace.csv")
     ap.add_argument("--pmc", action="append", default=[], help="GROUPS.json:counter_collection.csv")
