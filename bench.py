@@ -273,8 +273,34 @@ def stream_probe(g, torch, n=1 << 27, reps=10):
         ms = e0.elapsed_time(e1) / reps
         out[name + "_GB/s"] = round(nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b, c
+    out["gather"] = gather_probe(g, torch)
     torch.cuda.empty_cache()
     return out
+
+
+def gather_probe(g, torch, n=16_000_000, m=1_000_000, reps=10):
+    """The random-gather ceiling: y[i] = x[idx[i]] with 16M indices uniform over
+    an 8 MB x (the random sweep matrix's x and entry count), index and output
+    streamed.  Reported as gathers per second and as the streamed bytes
+    (4 + 8 per gather, plus x once) per second; the L2's fetch for it comes
+    from the profiles' DRAM request counters."""
+    rng = np.random.default_rng(41)
+    idx = torch.from_numpy(rng.integers(0, m, n).astype(np.int32)).cuda()
+    x = torch.rand(m, dtype=torch.float64, device="cuda")
+    y = torch.empty(n, dtype=torch.float64, device="cuda")
+    g.gather_probe(x, idx, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        g.gather_probe(x, idx, y)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    nb = n * 12 + m * 8
+    return {"n": n, "x_bytes": m * 8, "ms": round(ms, 5),
+            "gathers_per_s": round(n / (ms * 1e-3), 1),
+            "streamed_GB/s": round(nb / (ms * 1e-3) / 1e9, 1)}
 
 
 def poisson256_inputs(gen):
@@ -775,8 +801,9 @@ def run_sweep(args, g, gen, torch, result):
         result["calib_copy_bytes"] = nel * 8
         del src, dst
     result["stream"] = stream_probe(g, torch)
-    log("stream probe: copy %.0f GB/s, triad %.0f GB/s" % (result["stream"]["copy_GB/s"],
-                                                           result["stream"]["triad_GB/s"]))
+    log("stream probe: copy %.0f GB/s, triad %.0f GB/s; gather probe %.3f ms" %
+        (result["stream"]["copy_GB/s"], result["stream"]["triad_GB/s"],
+         result["stream"]["gather"]["ms"]))
     roofline["frac_of_stream_copy"] = round(achieved / result["stream"]["copy_GB/s"], 4)
     result["config"]["frac_of_stream_copy"] = round(value / result["stream"]["copy_GB/s"], 4)
     result["sellp"] = run_sellp(args, g, torch, base, mats, per_kernel)
@@ -793,18 +820,23 @@ def run_sweep(args, g, gen, torch, result):
 
 def profile_sweep(args, g, gen, torch):
     """Launch sequence for rocprofv3 runs: every sweep SpMV (and SELL-P on the
-    stencil) `reps` times in a group of its own, each group opened by a small
-    library COPY of 512 (k+1) doubles (grid 256 (k+1) threads) that marks
-    group k, and a 1 GiB COPY last (group "copy_1GiB") as the counters'
-    calibration transfer.  Returns the group names in order."""
+    stencil) `reps` times in a group of its own, then the random-gather probe,
+    each group opened by a small library COPY of 512 (k+1) doubles (grid
+    256 (k+1) threads) that marks group k, and a 1 GiB COPY last (group
+    "copy_1GiB") as the counters' calibration transfer.  Returns the groups."""
     mats, skipped, inputs, base = build_sweep(g, gen, torch)
     st = base["stencil27_128"].clone().convert("sellp")
     d = st.describe()
     mats.append({"matrix": "stencil27_128", "format": "sellp", "M": st,
                  "x": mats[0]["x"], "y": torch.empty(d.n_rows, dtype=torch.float64, device="cuda"),
                  "desc": d, "bytes": spmv_bytes(d)})
-    sep_src = torch.zeros(512 * (len(mats) + 2), dtype=torch.float64, device="cuda")
+    sep_src = torch.zeros(512 * (len(mats) + 3), dtype=torch.float64, device="cuda")
     sep_dst = torch.empty_like(sep_src)
+    rng = np.random.default_rng(41)
+    gn, gm = 16_000_000, 1_000_000
+    gidx = torch.from_numpy(rng.integers(0, gm, gn).astype(np.int32)).cuda()
+    gx = torch.rand(gm, dtype=torch.float64, device="cuda")
+    gy = torch.empty(gn, dtype=torch.float64, device="cuda")
     groups = []
     for k, e in enumerate(mats):
         g.stream(g.STREAM_COPY, sep_src[:512 * (k + 1)], sep_dst)
@@ -812,7 +844,14 @@ def profile_sweep(args, g, gen, torch):
             g.spmv(e["M"], 1.0, e["x"], 0.0, e["y"])
         groups.append({"name": "%s/%s" % (e["matrix"], e["format"]), "launches": args.steps,
                        "alg_bytes": int(e["bytes"])})
-    g.stream(g.STREAM_COPY, sep_src[:512 * (len(mats) + 1)], sep_dst)
+    # the random-gather probe as a group of its own
+    k = len(mats)
+    g.stream(g.STREAM_COPY, sep_src[:512 * (k + 1)], sep_dst)
+    for _ in range(args.steps):
+        g.gather_probe(gx, gidx, gy)
+    groups.append({"name": "gather_probe/16M_of_8MB", "launches": args.steps,
+                   "alg_bytes": gn * 12 + gm * 8})
+    g.stream(g.STREAM_COPY, sep_src[:512 * (k + 2)], sep_dst)
     nel = (1 << 30) // 8
     src = torch.ones(nel, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)

@@ -197,6 +197,15 @@ typedef enum gko_stream_op { GKO_STREAM_COPY = 0, GKO_STREAM_TRIAD = 1 } gko_str
 gko_status gko_stream(gko_context ctx, gko_stream_op op, int64_t n, const double *a,
                       const double *b, double s, double *c);
 
+/* Random-gather probe, the ceiling of an SpMV whose x gathers miss the L2:
+ * y[i] = x[idx[i]] for i < n (x: m FP64 values, idx: n int32 indices; an
+ * index outside [0, m) reads 0).  Index and output streams bypass the caches
+ * (non-temporal) as an SpMV's matrix streams do.  idx and y 16-byte aligned,
+ * 1 <= m < 2^28, x and y must not overlap (else GKO_ERR_INVALID_ARG).
+ * Asynchronous. */
+gko_status gko_gather_probe(gko_context ctx, int64_t n, const double *x, int64_t m,
+                            const int32_t *idx, double *y);
+
 /* ---------------------------------------------------------------- Krylov solvers (Sec. 6.2) */
 
 typedef enum gko_precision { GKO_PREC_FP64 = 0, GKO_PREC_MIXED_IR = 1 } gko_precision;

@@ -87,6 +87,7 @@ _SIGS = {
     "gko_dot": [_vp, _st, _i64, _vp, _vp, _vp],
     "gko_norm2": [_vp, _st, _i64, _vp, _vp],
     "gko_stream": [_vp, _st, _i64, _vp, _vp, _f64, _vp],
+    "gko_gather_probe": [_vp, _i64, _vp, _i64, _vp, _vp],
     "gko_context_set_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solver_opts": [_vp, ctypes.POINTER(SolverOpts)],
     "gko_context_get_solve_info": [_vp, ctypes.POINTER(_SolveInfo)],
@@ -159,6 +160,19 @@ def _torch():
 
 def _ptr(t) -> int:
     return 0 if t is None else int(t.data_ptr())
+
+
+def _vec(t, n: int, dtype, name: str):
+    """The C-ABI takes bare device pointers, so the binding checks what it can
+    see: `t` is a contiguous CUDA tensor of `dtype` with at least n elements."""
+    if t is None:
+        raise ValueError("%s: a device tensor is required" % name)
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("%s: expected a contiguous CUDA tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s: expected %s, got %s" % (name, dtype, t.dtype))
+    if t.numel() < n:
+        raise ValueError("%s: %d elements, at least %d needed" % (name, t.numel(), n))
 
 
 def _dtype_code(t) -> int:
@@ -278,6 +292,14 @@ class Matrix:
     def __init__(self, handle, ctx: Context):
         self.handle = handle
         self.ctx = ctx
+        self._dims = None
+
+    def _shape_dtype(self):
+        if self._dims is None:
+            d = self.describe()
+            torch = _torch()
+            self._dims = (d.n_rows, d.n_cols, torch.float64 if d.dtype == "f64" else torch.float32)
+        return self._dims
 
     @classmethod
     def from_csr(cls, row_ptr, col, val, n_cols: int | None = None, ctx: Context | None = None,
@@ -391,6 +413,9 @@ class Matrix:
 # ----------------------------------------------------------------------------- operations
 def spmv(A: Matrix, alpha: float, x, beta: float, y):
     """y <- alpha A x + beta y (asynchronous on the current stream)."""
+    n, m, dt = A._shape_dtype()
+    _vec(x, m, dt, "x")
+    _vec(y, n, dt, "y")
     _check(_lib.gko_spmv(A.handle, alpha, _ptr(x), beta, _ptr(y)))
     return y
 
@@ -402,6 +427,8 @@ def convert(A: Matrix, fmt: str) -> Matrix:
 def dot(x, y, ctx: Context | None = None):
     """x.y accumulated in FP64; returns a 0-d float64 device tensor."""
     torch = _torch()
+    _vec(x, 0, x.dtype, "x")
+    _vec(y, x.numel(), x.dtype, "y")
     ctx = ctx or default_context()
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(_lib.gko_dot(ctx.handle, _dtype_code(x), x.numel(), _ptr(x), _ptr(y), _ptr(out)))
@@ -410,6 +437,7 @@ def dot(x, y, ctx: Context | None = None):
 
 def norm2(x, ctx: Context | None = None):
     torch = _torch()
+    _vec(x, 0, x.dtype, "x")
     ctx = ctx or default_context()
     out = torch.empty((), dtype=torch.float64, device=x.device)
     _check(_lib.gko_norm2(ctx.handle, _dtype_code(x), x.numel(), _ptr(x), _ptr(out)))
@@ -421,12 +449,21 @@ STREAM_COPY, STREAM_TRIAD = 0, 1
 
 def stream(op: int, a, c, b=None, s: float = 0.0, ctx: Context | None = None):
     """Bandwidth probe on float64 device tensors: COPY c = a, TRIAD c = a + s b."""
+    torch = _torch()
+    _vec(a, 0, torch.float64, "a")
+    _vec(c, a.numel(), torch.float64, "c")
+    if op == STREAM_TRIAD:
+        _vec(b, a.numel(), torch.float64, "b")
     ctx = ctx or default_context()
     _check(_lib.gko_stream(ctx.handle, op, a.numel(), _ptr(a), _ptr(b), s, _ptr(c)))
     return c
 
 
 def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):
+    torch = _torch()
+    n = A._shape_dtype()[0]
+    _vec(b, n, torch.float64, "b")
+    _vec(x, n, torch.float64, "x")
     st = fn(A.handle, _ptr(b), _ptr(x), tol, maxit)
     err = last_error() if st != OK else ""   # read before the next call clears it
     info = A.ctx.solve_info()
@@ -436,6 +473,17 @@ def _solve(fn, A: Matrix, b, x, tol: float, maxit: int, raise_on_failure: bool):
     if st != OK and raise_on_failure:
         raise GkoError(st, err)
     return info
+
+
+def gather_probe(x, idx, y, ctx: Context | None = None):
+    """y[i] = x[idx[i]] (FP64 x and y, int32 idx; CUDA tensors): the random-gather ceiling."""
+    torch = _torch()
+    _vec(x, 1, torch.float64, "x")
+    _vec(idx, 0, torch.int32, "idx")
+    _vec(y, idx.numel(), torch.float64, "y")
+    ctx = ctx or default_context()
+    _check(_lib.gko_gather_probe(ctx.handle, idx.numel(), _ptr(x), x.numel(), _ptr(idx), _ptr(y)))
+    return y
 
 
 def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure: bool = False):

@@ -2091,6 +2091,21 @@ gko_status gko_stream(gko_context ctx, gko_stream_op op, int64_t n, const double
     });
 }
 
+gko_status gko_gather_probe(gko_context ctx, int64_t n, const double *x, int64_t m,
+                            const int32_t *idx, double *y) {
+    return guarded([&] {
+        require(ctx != nullptr, GKO_ERR_INVALID_ARG, "null context");
+        require(n >= 0 && m >= 1 && m < (int64_t(1) << 28), GKO_ERR_INVALID_ARG,
+                "n >= 0 and 1 <= m < 2^28 required");
+        require(n == 0 || (x && idx && y), GKO_ERR_INVALID_ARG, "null array");
+        require((((uintptr_t)idx | (uintptr_t)y) & 15) == 0, GKO_ERR_INVALID_ARG,
+                "idx and y must be 16-byte aligned");
+        require(!overlap(x, size_t(m) * 8, y, size_t(n) * 8), GKO_ERR_INVALID_ARG,
+                "x and y must not overlap");
+        HIPC(gather_probe(ctx->stream, n, x, m, idx, y));
+    });
+}
+
 gko_status gko_matrix_features(gko_matrix A, float *features) {
     return guarded([&] {
         require(A && features, GKO_ERR_INVALID_ARG, "null matrix or output");

@@ -209,6 +209,57 @@ hipError_t stream_op(hipStream_t s, int op, int64_t n, const double *a, const do
     return hipGetLastError();
 }
 
+// Random-gather probe: y[i] = x[idx[i]].  A wavefront takes 256 consecutive
+// elements as two runs of 128, each lane two adjacent elements per run, so
+// every index load (8 bytes a lane) and every store (16 bytes a lane) covers
+// one contiguous range; the four gathers are issued before any result is
+// used.  x is read through a buffer resource of m doubles, so an index
+// outside [0, m) reads 0 instead of faulting.  Index and output streams are
+// non-temporal, so the L2 holds x the way an SpMV's gathers do.
+typedef int32_t probe_i2 __attribute__((ext_vector_type(2)));
+typedef double probe_d2 __attribute__((ext_vector_type(2)));
+constexpr int kProbeBlock = 256;
+
+__device__ inline double probe_gather(__amdgpu_buffer_rsrc_t rx, int32_t c) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, c * 8, 0, 0));
+}
+
+__global__ __launch_bounds__(kProbeBlock) void gather_probe_kernel(
+    int64_t n, const double *__restrict__ x, int64_t m, const int32_t *__restrict__ idx,
+    double *__restrict__ y) {
+    const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)x, (short)0, (int)(m * 8 < INT_MAX ? m * 8 : INT_MAX), 0x00020000);
+    const int64_t wave = ((int64_t)blockIdx.x * kProbeBlock + threadIdx.x) / kWave;
+    const int lane = threadIdx.x % kWave;
+    const int64_t i0 = wave * 256 + 2 * lane, i1 = i0 + 128;
+    if (wave * 256 + 256 <= n) {
+        const probe_i2 c0 = __builtin_nontemporal_load(reinterpret_cast<const probe_i2 *>(idx + i0));
+        const probe_i2 c1 = __builtin_nontemporal_load(reinterpret_cast<const probe_i2 *>(idx + i1));
+        probe_d2 v0, v1;
+        v0.x = probe_gather(rx, c0.x);
+        v0.y = probe_gather(rx, c0.y);
+        v1.x = probe_gather(rx, c1.x);
+        v1.y = probe_gather(rx, c1.y);
+        __builtin_nontemporal_store(v0, reinterpret_cast<probe_d2 *>(y + i0));
+        __builtin_nontemporal_store(v1, reinterpret_cast<probe_d2 *>(y + i1));
+    } else {
+        const int64_t e[4] = {i0, i0 + 1, i1, i1 + 1};
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (e[u] < n) y[e[u]] = probe_gather(rx, idx[e[u]]);
+    }
+}
+
+hipError_t gather_probe(hipStream_t s, int64_t n, const double *x, int64_t m, const int32_t *idx,
+                        double *y) {
+    if (n == 0) return hipSuccess;
+    const int64_t waves = (n + 255) / 256;  // 256 elements per wavefront
+    const int64_t per_block = kProbeBlock / kWave;
+    gather_probe_kernel<<<(unsigned)((waves + per_block - 1) / per_block), kProbeBlock, 0, s>>>(
+        n, x, m, idx, y);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------ CSR -> ELL / HYB
 template <typename V>
 __global__ void csr_to_ell_kernel(int64_t n, int64_t ld, const int32_t *__restrict__ rp,

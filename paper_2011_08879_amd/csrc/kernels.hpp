@@ -95,6 +95,10 @@ hipError_t max_row_len(hipStream_t s, int64_t n, const int32_t *rp, int *maxlen)
 // hist: maxlen+1 device ints, zero on entry.
 hipError_t row_len_hist(hipStream_t s, int64_t n, const int32_t *rp, int *hist, int64_t maxlen);
 // STREAM probe: op 0 c = a, op 1 c = a + sc * b (two roundings).
+// y[i] = x[idx[i]] for i < n; x holds m doubles (an index outside reads 0).
+// Requires 16-byte aligned idx and y and m * 8 < 2^31.
+hipError_t gather_probe(hipStream_t s, int64_t n, const double *x, int64_t m, const int32_t *idx,
+                        double *y);
 hipError_t stream_op(hipStream_t s, int op, int64_t n, const double *a, const double *b, double sc,
                      double *c);
 hipError_t csr_to_ell(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,

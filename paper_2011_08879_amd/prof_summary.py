@@ -166,12 +166,34 @@ def to_markdown(res, command):
     head = ["# SpMV sweep (FP64): kernel durations and HBM traffic", "",
             "Workload: one SpMV y = A x per group on the 27-point stencil 128^3 (n = 2,097,152, "
             "nnz = 55,742,968) and the lognormal random matrix (n = 10^6, mean 16, longest row "
-            "10,000), each format as the sweep stores it; one MI355X (gfx950). Durations: "
+            "10,000), each format as the sweep stores it, and the random-gather probe (y[i] = "
+            "x[idx[i]], 16M uniform int32 indices into an 8 MB FP64 x, index and output "
+            "streamed); one MI355X (gfx950). Durations: "
             "kernel trace, mean per dispatch. HBM bytes per SpMV: 32 x "
             "(TCC_EA0_RDREQ_DRAM_32B_sum, TCC_EA0_WRREQ_WRITE_DRAM_32B_sum), no scale factor.",
             "", "Kernel sources (sha256 over csrc/): `%s`." % res["source_sha256"], "",
             "Commands (repo root, `export TMPDIR=/tmp`):", "", "```", command, "```", "", cal, ""]
-    return "\n".join(head + lines) + "\n"
+    return "\n".join(head + lines + sq_table(res)) + "\n"
+
+
+# Shader counters per SpMV, summed over all CUs: instructions issued by kind,
+# cycles with LDS instructions active and lost to bank conflicts, and the
+# GPU's active cycles (GRBM_GUI_ACTIVE, summed over the 8 XCDs).
+SQ_COLUMNS = ("SQ_WAVES", "SQ_INSTS_VALU", "SQ_INSTS_VMEM_RD", "SQ_ACTIVE_INST_LDS",
+              "SQ_LDS_BANK_CONFLICT", "SQ_WAIT_INST_ANY", "SQ_BUSY_CYCLES", "GRBM_GUI_ACTIVE")
+
+
+def sq_table(res):
+    rows = [(n, r.get("counters_per_launch", {})) for n, r in res["kernels"].items()]
+    if not any("SQ_INSTS_VALU" in c for _, c in rows):
+        return []
+    out = ["", "Shader counters per SpMV (one pass of their own; sums over all CUs):", "",
+           "| matrix/format | " + " | ".join(SQ_COLUMNS) + " |",
+           "|---|" + "---:|" * len(SQ_COLUMNS)]
+    for n, c in rows:
+        out.append("| %s | " % n + " | ".join(
+            "%.4g" % c[k] if k in c else "-" for k in SQ_COLUMNS) + " |")
+    return out
 
 
 def kernel_stats_table(path, top=25):

@@ -77,6 +77,7 @@ def test_null_handles_rejected(lib):
         "gko_dot": (None, 0, 0, None, None, None),
         "gko_norm2": (None, 0, 0, None, None),
         "gko_stream": (None, 0, 0, None, None, d(1.0), None),
+        "gko_gather_probe": (None, 0, None, 1, None, None),
         "gko_context_set_solver_opts": (None, None),
         "gko_context_get_solver_opts": (None, None),
         "gko_context_get_solve_info": (None, None),
@@ -134,3 +135,37 @@ def test_missing_library_fails_loudly(tmp_path):
     code = "import sys; sys.path.insert(0, %r)\ntry:\n import paper_2011_08879_amd\nexcept ImportError as e:\n print('IMPORTERROR', e)\n" % str(tmp_path)
     out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True).stdout
     assert "IMPORTERROR" in out
+
+
+def test_binding_checks_vectors_before_the_library(lib):
+    """The C-ABI sees bare pointers, so the binding rejects host tensors, wrong
+    element types and short outputs before any library call."""
+    import torch
+    import paper_2011_08879_amd as g
+    x = torch.zeros(8, dtype=torch.float64)
+    idx = torch.zeros(8, dtype=torch.int32)
+    with pytest.raises(ValueError, match="CUDA"):
+        g.gather_probe(x, idx, x)                      # host tensors
+    with pytest.raises(ValueError, match="CUDA"):
+        g.stream(g.STREAM_COPY, x, x)
+    with pytest.raises(ValueError):
+        g.dot(x, x)
+    with pytest.raises(ValueError):
+        g.norm2(x)
+    with pytest.raises(ValueError, match="required"):
+        g._vec(None, 1, torch.float64, "y")
+    # the element-type and length checks, on a stand-in for a contiguous device tensor
+    class Dev:
+        def __init__(self, n, dtype):
+            self.is_cuda, self.dtype, self._n = True, dtype, n
+
+        def is_contiguous(self):
+            return True
+
+        def numel(self):
+            return self._n
+    with pytest.raises(TypeError):
+        g._vec(Dev(8, torch.float32), 8, torch.float64, "x")
+    with pytest.raises(ValueError, match="at least 9"):
+        g._vec(Dev(8, torch.float64), 9, torch.float64, "y")
+    g._vec(Dev(9, torch.float64), 9, torch.float64, "y")

@@ -295,6 +295,23 @@ def test_stream_probe_exact(g, gen_mod):
         assert np.array_equal(host(c), a[:m])
 
 
+def test_gather_probe_exact(g, gen_mod):
+    """y = x[idx] bit for bit, including a ragged tail; indices outside x read 0."""
+    import torch
+    m, n = 1_000_003, 2_000_001
+    x = gen_mod.uniform(1, m)
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, m, n).astype(np.int32)
+    idx[7] = -3
+    idx[n - 1] = m
+    y = dev(np.full(n, np.nan))
+    g.gather_probe(dev(x), dev(idx), y)
+    want = np.where((idx >= 0) & (idx < m), x[np.clip(idx, 0, m - 1)], 0.0)
+    assert np.array_equal(host(y).view(np.int64), want.view(np.int64))
+    with pytest.raises(g.GkoError):
+        g.gather_probe(dev(x), dev(idx)[1:], y[1:])     # idx and y off the 16-byte grid
+
+
 def test_solver_statuses_large_grids(g, gen_mod, ctx):
     """The failure statuses also come out right when the reductions finish in
     the separate finalize kernel (grids of more than 64 blocks)."""
