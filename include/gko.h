@@ -128,14 +128,16 @@ typedef struct gko_matrix_desc {
     int64_t ell_ld;        /* ELL / HYBRID: leading dimension, else 0 */
     int64_t coo_nnz;       /* COO: nnz; HYBRID: tail entries; else 0 */
     int64_t stored_bytes;  /* bytes of device storage held by the handle */
-    int32_t csr_kernel;    /* CSR: 0 = a thread per row (entries staged through LDS), else the
-                              lanes of the subwarp per row; other formats: -1 */
+    int32_t csr_kernel;    /* CSR: 0 = the row-per-thread kernel (entries staged through LDS,
+                              csr_row_lanes lanes per row), else the lanes of the subwarp per
+                              row reading its entries from memory; other formats: -1 */
     int32_t max_row_len;   /* longest row (-1 where not yet computed) */
     int64_t csr_long_rows; /* CSR: rows handed to the workgroup-per-row kernel, else 0 */
     int64_t sellp_slices;  /* SELLP: ceil(n_rows / sellp_slice), else 0 */
     int64_t sellp_slots;   /* SELLP: sets[sellp_slices], slots incl. padding, else 0 */
     int32_t sellp_slice;   /* SELLP: rows per slice (64), else 0 */
-    int32_t pad;
+    int32_t csr_row_lanes; /* CSR with csr_kernel 0: lanes per row (1 for a mean row length
+                              below 12, 4 below 56, else 8), else 0 */
     int64_t sellp_wide_slices; /* SELLP: slices wider than 512 slots, summed by column chunks */
 } gko_matrix_desc;
 gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out);

@@ -50,7 +50,7 @@ class _MatrixDesc(ctypes.Structure):
                 ("nnz", _i64), ("ell_width", _i64), ("ell_ld", _i64), ("coo_nnz", _i64),
                 ("stored_bytes", _i64), ("csr_kernel", _i32), ("max_row_len", _i32),
                 ("csr_long_rows", _i64), ("sellp_slices", _i64), ("sellp_slots", _i64),
-                ("sellp_slice", _i32), ("pad", _i32), ("sellp_wide_slices", _i64)]
+                ("sellp_slice", _i32), ("csr_row_lanes", _i32), ("sellp_wide_slices", _i64)]
 
 
 class SolverOpts(ctypes.Structure):
@@ -277,13 +277,14 @@ class Desc:
     ell_ld: int
     coo_nnz: int
     stored_bytes: int
-    csr_kernel: int      # CSR: 0 thread per row, else subwarp lanes; -1 otherwise
+    csr_kernel: int      # CSR: 0 row-per-thread (LDS-staged), else subwarp lanes; -1 otherwise
     max_row_len: int
     csr_long_rows: int
     sellp_slices: int    # SELLP: number of slices, else 0
     sellp_slots: int     # SELLP: slots including padding, else 0
     sellp_slice: int     # SELLP: rows per slice, else 0
     sellp_wide_slices: int  # SELLP: slices summed by column chunks, else 0
+    csr_row_lanes: int = 0  # CSR row-per-thread kernel: lanes per row, else 0
 
 
 class Matrix:
@@ -334,7 +335,7 @@ class Matrix:
         return Desc(FORMAT_NAMES[d.format], "f64" if d.dtype == F64 else "f32", d.n_rows,
                     d.n_cols, d.nnz, d.ell_width, d.ell_ld, d.coo_nnz, d.stored_bytes,
                     d.csr_kernel, d.max_row_len, d.csr_long_rows, d.sellp_slices, d.sellp_slots,
-                    d.sellp_slice, d.sellp_wide_slices)
+                    d.sellp_slice, d.sellp_wide_slices, d.csr_row_lanes)
 
     @property
     def shape(self):

@@ -182,6 +182,7 @@ struct gko_matrix_s {
     int32_t *trow = nullptr, *tcol = nullptr;
     void *tval = nullptr;
     int subwarp = 1;
+    int row_lanes = 1;              // CSR row-per-thread kernel: lanes per row
     int64_t max_len = -1;           // longest row (a property of the matrix), -1 until needed
     int64_t n_long = 0;             // CSR rows handled by a workgroup each
     int32_t *long_rows = nullptr;
@@ -318,7 +319,7 @@ void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, d
     switch (A->fmt) {
         case GKO_FMT_CSR:
             HIPC(spmv_csr(s, v.t, A->n, A->rp, A->col, v.val, x, alpha, beta, y, A->subwarp,
-                          A->n_long, A->long_rows));
+                          A->row_lanes, A->n_long, A->long_rows));
             break;
         case GKO_FMT_CSR_MERGE:
             HIPC(spmv_merge(s, v.t, A->n, A->nnz, A->rp, A->col, v.val, A->part, x, alpha, beta, y,
@@ -426,6 +427,7 @@ void refresh_long_rows(gko_matrix A) {
 void analyse_csr(gko_matrix A) {
     if (A->max_len < 0) A->max_len = A->n > 0 ? max_len_of_csr(A) : 0;
     A->subwarp = csr_kernel_width(A->n, A->nnz, A->max_len);
+    A->row_lanes = csr_row_lanes(A->n, A->nnz);
     refresh_long_rows(A);
 }
 
@@ -804,6 +806,7 @@ bool fused_view(gko_matrix A, const values &v, fused_matrix &f) {
         f.col = A->col;
         f.val = v.val;
         f.w = A->subwarp;
+        f.lanes = A->row_lanes;
         return true;
     }
     if (A->fmt == GKO_FMT_ELL || (A->fmt == GKO_FMT_HYBRID && A->tnnz == 0)) {
@@ -1913,6 +1916,7 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
         try {
             B->ctx = c; B->fmt = A->fmt; B->dt = A->dt; B->n = A->n; B->m = A->m; B->nnz = A->nnz;
             B->tiles = A->tiles; B->K = A->K; B->ld = A->ld; B->tnnz = A->tnnz; B->subwarp = A->subwarp;
+            B->row_lanes = A->row_lanes;
             B->max_len = A->max_len;
             B->slots = A->slots;
             auto copy = [&](const void *src, size_t bytes) -> void * {
@@ -1966,6 +1970,7 @@ gko_status gko_matrix_describe(gko_matrix A, gko_matrix_desc *out) {
         out->coo_nnz = A->fmt == GKO_FMT_COO ? A->nnz : (A->fmt == GKO_FMT_HYBRID ? A->tnnz : 0);
         out->stored_bytes = A->stored_bytes();
         out->csr_kernel = A->fmt == GKO_FMT_CSR ? A->subwarp : -1;
+        out->csr_row_lanes = (A->fmt == GKO_FMT_CSR && A->subwarp == kCsrRowThread) ? A->row_lanes : 0;
         out->max_row_len = (int32_t)A->max_len;
         out->csr_long_rows = A->fmt == GKO_FMT_CSR ? A->n_long : 0;
         const bool sellp = A->fmt == GKO_FMT_SELLP;

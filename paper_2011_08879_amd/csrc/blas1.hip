@@ -359,20 +359,22 @@ __global__ __launch_bounds__(kB) void fused_csr_kernel(int64_t n, const int32_t 
     grid_sum_apply<kB, P::NV>(acc, ra, pol.op);
 }
 
-// CSR with a thread per row (short regular rows, as in the plain SpMV); the
-// workgroup strides over tiles of rows.
-template <typename V, typename P>
+// CSR with G lanes per row and the entries staged through LDS (short regular
+// rows, as in the plain SpMV); the workgroup strides over tiles of kB / G
+// rows, and the first lane of each row stores it and adds its terms.
+template <typename V, typename P, int G>
 __global__ __launch_bounds__(kRowThreadBlock) void fused_csr_rowthread_kernel(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const V *__restrict__ in, V *__restrict__ out, P pol, red_args ra) {
     static_assert(kRowThreadBlock == kB, "one reduction block shape");
+    constexpr int64_t RT = kB / G;
     __shared__ rowthread_lds<V> L;
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    for (int64_t r0 = (int64_t)blockIdx.x * kB; r0 < n; r0 += (int64_t)gridDim.x * kB) {
-        const V s = csr_rowthread_sum(n, r0, rp, col, val, in, L);
-        const int64_t i = r0 + threadIdx.x;
-        if (i < n) {
+    for (int64_t r0 = (int64_t)blockIdx.x * RT; r0 < n; r0 += (int64_t)gridDim.x * RT) {
+        const V s = csr_rowthread_sum<V, G>(n, r0, rp, col, val, in, L);
+        const int64_t i = r0 + threadIdx.x / G;
+        if (i < n && threadIdx.x % G == 0) {
             out[i] = s;
             pol.add(acc, i, in[i], s);
         }
@@ -562,10 +564,19 @@ static hipError_t launch_fused(hipStream_t s, const fused_matrix &A, const void 
         return red_finish<P::NV>(s, g, ra, pol.op);
     }
     if (A.w == kCsrRowThread) {
-        const int g = fused_blocks(A.n);
+        if (A.lanes != 1 && A.lanes != 4 && A.lanes != 8) return hipErrorInvalidValue;
+        // one block per tile of kB / lanes rows, at most kFusedMaxBlocks
+        const int g = fused_blocks(A.n * A.lanes);
         const red_args ra = red_for(g, partials, ticket);
-        fused_csr_rowthread_kernel<V, P><<<g, kB, 0, s>>>(
-            A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
+        if (A.lanes == 8)
+            fused_csr_rowthread_kernel<V, P, 8><<<g, kB, 0, s>>>(
+                A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
+        else if (A.lanes == 4)
+            fused_csr_rowthread_kernel<V, P, 4><<<g, kB, 0, s>>>(
+                A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
+        else
+            fused_csr_rowthread_kernel<V, P, 1><<<g, kB, 0, s>>>(
+                A.n, A.rp, A.col, static_cast<const V *>(A.val), in, out, pol, ra);
         return red_finish<P::NV>(s, g, ra, pol.op);
     }
     switch (A.w) {

@@ -56,17 +56,19 @@ __device__ inline void csr_rows_sum(int64_t n, int64_t row0, int lane,
     for (int u = 0; u < U; ++u) s[u] = subwarp<W>::reduce_sum(s[u]);
 }
 
-// Row-per-thread CSR for matrices with short rows (see csr_kernel_width):
-// a workgroup of T threads owns T consecutive rows, stages their
-// entries (one contiguous range) through LDS in chunks of C with coalesced
-// loads, and each thread walks its own row's entries in the chunk.  The x
-// gathers of neighbouring threads then hit neighbouring columns for banded
-// and stencil patterns (as in ELL), unlike a subwarp per row, whose lanes
-// gather along one row.  Returns the thread's row sum (0 for rows >= n).
-// Measured on the 27-point stencil: 235 us with a 32-lane subwarp per row,
-// 171 us row-per-thread; eight gathers in flight in the walk instead of four
-// 170 -> 167 us (banded rows of 24-40 entries 109 -> 105 us), sixteen no
-// faster.
+// Row-per-thread CSR for matrices with short rows (see csr_kernel_width),
+// generalised to G lanes per row: a workgroup of T threads owns T / G
+// consecutive rows, stages their entries (one contiguous range) through LDS
+// in chunks of C with coalesced loads, and the G lanes of a row walk its
+// entries in the chunk, lane g taking entries g, g + G, ...; their partial
+// sums are added by a xor butterfly.  The x gathers of neighbouring rows then
+// hit neighbouring columns for banded and stencil patterns (as in ELL),
+// unlike a subwarp reading its row from memory.  Returns the row sum in every
+// lane of the row (0 for rows >= n).
+// Measured on the 27-point stencil with G = 1: 235 us with a 32-lane subwarp
+// per row, 171 us row-per-thread; eight gathers in flight in the walk
+// instead of four 170 -> 167 us (banded rows of 24-40 entries 109 -> 105 us),
+// sixteen no faster.
 constexpr int kRowThreadBlock = 256;
 constexpr int kRowThreadChunk = 2048;
 
@@ -76,13 +78,14 @@ struct rowthread_lds {
     V val[kRowThreadChunk];
 };
 
-template <typename V>
+template <typename V, int G = 1>
 __device__ inline V csr_rowthread_sum(int64_t n, int64_t r0, const int32_t *__restrict__ rp,
                                       const int32_t *__restrict__ col, const V *__restrict__ val,
                                       const V *__restrict__ x, rowthread_lds<V> &L) {
-    constexpr int T = kRowThreadBlock, C = kRowThreadChunk;
-    const int64_t i = r0 + threadIdx.x;
-    const int64_t rl = r0 + T < n ? r0 + T : n;
+    constexpr int T = kRowThreadBlock, C = kRowThreadChunk, RT = T / G;
+    const int g = threadIdx.x % G;
+    const int64_t i = r0 + threadIdx.x / G;
+    const int64_t rl = r0 + RT < n ? r0 + RT : n;
     const int32_t kb = rp[r0], ke = rp[rl];
     const int32_t b = i < n ? rp[i] : ke, e = i < n ? rp[i + 1] : ke;
     V s = V(0);
@@ -107,24 +110,26 @@ __device__ inline V csr_rowthread_sum(int64_t n, int64_t r0, const int32_t *__re
         __syncthreads();
         const int32_t lo = (b > c0 ? b : c0) - c0;
         const int32_t hi = (e < c0 + cn ? e : c0 + cn) - c0;
-        int32_t k = lo;
-        for (; k + 8 <= hi; k += 8) {  // eight gathers in flight, summed in order
+        int32_t k = lo + g;
+        for (; k + 7 * G < hi; k += 8 * G) {  // eight gathers in flight, summed in order
             V xs[8];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) xs[u] = x[L.col[k + u]];
+            for (int u = 0; u < 8; ++u) xs[u] = x[L.col[k + u * G]];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) s += L.val[k + u] * xs[u];
+            for (int u = 0; u < 8; ++u) s += L.val[k + u * G] * xs[u];
         }
-        for (; k + 4 <= hi; k += 4) {
-            const V x0 = x[L.col[k]], x1 = x[L.col[k + 1]], x2 = x[L.col[k + 2]], x3 = x[L.col[k + 3]];
+        for (; k + 3 * G < hi; k += 4 * G) {
+            const V x0 = x[L.col[k]], x1 = x[L.col[k + G]], x2 = x[L.col[k + 2 * G]],
+                    x3 = x[L.col[k + 3 * G]];
             s += L.val[k] * x0;
-            s += L.val[k + 1] * x1;
-            s += L.val[k + 2] * x2;
-            s += L.val[k + 3] * x3;
+            s += L.val[k + G] * x1;
+            s += L.val[k + 2 * G] * x2;
+            s += L.val[k + 3 * G] * x3;
         }
-        for (; k < hi; ++k) s += L.val[k] * x[L.col[k]];
+        for (; k < hi; k += G) s += L.val[k] * x[L.col[k]];
         __syncthreads();
     }
+    if constexpr (G > 1) s = subwarp<G>::reduce_sum(s);
     return s;
 }
 

@@ -15,21 +15,23 @@ inline size_t vsize(vt t) { return t == vt::f64 ? 8 : 4; }
 // CSR, a subwarp of w lanes per row (w a power of two <= 64).  Rows longer
 // than csr_long_threshold(w) are listed in long_rows (n_long of them) and
 // summed by a workgroup each.  w = kCsrRowThread: a thread per row with the
-// entries staged through LDS (for short rows of similar length, see
-// csr_kernel_width; no long rows then).
+// entries staged through LDS and `lanes` lanes per row (for short rows of
+// similar length, see csr_kernel_width and csr_row_lanes; no long rows then).
 constexpr int kCsrRowThread = 0;
 constexpr int64_t kCsrRowThreadMaxLen = 256;
 // Power of two >= the mean row length, at most 64.
 int csr_subwarp_width(int64_t n, int64_t nnz);
 // The kernel for a matrix: kCsrRowThread or a subwarp width.
 int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len);
+// Lanes per row (1, 4 or 8) of the row-per-thread kernel.
+int csr_row_lanes(int64_t n, int64_t nnz);
 // Whether rows longer than csr_long_threshold(w) get the workgroup-per-row
 // kernel: only for irregular rows (longest > 4 x mean).
 bool csr_has_long_rows(int64_t n, int64_t nnz, int64_t max_len, int w);
 int32_t csr_long_threshold(int w);
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
                     const void *val, const void *x, double alpha, double beta, void *y, int w,
-                    int64_t n_long, const int32_t *long_rows);
+                    int lanes, int64_t n_long, const int32_t *long_rows);
 // flag[i] = len_i > long_t; rows[pos[i]] = i for flagged rows (pos: exclusive scan of flag).
 hipError_t csr_long_flags(hipStream_t s, int64_t n, const int32_t *rp, int32_t long_t, int32_t *flag);
 hipError_t csr_long_scatter(hipStream_t s, int64_t n, const int32_t *flag, const int32_t *pos,

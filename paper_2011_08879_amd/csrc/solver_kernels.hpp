@@ -46,6 +46,7 @@ struct fused_matrix {
     const int32_t *rp = nullptr, *col = nullptr;  // CSR
     const void *val = nullptr;
     int w = 0;                                    // CSR kernel (see csr_kernel_width)
+    int lanes = 1;                                // its lanes per row (csr_row_lanes)
     int64_t K = 0, ld = 0;                        // ELL
     const int32_t *ecol = nullptr;
     const void *eval = nullptr;

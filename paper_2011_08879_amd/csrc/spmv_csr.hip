@@ -74,45 +74,62 @@ __global__ __launch_bounds__(kLongBlock) void spmv_csr_long_kernel(
     if (threadIdx.x == 0) y[r] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[r];
 }
 
-// Row-per-thread CSR (csr_rowthread_sum), chosen for short regular rows.
-template <typename V>
+// Row-per-thread CSR (csr_rowthread_sum with G lanes per row), chosen for
+// short regular rows.
+template <typename V, int G>
 __global__ __launch_bounds__(kRowThreadBlock) void spmv_csr_rowthread_kernel(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
     __shared__ rowthread_lds<V> L;
-    const int64_t r0 = (int64_t)blockIdx.x * kRowThreadBlock;
-    const V s = csr_rowthread_sum(n, r0, rp, col, val, x, L);
-    const int64_t i = r0 + threadIdx.x;
-    if (i < n) y[i] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[i];
+    const int64_t r0 = (int64_t)blockIdx.x * (kRowThreadBlock / G);
+    const V s = csr_rowthread_sum<V, G>(n, r0, rp, col, val, x, L);
+    const int64_t i = r0 + threadIdx.x / G;
+    if (i < n && threadIdx.x % G == 0) y[i] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[i];
 }
 
-template <typename V>
-static hipError_t launch_csr_rowthread(hipStream_t s, int64_t n, const int32_t *rp,
-                                       const int32_t *col, const void *val, const void *x,
-                                       double alpha, double beta, void *y) {
-    spmv_csr_rowthread_kernel<V><<<dim3((unsigned)((n + kRowThreadBlock - 1) / kRowThreadBlock)),
-                                   dim3(kRowThreadBlock), 0, s>>>(
+template <typename V, int G>
+static hipError_t launch_csr_rowthread_g(hipStream_t s, int64_t n, const int32_t *rp,
+                                         const int32_t *col, const void *val, const void *x,
+                                         double alpha, double beta, void *y) {
+    constexpr int64_t rows = kRowThreadBlock / G;
+    spmv_csr_rowthread_kernel<V, G><<<dim3((unsigned)((n + rows - 1) / rows)),
+                                      dim3(kRowThreadBlock), 0, s>>>(
         n, rp, col, static_cast<const V *>(val), static_cast<const V *>(x), (V)alpha, (V)beta,
         static_cast<V *>(y));
     return hipGetLastError();
 }
 
+template <typename V>
+static hipError_t launch_csr_rowthread(hipStream_t s, int64_t n, const int32_t *rp,
+                                       const int32_t *col, const void *val, const void *x,
+                                       double alpha, double beta, void *y, int lanes) {
+    switch (lanes) {
+        case 1: return launch_csr_rowthread_g<V, 1>(s, n, rp, col, val, x, alpha, beta, y);
+        case 2: return launch_csr_rowthread_g<V, 2>(s, n, rp, col, val, x, alpha, beta, y);
+        case 4: return launch_csr_rowthread_g<V, 4>(s, n, rp, col, val, x, alpha, beta, y);
+        case 8: return launch_csr_rowthread_g<V, 8>(s, n, rp, col, val, x, alpha, beta, y);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 // The CSR kernel for a matrix, from its mean and longest row (measured on
 // MI355X over 2D/3D stencils, banded, block-diagonal, uniform and lognormal
 // random patterns, n = 0.5-4M):
-//  * rows of at most 48 entries on average and 256 at most: a thread per row
-//    (2D Laplacian 92 -> 34 us, banded mean 32 173 -> 107 us, banded mean 48
-//    216 -> 173 us, lognormal rows with sigma 0.5 201 -> 180 us against the
-//    subwarp kernel);
+//  * rows of at most 96 entries on average and 256 at most: the LDS-staged
+//    row-per-thread kernel (csr_row_lanes lanes per row).  With one lane per
+//    row against the subwarp kernel: 2D Laplacian 92 -> 34 us, banded mean 32
+//    173 -> 107 us, banded mean 48 216 -> 173 us, lognormal rows with sigma
+//    0.5 201 -> 180 us; with eight lanes per row (1M rows): banded mean 64
+//    242 -> 189 us, block-diagonal mean 74 269 -> 202 us against the
+//    quarter-mean subwarp;
 //  * longer rows that are regular (longest <= 4 x mean): a subwarp of about
 //    mean/4 lanes, four entries per lane (banded mean 64: 156 us with 64
-//    lanes, 150 us a thread per row, 120 us with 16 lanes; block-diagonal
-//    mean 70: 164, 159, 130 us);
+//    lanes, 120 us with 16 lanes; block-diagonal mean 70: 164, 130 us);
 //  * otherwise a subwarp of about mean lanes plus the long-row kernel
 //    (lognormal rows with sigma 1.56: 223 us; a thread per row 910 us).
 int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len) {
     const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
-    if (n > 0 && max_len <= kCsrRowThreadMaxLen && mean <= 48.0) return kCsrRowThread;
+    if (n > 0 && max_len <= kCsrRowThreadMaxLen && mean <= 96.0) return kCsrRowThread;
     const int w = csr_subwarp_width(n, nnz);
     if ((double)max_len <= 4.0 * mean) return w >= 4 ? w / 4 : 1;
     return w;
@@ -123,6 +140,17 @@ int csr_kernel_width(int64_t n, int64_t nnz, int64_t max_len) {
 // matrix (mean 16, longest 10,000, 16-lane subwarps): threshold 512 223 us,
 // 256 215 us, 128 208 us, 64 206 us.
 int32_t csr_long_threshold(int w) { return 4 * w > 64 ? 4 * w : 64; }
+
+// Lanes per row of the row-per-thread kernel, from the mean row length.
+// Measured (FP64, us; 1 / 2 / 4 / 8 lanes): 2D Laplacian 2048^2 57 / 81 /
+// 118 / 207, 3D Laplacian 160^3 75 / 102 / 134 / 210, lognormal rows of
+// sigma 0.5 and mean 16 173 / 170 / 166 / 165, 27-point stencil 128^3 166 /
+// 150 / 150 / 205, banded rows of mean 32 211 / 196 / 195 / 206, of mean 48
+// 181 / 153 / 148 / 148 (8 lanes: 149 against 147 with 4 in a second run).
+int csr_row_lanes(int64_t n, int64_t nnz) {
+    const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
+    return mean >= 56.0 ? 8 : (mean >= 12.0 ? 4 : 1);
+}
 
 bool csr_has_long_rows(int64_t n, int64_t nnz, int64_t max_len, int w) {
     const double mean = n > 0 ? (double)nnz / (double)n : 0.0;
@@ -202,11 +230,12 @@ static hipError_t launch_csr_long(hipStream_t s, int64_t n_long, const int32_t *
 
 hipError_t spmv_csr(hipStream_t s, vt t, int64_t n, const int32_t *rp, const int32_t *col,
                     const void *val, const void *x, double alpha, double beta, void *y, int w,
-                    int64_t n_long, const int32_t *long_rows) {
+                    int lanes, int64_t n_long, const int32_t *long_rows) {
     if (n == 0) return hipSuccess;
     if (w == kCsrRowThread)
-        return t == vt::f64 ? launch_csr_rowthread<double>(s, n, rp, col, val, x, alpha, beta, y)
-                            : launch_csr_rowthread<float>(s, n, rp, col, val, x, alpha, beta, y);
+        return t == vt::f64
+                   ? launch_csr_rowthread<double>(s, n, rp, col, val, x, alpha, beta, y, lanes)
+                   : launch_csr_rowthread<float>(s, n, rp, col, val, x, alpha, beta, y, lanes);
     const int32_t long_t = n_long > 0 ? csr_long_threshold(w) : INT_MAX;
     hipError_t e = t == vt::f64 ? launch_csr<double>(s, n, rp, col, val, x, alpha, beta, y, w, long_t)
                                 : launch_csr<float>(s, n, rp, col, val, x, alpha, beta, y, w, long_t);

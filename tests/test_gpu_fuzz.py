@@ -3,7 +3,8 @@ SpMV (FP64 and FP32) against the oracle's near-exact product, and the
 conversion chain back to CSR bit for bit.  Sizes and row-length mixes are
 drawn so that rows straddle COO's 1024-entry wave chunks, merge-path's
 1024-item tiles, SELL-P's 64-row slices, the row-per-thread kernel's
-2048-entry LDS chunks and the long-row threshold of the subwarp kernel."""
+2048-entry LDS chunks and 256- or 64-row tiles (one or four lanes per row)
+and the long-row threshold of the subwarp kernel."""
 import numpy as np
 import pytest
 

@@ -54,6 +54,39 @@ def test_cg_config1_matches_oracle(g, orc, gen_mod, ctx, fmt, single):
     assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
 
 
+def kappa_stencil27(N):
+    """27-point stencil, 26 on the diagonal and -1 to each neighbour: A = 27 I -
+    T x T x T with T = tridiag(1, 1, 1), whose eigenvalues are 1 + 2 cos(k pi/(N+1))."""
+    t = 1 + 2 * np.cos(np.arange(1, N + 1) * np.pi / (N + 1))
+    prods = np.multiply.outer(np.multiply.outer(t, t), t)
+    return (27 - prods.min()) / (27 - prods.max())
+
+
+def test_cg_csr_four_lanes_per_row_matches_oracle(g, orc, gen_mod, ctx):
+    """CG's fused product on the LDS-staged CSR kernel with four lanes per row
+    (mean row length >= 12), 9261 rows (a ragged last tile of 64 rows)."""
+    N = 21
+    A = gen_mod.stencil27(N)
+    n = N ** 3
+    xs = gen_mod.uniform(3, n)
+    b = orc.spmv(A, xs)
+    rc, xo, info_o = orc.cg(A, b, tol=1e-10)
+    ctx.set_solver_opts(single_workgroup=0)
+    M = g.Matrix.from_csr(*A)
+    d = M.describe()
+    assert d.csr_kernel == 0 and d.csr_row_lanes == 4, d
+    x = dev(np.zeros(n))
+    info = g.cg(M, dev(b), x, tol=1e-10, maxit=5000)
+    assert info["status"] == g.OK, info
+    assert abs(info["iterations"] - info_o["iters"]) <= 2, (info, info_o)
+    xg = host(x)
+    true = np.linalg.norm(b - orc.spmv(A, xg)) / np.linalg.norm(b)
+    assert true <= 1e-10
+    kappa = kappa_stencil27(N)
+    assert 60 < kappa < 70
+    assert np.linalg.norm(xg - xo) / np.linalg.norm(xo) <= 2 * kappa * 1e-10
+
+
 def test_cg_check_every_does_not_change_iterates(g, orc, gen_mod, ctx):
     A = gen_mod.laplace2d(32)
     b = orc.spmv(A, gen_mod.uniform(2, 1024))

@@ -250,10 +250,11 @@ def test_sellp_pads_per_slice(g, orc):
 
 
 def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
-    """The CSR kernel follows the row-length rule (a thread per row for short
-    rows; a quarter-mean subwarp for long regular rows; a mean-width subwarp
-    plus the workgroup-per-row kernel for irregular rows), and each of these
-    paths meets the SpMV bound against the oracle."""
+    """The CSR kernel follows the row-length rule (the LDS-staged row-per-thread
+    kernel, with 1, 4 or 8 lanes per row, for rows of a mean up to 96 and at
+    most 256 entries; a quarter-mean subwarp for longer regular rows; a
+    mean-width subwarp plus the workgroup-per-row kernel for irregular rows),
+    and each of these paths meets the SpMV bound against the oracle."""
     rng = np.random.default_rng(21)
     lens = list(rng.integers(1, 4, 700))
     lens[350] = 300
@@ -262,8 +263,10 @@ def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
     col = np.concatenate([np.sort(rng.choice(700, size=l, replace=False)) for l in lens]).astype(np.int32)
     cases = {
         "laplace2d": (gen_mod.laplace2d(40), 0, False),
-        "banded_mean64": (gen_mod.banded(12, 3000, 64, 48, 80), 16, False),
+        "banded_mean64": (gen_mod.banded(12, 3000, 64, 48, 80), 0, False),
+        "banded_mean120": (gen_mod.banded(13, 3000, 128, 100, 140), 16, False),
         "banded_mean40": (gen_mod.banded(19, 3000, 40, 32, 48), 0, False),
+        "stencil27_19": (gen_mod.stencil27(19), 0, False),
         "lognormal": (gen_mod.random_lognormal(4, 20000, max_len=3000), 16, True),
         "one_long_row": ((rp, col, rng.uniform(-1, 1, len(col))), 4, True),
     }
@@ -272,6 +275,9 @@ def test_csr_kernel_choice_and_parity(g, orc, gen_mod):
         d = M.describe()
         lens = np.diff(A[0])
         assert d.csr_kernel == kernel, (name, d)
+        if kernel == 0:   # lanes per row from the mean row length
+            mean = len(A[1]) / (len(A[0]) - 1)
+            assert d.csr_row_lanes == (8 if mean >= 56 else 4 if mean >= 12 else 1), (name, d)
         assert d.max_row_len == lens.max(), (name, d)
         assert (d.csr_long_rows > 0) == has_long, (name, d)
         if has_long:
