@@ -183,6 +183,7 @@ struct gko_matrix_s {
     void *tval = nullptr;
     int subwarp = 1;
     int row_lanes = 1;              // CSR row-per-thread kernel: lanes per row
+    bool merge_rows = false;        // CSR_MERGE: tiles sum their rows in parallel
     int64_t max_len = -1;           // longest row (a property of the matrix), -1 until needed
     int64_t n_long = 0;             // CSR rows handled by a workgroup each
     int32_t *long_rows = nullptr;
@@ -323,7 +324,7 @@ void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, d
             break;
         case GKO_FMT_CSR_MERGE:
             HIPC(spmv_merge(s, v.t, A->n, A->nnz, A->rp, A->col, v.val, A->part, x, alpha, beta, y,
-                            static_cast<int32_t *>(A->carry_a), A->carry_b));
+                            static_cast<int32_t *>(A->carry_a), A->carry_b, A->merge_rows));
             break;
         case GKO_FMT_COO:
             HIPC(spmv_coo(s, v.t, A->n, A->nnz, A->row, A->col, v.val, x, alpha, beta, y, false,
@@ -531,9 +532,11 @@ void csr_to_format(gko_matrix A, gko_format fmt) {
             dbuf part(c, 2 * (tiles + 1) * 4);
             HIPC(merge_partition(s, A->n, A->nnz, A->rp, part.as<int32_t>()));
             ensure_carries(A, tiles);
+            if (A->max_len < 0) A->max_len = A->n > 0 ? max_len_of_csr(A) : 0;
             c->sync();
             A->part = static_cast<int32_t *>(part.release());
             A->tiles = tiles;
+            A->merge_rows = merge_rows_parallel(A->n, A->nnz, A->max_len);
             A->fmt = GKO_FMT_CSR_MERGE;
             return;
         }
@@ -1917,6 +1920,7 @@ gko_status gko_matrix_clone(gko_matrix A, gko_matrix *out) {
             B->ctx = c; B->fmt = A->fmt; B->dt = A->dt; B->n = A->n; B->m = A->m; B->nnz = A->nnz;
             B->tiles = A->tiles; B->K = A->K; B->ld = A->ld; B->tnnz = A->tnnz; B->subwarp = A->subwarp;
             B->row_lanes = A->row_lanes;
+            B->merge_rows = A->merge_rows;
             B->max_len = A->max_len;
             B->slots = A->slots;
             auto copy = [&](const void *src, size_t bytes) -> void * {

@@ -41,10 +41,14 @@ hipError_t csr_long_scatter(hipStream_t s, int64_t n, const int32_t *flag, const
 int64_t merge_tiles(int64_t n, int64_t nnz);
 hipError_t merge_partition(hipStream_t s, int64_t n, int64_t nnz, const int32_t *rp,
                            int32_t *part /* 2*(tiles+1) */);
-// carry_row: tiles int32, carry_val: tiles values of type t.
+// carry_row: tiles int32, carry_val: tiles values of type t.  rows: sum each
+// tile's rows in parallel (merge_rows_parallel) instead of the merge walk.
 hipError_t spmv_merge(hipStream_t s, vt t, int64_t n, int64_t nnz, const int32_t *rp,
                       const int32_t *col, const void *val, const int32_t *part, const void *x,
-                      double alpha, double beta, void *y, int32_t *carry_row, void *carry_val);
+                      double alpha, double beta, void *y, int32_t *carry_row, void *carry_val,
+                      bool rows);
+// Whether a matrix's merge tiles sum their rows in parallel: regular rows.
+bool merge_rows_parallel(int64_t n, int64_t nnz, int64_t max_len);
 
 // COO: equal nonzero chunks per wavefront.  accumulate: y += alpha A x, rows
 // without entries untouched (used for the HYB tail).
