@@ -646,6 +646,7 @@ def run_batch(g, gen, torch, keep, nsys=10000, reps=3):
     return out
 
 
+WAVE_ROWS = 256   # largest system a wavefront solves alone in the batch's wavefront mode
 LDS_PEAK_GBS = 256 * 128 * 2.4   # 256 CUs x 128 B/clk x 2.4 GHz
 
 
@@ -655,18 +656,28 @@ def batch_bound(g, torch, B, vals, bh, G, its, measured_s, floor_bytes):
     * HBM: one read of every system, b and x0, one write of x.
     * LDS: per system and iteration the p gathers of its entries and one p
       store per row (8 bytes each), against 256 CUs x 128 B/clk.
-    * latency: an iteration cannot take less than on a workgroup alone on the
-      GPU.  t_iter(m) is measured on one-system batches (the smallest and the
-      largest system, in a batch of their own, kernel time at the batch's
-      workgroup size, full solve minus a one-iteration solve) and interpolated
-      in m; with R workgroups resident, the batch needs at least
-      max(sum_s its_s t_iter(m_s) / R, max_s its_s t_iter(m_s)).
+    * latency: an iteration cannot take less than on a workgroup (or, for the
+      small systems of the wavefront mode, a wavefront) alone on the GPU.
+      t_iter(m) is measured on one-system batches in the batch's workgroup
+      size and mode (the smallest and the largest system, and in the
+      wavefront mode also the largest system a wavefront takes and the
+      smallest one above it; kernel time of the full solve minus a
+      one-iteration solve) and interpolated in m within each kind; with R
+      workgroups resident, each running one system or, in the wavefront
+      mode, block / 64 small ones at a time, the batch needs at least
+      max(sum_s its_s t_iter(m_s) / (R slots_s), max_s its_s t_iter(m_s)).
     fraction = the largest bound / the measured time."""
     m = np.diff(B.row_off)
     nz = np.diff(B.nnz_off)
     resident, lds_bytes = G.launch_info()
+    waves = G.lds_mode == "waves"
+    small = (m <= WAVE_ROWS) if waves else np.zeros(len(m), bool)
+    probes = {int(np.argmin(m)), int(np.argmax(m))}
+    if waves and small.any() and (~small).any():
+        probes |= {int(np.flatnonzero(small)[np.argmax(m[small])]),
+                   int(np.flatnonzero(~small)[np.argmin(m[~small])])}
     t_iter = {}
-    for sid in (int(np.argmin(m)), int(np.argmax(m))):
+    for sid in sorted(probes):
         rp, c, _ = B.system(sid)
         k0, k1 = int(B.nnz_off[sid]), int(B.nnz_off[sid + 1])
         r0, r1 = int(B.row_off[sid]), int(B.row_off[sid + 1])
@@ -676,11 +687,11 @@ def batch_bound(g, torch, B, vals, bh, G, its, measured_s, floor_bytes):
         b1 = torch.from_numpy(np.ascontiguousarray(bh[r0:r1])).cuda()
         x1 = torch.zeros(r1 - r0, dtype=torch.float64, device="cuda")
         one.block = G.block
+        one.lds_mode = G.lds_mode
         ts = {}
         for mi in (1, 1000):
             best = None
             for _ in range(5):
-                one.block = G.block
                 st, it1, _ = one.solve(b1, x1, tol=1e-10, maxit=mi)
                 a, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
                 a.record()
@@ -692,14 +703,21 @@ def batch_bound(g, torch, B, vals, bh, G, its, measured_s, floor_bytes):
             ts[mi] = (best * 1e-3, int(it1.cpu()[0]))
         one.close()
         t_iter[int(m[sid])] = (ts[1000][0] - ts[1][0]) / max(ts[1000][1] - 1, 1)
-    (m0, t0), (m1, t1) = sorted(t_iter.items())
-    tm = t0 + (t1 - t0) * (m - m0) / max(m1 - m0, 1)
+    tm = np.empty(len(m))
+    for kind in (True, False):
+        sel = small == kind
+        if not sel.any():
+            continue
+        pts = sorted((k, v) for k, v in t_iter.items() if (k <= WAVE_ROWS if waves else False) == kind)
+        tm[sel] = np.interp(m[sel], [k for k, _ in pts], [v for _, v in pts])
+    slots = np.where(small, G.block // 64, 1)
     work = its.astype(np.float64) * tm
-    latency_s = max(work.sum() / resident, work.max())
+    latency_s = max(float((work / slots).sum()) / resident, float(work.max()))
     lds_s = float((its.astype(np.float64) * (nz + m) * 8).sum()) / (LDS_PEAK_GBS * 1e9)
     hbm_s = floor_bytes / (HBM_PEAK_GBS * 1e9)
     bound = max(latency_s, lds_s, hbm_s)
     return {"resident_workgroups": resident, "lds_bytes_per_workgroup": lds_bytes,
+            "mode": G.lds_mode,
             "t_iter_lone_us": {str(k): round(v * 1e6, 3) for k, v in t_iter.items()},
             "latency_floor_s": round(latency_s, 7), "lds_floor_s": round(lds_s, 7),
             "hbm_floor_s": round(hbm_s, 7), "bound": "latency" if bound == latency_s else

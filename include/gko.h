@@ -347,7 +347,7 @@ typedef struct gko_batch_s *gko_batch;
  *                            stored back to back from index row_off[i] + i.
  *   col_idx (int32)        : local column indices in [0, m_i).
  *   values                 : FP64 or FP32 (dt).
- * Systems are queued largest first (by nonzeros) for the solve.  A malformed
+ * Systems are queued largest first (by rows, then nonzeros) for the solve.  A malformed
  * system returns GKO_ERR_INVALID_ARG. */
 gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *row_off,
                                 const int64_t *nnz_off, const int32_t *row_ptr_local,
@@ -380,17 +380,26 @@ gko_status gko_batch_cg_solve(gko_batch B, const double *b, double *x, double to
 gko_status gko_batch_set_block(gko_batch B, int32_t block);
 gko_status gko_batch_get_block(gko_batch B, int32_t *block);
 
-/* What the persistent kernel keeps in LDS.  ALL: x, r, p and q of the
- * current system (rows that do not fit the register cache are read from
- * memory each iteration).  DIRECTION: every system's rows (up to 5 entries,
- * up to min(4, 1024 / block) rows per thread) and its x, r and q stay in
- * registers and only the direction p goes through LDS (m doubles per
- * workgroup instead of 4m): FP64 batches whose every system fits the
- * register cache at the workgroup size.  set_lds_mode(DIRECTION) fails with
- * GKO_ERR_UNSUPPORTED where it does not fit; a later set_block to a size
- * where it does not fit falls back to ALL.  get_lds_mode returns the mode in
- * effect. */
-typedef enum gko_batch_lds { GKO_BATCH_LDS_ALL = 0, GKO_BATCH_LDS_DIRECTION = 1 } gko_batch_lds;
+/* What the persistent kernel keeps in LDS, and how many systems a workgroup
+ * solves at a time.  ALL: x, r, p and q of the current system (rows that do
+ * not fit the register cache are read from memory each iteration).
+ * DIRECTION: every system's rows (up to 5 entries, up to min(4, 1024 /
+ * block) rows per thread) and its x, r and q stay in registers and only the
+ * direction p goes through LDS (m doubles per workgroup instead of 4m):
+ * FP64 batches whose every system fits the register cache at the workgroup
+ * size.  WAVE_SYSTEMS: as DIRECTION, and systems of at most 256 rows are
+ * solved one per wavefront (block / 64 of them per workgroup at a time, each
+ * wavefront taking its own systems from the queue, sums within the
+ * wavefront and no workgroup barrier); larger systems take the whole
+ * workgroup.  set_lds_mode(DIRECTION or WAVE_SYSTEMS) fails with
+ * GKO_ERR_UNSUPPORTED where DIRECTION does not fit; a later set_block to a
+ * size where it does not fit falls back to ALL.  get_lds_mode returns the
+ * mode in effect. */
+typedef enum gko_batch_lds {
+    GKO_BATCH_LDS_ALL = 0,
+    GKO_BATCH_LDS_DIRECTION = 1,
+    GKO_BATCH_WAVE_SYSTEMS = 2
+} gko_batch_lds;
 gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode);
 gko_status gko_batch_get_lds_mode(gko_batch B, int32_t *mode);
 
@@ -402,9 +411,10 @@ gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
                                  int64_t *lds_bytes_per_workgroup);
 
 /* Time one full batched solve for each workgroup size (64, 128, 256, 512)
- * and LDS mode on the given right-hand sides and keep the fastest pair for
- * this batch.  times_ms[8] (host) receives the timings, entry 2 j + mode for
- * size j of that list (infinity where the mode does not fit); *block_out
+ * and mode of gko_batch_lds on the given right-hand sides and keep the
+ * fastest pair for this batch.  times_ms[12] (host) receives the timings,
+ * entry 3 j + mode for size j of that list (infinity where the mode does not
+ * fit); *block_out
  * (host) the chosen size (gko_batch_get_lds_mode gives the mode).
  * x, iters and relres are scratch outputs as in gko_batch_cg_solve.
  * The choice is also stored in the on-disk autotune cache, a text file of

@@ -493,7 +493,7 @@ def cg(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000, raise_on_failure
 
 
 CG_NOALLOC_MAX_ROWS = 2752448   # GKO_CG_NOALLOC_MAX_ROWS
-BATCH_LDS_MODES = ("all", "direction")   # gko_batch_lds
+BATCH_LDS_MODES = ("all", "direction", "waves")   # gko_batch_lds
 
 
 def cg_noalloc(A: Matrix, b, x, tol: float = 1e-10, maxit: int = 10000,
@@ -602,7 +602,7 @@ class Batch:
         Returns (block, {(block, mode): ms}) (ms infinite where a mode does not fit)."""
         it, rr = self._outs()
         blk = _i32()
-        ms = (ctypes.c_float * 8)()
+        ms = (ctypes.c_float * (4 * len(BATCH_LDS_MODES)))()
         _check(_lib.gko_batch_autotune(self.handle, _ptr(b), _ptr(x), tol, maxit, _ptr(it),
                                        _ptr(rr), ctypes.byref(blk), ms))
         keys = [(bk, md) for bk in (64, 128, 256, 512) for md in BATCH_LDS_MODES]

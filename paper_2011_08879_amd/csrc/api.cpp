@@ -1147,6 +1147,8 @@ struct gko_batch_s {
     int64_t nsys = 0, rows = 0, nnz = 0, max_m = 0, max_row_len = 0;
     bool want_lean = true;  // direction-only LDS requested (used where it fits)
     bool lean = false;      // in effect: only the direction in LDS (FP64, rows in registers)
+    bool want_waves = false;  // small systems one per wavefront requested (with lean)
+    bool waves = false;       // in effect
     int64_t *row_off = nullptr, *nnz_off = nullptr;
     int32_t *rp_local = nullptr, *col = nullptr, *order = nullptr;
     void *val = nullptr;
@@ -1176,6 +1178,17 @@ bool batch_lean_ok(const gko_batch_s *B, int block) {
 void batch_use_block(gko_batch B, int block) {
     B->block = block;
     B->lean = B->want_lean && batch_lean_ok(B, block);
+    B->waves = B->want_waves && B->lean;
+}
+
+// The mode of gko_batch_set_lds_mode in effect.
+int batch_mode(const gko_batch_s *B) {
+    return B->waves ? GKO_BATCH_WAVE_SYSTEMS : B->lean ? GKO_BATCH_LDS_DIRECTION : GKO_BATCH_LDS_ALL;
+}
+
+void batch_want_mode(gko_batch B, int mode) {
+    B->want_lean = mode != GKO_BATCH_LDS_ALL;
+    B->want_waves = mode == GKO_BATCH_WAVE_SYSTEMS;
 }
 
 gko_status batch_run(gko_batch B, const double *b, double *x, double tol, int32_t maxit,
@@ -1202,6 +1215,7 @@ gko_status batch_run(gko_batch B, const double *b, double *x, double tol, int32_
     a.max_row_len = B->max_row_len;
     a.block = B->block;
     a.lean = B->lean;
+    a.waves = B->waves;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (ms) {
         HIPC(hipEventCreate(&e0));
@@ -1621,11 +1635,14 @@ gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *ro
         const int64_t rows = ro[nsys], nnz = no[nsys];
         require(nnz < std::numeric_limits<int32_t>::max(), GKO_ERR_UNSUPPORTED, "nnz must be below 2^31");
         require(nnz == 0 || (col_idx && values), GKO_ERR_INVALID_ARG, "null columns or values");
-        // queue order: largest systems first (ties by index)
+        // queue order: most rows first, then most nonzeros (ties by index); the
+        // wavefront mode relies on the rows never increasing along the queue
         std::vector<int32_t> order(nsys);
         std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(),
-                         [&](int32_t a, int32_t b) { return nz[a] > nz[b]; });
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+            const int64_t ma = ro[a + 1] - ro[a], mb = ro[b + 1] - ro[b];
+            return ma != mb ? ma > mb : nz[a] > nz[b];
+        });
         auto B = new gko_batch_s();
         B->ctx = ctx;
         try {
@@ -1664,8 +1681,8 @@ gko_status gko_batch_create_csr(gko_context ctx, int64_t nsys, const int64_t *ro
             int cb = 0, cm = 0;
             const std::string cv = cache_lookup(batch_cache_key(B));
             if (std::sscanf(cv.c_str(), "%d %d", &cb, &cm) == 2 &&
-                (cb == 64 || cb == 128 || cb == 256 || cb == 512) && (cm == 0 || cm == 1)) {
-                B->want_lean = cm == 1;
+                (cb == 64 || cb == 128 || cb == 256 || cb == 512) && cm >= 0 && cm <= 2) {
+                batch_want_mode(B, cm);
                 B->block = cb;
             }
             batch_use_block(B, B->block);
@@ -1702,21 +1719,23 @@ gko_status gko_batch_launch_info(gko_batch B, int32_t *resident_workgroups,
                 "null batch or output");
         const vt t = B->dt == GKO_F64 ? vt::f64 : vt::f32;
         int r = 0;
-        HIPC(batch_resident(t, B->block, B->max_m, B->lean, &r));
+        HIPC(batch_resident(t, B->block, B->max_m, B->lean, B->waves, &r));
         *resident_workgroups = r;
-        *lds_bytes_per_workgroup = (int64_t)batch_lds_bytes(t, B->max_m, B->lean);
+        *lds_bytes_per_workgroup =
+            (int64_t)batch_lds_bytes(t, B->max_m, B->lean, B->waves, B->block);
     });
 }
 
 gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode) {
     return guarded([&] {
         require(B != nullptr, GKO_ERR_INVALID_ARG, "null batch");
-        require(mode == GKO_BATCH_LDS_ALL || mode == GKO_BATCH_LDS_DIRECTION, GKO_ERR_INVALID_ARG,
-                "unknown LDS mode");
+        require(mode == GKO_BATCH_LDS_ALL || mode == GKO_BATCH_LDS_DIRECTION ||
+                    mode == GKO_BATCH_WAVE_SYSTEMS,
+                GKO_ERR_INVALID_ARG, "unknown LDS mode");
         require(mode == GKO_BATCH_LDS_ALL || batch_lean_ok(B, B->block), GKO_ERR_UNSUPPORTED,
                 "direction-only LDS needs FP64 values and every system in the register cache at "
                 "this workgroup size");
-        B->want_lean = mode == GKO_BATCH_LDS_DIRECTION;
+        batch_want_mode(B, mode);
         batch_use_block(B, B->block);
     });
 }
@@ -1724,7 +1743,7 @@ gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode) {
 gko_status gko_batch_get_lds_mode(gko_batch B, int32_t *mode) {
     return guarded([&] {
         require(B && mode, GKO_ERR_INVALID_ARG, "null batch or output");
-        *mode = B->lean ? GKO_BATCH_LDS_DIRECTION : GKO_BATCH_LDS_ALL;
+        *mode = batch_mode(B);
     });
 }
 
@@ -1754,25 +1773,26 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
     return guarded([&] {
         check_batch_solve_args(B, b, x, tol, maxit, iters_out, relres_out);
         const int cand[4] = {64, 128, 256, 512};
-        int best = B->block, best_mode = B->lean ? 1 : 0;
+        constexpr int kModes = 3;  // gko_batch_lds
+        int best = B->block, best_mode = batch_mode(B);
         float best_ms = std::numeric_limits<float>::infinity();
         for (int j = 0; j < 4; ++j)
-            for (int mode = 0; mode < 2; ++mode) {
+            for (int mode = 0; mode < kModes; ++mode) {
                 float ms = std::numeric_limits<float>::infinity();
-                if (mode == 0 || batch_lean_ok(B, cand[j])) {
-                    B->want_lean = mode == 1;
+                if (mode == GKO_BATCH_LDS_ALL || batch_lean_ok(B, cand[j])) {
+                    batch_want_mode(B, mode);
                     batch_use_block(B, cand[j]);
                     (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);  // warm-up
                     (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, &ms);
                 }
-                if (times_ms) times_ms[2 * j + mode] = ms;
+                if (times_ms) times_ms[kModes * j + mode] = ms;
                 if (ms < best_ms) {
                     best_ms = ms;
                     best = cand[j];
                     best_mode = mode;
                 }
             }
-        B->want_lean = best_mode == 1;
+        batch_want_mode(B, best_mode);
         batch_use_block(B, best);
         if (block_out) *block_out = best;
         cache_store(batch_cache_key(B), std::to_string(best) + " " + std::to_string(best_mode));

