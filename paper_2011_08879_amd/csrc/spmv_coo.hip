@@ -63,16 +63,30 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
         // first row of the next group (wave-uniform address: a scalar load)
         const int64_t nxt = base + kWave * kCooHoist;
         const int32_t next_group_row = nxt < ce ? row[nxt] : -2;
+        // A whole group (uniform) loads without bounds tests: the tested loads
+        // compile to one exec-masked block each (27-point stencil 219 -> 202 us).
+        if (nxt <= ce) {
 #pragma unroll
-        for (int j = 0; j < kCooHoist; ++j) {
-            const int64_t k = base + j * kWave + lane;
-            const bool valid = k < ce;
-            rb[j] = valid ? load_stream(row + k) : INT_MAX;
-            cb_[j] = valid ? load_stream(col + k) : -1;
-            vb[j] = valid ? load_stream(val + k) : V(0);
+            for (int j = 0; j < kCooHoist; ++j) {
+                const int64_t k = base + j * kWave + lane;
+                rb[j] = load_stream(row + k);
+                cb_[j] = load_stream(col + k);
+                vb[j] = load_stream(val + k);
+            }
+#pragma unroll
+            for (int j = 0; j < kCooHoist; ++j) pb[j] = vb[j] * x[cb_[j]];
+        } else {
+#pragma unroll
+            for (int j = 0; j < kCooHoist; ++j) {
+                const int64_t k = base + j * kWave + lane;
+                const bool valid = k < ce;
+                rb[j] = valid ? load_stream(row + k) : INT_MAX;
+                cb_[j] = valid ? load_stream(col + k) : -1;
+                vb[j] = valid ? load_stream(val + k) : V(0);
+            }
+#pragma unroll
+            for (int j = 0; j < kCooHoist; ++j) pb[j] = cb_[j] >= 0 ? vb[j] * x[cb_[j]] : V(0);
         }
-#pragma unroll
-        for (int j = 0; j < kCooHoist; ++j) pb[j] = cb_[j] >= 0 ? vb[j] * x[cb_[j]] : V(0);
 
 #pragma unroll
         for (int j = 0; j < kCooHoist; ++j) {
