@@ -387,14 +387,15 @@ gko_status gko_batch_get_block(gko_batch B, int32_t *block);
  * block) rows per thread) and its x, r and q stay in registers and only the
  * direction p goes through LDS (m doubles per workgroup instead of 4m):
  * FP64 batches whose every system fits the register cache at the workgroup
- * size.  WAVE_SYSTEMS: as DIRECTION, and systems of at most 256 rows are
- * solved one per wavefront (block / 64 of them per workgroup at a time, each
- * wavefront taking its own systems from the queue, sums within the
- * wavefront and no workgroup barrier); larger systems take the whole
- * workgroup.  set_lds_mode(DIRECTION or WAVE_SYSTEMS) fails with
- * GKO_ERR_UNSUPPORTED where DIRECTION does not fit; a later set_block to a
- * size where it does not fit falls back to ALL.  get_lds_mode returns the
- * mode in effect. */
+ * size.  WAVE_SYSTEMS: systems of at most 256 rows are solved one per
+ * wavefront with their rows in registers (block / 64 of them per workgroup
+ * at a time, each wavefront taking its own systems from the queue, sums
+ * within the wavefront and no workgroup barrier); larger systems take the
+ * whole workgroup.  FP64 batches use it with the DIRECTION layout (where
+ * DIRECTION fits), FP32 batches with the ALL layout (where every row has at
+ * most 5 entries).  set_lds_mode fails with GKO_ERR_UNSUPPORTED where the
+ * mode does not fit; a later set_block to a size where it does not fit
+ * falls back to ALL.  get_lds_mode returns the mode in effect. */
 typedef enum gko_batch_lds {
     GKO_BATCH_LDS_ALL = 0,
     GKO_BATCH_LDS_DIRECTION = 1,

@@ -1173,12 +1173,23 @@ bool batch_lean_ok(const gko_batch_s *B, int block) {
     return batch_lean_fits(B->dt == GKO_F64 ? vt::f64 : vt::f32, block, B->max_m, B->max_row_len);
 }
 
+bool batch_waves_ok(const gko_batch_s *B, bool lean) {
+    return batch_waves_fit(B->dt == GKO_F64 ? vt::f64 : vt::f32, lean, B->max_row_len);
+}
+
+// Whether mode (gko_batch_lds) can run at this workgroup size.
+bool batch_mode_ok(const gko_batch_s *B, int mode, int block) {
+    if (mode == GKO_BATCH_LDS_ALL) return true;
+    if (mode == GKO_BATCH_LDS_DIRECTION) return batch_lean_ok(B, block);
+    return batch_waves_ok(B, batch_lean_ok(B, block));
+}
+
 // The workgroup size and the LDS mode (direction only where requested and
 // where every system fits the register cache at that size).
 void batch_use_block(gko_batch B, int block) {
     B->block = block;
     B->lean = B->want_lean && batch_lean_ok(B, block);
-    B->waves = B->want_waves && B->lean;
+    B->waves = B->want_waves && batch_waves_ok(B, B->lean);
 }
 
 // The mode of gko_batch_set_lds_mode in effect.
@@ -1732,9 +1743,10 @@ gko_status gko_batch_set_lds_mode(gko_batch B, int32_t mode) {
         require(mode == GKO_BATCH_LDS_ALL || mode == GKO_BATCH_LDS_DIRECTION ||
                     mode == GKO_BATCH_WAVE_SYSTEMS,
                 GKO_ERR_INVALID_ARG, "unknown LDS mode");
-        require(mode == GKO_BATCH_LDS_ALL || batch_lean_ok(B, B->block), GKO_ERR_UNSUPPORTED,
+        require(batch_mode_ok(B, mode, B->block), GKO_ERR_UNSUPPORTED,
                 "direction-only LDS needs FP64 values and every system in the register cache at "
-                "this workgroup size");
+                "this workgroup size; wavefront systems need that (FP64) or every row in the "
+                "register cache (FP32)");
         batch_want_mode(B, mode);
         batch_use_block(B, B->block);
     });
@@ -1779,7 +1791,7 @@ gko_status gko_batch_autotune(gko_batch B, const double *b, double *x, double to
         for (int j = 0; j < 4; ++j)
             for (int mode = 0; mode < kModes; ++mode) {
                 float ms = std::numeric_limits<float>::infinity();
-                if (mode == GKO_BATCH_LDS_ALL || batch_lean_ok(B, cand[j])) {
+                if (batch_mode_ok(B, mode, cand[j])) {
                     batch_want_mode(B, mode);
                     batch_use_block(B, cand[j]);
                     (void)batch_run(B, b, x, tol, maxit, iters_out, relres_out, nullptr);  // warm-up

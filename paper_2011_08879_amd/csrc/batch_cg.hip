@@ -78,6 +78,7 @@ __device__ inline void wave_sync() {
 template <int T>
 struct wg_team {
     static constexpr int kSize = T;
+    static constexpr bool kIsWave = false;
     double (*red2)[T / kWave];  // the CG loop's two alternating reduction buffers
     double *red;
     __device__ int tid() const { return threadIdx.x; }
@@ -88,6 +89,7 @@ struct wg_team {
 
 struct wave_team {
     static constexpr int kSize = kWave;
+    static constexpr bool kIsWave = true;
     __device__ int tid() const { return threadIdx.x % kWave; }
     __device__ double sum_once(double v, int) const { return wave_total(v); }
     __device__ double sum(double v) const { return wave_total(v); }
@@ -279,6 +281,68 @@ __device__ inline int cg_cached(int32_t m, const sys_regs<VA, Team::kSize> &regs
     return it;
 }
 
+// FP32 storage: FP32 CG iterations inside FP64 iterative refinement, with
+// x and r (FP64) and the inner d, r, p, q (FP32) in LDS from x64 on (32 bytes
+// per row).  Returns the inner iterations; x is left in x64.
+template <typename VA, typename Team>
+__device__ inline int solve_refined(const sys_view &S, const VA *__restrict__ A,
+                                    const double *__restrict__ bs, double bnorm,
+                                    const sys_regs<VA, Team::kSize> &regs, bool cached, double tol,
+                                    int maxit, double *x64, const Team &team, int *flag) {
+    constexpr int T = Team::kSize;
+    double *r64 = x64 + S.m;
+    float *d = reinterpret_cast<float *>(r64 + S.m);
+    float *r = d + S.m, *p = r + S.m, *q = p + S.m;
+    for (int i = team.tid(); i < S.m; i += T) {
+        x64[i] = 0.0;
+        r64[i] = bs[i];
+    }
+    team.sync();
+    int its = 0;
+    *flag = 0;
+    double rn = bnorm, prev = INFINITY;
+    for (int outer = 0; outer < 20; ++outer) {
+        if (!(rn > tol * bnorm) || !(rn <= 0.5 * prev)) break;
+        prev = rn;
+        double tau = 0.5 * (tol * bnorm / rn);
+        if (tau < 1e-5) tau = 1e-5;
+        double rt2 = 0.0;
+        for (int i = team.tid(); i < S.m; i += T) {
+            const float ri = (float)(r64[i] / rn);
+            d[i] = 0.0f;
+            r[i] = ri;
+            p[i] = ri;
+            rt2 += (double)ri * (double)ri;
+        }
+        rt2 = team.sum(rt2);
+        if constexpr (Team::kIsWave) {
+            // a wavefront only takes systems whose rows are all cached
+            its += cg_cached<VA, float, Team>(S.m, regs, d, r, p, rt2, tau * tau * rt2, maxit - its,
+                                              team, flag);
+        } else {
+            its += cached ? cg_cached<VA, float, Team>(S.m, regs, d, r, p, rt2, tau * tau * rt2,
+                                                       maxit - its, team, flag)
+                          : cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
+                                                    maxit - its, team.red2, flag);
+        }
+        if (*flag) break;
+        // x += |r| d, then the FP64 residual b - A x
+        for (int i = team.tid(); i < S.m; i += T) x64[i] = x64[i] + rn * (double)d[i];
+        team.sync();
+        double loc = 0.0;
+        for (int i = team.tid(); i < S.m; i += T) {
+            double s = 0.0;
+            for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * x64[S.col[k]];
+            const double ri = bs[i] - s;
+            r64[i] = ri;
+            loc += ri * ri;
+        }
+        rn = sqrt(team.sum(loc));
+        if (its >= maxit) break;
+    }
+    return its;
+}
+
 // A view of system sid of the batch.
 __device__ inline sys_view system_view(int32_t sid, const int64_t *__restrict__ row_off,
                                        const int64_t *__restrict__ nnz_off,
@@ -327,8 +391,9 @@ __device__ inline unsigned pop_wave(unsigned *counter) {
     return (unsigned)__builtin_amdgcn_readfirstlane((int)q);
 }
 
-// One system solved by one wavefront (LEAN: rows in registers, p then x in
-// this wavefront's LDS slice pw of kWaveRows doubles).
+// One system solved by one wavefront, its rows in registers.  FP64 (LEAN):
+// p, then x, in this wavefront's LDS slice pw (kWaveRows doubles); FP32
+// storage: the refinement's vectors in pw (4 kWaveRows doubles).
 template <typename VA>
 __device__ inline void solve_on_wave(int32_t sid, const int64_t *__restrict__ row_off,
                                      const int64_t *__restrict__ nnz_off,
@@ -344,19 +409,25 @@ __device__ inline void solve_on_wave(int32_t sid, const int64_t *__restrict__ ro
     double bb = 0.0;
     for (int i = team.tid(); i < S.m; i += kWave) bb += bs[i] * bs[i];
     bb = team.sum(bb);
+    const double bnorm = sqrt(bb);
     sys_regs<VA, kWave> regs;
     int its = 0, flag = 2;
-    if (regs.load(S, A, team))
-        its = cg_cached<VA, double, wave_team, true>(S.m, regs, nullptr, bs, pw, bb,
-                                                     tol * tol * bb, maxit, team, &flag);
+    if (regs.load(S, A, team)) {
+        if constexpr (sizeof(VA) == 8)
+            its = cg_cached<VA, double, wave_team, true>(S.m, regs, nullptr, bs, pw, bb,
+                                                         tol * tol * bb, maxit, team, &flag);
+        else
+            its = solve_refined(S, A, bs, bnorm, regs, true, tol, maxit, pw, team, &flag);
+    }
     team.sync();
-    finish_system(sid, S, A, bs, pw, xout, sqrt(bb), tol, its, flag, iters, relres, status, team);
+    finish_system(sid, S, A, bs, pw, xout, bnorm, tol, its, flag, iters, relres, status, team);
     team.sync();  // pw is rewritten by the next system
 }
 
 // LEAN (FP64 batches whose every system fits the register cache): only the
 // direction p, later x, is in LDS, m doubles per workgroup instead of 4m.
-// WAVES (with LEAN): systems of at most kWaveRows rows one per wavefront.
+// WAVES (FP64 with LEAN, or FP32 storage whose rows all fit the register
+// cache): systems of at most kWaveRows rows one per wavefront.
 template <typename VA, int T, bool LEAN, bool WAVES>
 __global__ __launch_bounds__(T, (WAVES && T == 256) ? 4 : 1) void batch_cg_kernel(
     int64_t nsys, const int64_t *__restrict__ row_off, const int64_t *__restrict__ nnz_off,
@@ -369,7 +440,7 @@ __global__ __launch_bounds__(T, (WAVES && T == 256) ? 4 : 1) void batch_cg_kerne
     __shared__ double red2[2][T / kWave];
     __shared__ unsigned s_next;
     constexpr bool kRefine = sizeof(VA) == 4;  // FP32 storage: FP32 CG inside FP64 refinement
-    static_assert(!WAVES || (LEAN && !kRefine), "the wavefront mode runs LEAN FP64 systems");
+    static_assert(!WAVES || LEAN != kRefine, "the wavefront mode runs LEAN FP64 or FP32 systems");
     const wg_team<T> team{red2, red};
     for (;;) {
         if (threadIdx.x == 0) s_next = atomicAdd(counter, 1u);
@@ -386,7 +457,7 @@ __global__ __launch_bounds__(T, (WAVES && T == 256) ? 4 : 1) void batch_cg_kerne
                 // systems of its own (wavefront 0 this one) until the queue
                 // is empty, and the workgroup passes no barrier again.
                 const int wv = threadIdx.x / kWave;
-                double *pw = lds + wv * kWaveRows;
+                double *pw = lds + wv * kWaveRows * (kRefine ? 4 : 1);
                 for (unsigned q = wv == 0 ? qi : pop_wave(counter); q < nsys; q = pop_wave(counter))
                     solve_on_wave(order[q], row_off, nnz_off, rp_local, col, val, b, xout, tol,
                                   maxit, iters, relres, status, pw);
@@ -423,49 +494,7 @@ __global__ __launch_bounds__(T, (WAVES && T == 256) ? 4 : 1) void batch_cg_kerne
                          : cg_in_lds<VA, double, T>(S, A, x64, r, p, q, bb, tol * tol * bb, maxit,
                                                     red2, &flag);
         } else {
-            double *r64 = x64 + S.m;
-            float *d = reinterpret_cast<float *>(r64 + S.m);
-            float *r = d + S.m, *p = r + S.m, *q = p + S.m;
-            for (int i = threadIdx.x; i < S.m; i += T) {
-                x64[i] = 0.0;
-                r64[i] = bs[i];
-            }
-            wg_sync<T>();
-            double rn = bnorm, prev = INFINITY;
-            for (int outer = 0; outer < 20; ++outer) {
-                if (!(rn > tol * bnorm) || !(rn <= 0.5 * prev)) break;
-                prev = rn;
-                double tau = 0.5 * (tol * bnorm / rn);
-                if (tau < 1e-5) tau = 1e-5;
-                double rt2 = 0.0;
-                for (int i = threadIdx.x; i < S.m; i += T) {
-                    const float ri = (float)(r64[i] / rn);
-                    d[i] = 0.0f;
-                    r[i] = ri;
-                    p[i] = ri;
-                    rt2 += (double)ri * (double)ri;
-                }
-                rt2 = wg_sum<T>(rt2, red);
-                its += cached ? cg_cached<VA, float, wg_team<T>>(S.m, regs, d, r, p, rt2,
-                                                                 tau * tau * rt2, maxit - its, team,
-                                                                 &flag)
-                              : cg_in_lds<VA, float, T>(S, A, d, r, p, q, rt2, tau * tau * rt2,
-                                                        maxit - its, red2, &flag);
-                if (flag) break;
-                // x += |r| d, then the FP64 residual b - A x
-                for (int i = threadIdx.x; i < S.m; i += T) x64[i] = x64[i] + rn * (double)d[i];
-                wg_sync<T>();
-                double loc = 0.0;
-                for (int i = threadIdx.x; i < S.m; i += T) {
-                    double s = 0.0;
-                    for (int32_t k = S.rp[i]; k < S.rp[i + 1]; ++k) s += (double)A[k] * x64[S.col[k]];
-                    const double ri = bs[i] - s;
-                    r64[i] = ri;
-                    loc += ri * ri;
-                }
-                rn = sqrt(wg_sum<T>(loc, red));
-                if (its >= maxit) break;
-            }
+            its = solve_refined(S, A, bs, bnorm, regs, cached, tol, maxit, x64, team, &flag);
         }
         // true residual of the final x (FP64), x to global memory
         wg_sync<T>();
@@ -515,11 +544,14 @@ __global__ void batch_reset_kernel(unsigned *counter, int *status) {
 }
 
 size_t batch_lds_bytes(vt t, int64_t max_m, bool lean, bool waves, int block) {
-    if (lean) {
-        const int64_t slices = waves ? (int64_t)(block / kWave) * kWaveRows : 0;
-        return (size_t)(max_m > slices ? max_m : slices) * 8;
-    }
-    return (size_t)max_m * (t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4);
+    // bytes per row: p (LEAN), x r p q (FP64), x r in FP64 and d r p q in FP32
+    const int64_t per_row = lean ? 8 : t == vt::f64 ? 4 * 8 : 2 * 8 + 4 * 4;
+    const int64_t rows = waves ? (int64_t)(block / kWave) * kWaveRows : 0;
+    return (size_t)((max_m > rows ? max_m : rows) * per_row);
+}
+
+bool batch_waves_fit(vt t, bool lean, int64_t max_row_len) {
+    return t == vt::f64 ? lean : max_row_len <= kBatchCacheLen;
 }
 
 bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len) {
@@ -556,8 +588,10 @@ static hipError_t resident_v(int block, int64_t max_m, int *out) {
 }
 
 hipError_t batch_resident(vt t, int block, int64_t max_m, bool lean, bool waves, int *workgroups) {
-    if ((lean && t != vt::f64) || (waves && !lean)) return hipErrorInvalidValue;
-    if (t == vt::f32) return resident_v<float, false, false>(block, max_m, workgroups);
+    if ((lean && t != vt::f64) || (waves && t == vt::f64 && !lean)) return hipErrorInvalidValue;
+    if (t == vt::f32)
+        return waves ? resident_v<float, false, true>(block, max_m, workgroups)
+                     : resident_v<float, false, false>(block, max_m, workgroups);
     if (!lean) return resident_v<double, false, false>(block, max_m, workgroups);
     return waves ? resident_v<double, true, true>(block, max_m, workgroups)
                  : resident_v<double, true, false>(block, max_m, workgroups);
@@ -594,8 +628,10 @@ static hipError_t launch_batch_v(hipStream_t s, const batch_args &a) {
 hipError_t batch_cg(hipStream_t s, vt t, const batch_args &a) {
     if (a.nsys == 0) return hipSuccess;
     if (a.lean && !batch_lean_fits(t, a.block, a.max_m, a.max_row_len)) return hipErrorInvalidValue;
-    if (a.waves && !a.lean) return hipErrorInvalidValue;
-    if (t == vt::f32) return launch_batch_v<float, false, false>(s, a);
+    if (a.waves && !batch_waves_fit(t, a.lean, a.max_row_len)) return hipErrorInvalidValue;
+    if (t == vt::f32)
+        return a.waves ? launch_batch_v<float, false, true>(s, a)
+                       : launch_batch_v<float, false, false>(s, a);
     if (!a.lean) return launch_batch_v<double, false, false>(s, a);
     return a.waves ? launch_batch_v<double, true, true>(s, a)
                    : launch_batch_v<double, true, false>(s, a);

@@ -36,7 +36,7 @@ struct batch_args {
     int64_t max_row_len;      // longest row of any system
     int block;                // workgroup size: 64, 128, 256 or 512
     bool lean;                // only p in LDS (batch_lean_fits must hold)
-    bool waves;               // with lean: systems of <= kWaveRows rows one per wavefront
+    bool waves;               // systems of <= kWaveRows rows one per wavefront (batch_waves_fit)
 };
 
 // Rows of up to this many entries are held in registers for a system's solve.
@@ -46,6 +46,9 @@ constexpr int kBatchCacheLen = 5;
 constexpr int kWaveRows = 4 * 64;
 
 size_t batch_lds_bytes(vt t, int64_t max_m, bool lean, bool waves, int block);
+// Whether the wavefront mode can run: FP64 with the direction-only layout
+// (lean), FP32 storage when every row fits the register cache.
+bool batch_waves_fit(vt t, bool lean, int64_t max_row_len);
 // Whether every system of the batch fits the register cache at this
 // workgroup size (FP64 only), so that only p needs LDS.
 bool batch_lean_fits(vt t, int block, int64_t max_m, int64_t max_row_len);

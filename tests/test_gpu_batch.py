@@ -74,19 +74,23 @@ def test_batch_fp32_refined_matches_oracle(g, orc, gen_mod):
     rc, xo, it_o, rr_o = orc.batch_ir_cg(B.row_off, B.nnz_off, B.row_ptr, B.col, vals, b, tol=1e-10)
     assert rc == orc.OK and np.all(rr_o <= 1e-10)
     G = g.Batch(B.row_off, B.nnz_off, B.row_ptr, B.col, v32, dtype=torch.float32)
-    x = dev(np.zeros(B.xstar.shape))
-    st, it, rr = G.solve(dev(b), x, tol=1e-10)
-    assert st == g.OK
-    xg, itg, rrg = host(x), host(it), host(rr)
-    assert np.all(rrg <= 1e-10)
-    # same refinement schedule; FP32 rounding may move each inner stop by a few steps
-    assert np.all(np.abs(itg - it_o) <= np.maximum(6, it_o // 10)), np.abs(itg - it_o).max()
-    for i in range(0, B.nsys, 7):
-        r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
-        rp, c, _ = B.system(i)
-        k0, k1 = int(B.nnz_off[i]), int(B.nnz_off[i + 1])
-        true = np.linalg.norm(b[r0:r1] - orc.spmv((rp, c, vals[k0:k1]), xg[r0:r1])) / np.linalg.norm(b[r0:r1])
-        assert true <= 1e-10
+    for block, mode in ((G.block, G.lds_mode), (256, "waves"), (128, "waves")):
+        G.block = block
+        G.lds_mode = mode
+        assert G.lds_mode == mode
+        x = dev(np.zeros(B.xstar.shape))
+        st, it, rr = G.solve(dev(b), x, tol=1e-10)
+        assert st == g.OK
+        xg, itg, rrg = host(x), host(it), host(rr)
+        assert np.all(rrg <= 1e-10)
+        # same refinement schedule; FP32 rounding may move each inner stop by a few steps
+        assert np.all(np.abs(itg - it_o) <= np.maximum(6, it_o // 10)), np.abs(itg - it_o).max()
+        for i in range(0, B.nsys, 7):
+            r0, r1 = int(B.row_off[i]), int(B.row_off[i + 1])
+            rp, c, _ = B.system(i)
+            k0, k1 = int(B.nnz_off[i]), int(B.nnz_off[i + 1])
+            true = np.linalg.norm(b[r0:r1] - orc.spmv((rp, c, vals[k0:k1]), xg[r0:r1])) / np.linalg.norm(b[r0:r1])
+            assert true <= 1e-10
 
 
 def test_batch_deterministic_and_autotune(g, orc, gen_mod):
