@@ -552,7 +552,38 @@ def run_krylov(g, torch, ctx, M, b, n):
                                                          out[name]["alg_GB/s"]))
     ctx.set_solver_opts()
     out["cg_vs_pipecg_by_size"] = cg_vs_pipecg(g, torch, ctx)
+    out["gmres_small_systems"] = gmres_small(g, torch, ctx)
     return out
+
+
+def gmres_small(g, torch, ctx):
+    """GMRES(30) on small 3D Poisson matrices (CSR), the whole solve on one
+    workgroup against the multi-kernel path: us per Arnoldi step over 300
+    steps (tol 1e-30, so every step runs; restarts included)."""
+    import gen
+    res = {}
+    for N in (12, 16):   # 1,728 and 4,096 rows (the one-workgroup solve takes up to 4,096)
+        A = gen.laplace3d(N)
+        n = N ** 3
+        M = g.Matrix.from_csr(*A)
+        b = torch.from_numpy(gen.uniform(5, n)).cuda()
+        row = {}
+        for label, single in (("one_workgroup", 1), ("multi_kernel", 0)):
+            ctx.set_solver_opts(krylov_dim=30, single_workgroup=single)
+            best = None
+            for _ in range(3):
+                x = torch.zeros(n, dtype=torch.float64, device="cuda")
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                info = g.gmres(M, b, x, tol=1e-30, maxit=300)
+                el = time.perf_counter() - t0
+                best = el if best is None else min(best, el)
+            row[label + "_us_per_step"] = round(best / info["iterations"] * 1e6, 2)
+        ctx.set_solver_opts()
+        res["poisson3d_%d" % N] = row
+        log("gmres(30) n=%d: one workgroup %.1f, multi-kernel %.1f us per step" %
+            (n, row["one_workgroup_us_per_step"], row["multi_kernel_us_per_step"]))
+    return res
 
 
 def cg_vs_pipecg(g, torch, ctx):

@@ -223,8 +223,10 @@ typedef struct gko_solver_opts {
     int32_t max_outer;   /* MIXED_IR: outer step cap (default 20) */
     int32_t single_workgroup; /* 1 (default): FP64 unpreconditioned CG on a CSR matrix whose
                                  direction vector fits in one workgroup's LDS (n up to 8192 on
-                                 gfx950) runs as one launch on one workgroup; 0: always the
-                                 multi-kernel path.  Same steps and stopping test either way. */
+                                 gfx950), and GMRES on a CSR matrix of up to 4096 rows with a
+                                 restart length of up to 64, run as one launch on one
+                                 workgroup; 0: always the multi-kernel path.  Same steps and
+                                 stopping tests either way. */
     int32_t krylov_dim;  /* GMRES restart length m, 1..128 (default 30) */
     int32_t graphs;      /* 1 (default): on matrices of at most 2^20 rows, the multi-kernel
                             CG, flexible CG, pipelined CG, BiCGSTAB and CGS loops capture one

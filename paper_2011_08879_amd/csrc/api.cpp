@@ -2670,6 +2670,23 @@ gko_status gko_gmres_solve(gko_matrix A, const void *b, void *x, double tol, int
         const values v = own_values(A);
         const int64_t ldv = gmres_ld(n);
         dbuf V(c, (size_t)(m + 1) * ldv * 8);
+        if (c->opts.single_workgroup && n <= gmres_small_max_rows() && m <= kGmresSmallKrylov &&
+            (A->fmt == GKO_FMT_CSR || A->fmt == GKO_FMT_CSR_MERGE)) {
+            // the whole solve on one workgroup, one launch
+            dbuf state(c, sizeof(gmres_state));
+            auto *S = state.as<gmres_state>();
+            HIPC(gmres_small(s, n, m, A->rp, A->col, static_cast<const double *>(v.val),
+                             static_cast<const double *>(b), static_cast<double *>(x), V.as<double>(),
+                             ldv, tol * bnorm, maxit, S));
+            gmres_state h{};
+            HIPC(hipMemcpyAsync(&h, S, sizeof(h), hipMemcpyDeviceToHost, s));
+            c->sync();
+            c->info.iterations = h.iter;
+            c->info.outer_iterations = h.cycles;
+            c->info.reorthogonalized = h.reorths;
+            c->info.rel_residual = h.est / bnorm;
+            return h.done;
+        }
         // work arrays carved from one buffer
         const int64_t np = gmres_partial_elems(n, m);
         const int64_t sizes[] = {np, m + 2, m + 2, 1, 1, m + 1, (int64_t)(m + 1) * m, m, m,

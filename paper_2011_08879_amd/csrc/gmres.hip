@@ -389,6 +389,242 @@ __global__ void gmres_cycle_kernel(const double *__restrict__ rr, gmres_state *s
     }
 }
 
+// ------------------------------------------------------------ one workgroup
+// The whole restarted GMRES(m) of a small CSR system in one launch of one
+// 1024-thread workgroup: the same steps, criteria and state as the kernels
+// above, without a launch or host poll per step.  Thread t owns rows t,
+// t + 1024, ...; w of those rows stays in registers through a step; the
+// basis lives in global memory (L2-resident at these sizes); the rotated
+// Hessenberg R, g and the rotations in LDS.  Per-vector sums are wave DPP
+// sums, then the waves' totals are added in wave order; the small scalar
+// work (the column's rotations, the back substitution) runs on thread 0.
+constexpr int kSGT = 1024;
+constexpr int kSGRows = 4;
+constexpr int kSGWaves = kSGT / kWave;
+
+struct small_gmres_lds {
+    double red[kSGWaves][kGmresSmallKrylov + 2];
+    double R[kGmresSmallKrylov][kGmresSmallKrylov];  // R[i][j], i <= j
+    double g[kGmresSmallKrylov + 1], cs[kGmresSmallKrylov], sn[kGmresSmallKrylov];
+    double h[kGmresSmallKrylov + 2], h2[kGmresSmallKrylov + 2], y[kGmresSmallKrylov];
+    double hcol[kGmresSmallKrylov + 1];
+    double hn, est, ww;
+    int cycle_done, breakdown;
+};
+
+// Vectors taken together by the passes over the basis, so that their loads
+// are in flight at once.
+constexpr int kSGVecs = 4;
+
+// out[i] = V_i . w for i < k, out[k] = w . w (w: this thread's rows).
+__device__ inline void sg_dots(int k, int64_t n, const double *__restrict__ V, int64_t ldv,
+                               const double (&w)[kSGRows], double *out, small_gmres_lds &L) {
+    const int t = threadIdx.x, lane = t % kWave, wv = t / kWave;
+    for (int i0 = 0; i0 <= k; i0 += kSGVecs) {
+        double s[kSGVecs];
+#pragma unroll
+        for (int u = 0; u < kSGVecs; ++u) s[u] = 0.0;
+#pragma unroll
+        for (int r = 0; r < kSGRows; ++r) {
+            const int64_t row = t + (int64_t)r * kSGT;
+            if (row < n) {
+#pragma unroll
+                for (int u = 0; u < kSGVecs; ++u) {
+                    const int i = i0 + u;
+                    if (i < k) s[u] += V[(int64_t)i * ldv + row] * w[r];
+                    else if (i == k) s[u] += w[r] * w[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSGVecs; ++u) {
+            if (i0 + u > k) break;
+            const double tot = wave_total(s[u]);
+            if (lane == 0) L.red[wv][i0 + u] = tot;
+        }
+    }
+    __syncthreads();
+    if (t <= k) {
+        double s = 0.0;
+        for (int q = 0; q < kSGWaves; ++q) s += L.red[q][t];
+        out[t] = s;
+    }
+    __syncthreads();
+}
+
+// w -= sum_{i < k} c_i V_i over this thread's rows, in ascending i, two
+// vectors' loads at a time (four would spill).
+__device__ inline void sg_subtract(int k, int64_t n, const double *__restrict__ V, int64_t ldv,
+                                   const double *c, double (&w)[kSGRows]) {
+    constexpr int U = 2;
+    const int t = threadIdx.x;
+    for (int i0 = 0; i0 < k; i0 += U) {
+        double v[U][kSGRows];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int r = 0; r < kSGRows; ++r) {
+                const int64_t row = t + (int64_t)r * kSGT;
+                v[u][r] = (i0 + u < k && row < n) ? V[(int64_t)(i0 + u) * ldv + row] : 0.0;
+            }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u < k)
+#pragma unroll
+                for (int r = 0; r < kSGRows; ++r) w[r] = w[r] - c[i0 + u] * v[u][r];
+    }
+}
+
+// y = A v over this thread's rows (CSR rows from memory), four entries of a
+// row in flight.
+__device__ inline void sg_spmv(int64_t n, const int32_t *__restrict__ rp,
+                               const int32_t *__restrict__ col, const double *__restrict__ val,
+                               const double *__restrict__ v, double (&y)[kSGRows]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int r = 0; r < kSGRows; ++r) {
+        const int64_t row = t + (int64_t)r * kSGT;
+        double s = 0.0;
+        if (row < n) {
+            const int32_t b = rp[row], e = rp[row + 1];
+            int32_t q = b;
+            for (; q + 4 <= e; q += 4) {
+                const int32_t c0 = col[q], c1 = col[q + 1], c2 = col[q + 2], c3 = col[q + 3];
+                const double x0 = v[c0], x1 = v[c1], x2 = v[c2], x3 = v[c3];
+                s += val[q] * x0;
+                s += val[q + 1] * x1;
+                s += val[q + 2] * x2;
+                s += val[q + 3] * x3;
+            }
+            for (; q < e; ++q) s += val[q] * v[col[q]];
+        }
+        y[r] = s;
+    }
+}
+
+__global__ __launch_bounds__(kSGT) void gmres_small_kernel(
+    int64_t n, int m, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+    const double *__restrict__ val, const double *__restrict__ b, double *__restrict__ x,
+    double *__restrict__ V, int64_t ldv, double stop, int maxit, gmres_state *out) {
+    __shared__ small_gmres_lds L;
+    const int t = threadIdx.x;
+    if (t == 0) L.est = 0.0;  // visible after the first sum's barrier
+    int iter = 0, cycles = 0, reorths = 0, done = kRunning, k = 0;
+    double beta = 0.0;
+    double w[kSGRows];
+    for (;;) {
+        // cycle start: v0 = b - A x and its norm
+        sg_spmv(n, rp, col, val, x, w);
+#pragma unroll
+        for (int r = 0; r < kSGRows; ++r) {
+            const int64_t row = t + (int64_t)r * kSGT;
+            w[r] = row < n ? b[row] - w[r] : 0.0;
+        }
+        sg_dots(0, n, V, ldv, w, L.h, L);
+        beta = sqrt(L.h[0]);
+        if (std::isnan(beta) || std::isinf(beta)) { done = kBreakdown; break; }
+        if (beta <= stop) { done = kConverged; break; }
+        if (iter >= maxit) { done = kMaxIter; break; }
+        ++cycles;
+#pragma unroll
+        for (int r = 0; r < kSGRows; ++r) {
+            const int64_t row = t + (int64_t)r * kSGT;
+            if (row < n) V[row] = w[r] / beta;
+        }
+        if (t == 0) L.g[0] = beta;
+        __syncthreads();
+        for (int j = 0; j < m; ++j) {
+            // w = A v_j
+            sg_spmv(n, rp, col, val, V + (int64_t)j * ldv, w);
+            // classical Gram-Schmidt, a second round when the first lost
+            // more than 1/sqrt(2) of w
+            sg_dots(j + 1, n, V, ldv, w, L.h, L);
+            sg_subtract(j + 1, n, V, ldv, L.h, w);
+            sg_dots(j + 1, n, V, ldv, w, L.h2, L);
+            double ww = L.h2[j + 1];
+            const bool reorth = 2.0 * L.h2[j + 1] < L.h[j + 1];
+            if (reorth) {
+                ++reorths;
+                sg_subtract(j + 1, n, V, ldv, L.h2, w);
+                sg_dots(0, n, V, ldv, w, &L.ww, L);
+                ww = L.ww;
+            }
+            ++iter;
+            k = j + 1;
+            if (t == 0) {
+                // the column of H, the earlier rotations, the new one
+                double *hcol = L.hcol;
+                for (int i = 0; i <= j; ++i) hcol[i] = reorth ? L.h[i] + L.h2[i] : L.h[i];
+                const double hn = sqrt(ww);
+                for (int i = 0; i < j; ++i) {
+                    const double a = hcol[i], c = hcol[i + 1];
+                    hcol[i] = L.cs[i] * a + L.sn[i] * c;
+                    hcol[i + 1] = -L.sn[i] * a + L.cs[i] * c;
+                }
+                const double a = hcol[j];
+                const double d = sqrt(a * a + hn * hn);
+                L.hn = hn;
+                L.breakdown = 0;
+                L.cycle_done = 0;
+                if (!(d > 0.0)) {
+                    L.breakdown = 1;
+                } else {
+                    L.cs[j] = a / d;
+                    L.sn[j] = hn / d;
+                    hcol[j] = d;
+                    for (int i = 0; i <= j; ++i) L.R[i][j] = hcol[i];
+                    L.g[j + 1] = -L.sn[j] * L.g[j];
+                    L.g[j] = L.cs[j] * L.g[j];
+                    const double est = fabs(L.g[j + 1]);
+                    L.est = est;
+                    if (std::isnan(est)) L.breakdown = 1;
+                    else if (est <= stop || hn == 0.0 || iter >= maxit || j + 1 == m)
+                        L.cycle_done = 1;
+                }
+            }
+            __syncthreads();
+            if (L.breakdown) { done = kBreakdown; break; }
+            if (L.cycle_done) break;
+            const double hn = L.hn;
+            double *vn = V + (int64_t)(j + 1) * ldv;
+#pragma unroll
+            for (int r = 0; r < kSGRows; ++r) {
+                const int64_t row = t + (int64_t)r * kSGT;
+                if (row < n) vn[row] = w[r] / hn;
+            }
+            __syncthreads();
+        }
+        if (done == kBreakdown) break;
+        // cycle end: R y = g over the k columns, x += V_k y
+        if (t == 0)
+            for (int i = k - 1; i >= 0; --i) {
+                double s = L.g[i];
+                for (int l = i + 1; l < k; ++l) s = s - L.R[i][l] * L.y[l];
+                L.y[i] = s / L.R[i][i];
+            }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < kSGRows; ++r) {
+            const int64_t row = t + (int64_t)r * kSGT;
+            if (row < n) {
+                double xl = x[row];
+                for (int i = 0; i < k; ++i) xl = xl + L.y[i] * V[(int64_t)i * ldv + row];
+                x[row] = xl;
+            }
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        out->iter = iter;
+        out->cycles = cycles;
+        out->reorths = reorths;
+        out->done = done;
+        out->est = L.est;
+        out->beta = beta;
+        out->k = k;
+    }
+}
+
 }  // namespace
 
 int64_t gmres_ld(int64_t n) { return (n + 63) / 64 * 64; }
@@ -426,6 +662,17 @@ hipError_t gmres_cycle_start(hipStream_t s, int64_t n, double *V, gmres_state *s
     gmres_sum_kernel<<<1, kG, 0, s>>>(g, wk.partials, wk.upd1, st, 2);
     gmres_cycle_kernel<<<1, 1, 0, s>>>(wk.upd1, st, wk.g);
     gmres_scale_kernel<<<reduction_blocks(n), kG, 0, s>>>(n, V, st);
+    return hipGetLastError();
+}
+
+int64_t gmres_small_max_rows() { return (int64_t)kSGT * kSGRows; }
+
+hipError_t gmres_small(hipStream_t s, int64_t n, int m, const int32_t *rp, const int32_t *col,
+                       const double *val, const double *b, double *x, double *V, int64_t ldv,
+                       double stop, int maxit, gmres_state *out) {
+    if (n < 1 || n > gmres_small_max_rows() || m < 1 || m > kGmresSmallKrylov)
+        return hipErrorInvalidValue;
+    gmres_small_kernel<<<1, kSGT, 0, s>>>(n, m, rp, col, val, b, x, V, ldv, stop, maxit, out);
     return hipGetLastError();
 }
 

@@ -127,6 +127,7 @@ hipError_t cgs_direction(hipStream_t s, int64_t n, const void *r, const void *q,
 // the cycle with gmres_cycle_end (x += V_k y).  Flags and scalars live in
 // gmres_state; every kernel of a closed cycle returns at once.
 constexpr int kGmresMaxKrylov = 128;   // largest restart length
+constexpr int kGmresSmallKrylov = 64;  // largest restart length of the one-workgroup solve
 constexpr int kGmresMaxBlocks = 2048;  // grid of the multi-vector passes (1024: 12% slower)
 struct gmres_state {
     double stop;        // tol * ||b||
@@ -161,6 +162,14 @@ hipError_t gmres_arnoldi_step(hipStream_t s, int64_t n, int m, int j, double *V,
                               gmres_state *st, const gmres_work &wk);
 hipError_t gmres_cycle_end(hipStream_t s, int64_t n, int m, const double *V, int64_t ldv, double *x,
                            gmres_state *st, const gmres_work &wk);
+// The whole solve of a small CSR system (n <= gmres_small_max_rows(), m <=
+// kGmresSmallKrylov) in one launch of one workgroup, from x (in/out), with
+// the basis in V ((m + 1) ldv doubles).  out: iter, cycles, reorths, done,
+// est, beta, k as the multi-kernel path leaves them in gmres_state.
+int64_t gmres_small_max_rows();
+hipError_t gmres_small(hipStream_t s, int64_t n, int m, const int32_t *rp, const int32_t *col,
+                       const double *val, const double *b, double *x, double *V, int64_t ldv,
+                       double stop, int maxit, gmres_state *out);
 
 // Mixed precision helpers.
 hipError_t scaled_cast(hipStream_t s, int64_t n, const double *r, const double *norm, float *rt);

@@ -194,3 +194,55 @@ def test_batch_edge_cases_and_statuses(g, orc):
     with pytest.raises(g.GkoError):
         g.Batch(np.array([0, n_big], np.int64), np.array([0, n_big], np.int64),
                 np.arange(n_big + 1, dtype=np.int32), np.arange(n_big, dtype=np.int32), np.ones(n_big))
+
+
+@pytest.mark.parametrize("f32", [False, True], ids=["f64", "f32"])
+def test_batch_wave_mode_statuses(g, orc, f32):
+    """The wavefront mode on small and boundary systems: a 1x1, a 2x2 SPD, an
+    indefinite diagonal system (NOT_SPD), a zero right-hand side (x = 0) and
+    3-point systems of 255, 256 (a wavefront's limit) and 257 rows (the
+    workgroup path), next to each other in one batch."""
+    import torch
+    sizes = [255, 256, 257]
+    row_off, nnz_off, rps, cols, vals = [0], [0], [], [], []
+
+    def add(rp, col, val):
+        rps.append(np.asarray(rp, np.int32))
+        cols.append(np.asarray(col, np.int32))
+        vals.append(np.asarray(val, np.float64))
+        row_off.append(row_off[-1] + len(rp) - 1)
+        nnz_off.append(nnz_off[-1] + len(col))
+
+    add([0, 1], [0], [4.0])
+    add([0, 2, 4], [0, 1, 0, 1], [2.0, -1.0, -1.0, 2.0])
+    for m in sizes + [64]:
+        rp = np.concatenate([[0], np.cumsum([2] + [3] * (m - 2) + [2])])
+        col = np.concatenate([[0, 1]] + [[i - 1, i, i + 1] for i in range(1, m - 1)] + [[m - 2, m - 1]])
+        val = np.concatenate([[2.5, -1.0]] + [[-1.0, 2.5, -1.0]] * (m - 2) + [[-1.0, 2.5]])
+        add(rp, col, val)
+    add([0, 1, 2], [0, 1], [1.0, -1.0])
+    nsys = len(rps)
+    rp_all, col_all, val_all = np.concatenate(rps), np.concatenate(cols), np.concatenate(vals)
+    rng = np.random.default_rng(3)
+    b = rng.uniform(-1, 1, row_off[-1])
+    zero = slice(row_off[5], row_off[6])          # the 64-row system gets b = 0
+    b[zero] = 0.0
+    b[row_off[6]:row_off[7]] = [0.1, 1.0]         # p.q = 0.01 - 1 < 0 at the first step
+    if f32:
+        val_all = val_all.astype(np.float32)
+    G = g.Batch(np.array(row_off, np.int64), np.array(nnz_off, np.int64), rp_all, col_all, val_all,
+                dtype=torch.float32 if f32 else torch.float64)
+    G.block = 256
+    G.lds_mode = "waves"
+    assert G.lds_mode == "waves"
+    x = dev(np.full(row_off[-1], np.nan))
+    st, it, rr = G.solve(dev(b), x, tol=1e-10)
+    assert st == g.ERR_NOT_SPD
+    xg, rrg = host(x), host(rr)
+    assert np.all(xg[zero] == 0.0) and rrg[5] == 0.0
+    for i in range(nsys - 1):                     # every system but the indefinite one converged
+        r0, r1 = row_off[i], row_off[i + 1]
+        A = (rps[i], cols[i], val_all[nnz_off[i]:nnz_off[i + 1]].astype(np.float64))
+        if i != 5:
+            true = np.linalg.norm(b[r0:r1] - orc.spmv(A, xg[r0:r1])) / np.linalg.norm(b[r0:r1])
+            assert true <= 1e-10 and rrg[i] <= 1e-10, (i, true, rrg[i])

@@ -193,6 +193,38 @@ def test_gmres_restart_lengths_laplace(g, orc, gen_mod, ctx, m):
         assert relres(orc, A, b, host(x)) <= tol
 
 
+@pytest.mark.parametrize("m,maxit", [(5, 20000), (30, 20000), (64, 20000), (8, 37)])
+def test_gmres_one_workgroup_matches_multikernel(g, orc, gen_mod, ctx, m, maxit):
+    """Small CSR systems (n <= 4096, m <= 64) run the whole GMRES in one
+    workgroup launch; the multi-kernel path (single_workgroup = 0) takes the
+    same steps: equal iteration and cycle counts up to rounding, both
+    solutions within the oracle's tolerance (maxit = 37 stops inside a
+    cycle)."""
+    A = gen_mod.convdiff2d(60, 0.5)
+    n = 3600
+    b = orc.spmv(A, gen_mod.uniform(9, n))
+    rc, xo, info_o = orc.gmres(A, b, tol=1e-10, maxit=maxit, m=m)
+    out = {}
+    for single in (1, 0):
+        ctx.set_solver_opts(krylov_dim=m, single_workgroup=single)
+        M = g.Matrix.from_csr(*A)
+        x = dev(np.zeros(n))
+        out[single] = (g.gmres(M, dev(b), x, tol=1e-10, maxit=maxit), host(x))
+    (i1, x1), (i0, x0) = out[1], out[0]
+    want = g.OK if rc == orc.OK else g.ERR_NOT_CONVERGED
+    assert i1["status"] == i0["status"] == want, (i1, i0, info_o)
+    assert abs(i1["iterations"] - i0["iterations"]) <= max(2, i0["iterations"] // 50), (i1, i0)
+    assert abs(i1["iterations"] - info_o["iters"]) <= max(3, info_o["iters"] // 20), (i1, info_o)
+    assert abs(i1["outer_iterations"] - i0["outer_iterations"]) <= 1
+    if want == g.OK:
+        assert relres(orc, A, b, x1) <= 1e-10
+        assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-8
+    else:
+        assert i1["iterations"] == i0["iterations"] == maxit
+        assert np.linalg.norm(x1 - x0) / np.linalg.norm(x0) <= 1e-10
+        assert abs(i1["rel_residual"] - i0["rel_residual"]) <= 1e-10
+
+
 def test_gmres_statuses(g, gen_mod, ctx):
     d = np.array([1.0, 2.0, 3.0] * 17)[:50]
     Dm = g.Matrix.from_csr(np.arange(51, dtype=np.int32), np.arange(50, dtype=np.int32), d)
