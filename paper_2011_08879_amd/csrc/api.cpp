@@ -317,6 +317,12 @@ values own_values(gko_matrix A) { return {A->type(), A->val, A->eval, A->tval}; 
 
 void spmv_dispatch(gko_matrix A, const values &v, double alpha, const void *x, double beta, void *y) {
     hipStream_t s = A->ctx->stream;
+    // No entries: y <- beta y.  The ELL kernels read x[0] for padding slots,
+    // so the kernels below run only when x has an element.
+    if (A->nnz == 0) {
+        HIPC(scale(s, v.t, A->n, beta, y));
+        return;
+    }
     switch (A->fmt) {
         case GKO_FMT_CSR:
             HIPC(spmv_csr(s, v.t, A->n, A->rp, A->col, v.val, x, alpha, beta, y, A->subwarp,

@@ -72,7 +72,7 @@ def poisson(gen_mod, orc):
 @pytest.fixture(scope="module")
 def poisson_oracle_x(orc, poisson):
     """The oracle's FP64 block-Jacobi(8) PCG solution of the config-3 system
-    (serial; about 100 s on the GPU machine's host)."""
+    (serial; about 100 s on one host core)."""
     A, xs, b = poisson
     rc, inv = orc.bj_invert(A, 8)
     rc, x, info = orc.cg(A, b, tol=1e-10, maxit=20000, bj_inv=inv)
