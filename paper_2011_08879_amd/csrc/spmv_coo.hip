@@ -59,7 +59,7 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
     for (int64_t base = cb; base < ce; base += kWave * kCooHoist) {
         // loads of kCooHoist batches first, then their x gathers
         int32_t rb[kCooHoist], cb_[kCooHoist];
-        V vb[kCooHoist], pb[kCooHoist];
+        V vb[kCooHoist], pb[kCooHoist], yb[kCooHoist];
         // first row of the next group (wave-uniform address: a scalar load)
         const int64_t nxt = base + kWave * kCooHoist;
         const int32_t next_group_row = nxt < ce ? row[nxt] : -2;
@@ -75,6 +75,14 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
             }
 #pragma unroll
             for (int j = 0; j < kCooHoist; ++j) pb[j] = vb[j] * x[cb_[j]];
+            // Accumulating (the COO part of HYB): the old y of every lane's
+            // row, read with the group's loads.  Read where a segment ends, it
+            // sat in a branch that waited for it once per batch (lognormal
+            // HYB 192 -> 187 us).  Only this wave writes these rows.
+            if constexpr (ACC) {
+#pragma unroll
+                for (int j = 0; j < kCooHoist; ++j) yb[j] = y[rb[j]];
+            }
         } else {
 #pragma unroll
             for (int j = 0; j < kCooHoist; ++j) {
@@ -86,6 +94,10 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
             }
 #pragma unroll
             for (int j = 0; j < kCooHoist; ++j) pb[j] = cb_[j] >= 0 ? vb[j] * x[cb_[j]] : V(0);
+            if constexpr (ACC) {
+#pragma unroll
+                for (int j = 0; j < kCooHoist; ++j) yb[j] = cb_[j] >= 0 ? y[rb[j]] : V(0);
+            }
         }
 
 #pragma unroll
@@ -120,7 +132,7 @@ __global__ __launch_bounds__(kCooBlock) void spmv_coo_kernel(
             if (seg_end) {
                 if (r == first_row && open_start) head[c] = p;
                 else if (r == last_row && open_end) tail[c] = p;
-                else y[r] = combine(alpha, beta, p, ACC || beta != V(0) ? y[r] : V(0), ACC);
+                else y[r] = combine(alpha, beta, p, ACC ? yb[j] : beta != V(0) ? y[r] : V(0), ACC);
             }
             // a row still open at the batch end carries into the next batch
             carry_row = lane_value(seg_end ? -1 : r, kWave - 1);
