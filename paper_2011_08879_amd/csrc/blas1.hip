@@ -371,7 +371,8 @@ __global__ __launch_bounds__(kRowThreadBlock) void fused_csr_rowthread_kernel(
     __shared__ rowthread_lds<V> L;
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    for (int64_t r0 = (int64_t)blockIdx.x * RT; r0 < n; r0 += (int64_t)gridDim.x * RT) {
+    // each round of the grid stride gives each XCD one contiguous range of rows
+    for (int64_t r0 = xcd_block(blockIdx.x, gridDim.x) * RT; r0 < n; r0 += (int64_t)gridDim.x * RT) {
         const V s = csr_rowthread_sum<V, G>(n, r0, rp, col, val, in, L);
         const int64_t i = r0 + threadIdx.x / G;
         if (i < n && threadIdx.x % G == 0) {
