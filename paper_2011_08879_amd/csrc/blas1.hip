@@ -392,7 +392,8 @@ __global__ __launch_bounds__(kB) void fused_ell_kernel(int64_t n, int64_t K, int
                                                        P pol, red_args ra) {
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    for (int64_t i = 2 * ((int64_t)blockIdx.x * kB + threadIdx.x); i < n;
+    // XCD-contiguous rows in each round of the grid stride (as the plain SpMV)
+    for (int64_t i = 2 * (xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x); i < n;
          i += 2 * (int64_t)gridDim.x * kB) {
         V s0, s1;
         ell_pair_rows(K, ld, i, ecol, eval, in, s0, s1);
@@ -420,7 +421,7 @@ __global__ __launch_bounds__(kB) void fused_sellp_kernel(int64_t n, const int64_
     static_assert(kB % kSellpSlice == 0, "whole slices per workgroup");
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    int64_t i = (int64_t)blockIdx.x * kB + threadIdx.x;
+    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;  // XCD-contiguous rows
     if constexpr (STRIDE) {
         for (; i < n; i += (int64_t)gridDim.x * kB) {
             const V s0 = sellp_row(i, sets, scol, sval, in);
