@@ -371,8 +371,9 @@ __global__ __launch_bounds__(kRowThreadBlock) void fused_csr_rowthread_kernel(
     __shared__ rowthread_lds<V> L;
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    // each round of the grid stride gives each XCD one contiguous range of rows
-    for (int64_t r0 = xcd_block(blockIdx.x, gridDim.x) * RT; r0 < n; r0 += (int64_t)gridDim.x * RT) {
+    // up to kXcdRowsMax rows, each round of the grid stride gives each XCD
+    // one contiguous range of rows
+    for (int64_t r0 = row_block_order(n) * RT; r0 < n; r0 += (int64_t)gridDim.x * RT) {
         const V s = csr_rowthread_sum<V, G>(n, r0, rp, col, val, in, L);
         const int64_t i = r0 + threadIdx.x / G;
         if (i < n && threadIdx.x % G == 0) {
@@ -392,8 +393,8 @@ __global__ __launch_bounds__(kB) void fused_ell_kernel(int64_t n, int64_t K, int
                                                        P pol, red_args ra) {
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    // XCD-contiguous rows in each round of the grid stride (as the plain SpMV)
-    for (int64_t i = 2 * (xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x); i < n;
+    // workgroup order as in the plain SpMV (row_block_order)
+    for (int64_t i = 2 * (row_block_order(n) * kB + threadIdx.x); i < n;
          i += 2 * (int64_t)gridDim.x * kB) {
         V s0, s1;
         ell_pair_rows(K, ld, i, ecol, eval, in, s0, s1);
@@ -421,7 +422,7 @@ __global__ __launch_bounds__(kB) void fused_sellp_kernel(int64_t n, const int64_
     static_assert(kB % kSellpSlice == 0, "whole slices per workgroup");
     if (pol.skip()) return;
     double acc[P::NV] = {};
-    int64_t i = xcd_block(blockIdx.x, gridDim.x) * kB + threadIdx.x;  // XCD-contiguous rows
+    int64_t i = row_block_order(n) * kB + threadIdx.x;
     if constexpr (STRIDE) {
         for (; i < n; i += (int64_t)gridDim.x * kB) {
             const V s0 = sellp_row(i, sets, scol, sval, in);

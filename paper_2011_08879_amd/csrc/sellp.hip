@@ -29,8 +29,8 @@ __global__ __launch_bounds__(kSellpBlock) void spmv_sellp_kernel(int64_t n,
                                                                  const V *__restrict__ sval,
                                                                  const V *__restrict__ x, V alpha,
                                                                  V beta, V *__restrict__ y) {
-    // each XCD takes one contiguous range of slices (stencil 133.5 -> 131.6 us)
-    const int64_t i = xcd_block(blockIdx.x, gridDim.x) * kSellpBlock + threadIdx.x;
+    // up to kXcdRowsMax rows each XCD takes one contiguous range of slices
+    const int64_t i = row_block_order(n) * kSellpBlock + threadIdx.x;
     if (i >= n) return;
     const sellp_slice_of sl = sellp_slice(i, sets);
     if (sl.w > kSellpWide) return;  // the whole wavefront: the wide-slice kernels

@@ -92,10 +92,9 @@ __global__ __launch_bounds__(kRowThreadBlock) void spmv_csr_rowthread_kernel(
     int64_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
     const V *__restrict__ val, const V *__restrict__ x, V alpha, V beta, V *__restrict__ y) {
     __shared__ rowthread_lds<V> L;
-    // each XCD takes one contiguous range of rows, so the x lines that
-    // neighbouring rows share are fetched into one L2 (27-point stencil
-    // 149.5 -> 145.3 us)
-    const int64_t r0 = xcd_block(blockIdx.x, gridDim.x) * (kRowThreadBlock / G);
+    // up to kXcdRowsMax rows each XCD takes one contiguous range of rows, so
+    // the x lines that neighbouring rows share are fetched into one L2
+    const int64_t r0 = row_block_order(n) * (kRowThreadBlock / G);
     const V s = csr_rowthread_sum<V, G>(n, r0, rp, col, val, x, L);
     const int64_t i = r0 + threadIdx.x / G;
     if (i < n && threadIdx.x % G == 0) y[i] = (beta == V(0)) ? alpha * s : alpha * s + beta * y[i];
