@@ -69,6 +69,23 @@ def poisson(gen_mod, orc):
     return A, xs, b
 
 
+@pytest.mark.parametrize("fmt", ["csr", "ell", "sellp"])
+def test_poisson256_spmv_full_size(g, orc, gen_mod, poisson, fmt):
+    """SpMV on the 7-point Poisson 256^3 (16.8M rows): above the row count up
+    to which the row-blocked kernels order their workgroups by XCD, so this
+    covers their hardware-order path against the Dot2 oracle."""
+    import torch
+    A, xs, _ = poisson
+    n = len(A[0]) - 1
+    M = g.Matrix.from_csr(*A).convert(fmt)
+    y = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    g.spmv(M, 1.0, dev(xs), 0.0, y)
+    ref = orc.spmv_dot2(A, xs)
+    absy = orc.spmv_absbound(A, xs)
+    assert_spmv_close(host(y), ref, absy, np.diff(A[0]), False, "poisson256/%s" % fmt)
+    M.close()
+
+
 @pytest.fixture(scope="module")
 def poisson_oracle_x(orc, poisson):
     """The oracle's FP64 block-Jacobi(8) PCG solution of the config-3 system
