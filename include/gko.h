@@ -166,7 +166,8 @@ gko_status gko_matrix_export_sellp(gko_matrix A, int64_t *slice_sets, int32_t *s
 
 /* y <- alpha * A * x + beta * y in A's value type (alpha and beta rounded to
  * it).  x: n_cols device values, y: n_rows device values, both of A's dtype.
- * beta == 0 means y is not read.  x and y must not overlap
+ * beta == 0 means y is not read.  With no entries, y <- beta y and x is not
+ * read (it may be NULL when n_cols == 0).  x and y must not overlap
  * (GKO_ERR_INVALID_ARG).  Asynchronous; deterministic (bitwise repeatable). */
 gko_status gko_spmv(gko_matrix A, double alpha, const void *x, double beta, void *y);
 
